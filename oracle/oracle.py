@@ -1,0 +1,185 @@
+"""ctypes front end of the C oracle (test infrastructure only).
+
+The C source ``relay_oracle.c`` is compiled with gcc (-O2, -ffp-contract=off,
+no fast-math) into ``liboracle_relay.so`` next to this file.  Decoding is split
+into shot chunks run on a thread pool; ctypes releases the GIL during each call,
+so the chunks run in parallel on the host cores.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "relay_oracle.c")
+_SO = os.path.join(_HERE, "liboracle_relay.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library (gcc, canonical FP: no contraction)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class OracleParams(ctypes.Structure):
+    _fields_ = [
+        ("num_legs", ctypes.c_int32),
+        ("iters_first", ctypes.c_int32),
+        ("iters_leg", ctypes.c_int32),
+        ("num_solutions", ctypes.c_int32),
+        ("gamma_first", ctypes.c_float),
+        ("gamma_lo", ctypes.c_float),
+        ("gamma_hi", ctypes.c_float),
+        ("llr_clip", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("anchor", ctypes.c_int32),
+        ("max_total_iters", ctypes.c_int32),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=True)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int, ctypes.c_long
+        L.ro_philox4x32_10.argtypes = [P, P, P]
+        L.ro_philox4x32_10.restype = None
+        L.ro_gamma_f32.argtypes = [ctypes.c_uint64, i32, i32, ctypes.c_float, ctypes.c_float]
+        L.ro_gamma_f32.restype = ctypes.c_float
+        for sfx in ("f32", "f64"):
+            f = getattr(L, f"ro_decode_{sfx}")
+            f.argtypes = [i32, i32, i64, P, P, P, ctypes.POINTER(OracleParams), i64, P, P, P, P, P, P,
+                          P]
+            f.restype = i32
+            f = getattr(L, f"ro_trace_{sfx}")
+            f.argtypes = [i32, i32, i64, P, P, P, ctypes.c_double, P, i32, ctypes.c_double, i64, P, P]
+            f.restype = i32
+            f = getattr(L, f"ro_minsum_trace_{sfx}")
+            f.argtypes = [i32, i32, i64, P, P, P, i32, i64, P, P]
+            f.restype = i32
+        L.ro_sumproduct_trace.argtypes = [i32, i32, i64, P, P, P, i32, i64, P, P]
+        L.ro_sumproduct_trace.restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(key, ctr):
+    k = np.asarray(key, dtype=np.uint32)
+    c = np.asarray(ctr, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ro_philox4x32_10(_ptr(k), _ptr(c), _ptr(out))
+    return out
+
+
+def gamma_f32(seed, leg, j, lo, hi) -> np.float32:
+    return np.float32(lib().ro_gamma_f32(int(seed), int(leg), int(j), float(lo), float(hi)))
+
+
+def _coo(rows, cols):
+    return (np.ascontiguousarray(rows, dtype=np.int32), np.ascontiguousarray(cols, dtype=np.int32))
+
+
+def decode(m, n, rows, cols, prior, params: dict, syn, precision="f32", threads=None,
+           chunk=None, want_llr=False):
+    """Relay-decode syndromes [B, M]; returns dict of corr/conv/legs/iters/weight
+    (and final marginals ``llr`` [B, N] when ``want_llr``)."""
+    rows, cols = _coo(rows, cols)
+    prior = np.ascontiguousarray(prior, dtype=np.float64)
+    syn = np.ascontiguousarray(syn, dtype=np.uint8)
+    b = syn.shape[0]
+    p = OracleParams(**params)
+    corr = np.zeros((b, n), np.uint8)
+    conv = np.zeros(b, np.uint8)
+    legs = np.zeros(b, np.int32)
+    iters = np.zeros(b, np.int32)
+    weight = np.zeros(b, np.float64)
+    llr = np.zeros((b, n), np.float32 if precision == "f32" else np.float64) if want_llr else None
+    fn = getattr(lib(), f"ro_decode_{precision}")
+    threads = threads or os.cpu_count() or 1
+    chunk = chunk or max(1, min(256, (b + threads - 1) // max(threads, 1)))
+
+    def run(s0):
+        s1 = min(b, s0 + chunk)
+        rc = fn(m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(prior), ctypes.byref(p), s1 - s0,
+                _ptr(syn[s0:s1]), _ptr(corr[s0:s1]), _ptr(conv[s0:s1]), _ptr(legs[s0:s1]),
+                _ptr(iters[s0:s1]), _ptr(weight[s0:s1]),
+                _ptr(llr[s0:s1]) if want_llr else None)
+        if rc != 0:
+            raise ValueError(f"oracle decode failed with code {rc}")
+
+    starts = list(range(0, b, chunk))
+    if threads == 1 or len(starts) <= 1:
+        for s in starts:
+            run(s)
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(run, starts))
+    out = {"corr": corr, "conv": conv, "legs": legs, "iters": iters, "weight": weight}
+    if want_llr:
+        out["llr"] = llr
+    return out
+
+
+def trace(m, n, rows, cols, prior, gamma, t_iters, syn, scale=1.0, precision="f32",
+          llr_clip=2.0 ** 64):
+    """Marginal trace [B, T+1, N] of one leg with per-column gamma, no early stop."""
+    rows, cols = _coo(rows, cols)
+    prior = np.ascontiguousarray(prior, dtype=np.float64)
+    dt = np.float32 if precision == "f32" else np.float64
+    gamma = np.ascontiguousarray(np.broadcast_to(np.asarray(gamma, dtype=dt), (n,)))
+    syn = np.ascontiguousarray(syn, dtype=np.uint8)
+    b = syn.shape[0]
+    out = np.zeros((b, t_iters + 1, n), dt)
+    rc = getattr(lib(), f"ro_trace_{precision}")(m, n, rows.size, _ptr(rows), _ptr(cols),
+                                                 _ptr(prior), float(scale), _ptr(gamma),
+                                                 int(t_iters), float(llr_clip), b, _ptr(syn),
+                                                 _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle trace failed with code {rc}")
+    return out
+
+
+def minsum_trace(m, n, rows, cols, llr, t_iters, syn, precision="f32"):
+    rows, cols = _coo(rows, cols)
+    dt = np.float32 if precision == "f32" else np.float64
+    llr = np.ascontiguousarray(llr, dtype=dt)
+    syn = np.ascontiguousarray(syn, dtype=np.uint8)
+    b = syn.shape[0]
+    out = np.zeros((b, t_iters + 1, n), dt)
+    rc = getattr(lib(), f"ro_minsum_trace_{precision}")(m, n, rows.size, _ptr(rows), _ptr(cols),
+                                                        _ptr(llr), int(t_iters), b, _ptr(syn),
+                                                        _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle minsum failed with code {rc}")
+    return out
+
+
+def sumproduct_trace(m, n, rows, cols, llr, t_iters, syn):
+    rows, cols = _coo(rows, cols)
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    syn = np.ascontiguousarray(syn, dtype=np.uint8)
+    b = syn.shape[0]
+    out = np.zeros((b, t_iters + 1, n), np.float64)
+    rc = lib().ro_sumproduct_trace(m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(llr),
+                                   int(t_iters), b, _ptr(syn), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle sum-product failed with code {rc}")
+    return out
