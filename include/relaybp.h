@@ -1,0 +1,200 @@
+/*
+ * relaybp.h -- C ABI of the MI355X (gfx950) Relay-BP decoding library.
+ *
+ * The library decodes large batches of independent syndromes with Relay-BP:
+ * successive legs of memory-augmented min-sum belief propagation (DMem-BP)
+ * over the Tanner graph of a binary check / detector-error-model matrix H.
+ *
+ * Decoding problem (paper Sec. 2.1, circuit-decoding-problem paragraph): a
+ * matrix H in F_2^{M x N}, independent fault probabilities p_j; a fault set F
+ * produces the syndrome sigma = H F over F_2; the decoder returns a
+ * correction F_hat.  Relay (paper Sec. 2.3, Relay decoding) runs up to R legs;
+ * leg r runs at most T_r iterations of DMem-BP with memory strengths
+ * Gamma_r = (gamma_{r,1..N}); leg r >= 2 starts from the final marginals of
+ * leg r-1; a leg stops at the first iteration whose hard decision satisfies
+ * H F_hat = sigma; decoding stops after S such solutions (lowest weight kept).
+ *
+ * Conventions shared by every call:
+ *  - Plain C types only.  Pointers named d_* are device pointers (memory on
+ *    the context's GPU, e.g. a torch tensor's data_ptr()); all others are
+ *    host pointers.  `stream` is a hipStream_t passed as void* (NULL means
+ *    the device's null stream).
+ *  - Ownership: the caller owns every buffer it passes and must keep device
+ *    buffers alive until the enqueued work completes.  A context owns its
+ *    device copies of the graph, priors, parameters and workspace and frees
+ *    them in rb_destroy.
+ *  - Asynchrony: rb_decode and rb_trace only validate their arguments and
+ *    enqueue kernels on `stream`; they return before the GPU work finishes
+ *    and never synchronise or allocate.  A context is used by one stream at
+ *    a time (calls on one context must not overlap on different streams).
+ *  - Errors: every call returns an rb_status.  Argument and shape errors are
+ *    detected on the host before any GPU work is enqueued; the call then has
+ *    no effect.  rb_last_error_message() returns a thread-local description
+ *    of the last failure on the calling thread.
+ *  - Layouts: matrices are row-major and dense in their last dimension;
+ *    batches are indexed by shot first ([B][...]).
+ */
+#ifndef RELAYBP_H
+#define RELAYBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rb_ctx rb_ctx;
+
+typedef enum {
+    RB_OK = 0,
+    RB_E_INVALID_ARG = 1,     /* null pointer, negative count, bad parameter value */
+    RB_E_SHAPE = 2,           /* M, N, index or batch size out of range */
+    RB_E_DUPLICATE_ENTRY = 3, /* a (row, col) pair listed twice (would cancel over F_2) */
+    RB_E_PRIOR_RANGE = 4,     /* a prior outside (0, 1) or not finite */
+    RB_E_DEVICE = 5,          /* HIP runtime failure or no usable device */
+    RB_E_OOM = 6,             /* device or host allocation failed */
+    RB_E_WORKSPACE = 7,       /* caller-provided buffer too small */
+    RB_E_UNSUPPORTED = 8,     /* graph exceeds every kernel configuration built in */
+    RB_E_NONFINITE = 9        /* non-finite value where a finite one is required */
+} rb_status;
+
+/* Anchor of the memory term in legs r >= 2 (leg 1 always uses w_j). */
+enum { RB_ANCHOR_CHAIN = 0, /* lambda^{(r)}(0) = clip(Lambda^{(r-1)}(T_{r-1})), paper Sec. 2.3 */
+       RB_ANCHOR_PRIOR = 1  /* lambda^{(r)}(0) = w_j = log((1-p_j)/p_j) in every leg */ };
+
+/*
+ * Decoder parameters (paper Sec. 2.3 Relay chaining; values used by the paper
+ * in its appendix on Relay resources: S = 1, T_1 = 80, T_r = 60, 300 legs after
+ * the first, gamma_0 = 0.125, gamma ~ U[-0.24, 0.66]).
+ *   num_legs        R, the total number of legs including leg 1 (>= 1)
+ *   iters_first     T_1, iteration cap of leg 1 (>= 1)
+ *   iters_leg       T_r, iteration cap of every leg r >= 2 (>= 1)
+ *   num_solutions   S, stop after this many converged legs (>= 1)
+ *   gamma_first     memory strength of every column in leg 1
+ *   gamma_lo/hi     gamma_{r,j} = lo + (hi - lo) u for r >= 2, u in [0, 1) drawn by
+ *                   Philox4x32-10 (key = seed, counter = (floor(j/4), r, 0, 0), word j mod 4,
+ *                   u = (word >> 8) 2^-24); the same Gamma_r for every shot
+ *   llr_clip        L > 0: messages, marginals and the memory term saturate to [-L, L]
+ *   seed            64-bit Philox key for the memory strengths
+ *   anchor          RB_ANCHOR_CHAIN or RB_ANCHOR_PRIOR
+ *   max_total_iters total iteration cutoff per shot across legs (0 = none); a shot
+ *                   that reaches it without S solutions stops (paper Sec. 7: runs
+ *                   past the cycle cutoff count as failures)
+ */
+typedef struct {
+    int32_t num_legs;
+    int32_t iters_first;
+    int32_t iters_leg;
+    int32_t num_solutions;
+    float gamma_first;
+    float gamma_lo;
+    float gamma_hi;
+    float llr_clip;
+    uint64_t seed;
+    int32_t anchor;
+    int32_t max_total_iters;
+} rb_params;
+
+/* Kernel configuration chosen for a context (read-only diagnostics). */
+typedef struct {
+    int32_t M, N;
+    int64_t num_edges;      /* E = nnz(H) */
+    int32_t max_row_degree, max_col_degree;
+    int32_t variant;        /* index into the built-in configuration table */
+    int32_t lanes_per_shot; /* G: lanes cooperating on one syndrome */
+    int32_t checks_per_lane, row_slots, cols_per_lane, col_slots;
+    int32_t shots_per_block, threads_per_block;
+    int32_t lds_bytes_per_block;
+    int32_t blocks_per_cu, grid_blocks;
+    int32_t num_variants;   /* size of the configuration table */
+} rb_info;
+
+/* Fills *out with the paper's parameters (R = 301 legs in total, T_1 = 80,
+ * T_r = 60, S = 1, gamma_0 = 0.125, gamma in [-0.24, 0.66], L = 2^64,
+ * anchor CHAIN, no cutoff, seed 0x52454C4159).  RB_E_INVALID_ARG if out is NULL. */
+rb_status rb_params_default(rb_params *out);
+
+/*
+ * Builds a decoder for H (COO) and priors on `device`.
+ *   M, N          rows (checks / detectors) and columns (faults), both >= 1
+ *   nnz           number of ones in H (>= 0); rows[k], cols[k] for k < nnz are
+ *                 host int32 arrays with 0 <= rows[k] < M, 0 <= cols[k] < N, in
+ *                 any order, without duplicates; empty rows and columns are allowed
+ *   prior_p       host double[N], each in (0, 1); w_j = log((1-p_j)/p_j) is
+ *                 evaluated in FP64 and rounded to FP32 (p_j = 1/2 gives w_j = 0)
+ *   params        host pointer, copied
+ * On success *out receives a new context (release with rb_destroy).  Builds
+ * the check-major (CSR) and fault-major (CSC) edge layouts, the per-lane
+ * gather tables of the chosen kernel configuration and the table of memory
+ * strengths Gamma_1..Gamma_R on the device.  This call allocates and
+ * synchronises the device.
+ */
+rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32_t *rows,
+                    const int32_t *cols, const double *prior_p, const rb_params *params,
+                    int32_t device);
+
+/* Releases a context (NULL is a no-op).  Synchronises the context's device. */
+void rb_destroy(rb_ctx *ctx);
+
+/*
+ * Relay-decodes B syndromes (paper Sec. 2.3: Relay decoding, convergence
+ * criterion, Relay chaining).
+ *   d_syndromes  uint8 [B][M], nonzero = 1
+ *   d_corr       uint8 [B][N] out: the lowest-weight converged solution, or the
+ *                last hard decision (F_hat_j = 1 iff Lambda_j < 0) if no leg converged
+ *   d_conv       uint8 [B] out: 1 iff at least one leg converged (H F_hat = sigma)
+ *   d_legs       int32 [B] out: index (1-based) of the last leg started
+ *   d_iters      int32 [B] out: iterations executed over all legs
+ *   d_weight     double [B] out or NULL: sum_j F_hat_j w_j of d_corr
+ *   d_final_llr  float [B][N] out or NULL: marginals Lambda after the last iteration
+ * B == 0 is a no-op.  Returns RB_E_INVALID_ARG for null required pointers or
+ * B < 0.  Enqueues on `stream`; no allocation, no synchronisation.
+ */
+rb_status rb_decode(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, uint8_t *d_corr,
+                    uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters, double *d_weight,
+                    float *d_final_llr, void *stream);
+
+/*
+ * Runs exactly T iterations of one DMem-BP leg from the leg-1 initialisation
+ * (paper Sec. 2.3: nu(0) = lambda(0) = Lambda(0) = w) with per-column memory
+ * strengths and scaled channel LLRs w'_j = scale * w_j, without the
+ * convergence stop, and records the marginals.
+ *   d_syndromes  uint8 [B][M]
+ *   d_gamma      float [N] memory strengths gamma_j (device)
+ *   T            >= 0 iterations
+ *   d_trace      float [B][T+1][N] out: Lambda_j(t) for t = 0..T
+ * Same kernels as rb_decode (message-level parity hook).  Enqueues on `stream`.
+ */
+rb_status rb_trace(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, const float *d_gamma,
+                   float scale, int32_t T, float *d_trace, void *stream);
+
+/* Copies the FP32 channel LLRs w_j (host float[N]) -- test hook. */
+rb_status rb_get_llr(const rb_ctx *ctx, float *host_w);
+
+/* Copies the device table of memory strengths (host float[R][N], row r-1 =
+ * Gamma_r) -- test hook for the counter-based generator. */
+rb_status rb_get_gamma_table(const rb_ctx *ctx, float *host_gamma);
+
+/* Fills *info with the context's kernel configuration. */
+rb_status rb_get_info(const rb_ctx *ctx, rb_info *info);
+
+/* Selects kernel configuration `variant` (index into the built-in table) for
+ * later decodes; RB_E_UNSUPPORTED if the graph does not fit it.  Rebuilds the
+ * gather tables (allocates and synchronises). */
+rb_status rb_set_variant(rb_ctx *ctx, int32_t variant);
+
+/* Synchronises the context's device and reports asynchronous HIP errors. */
+rb_status rb_sync_status(rb_ctx *ctx);
+
+/* Static description of a status code (never NULL). */
+const char *rb_status_string(rb_status status);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *rb_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RELAYBP_H */

@@ -1,0 +1,226 @@
+"""ctypes binding of the Relay-BP C ABI (``include/relaybp.h``).
+
+Argument marshalling only: every step of decoding runs in the HIP kernels of
+``librelaybp.so``.  Device buffers are torch CUDA (HIP) tensors; the stream is
+torch's current stream of the tensor's device.  There is no CPU fallback: if
+the library is not built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librelaybp.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "relaybp.h")
+
+STATUS = {
+    0: "RB_OK", 1: "RB_E_INVALID_ARG", 2: "RB_E_SHAPE", 3: "RB_E_DUPLICATE_ENTRY",
+    4: "RB_E_PRIOR_RANGE", 5: "RB_E_DEVICE", 6: "RB_E_OOM", 7: "RB_E_WORKSPACE",
+    8: "RB_E_UNSUPPORTED", 9: "RB_E_NONFINITE",
+}
+ANCHOR_CHAIN, ANCHOR_PRIOR = 0, 1
+
+
+class RelayError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class RBParams(ctypes.Structure):
+    _fields_ = [
+        ("num_legs", ctypes.c_int32),
+        ("iters_first", ctypes.c_int32),
+        ("iters_leg", ctypes.c_int32),
+        ("num_solutions", ctypes.c_int32),
+        ("gamma_first", ctypes.c_float),
+        ("gamma_lo", ctypes.c_float),
+        ("gamma_hi", ctypes.c_float),
+        ("llr_clip", ctypes.c_float),
+        ("seed", ctypes.c_uint64),
+        ("anchor", ctypes.c_int32),
+        ("max_total_iters", ctypes.c_int32),
+    ]
+
+
+class RBInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("M", "N")] + [("num_edges", ctypes.c_int64)] + [
+        (n, ctypes.c_int32) for n in (
+            "max_row_degree", "max_col_degree", "variant", "lanes_per_shot", "checks_per_lane",
+            "row_slots", "cols_per_lane", "col_slots", "shots_per_block", "threads_per_block",
+            "lds_bytes_per_block", "blocks_per_cu", "grid_blocks", "num_variants")]
+
+
+_lib = None
+
+
+def load_library():
+    """Loads librelaybp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2511_21660_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.rb_params_default.argtypes = [ctypes.POINTER(RBParams)]
+    L.rb_create.argtypes = [ctypes.POINTER(P), i32, i32, i64, P, P, P, ctypes.POINTER(RBParams), i32]
+    L.rb_destroy.argtypes = [P]
+    L.rb_destroy.restype = None
+    L.rb_decode.argtypes = [P, i64, P, P, P, P, P, P, P, P]
+    L.rb_trace.argtypes = [P, i64, P, P, ctypes.c_float, i32, P, P]
+    L.rb_get_llr.argtypes = [P, P]
+    L.rb_get_gamma_table.argtypes = [P, P]
+    L.rb_get_info.argtypes = [P, ctypes.POINTER(RBInfo)]
+    L.rb_set_variant.argtypes = [P, i32]
+    L.rb_sync_status.argtypes = [P]
+    L.rb_status_string.argtypes = [ctypes.c_int]
+    L.rb_status_string.restype = ctypes.c_char_p
+    L.rb_last_error_message.argtypes = []
+    L.rb_last_error_message.restype = ctypes.c_char_p
+    for name in ("rb_params_default", "rb_create", "rb_decode", "rb_trace", "rb_get_llr",
+                 "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def header_functions(path: str = HEADER_PATH):
+    """Names of the functions declared in the public header."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rb_[a-z_]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != 0:
+        L = load_library()
+        raise RelayError(status, L.rb_last_error_message().decode())
+
+
+def default_params(**overrides) -> RBParams:
+    p = RBParams()
+    _check(load_library().rb_params_default(ctypes.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Decoder:
+    """Relay-BP decoder for one check matrix and prior vector on one GPU."""
+
+    def __init__(self, m, n, rows, cols, prior, params=None, device=0, **overrides):
+        L = load_library()
+        self.m, self.n = int(m), int(n)
+        self.device = int(device)
+        if params is None:
+            params = default_params(**overrides)
+        elif isinstance(params, dict):
+            params = default_params(**params, **overrides)
+        self.params = params
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        prior = np.ascontiguousarray(np.broadcast_to(np.asarray(prior, np.float64), (self.n,)))
+        h = ctypes.c_void_p()
+        _check(L.rb_create(ctypes.byref(h), self.m, self.n, rows.size,
+                           rows.ctypes.data_as(ctypes.c_void_p), cols.ctypes.data_as(ctypes.c_void_p),
+                           prior.ctypes.data_as(ctypes.c_void_p), ctypes.byref(params), self.device))
+        self._h = h
+
+    @classmethod
+    def from_problem(cls, problem, device=0, **params):
+        return cls(problem.m, problem.n, problem.rows, problem.cols, problem.prior,
+                   device=device, **params)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().rb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self):
+        import torch
+
+        return torch.device("cuda", self.device)
+
+    def decode(self, syndromes, want_weight=True, want_llr=False, out=None):
+        """syndromes: uint8 CUDA tensor [B, M].  Returns a dict of CUDA tensors
+        corr [B, N] u8, conv [B] u8, legs [B] i32, iters [B] i32, and optionally
+        weight [B] f64 and llr [B, N] f32.  Work is enqueued on the current stream."""
+        import torch
+
+        if syndromes.dtype != torch.uint8 or syndromes.dim() != 2 or syndromes.shape[1] != self.m:
+            raise ValueError(f"syndromes must be uint8 [B, {self.m}]")
+        if not syndromes.is_cuda:
+            raise ValueError("syndromes must be a CUDA (HIP) tensor")
+        syndromes = syndromes.contiguous()
+        b = syndromes.shape[0]
+        dev = syndromes.device
+        if out is None:
+            out = {
+                "corr": torch.empty((b, self.n), dtype=torch.uint8, device=dev),
+                "conv": torch.empty(b, dtype=torch.uint8, device=dev),
+                "legs": torch.empty(b, dtype=torch.int32, device=dev),
+                "iters": torch.empty(b, dtype=torch.int32, device=dev),
+            }
+            if want_weight:
+                out["weight"] = torch.empty(b, dtype=torch.float64, device=dev)
+            if want_llr:
+                out["llr"] = torch.empty((b, self.n), dtype=torch.float32, device=dev)
+        _check(load_library().rb_decode(self._h, b, _ptr(syndromes), _ptr(out["corr"]),
+                                        _ptr(out["conv"]), _ptr(out["legs"]), _ptr(out["iters"]),
+                                        _ptr(out.get("weight")), _ptr(out.get("llr")),
+                                        _stream(dev)))
+        return out
+
+    def trace(self, syndromes, gamma, t_iters, scale=1.0):
+        """Marginals Lambda(t), t = 0..T, of one leg with per-column gamma: [B, T+1, N]."""
+        import torch
+
+        syndromes = syndromes.contiguous()
+        gamma = gamma.to(device=syndromes.device, dtype=torch.float32).contiguous()
+        b = syndromes.shape[0]
+        tr = torch.empty((b, t_iters + 1, self.n), dtype=torch.float32, device=syndromes.device)
+        _check(load_library().rb_trace(self._h, b, _ptr(syndromes), _ptr(gamma), float(scale),
+                                       int(t_iters), _ptr(tr), _stream(syndromes.device)))
+        return tr
+
+    def llr(self) -> np.ndarray:
+        w = np.zeros(self.n, np.float32)
+        _check(load_library().rb_get_llr(self._h, w.ctypes.data_as(ctypes.c_void_p)))
+        return w
+
+    def gamma_table(self) -> np.ndarray:
+        g = np.zeros((self.params.num_legs, self.n), np.float32)
+        _check(load_library().rb_get_gamma_table(self._h, g.ctypes.data_as(ctypes.c_void_p)))
+        return g
+
+    def info(self) -> dict:
+        inf = RBInfo()
+        _check(load_library().rb_get_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in RBInfo._fields_}
+
+    def set_variant(self, v: int):
+        _check(load_library().rb_set_variant(self._h, int(v)))
+
+    def sync(self):
+        _check(load_library().rb_sync_status(self._h))
