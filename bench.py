@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100000, help="oracle shots per p")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="after timing, run one plain device copy kernel of MB MiB (int32 "
+                         "bitwise_not: reads and writes MB MiB) to scale HBM counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -178,6 +181,16 @@ def main():
                          f"({4 * n_cpu} of {n_shots}), same inputs, {tc:.1f} s",
                "paired_with_gpu_bit_exact": agree}
 
+    copy_bytes = 0
+    if args.calibrate_copy > 0:
+        n_el = args.calibrate_copy * (1 << 20) // 4
+        src = torch.arange(n_el, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.bitwise_not(src, out=dst)
+        torch.cuda.synchronize()
+        copy_bytes = n_el * 4
+
     info = decs[0].info()
     line = {
         "metric": "syndromes decoded/s at matched LER; edge-updates/s and % HBM/LDS roofline",
@@ -199,6 +212,8 @@ def main():
                    "gamma_first": 0.125, "gamma_range": [-0.24, 0.66], "anchor": "chain",
                    "parallelism": "single_gpu"},
         "edge_updates_per_s": eu_per_s,
+        "launch_ms_by_p": {str(p): float(np.mean([pl[q] for pl in per_launch]))
+                           for q, p in enumerate(ps)},
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS,
                      "unit": "Tops/s", "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": None,
                      "kernel": "relay_group_kernel", "kernel_ms_per_launch": kernel_ms,
@@ -212,6 +227,8 @@ def main():
                                                "grid_blocks")},
         "cpu_baseline": cpu,
     }
+    if copy_bytes:
+        line["copy_calibration_bytes_each_way"] = copy_bytes
     print(json.dumps(line), flush=True)
 
 

@@ -105,6 +105,7 @@ typedef struct {
     int32_t lanes_per_shot; /* G: lanes cooperating on one syndrome */
     int32_t checks_per_lane, row_slots, cols_per_lane, col_slots;
     int32_t shots_per_block, threads_per_block;
+    int32_t waves_per_simd_target; /* occupancy the kernel's register budget aims at */
     int32_t lds_bytes_per_block;
     int32_t blocks_per_cu, grid_blocks;
     int32_t num_variants;   /* size of the configuration table */
@@ -183,6 +184,121 @@ rb_status rb_get_info(const rb_ctx *ctx, rb_info *info);
  * later decodes; RB_E_UNSUPPORTED if the graph does not fit it.  Rebuilds the
  * gather tables (allocates and synchronises). */
 rb_status rb_set_variant(rb_ctx *ctx, int32_t variant);
+
+/*
+ * Measures every built-in kernel configuration the graph fits on B syndromes
+ * (d_syndromes, uint8 [B][M] on the device), `reps` timed launches each after
+ * one warm-up, and keeps the fastest for later decodes.  Results do not
+ * depend on the configuration (only speed does).  Allocates scratch outputs,
+ * uses the null stream and synchronises the device: call it once after
+ * rb_create, not inside a captured or latency-critical region.
+ *   chosen_variant  out (nullable): index of the configuration kept
+ *   best_ms         out (nullable): its mean time per decode, milliseconds
+ */
+rb_status rb_autotune(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, int32_t reps,
+                      int32_t *chosen_variant, float *best_ms);
+
+/*
+ * Longest-first scheduling for rb_decode: allocates (once, synchronising the
+ * device) a workspace for batches of up to B syndromes.  Decodes of at most B
+ * syndromes then first sort their shots by decreasing syndrome weight on the
+ * device, so that hard syndromes start early and the persistent queue ends
+ * with short ones; results are identical, only the order of work changes.
+ * Block-kernel (large-graph) contexts ignore it.  Not for mixed contexts.
+ */
+rb_status rb_reserve(rb_ctx *ctx, int64_t B);
+
+/* Bytes of device workspace rb_decode_multi needs for B syndromes (also the
+ * size rb_reserve allocates for a single-code context). */
+size_t rb_workspace_size(const rb_ctx *ctx, int64_t B);
+
+/* One code of a mixed batch (same meaning as the arguments of rb_create). */
+typedef struct {
+    int32_t M, N;
+    int64_t nnz;
+    const int32_t *rows;
+    const int32_t *cols;
+    const double *prior_p;
+} rb_code_desc;
+
+/*
+ * Builds one decoder for several codes (1..64) whose syndromes are decoded
+ * together by rb_decode_multi in one persistent launch.  Every code is planned
+ * on a tile of the mixed kernel (small and medium graphs; RB_E_UNSUPPORTED
+ * otherwise) and shares `params`.  Allocates and synchronises the device.
+ */
+rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *codes,
+                          const rb_params *params, int32_t device);
+
+/*
+ * Relay-decodes B syndromes of mixed codes in one launch (paper Sec. 2.3
+ * per syndrome; the batching is this library's).  Let M_max / N_max be the
+ * largest M / N over the codes.
+ *   d_code_id    int32 [B]: code of each syndrome (index into the rb_create_multi
+ *                list); a shot with an id outside [0, n_codes) is skipped and its
+ *                outputs are left untouched
+ *   d_syndromes  uint8 [B][M_max]: row b holds the code's M syndrome bits first
+ *   d_corr       uint8 [B][N_max] out (first N entries of row b are meaningful);
+ *   d_conv, d_legs, d_iters, d_weight, d_final_llr ([B][N_max]) as in rb_decode
+ *   d_workspace  device buffer of at least rb_workspace_size(ctx, B) bytes, owned
+ *                by the caller, not used concurrently by another call
+ * Per code the shots are ordered by decreasing syndrome weight; each wave of
+ * the launch decodes one code at a time with that code's tile.  Enqueues on
+ * `stream` only (no allocation, no synchronisation, no memset): the call can
+ * be captured in a hipGraph and replayed.  Results equal per-code rb_decode.
+ */
+rb_status rb_decode_multi(rb_ctx *ctx, int64_t B, const int32_t *d_code_id,
+                          const uint8_t *d_syndromes, uint8_t *d_corr, uint8_t *d_conv,
+                          int32_t *d_legs, int32_t *d_iters, double *d_weight, float *d_final_llr,
+                          void *d_workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Autotunes a mixed context: for every code k with sample_b[k] > 0, times each
+ * tile of the mixed kernel that fits the code on d_samples[k] (uint8
+ * [sample_b[k]][M_k], device) and keeps the fastest.  chosen_variants
+ * (nullable, int32 [n_codes]) receives the configuration kept per code.
+ * Allocates scratch and synchronises the device.
+ */
+rb_status rb_autotune_multi(rb_ctx *ctx, const int64_t *sample_b, const uint8_t *const *d_samples,
+                            int32_t reps, int32_t *chosen_variants);
+
+/*
+ * Differentiable decoding (learned memory strengths).  The forward pass is one
+ * DMem-BP leg from the leg-1 initialisation (paper Sec. 2.3) run for exactly T
+ * iterations with learnable per-column memory strengths gamma_j and channel
+ * LLRs w'_j = s * w_j with a learnable scale s, in the decoder's FP32
+ * arithmetic (Lambda(T) equals rb_trace's last row); it checkpoints the
+ * messages every `ckpt_every` iterations into a caller-owned tape.  The
+ * backward pass is the hand-written adjoint of that unrolled min-sum: it
+ * recomputes each segment from its checkpoint and sweeps it in reverse,
+ * routing gradients through the check minima (argmin / second argmin) and not
+ * through signs or saturated clips.
+ *
+ * rb_train_tape_size: bytes of tape for (B, T, ckpt_every); 0 on bad input.
+ */
+size_t rb_train_tape_size(const rb_ctx *ctx, int64_t B, int32_t T, int32_t ckpt_every);
+
+/*
+ * Forward pass.  d_syndromes uint8 [B][M]; d_gamma float [N] and d_scale
+ * float [1] on the device (read when the kernel runs, so a training loop never
+ * synchronises); d_llr_out float [B][N] out: Lambda(T); d_tape at least
+ * rb_train_tape_size bytes, caller-owned, kept until rb_backward has run.
+ * RB_E_UNSUPPORTED for graphs whose training state exceeds 64 KiB of LDS.
+ */
+rb_status rb_forward_train(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, const float *d_gamma,
+                           const float *d_scale, int32_t T, int32_t ckpt_every, float *d_llr_out,
+                           void *d_tape, size_t tape_bytes, void *stream);
+
+/*
+ * Backward pass for the same (B, syndromes, gamma, scale, T, ckpt_every, tape)
+ * as the preceding rb_forward_train.  d_dllr float [B][N]: dLoss/dLambda(T).
+ * d_dgamma float [N] and d_dscale float [1] are overwritten with dLoss/dgamma
+ * and dLoss/ds summed over the batch in a fixed order (deterministic).
+ */
+rb_status rb_backward(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, const float *d_gamma,
+                      const float *d_scale, int32_t T, int32_t ckpt_every, void *d_tape,
+                      size_t tape_bytes, const float *d_dllr, float *d_dgamma, float *d_dscale,
+                      void *stream);
 
 /* Synchronises the context's device and reports asynchronous HIP errors. */
 rb_status rb_sync_status(rb_ctx *ctx);

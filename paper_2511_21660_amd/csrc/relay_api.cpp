@@ -61,10 +61,26 @@ struct rb_ctx {
     uint32_t *d_lam_off = nullptr;
     uint32_t *d_mu_off = nullptr;
     unsigned long long *d_queue = nullptr;
-    // plan
+    // plan: variants [0, num_variants) are group-kernel tiles, then block-kernel shapes
     int variant = -1;
+    bool block = false;
     rb::TileShape shape{};
-    uint32_t slot_bytes = 0, lampad_off = 0, mupad_off = 0, mu0_off = 0;
+    rb::BlockShape bshape{};
+    uint32_t red_off = 0;
+    int32_t *d_chk_row = nullptr, *d_wave_deg = nullptr, *d_wave_base = nullptr;
+    // longest-first shot lists for single-code decodes (rb_reserve)
+    void *d_ws = nullptr;
+    int64_t ws_capacity = 0;
+    int32_t *d_code_m = nullptr;  // [ncodes] rows per code (1 entry for a single code)
+    // mixed-code context (rb_create_multi)
+    bool multi = false;
+    std::vector<rb_ctx *> subs;
+    rb::CodeStatic *d_codes = nullptr;
+    unsigned long long *d_queues = nullptr;
+    int32_t m_max = 0, n_max = 0;
+    // CSR / CSC on the device (training kernels)
+    int32_t *d_rowptr = nullptr, *d_colidx = nullptr, *d_colptr = nullptr, *d_cedge = nullptr;
+    uint32_t lampad_off = 0, mupad_off = 0, mu0_off = 0;
     int lds_bytes = 0;
     int blocks_per_cu[2] = {0, 0};  // [trace]
     int num_cu = 0;
@@ -75,20 +91,27 @@ namespace {
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 struct Layout {
-    uint32_t slot_bytes, lampad_off, mupad_off, mu0_off;
+    uint32_t lampad_off, mupad_off, mu0_off;  // interleaved byte offsets (word w -> 4 * w * NS)
+    uint32_t word;                            // bytes between consecutive words of a slot
+    int rs;                                   // words per check-message row
     int lds_bytes;
 };
 
+// Slot layout in words: Lambda[0..G*VPT) (faults j >= N are spare words the
+// padded lanes write), +inf pad, -0 pad, then G*CPT check-message rows of
+// RS = DC|1 words.  The NS = 64/G slots of a wave are interleaved word by word.
 Layout slot_layout(const rb::TileShape &s, int N) {
     Layout l{};
-    l.lampad_off = 4u * (uint32_t)N;
-    l.mupad_off = l.lampad_off + 4u;
-    l.mu0_off = (l.mupad_off + 4u + 7u) & ~7u;
-    uint32_t words = (l.mu0_off + 4u * (uint32_t)(s.G * s.CPT * s.DC)) / 4u;
-    words = (words + 1u) & ~1u;
-    while (words % 32u != 2u) words += 2u;  // spread slots over LDS banks
-    l.slot_bytes = 4u * words;
-    l.lds_bytes = (int)(l.slot_bytes * (uint32_t)(64 / s.G));
+    const uint32_t ns = (uint32_t)(64 / s.G);
+    const uint32_t nl = (uint32_t)std::max(N, s.G * s.VPT);
+    l.word = 4u * ns;
+    l.rs = s.DC | 1;
+    l.lampad_off = l.word * nl;
+    l.mupad_off = l.word * (nl + 1);
+    l.mu0_off = l.word * (nl + 2);
+    const uint64_t words = (uint64_t)(nl + 2) + (uint64_t)s.G * s.CPT * l.rs;
+    const uint64_t bytes = words * l.word;
+    l.lds_bytes = bytes > (1u << 30) ? (1 << 30) : (int)bytes;
     return l;
 }
 
@@ -98,25 +121,31 @@ bool variant_fits(const rb_ctx *c, const rb::TileShape &s) {
     return slot_layout(s, c->N).lds_bytes <= 64 * 1024;
 }
 
-// Estimated lane-operations per shot-iteration (lockstep: a slot pays for all
-// of its padded rows and columns): about 10 per check edge, 2 per fault edge,
-// 6 per fault.
+// Initial choice before any measurement: estimated lane-operations per
+// shot-iteration (a slot pays for all of its padded rows and columns: about
+// 10 per check edge, 2 per fault edge, 6 per fault), discounted by the
+// occupancy the register budget allows.  rb_autotune replaces this guess by
+// measurement.
 double variant_cost(const rb::TileShape &s) {
-    return (double)s.G * (10.0 * s.CPT * s.DC + 2.0 * s.VPT * s.DV + 6.0 * s.VPT);
+    const double work = (double)s.G * (10.0 * s.CPT * s.DC + 2.0 * s.VPT * s.DV + 6.0 * s.VPT);
+    const double occ = s.waves >= 4 ? 1.0 : s.waves == 3 ? 1.1 : s.waves == 2 ? 1.3 : 1.8;
+    return work * occ;
 }
 
 rb_status build_plan(rb_ctx *c, int v) {
     const rb::TileShape s = rb::variant_shape(v);
     const Layout lay = slot_layout(s, c->N);
-    std::vector<uint32_t> lam((size_t)s.G * s.CPT * s.DC, lay.lampad_off);
-    std::vector<uint32_t> mu((size_t)s.G * s.VPT * s.DV, lay.mupad_off);
+    const int nl = s.CPT * s.DC, nm = s.VPT * s.DV;
+    const int nlp = (nl + 1) / 2, nmp = (nm + 1) / 2;
+    std::vector<uint16_t> lam16((size_t)s.G * nlp * 2, (uint16_t)lay.lampad_off);
+    std::vector<uint16_t> mu16((size_t)s.G * nmp * 2, (uint16_t)lay.mupad_off);
     for (int g = 0; g < s.G; ++g) {
         for (int cc = 0; cc < s.CPT; ++cc) {
             const int i = g + s.G * cc;
             if (i >= c->M) continue;
             const int64_t b = c->rowptr[i], e = c->rowptr[i + 1];
             for (int64_t k = 0; k < e - b; ++k)
-                lam[((size_t)g * s.CPT + cc) * s.DC + k] = 4u * (uint32_t)c->colidx[b + k];
+                lam16[(size_t)g * nlp * 2 + cc * s.DC + k] = (uint16_t)(lay.word * (uint32_t)c->colidx[b + k]);
         }
         for (int vv = 0; vv < s.VPT; ++vv) {
             const int j = g + s.G * vv;
@@ -124,11 +153,15 @@ rb_status build_plan(rb_ctx *c, int v) {
             const int64_t b = c->colptr[j], e = c->colptr[j + 1];
             for (int64_t k = 0; k < e - b; ++k) {
                 const int i = c->rowidx[b + k];
-                const uint32_t word = (uint32_t)i * s.DC + (uint32_t)c->cpos[b + k];
-                mu[((size_t)g * s.VPT + vv) * s.DV + k] = lay.mu0_off + 4u * word;
+                const uint32_t word = (uint32_t)i * (uint32_t)lay.rs + (uint32_t)c->cpos[b + k];
+                mu16[(size_t)g * nmp * 2 + vv * s.DV + k] = (uint16_t)(lay.mu0_off + lay.word * word);
             }
         }
     }
+    // pack pairs (entry 2q in the low half, 2q+1 in the high half)
+    std::vector<uint32_t> lam((size_t)s.G * nlp), mu((size_t)s.G * nmp);
+    for (size_t q = 0; q < lam.size(); ++q) lam[q] = (uint32_t)lam16[2 * q] | ((uint32_t)lam16[2 * q + 1] << 16);
+    for (size_t q = 0; q < mu.size(); ++q) mu[q] = (uint32_t)mu16[2 * q] | ((uint32_t)mu16[2 * q + 1] << 16);
     (void)hipFree(c->d_lam_off);
     (void)hipFree(c->d_mu_off);
     c->d_lam_off = nullptr;
@@ -137,9 +170,13 @@ rb_status build_plan(rb_ctx *c, int v) {
     RB_HIP(hipMalloc(&c->d_mu_off, mu.size() * 4), "hipMalloc(mu_off)");
     RB_HIP(hipMemcpy(c->d_lam_off, lam.data(), lam.size() * 4, hipMemcpyHostToDevice), "copy lam_off");
     RB_HIP(hipMemcpy(c->d_mu_off, mu.data(), mu.size() * 4, hipMemcpyHostToDevice), "copy mu_off");
+    {
+        size_t st_lds = 0;
+        RB_HIP(rb::variant_static_lds(v, &st_lds), "kernel attributes");
+        if (st_lds != 0) return fail(RB_E_DEVICE, "internal: group kernel uses static LDS");
+    }
     c->variant = v;
     c->shape = s;
-    c->slot_bytes = lay.slot_bytes;
     c->lampad_off = lay.lampad_off;
     c->mupad_off = lay.mupad_off;
     c->mu0_off = lay.mu0_off;
@@ -153,6 +190,156 @@ rb_status build_plan(rb_ctx *c, int v) {
         c->blocks_per_cu[tr] = blocks;
     }
     return RB_OK;
+}
+
+int total_variants() { return rb::num_variants() + rb::num_block_variants(); }
+
+struct BlockLayout {
+    uint32_t lampad_off, mupad_off, red_off, mu0_off;
+    int lds_bytes;
+    int npad;
+};
+
+// Block-kernel LDS: Lambda[TPB*VPT], +inf cell, -0 cell, reduction scratch,
+// then the wave-ELL message rows (wave w: wave_deg[w] rows of 64 words).
+BlockLayout block_layout(const rb::BlockShape &s, int64_t msg_words) {
+    BlockLayout l{};
+    l.npad = s.TPB * s.VPT;
+    l.lampad_off = 4u * (uint32_t)l.npad;
+    l.mupad_off = l.lampad_off + 4u;
+    l.red_off = (l.mupad_off + 4u + 7u) & ~7u;
+    l.mu0_off = (l.red_off + 8u * (uint32_t)(s.TPB / 64) + 8u + 15u) & ~15u;
+    const int64_t bytes = (int64_t)l.mu0_off + 4 * msg_words;
+    l.lds_bytes = bytes > (1 << 30) ? (1 << 30) : (int)bytes;
+    return l;
+}
+
+// checks sorted by decreasing degree (stable); wave-ELL row counts
+void block_order(const rb_ctx *c, const rb::BlockShape &s, std::vector<int32_t> &order,
+                 std::vector<int32_t> &wdeg, std::vector<int32_t> &wbase, int64_t &words) {
+    order.resize((size_t)c->M);
+    for (int32_t i = 0; i < c->M; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return (c->rowptr[x + 1] - c->rowptr[x]) > (c->rowptr[y + 1] - c->rowptr[y]);
+    });
+    const int nw = s.TPB / 64;
+    wdeg.assign((size_t)nw, 0);
+    wbase.assign((size_t)nw, 0);
+    for (int32_t t = 0; t < c->M; ++t) {
+        const int32_t i = order[t];
+        wdeg[t / 64] = std::max<int32_t>(wdeg[t / 64], (int32_t)(c->rowptr[i + 1] - c->rowptr[i]));
+    }
+    words = 0;
+    for (int w = 0; w < nw; ++w) {
+        wbase[w] = (int32_t)words;
+        words += (int64_t)wdeg[w] * 64;
+    }
+}
+
+bool block_fits(const rb_ctx *c, const rb::BlockShape &s) {
+    if (c->M > s.TPB || ceil_div(c->N, s.TPB) > s.VPT) return false;
+    if (c->max_row > s.DCMAX || c->max_col > s.DV) return false;
+    std::vector<int32_t> order, wdeg, wbase;
+    int64_t words = 0;
+    block_order(c, s, order, wdeg, wbase, words);
+    const BlockLayout l = block_layout(s, words);
+    if (l.lampad_off + 8u > 65535u) return false;                   // 16-bit Lambda addresses
+    if ((int64_t)(l.mu0_off / 4u) + words > 65535) return false;    // 16-bit message indices
+    return l.lds_bytes <= 160 * 1024;
+}
+
+bool any_fits(const rb_ctx *c, int v) {
+    if (v < rb::num_variants()) return variant_fits(c, rb::variant_shape(v));
+    return block_fits(c, rb::block_variant_shape(v - rb::num_variants()));
+}
+
+template <typename T>
+rb_status upload(T **dst, const std::vector<T> &src, const char *what) {
+    (void)hipFree(*dst);
+    *dst = nullptr;
+    RB_HIP(hipMalloc(dst, std::max<size_t>(1, src.size()) * sizeof(T)), what);
+    RB_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), what);
+    return RB_OK;
+}
+
+rb_status build_block_plan(rb_ctx *c, int bv) {
+    const rb::BlockShape s = rb::block_variant_shape(bv);
+    std::vector<int32_t> order, wdeg, wbase;
+    int64_t words = 0;
+    block_order(c, s, order, wdeg, wbase, words);
+    const BlockLayout lay = block_layout(s, words);
+    std::vector<int32_t> rank((size_t)c->M), chk_row((size_t)s.TPB, -1);
+    for (int32_t t = 0; t < c->M; ++t) {
+        rank[order[t]] = t;
+        chk_row[t] = order[t];
+    }
+    const int ncp = s.DCMAX / 2, nmp = s.VPT * s.DV / 2;
+    std::vector<uint16_t> col16((size_t)s.TPB * s.DCMAX, (uint16_t)lay.lampad_off);
+    std::vector<uint16_t> mu16((size_t)s.TPB * s.VPT * s.DV, (uint16_t)(lay.mupad_off / 4u));
+    for (int32_t t = 0; t < c->M; ++t) {
+        const int32_t i = order[t];
+        for (int64_t k = 0; k < c->rowptr[i + 1] - c->rowptr[i]; ++k)
+            col16[(size_t)t * s.DCMAX + k] = (uint16_t)(4u * (uint32_t)c->colidx[c->rowptr[i] + k]);
+    }
+    for (int32_t t = 0; t < s.TPB; ++t)
+        for (int v = 0; v < s.VPT; ++v) {
+            const int64_t j = (int64_t)t + (int64_t)s.TPB * v;
+            if (j >= c->N) continue;
+            for (int64_t k = 0; k < c->colptr[j + 1] - c->colptr[j]; ++k) {
+                const int32_t i = c->rowidx[c->colptr[j] + k];
+                const int32_t ti = rank[i];
+                const int64_t word = (int64_t)(lay.mu0_off / 4u) + wbase[ti / 64] +
+                                     (int64_t)c->cpos[c->colptr[j] + k] * 64 + (ti % 64);
+                mu16[((size_t)t * s.VPT + v) * s.DV + k] = (uint16_t)word;
+            }
+        }
+    // transpose to [pair][thread] so a load of one pair index is coalesced
+    std::vector<uint32_t> col_pk((size_t)ncp * s.TPB), mu_pk((size_t)nmp * s.TPB);
+    for (int32_t t = 0; t < s.TPB; ++t) {
+        for (int e = 0; e < ncp; ++e)
+            col_pk[(size_t)e * s.TPB + t] = (uint32_t)col16[(size_t)t * s.DCMAX + 2 * e] |
+                                           ((uint32_t)col16[(size_t)t * s.DCMAX + 2 * e + 1] << 16);
+        for (int e = 0; e < nmp; ++e)
+            mu_pk[(size_t)e * s.TPB + t] = (uint32_t)mu16[(size_t)t * s.VPT * s.DV + 2 * e] |
+                                          ((uint32_t)mu16[(size_t)t * s.VPT * s.DV + 2 * e + 1] << 16);
+    }
+    rb_status st;
+    if ((st = upload(&c->d_lam_off, col_pk, "upload check table")) != RB_OK) return st;
+    if ((st = upload(&c->d_mu_off, mu_pk, "upload fault table")) != RB_OK) return st;
+    if ((st = upload(&c->d_chk_row, chk_row, "upload row map")) != RB_OK) return st;
+    if ((st = upload(&c->d_wave_deg, wdeg, "upload wave degrees")) != RB_OK) return st;
+    if ((st = upload(&c->d_wave_base, wbase, "upload wave bases")) != RB_OK) return st;
+    {
+        size_t st_lds = 0;
+        RB_HIP(rb::block_static_lds(bv, &st_lds), "kernel attributes");
+        if (st_lds != 0) return fail(RB_E_DEVICE, "internal: block kernel uses static LDS");
+    }
+    RB_HIP(rb::block_prepare(bv, (size_t)lay.lds_bytes), "allow dynamic LDS");
+    c->variant = rb::num_variants() + bv;
+    c->block = true;
+    c->bshape = s;
+    c->lampad_off = lay.lampad_off;
+    c->mupad_off = lay.mupad_off;
+    c->red_off = lay.red_off;
+    c->mu0_off = lay.mu0_off;
+    c->lds_bytes = lay.lds_bytes;
+    const bool prior = c->params.anchor == RB_ANCHOR_PRIOR;
+    for (int tr = 0; tr < 2; ++tr) {
+        int blocks = 0;
+        RB_HIP(rb::block_variant_occupancy(bv, prior, tr != 0, (size_t)lay.lds_bytes, &blocks),
+               "occupancy query");
+        if (blocks < 1) return fail(RB_E_UNSUPPORTED, "block configuration does not fit on a CU");
+        c->blocks_per_cu[tr] = blocks;
+    }
+    return RB_OK;
+}
+
+rb_status plan(rb_ctx *c, int v) {
+    if (v < rb::num_variants()) {
+        c->block = false;
+        return build_plan(c, v);
+    }
+    return build_block_plan(c, v - rb::num_variants());
 }
 
 rb_status check_params(const rb_params *p) {
@@ -287,6 +474,11 @@ rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32
         }
     }
     if (best < 0) {
+        // large graphs: the first block-kernel shape that fits
+        for (int bv = 0; bv < rb::num_block_variants() && best < 0; ++bv)
+            if (block_fits(c, rb::block_variant_shape(bv))) best = rb::num_variants() + bv;
+    }
+    if (best < 0) {
         const std::string msg = "graph exceeds every built-in kernel configuration (M=" +
                                 std::to_string(M) + ", N=" + std::to_string(N) +
                                 ", max row degree " + std::to_string(c->max_row) +
@@ -317,8 +509,18 @@ rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32
                                     params->gamma_hi, nullptr)) != hipSuccess)
         return bail(hip_fail(e, "gamma table kernel"));
     if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(hip_fail(e, "gamma table sync"));
-    st = build_plan(c, best);
+    st = plan(c, best);
     if (st != RB_OK) return bail(st);
+    {
+        std::vector<int32_t> rp(c->rowptr.begin(), c->rowptr.end()), cp(c->colptr.begin(), c->colptr.end());
+        std::vector<int32_t> ce((size_t)nnz);
+        for (int64_t k = 0; k < nnz; ++k) ce[k] = (int32_t)(c->rowptr[c->rowidx[k]] + c->cpos[k]);
+        if ((st = upload(&c->d_rowptr, rp, "upload rowptr")) != RB_OK ||
+            (st = upload(&c->d_colidx, c->colidx, "upload colidx")) != RB_OK ||
+            (st = upload(&c->d_colptr, cp, "upload colptr")) != RB_OK ||
+            (st = upload(&c->d_cedge, ce, "upload edge map")) != RB_OK)
+            return bail(st);
+    }
     *out = c;
     return RB_OK;
 }
@@ -333,7 +535,27 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_queue);
         (void)hipFree(c->d_lam_off);
         (void)hipFree(c->d_mu_off);
+        (void)hipFree(c->d_chk_row);
+        (void)hipFree(c->d_wave_deg);
+        (void)hipFree(c->d_wave_base);
     }
+    if (c->d_rowptr || c->d_colidx || c->d_colptr || c->d_cedge) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(c->d_rowptr);
+        (void)hipFree(c->d_colidx);
+        (void)hipFree(c->d_colptr);
+        (void)hipFree(c->d_cedge);
+    }
+    if (c->d_ws || c->d_code_m || c->d_codes || c->d_queues) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(c->d_ws);
+        (void)hipFree(c->d_code_m);
+        (void)hipFree(c->d_codes);
+        (void)hipFree(c->d_queues);
+    }
+    for (rb_ctx *s : c->subs) rb_destroy(s);
     delete c;
 }
 
@@ -341,7 +563,11 @@ static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     rb::GroupArgs a{};
     a.M = c->M;
     a.N = c->N;
+    a.syn_stride = c->M;
+    a.corr_stride = c->N;
     a.B = B;
+    a.count = B;
+    a.list = nullptr;
     a.syn = syn;
     a.w = c->d_w;
     a.gamma = c->d_gamma;
@@ -354,7 +580,6 @@ static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     a.num_solutions = c->params.num_solutions;
     a.max_total_iters = c->params.max_total_iters;
     a.L = c->params.llr_clip;
-    a.slot_bytes = c->slot_bytes;
     a.lampad_off = c->lampad_off;
     a.mupad_off = c->mupad_off;
     a.mu0_off = c->mu0_off;
@@ -362,11 +587,66 @@ static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     return a;
 }
 
+static rb::BlockArgs block_args(const rb::GroupArgs &g, const rb_ctx *c) {
+    rb::BlockArgs b{};
+    b.M = g.M;
+    b.N = g.N;
+    b.B = g.B;
+    b.syn = g.syn;
+    b.corr = g.corr;
+    b.conv = g.conv;
+    b.legs = g.legs;
+    b.iters = g.iters;
+    b.weight = g.weight;
+    b.final_llr = g.final_llr;
+    b.w = g.w;
+    b.gamma = g.gamma;
+    b.chk_col = c->d_lam_off;
+    b.col_mu = c->d_mu_off;
+    b.chk_row = c->d_chk_row;
+    b.wave_deg = c->d_wave_deg;
+    b.wave_base = c->d_wave_base;
+    b.queue = g.queue;
+    b.num_legs = g.num_legs;
+    b.iters_first = g.iters_first;
+    b.iters_leg = g.iters_leg;
+    b.num_solutions = g.num_solutions;
+    b.max_total_iters = g.max_total_iters;
+    b.L = g.L;
+    b.lampad_off = c->lampad_off;
+    b.mupad_off = c->mupad_off;
+    b.red_off = c->red_off;
+    b.mu0_off = c->mu0_off;
+    b.trace_gamma = g.trace_gamma;
+    b.scale = g.scale;
+    b.trace_T = g.trace_T;
+    b.trace = g.trace;
+    return b;
+}
+
+static int shots_per_block(const rb_ctx *c) { return c->block ? 1 : 64 / c->shape.G; }
+
 static int grid_for(const rb_ctx *c, int64_t B, int trace) {
-    const int shots_per_block = 64 / c->shape.G;
-    const int64_t need = (B + shots_per_block - 1) / shots_per_block;
+    const int spb = shots_per_block(c);
+    const int64_t need = (B + spb - 1) / spb;
     const int64_t full = (int64_t)c->blocks_per_cu[trace] * c->num_cu;
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, full));
+}
+
+static rb_status launch(rb_ctx *c, const rb::GroupArgs &a, bool trace, hipStream_t s) {
+    const bool prior = !trace && c->params.anchor == RB_ANCHOR_PRIOR;
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(rb::launch_reset_queue(c->d_queue, s), "queue reset");
+    const int grid = grid_for(c, a.B, trace ? 1 : 0);
+    if (c->block) {
+        RB_HIP(rb::launch_block(c->variant - rb::num_variants(), prior, trace, block_args(a, c), grid,
+                                (size_t)c->lds_bytes, s),
+               "relay block kernel launch");
+    } else {
+        RB_HIP(rb::launch_group(c->variant, prior, trace, a, grid, (size_t)c->lds_bytes, s),
+               "relay kernel launch");
+    }
+    return RB_OK;
 }
 
 rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr, uint8_t *d_conv,
@@ -378,6 +658,7 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
     if (B == 0) return RB_OK;
     if (!d_syn || !d_corr || !d_conv || !d_legs || !d_iters)
         return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use rb_decode_multi");
     rb::GroupArgs a = base_args(c, B, d_syn);
     a.corr = d_corr;
     a.conv = d_conv;
@@ -385,19 +666,26 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
     a.iters = d_iters;
     a.weight = d_weight;
     a.final_llr = d_final_llr;
-    hipStream_t s = (hipStream_t)stream;
-    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
-    RB_HIP(rb::launch_reset_queue(c->d_queue, s), "queue reset");
-    RB_HIP(rb::launch_group(c->variant, c->params.anchor == RB_ANCHOR_PRIOR, false, a,
-                            grid_for(c, B, 0), (size_t)c->lds_bytes, s),
-           "relay kernel launch");
-    return RB_OK;
+    if (!c->block && c->d_ws && B <= c->ws_capacity) {
+        // longest-first order: shot list sorted by decreasing syndrome weight
+        hipStream_t s = (hipStream_t)stream;
+        RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+        RB_HIP(rb::launch_shot_lists(B, d_syn, c->M, nullptr, c->d_code_m, 1, c->d_ws, c->d_queue, s),
+               "shot list kernels");
+        a.list = (const int32_t *)c->d_ws + (size_t)(rb::kListHeader + B);
+        RB_HIP(rb::launch_group(c->variant, c->params.anchor == RB_ANCHOR_PRIOR, false, a,
+                                grid_for(c, B, 0), (size_t)c->lds_bytes, s),
+               "relay kernel launch");
+        return RB_OK;
+    }
+    return launch(c, a, false, (hipStream_t)stream);
 }
 
 rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma, float scale,
                    int32_t T, float *d_trace, void *stream) {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: trace one code's own context");
     if (B < 0 || T < 0) return fail(RB_E_INVALID_ARG, "B and T must be >= 0");
     if (!std::isfinite(scale)) return fail(RB_E_NONFINITE, "scale must be finite");
     if (B == 0) return RB_OK;
@@ -407,22 +695,19 @@ rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_ga
     a.scale = scale;
     a.trace_T = T;
     a.trace = d_trace;
-    hipStream_t s = (hipStream_t)stream;
-    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
-    RB_HIP(rb::launch_reset_queue(c->d_queue, s), "queue reset");
-    RB_HIP(rb::launch_group(c->variant, false, true, a, grid_for(c, B, 1), (size_t)c->lds_bytes, s),
-           "relay trace launch");
-    return RB_OK;
+    return launch(c, a, true, (hipStream_t)stream);
 }
 
 rb_status rb_get_llr(const rb_ctx *c, float *host_w) {
     if (!c || !host_w) return fail(RB_E_INVALID_ARG, "NULL argument");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context");
     std::memcpy(host_w, c->w.data(), sizeof(float) * (size_t)c->N);
     return RB_OK;
 }
 
 rb_status rb_get_gamma_table(const rb_ctx *c, float *host_gamma) {
     if (!c || !host_gamma) return fail(RB_E_INVALID_ARG, "NULL argument");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context");
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(hipMemcpy(host_gamma, c->d_gamma, sizeof(float) * (size_t)c->N * (size_t)c->params.num_legs,
                      hipMemcpyDeviceToHost),
@@ -439,27 +724,410 @@ rb_status rb_get_info(const rb_ctx *c, rb_info *info) {
     info->max_row_degree = c->max_row;
     info->max_col_degree = c->max_col;
     info->variant = c->variant;
-    info->lanes_per_shot = c->shape.G;
-    info->checks_per_lane = c->shape.CPT;
-    info->row_slots = c->shape.DC;
-    info->cols_per_lane = c->shape.VPT;
-    info->col_slots = c->shape.DV;
-    info->shots_per_block = 64 / c->shape.G;
-    info->threads_per_block = 64;
+    if (c->block) {
+        info->lanes_per_shot = c->bshape.TPB;
+        info->checks_per_lane = 1;
+        info->row_slots = c->bshape.DCMAX;
+        info->cols_per_lane = c->bshape.VPT;
+        info->col_slots = c->bshape.DV;
+        info->shots_per_block = 1;
+        info->threads_per_block = c->bshape.TPB;
+        info->waves_per_simd_target = c->bshape.waves;
+    } else {
+        info->lanes_per_shot = c->shape.G;
+        info->checks_per_lane = c->shape.CPT;
+        info->row_slots = c->shape.DC;
+        info->cols_per_lane = c->shape.VPT;
+        info->col_slots = c->shape.DV;
+        info->shots_per_block = 64 / c->shape.G;
+        info->threads_per_block = 64;
+        info->waves_per_simd_target = c->shape.waves;
+    }
     info->lds_bytes_per_block = c->lds_bytes;
     info->blocks_per_cu = c->blocks_per_cu[0];
     info->grid_blocks = c->blocks_per_cu[0] * c->num_cu;
-    info->num_variants = rb::num_variants();
+    info->num_variants = total_variants();
     return RB_OK;
 }
 
 rb_status rb_set_variant(rb_ctx *c, int32_t v) {
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
-    if (v < 0 || v >= rb::num_variants()) return fail(RB_E_INVALID_ARG, "variant out of range");
-    if (!variant_fits(c, rb::variant_shape(v))) return fail(RB_E_UNSUPPORTED, "graph does not fit the variant");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use rb_autotune_multi");
+    if (v < 0 || v >= total_variants()) return fail(RB_E_INVALID_ARG, "variant out of range");
+    if (!any_fits(c, v)) return fail(RB_E_UNSUPPORTED, "graph does not fit the variant");
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(hipDeviceSynchronize(), "sync before re-plan");
-    return build_plan(c, v);
+    return plan(c, v);
+}
+
+// mean time of one decode of B syndromes with the context's current plan
+static rb_status time_variant(rb_ctx *c, int64_t B, const uint8_t *d_syn, int32_t reps, float *ms_out) {
+    uint8_t *corr = nullptr, *conv = nullptr;
+    int32_t *legs = nullptr, *iters = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(corr);
+        (void)hipFree(conv);
+        (void)hipFree(legs);
+        (void)hipFree(iters);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&corr, (size_t)B * c->N)) != hipSuccess || (e = hipMalloc(&conv, (size_t)B)) != hipSuccess ||
+        (e = hipMalloc(&legs, (size_t)B * 4)) != hipSuccess || (e = hipMalloc(&iters, (size_t)B * 4)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "timing allocation");
+    }
+    rb_status st = rb_decode(c, B, d_syn, corr, conv, legs, iters, nullptr, nullptr, nullptr);
+    if (st == RB_OK) {
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps && st == RB_OK; ++r)
+            st = rb_decode(c, B, d_syn, corr, conv, legs, iters, nullptr, nullptr, nullptr);
+        (void)hipEventRecord(e1, nullptr);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "timing");
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *ms_out = ms / (float)reps;
+    }
+    cleanup();
+    return st;
+}
+
+rb_status rb_autotune(rb_ctx *c, int64_t B, const uint8_t *d_syn, int32_t reps,
+                      int32_t *chosen_variant, float *best_ms) {
+    g_last_error.clear();
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use rb_autotune_multi");
+    if (B < 1 || !d_syn || reps < 1) return fail(RB_E_INVALID_ARG, "need B >= 1, syndromes, reps >= 1");
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(hipDeviceSynchronize(), "sync before autotune");
+    uint8_t *corr = nullptr, *conv = nullptr;
+    int32_t *legs = nullptr, *iters = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(corr);
+        (void)hipFree(conv);
+        (void)hipFree(legs);
+        (void)hipFree(iters);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&corr, (size_t)B * c->N)) != hipSuccess || (e = hipMalloc(&conv, (size_t)B)) != hipSuccess ||
+        (e = hipMalloc(&legs, (size_t)B * 4)) != hipSuccess || (e = hipMalloc(&iters, (size_t)B * 4)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "autotune allocation");
+    }
+    int best = -1;
+    float best_t = 0.0f;
+    for (int v = 0; v < total_variants(); ++v) {
+        if (!any_fits(c, v)) continue;
+        rb_status st = plan(c, v);
+        if (st != RB_OK) continue;
+        st = rb_decode(c, B, d_syn, corr, conv, legs, iters, nullptr, nullptr, nullptr);  // warm-up
+        if (st != RB_OK) {
+            cleanup();
+            return st;
+        }
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; ++r) (void)rb_decode(c, B, d_syn, corr, conv, legs, iters, nullptr, nullptr, nullptr);
+        (void)hipEventRecord(e1, nullptr);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "autotune timing");
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (best < 0 || ms < best_t) {
+            best = v;
+            best_t = ms;
+        }
+    }
+    cleanup();
+    if (best < 0) return fail(RB_E_UNSUPPORTED, "no kernel configuration fits");
+    rb_status st = plan(c, best);
+    if (st != RB_OK) return st;
+    if (chosen_variant) *chosen_variant = best;
+    if (best_ms) *best_ms = best_t;
+    return RB_OK;
+}
+
+static int64_t train_shot_floats(const rb_ctx *c, int32_t T, int32_t C) {
+    const int64_t nck = (T + C - 1) / C;
+    return (int64_t)c->N + (nck + C) * ((int64_t)c->N + c->E);
+}
+
+size_t rb_train_tape_size(const rb_ctx *c, int64_t B, int32_t T, int32_t ckpt_every) {
+    if (!c || c->multi || B < 0 || T < 0 || ckpt_every < 1) return 0;
+    return sizeof(float) * (size_t)B * ((size_t)train_shot_floats(c, T, ckpt_every) + (size_t)c->N + 1);
+}
+
+static rb_status train_args(const rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma,
+                            const float *d_scale, int32_t T, int32_t C, void *d_tape, size_t tape_bytes,
+                            rb::TrainArgs *a) {
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context");
+    if (B < 0 || T < 0 || C < 1) return fail(RB_E_INVALID_ARG, "need B >= 0, T >= 0, ckpt_every >= 1");
+    if (B > INT32_MAX) return fail(RB_E_SHAPE, "B exceeds 2^31 - 1");
+    if (B > 0 && (!d_syn || !d_gamma || !d_scale || !d_tape)) return fail(RB_E_INVALID_ARG, "NULL device pointer");
+    if (tape_bytes < rb_train_tape_size(c, B, T, C)) return fail(RB_E_WORKSPACE, "tape too small");
+    if (rb::train_lds_bytes(c->N, (int)c->E) > 64 * 1024) return fail(RB_E_UNSUPPORTED, "graph too large for training");
+    rb::TrainArgs t{};
+    t.M = c->M;
+    t.N = c->N;
+    t.E = (int32_t)c->E;
+    t.B = B;
+    t.syn = d_syn;
+    t.w = c->d_w;
+    t.gamma = d_gamma;
+    t.scale = d_scale;
+    t.T = T;
+    t.C = C;
+    t.L = c->params.llr_clip;
+    t.rowptr = c->d_rowptr;
+    t.colidx = c->d_colidx;
+    t.colptr = c->d_colptr;
+    t.cedge = c->d_cedge;
+    t.tape = (float *)d_tape;
+    t.shot_floats = train_shot_floats(c, T, C);
+    t.gamma_part = t.tape + (size_t)B * (size_t)t.shot_floats;
+    t.scale_part = t.gamma_part + (size_t)B * c->N;
+    *a = t;
+    return RB_OK;
+}
+
+rb_status rb_forward_train(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma, const float *d_scale,
+                           int32_t T, int32_t ckpt_every, float *d_llr_out, void *d_tape, size_t tape_bytes,
+                           void *stream) {
+    g_last_error.clear();
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    rb::TrainArgs a{};
+    rb_status st = train_args(c, B, d_syn, d_gamma, d_scale, T, ckpt_every, d_tape, tape_bytes, &a);
+    if (st != RB_OK) return st;
+    if (B == 0) return RB_OK;
+    if (!d_llr_out) return fail(RB_E_INVALID_ARG, "d_llr_out is NULL");
+    a.llr_out = d_llr_out;
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(rb::launch_train_forward(a, (hipStream_t)stream), "training forward launch");
+    return RB_OK;
+}
+
+rb_status rb_backward(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma, const float *d_scale,
+                      int32_t T, int32_t ckpt_every, void *d_tape, size_t tape_bytes, const float *d_dllr,
+                      float *d_dgamma, float *d_dscale, void *stream) {
+    g_last_error.clear();
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    rb::TrainArgs a{};
+    rb_status st = train_args(c, B, d_syn, d_gamma, d_scale, T, ckpt_every, d_tape, tape_bytes, &a);
+    if (st != RB_OK) return st;
+    if (!d_dgamma || !d_dscale || (B > 0 && !d_dllr)) return fail(RB_E_INVALID_ARG, "NULL gradient pointer");
+    a.dllr = d_dllr;
+    a.dgamma = d_dgamma;
+    a.dscale = d_dscale;
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(rb::launch_train_backward(a, (hipStream_t)stream), "training backward launch");
+    return RB_OK;
+}
+
+size_t rb_workspace_size(const rb_ctx *c, int64_t B) {
+    if (!c || B < 0) return 0;
+    return rb::shot_list_bytes(B, c->multi ? (int)c->subs.size() : 1);
+}
+
+rb_status rb_reserve(rb_ctx *c, int64_t B) {
+    g_last_error.clear();
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (B < 0 || B > INT32_MAX) return fail(RB_E_INVALID_ARG, "B must be in [0, 2^31)");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code contexts take a caller workspace");
+    if (B <= c->ws_capacity) return RB_OK;
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(hipDeviceSynchronize(), "sync before reserve");
+    (void)hipFree(c->d_ws);
+    c->d_ws = nullptr;
+    c->ws_capacity = 0;
+    RB_HIP(hipMalloc(&c->d_ws, rb::shot_list_bytes(B, 1)), "hipMalloc(workspace)");
+    if (!c->d_code_m) {
+        std::vector<int32_t> m1(1, c->M);
+        rb_status st = upload(&c->d_code_m, m1, "upload code rows");
+        if (st != RB_OK) return st;
+    }
+    c->ws_capacity = B;
+    return RB_OK;
+}
+
+namespace {
+
+// per-code data the mixed kernel reads
+rb_status upload_codes(rb_ctx *m) {
+    std::vector<rb::CodeStatic> cs(m->subs.size());
+    int lds = 0;
+    for (size_t k = 0; k < m->subs.size(); ++k) {
+        const rb_ctx *s = m->subs[k];
+        cs[k].M = s->M;
+        cs[k].N = s->N;
+        cs[k].tile = rb::mixed_tile_of_variant(s->variant);
+        cs[k].w = s->d_w;
+        cs[k].gamma = s->d_gamma;
+        cs[k].lam_off = s->d_lam_off;
+        cs[k].mu_off = s->d_mu_off;
+        cs[k].lampad_off = s->lampad_off;
+        cs[k].mupad_off = s->mupad_off;
+        cs[k].mu0_off = s->mu0_off;
+        lds = std::max(lds, s->lds_bytes);
+        if (cs[k].tile < 0) return fail(RB_E_UNSUPPORTED, "code planned outside the mixed tile set");
+    }
+    rb_status st = upload(&m->d_codes, cs, "upload code table");
+    if (st != RB_OK) return st;
+    m->lds_bytes = lds;
+    int blocks = 0;
+    RB_HIP(rb::mixed_occupancy(m->params.anchor == RB_ANCHOR_PRIOR, (size_t)lds, &blocks), "occupancy query");
+    if (blocks < 1) return fail(RB_E_UNSUPPORTED, "mixed kernel does not fit on a CU");
+    m->blocks_per_cu[0] = m->blocks_per_cu[1] = blocks;
+    return RB_OK;
+}
+
+}  // namespace
+
+rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *codes, const rb_params *params,
+                          int32_t device) {
+    g_last_error.clear();
+    if (!out) return fail(RB_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_codes < 1 || n_codes > 64 || !codes) return fail(RB_E_INVALID_ARG, "need 1..64 code descriptors");
+    rb_status st = check_params(params);
+    if (st != RB_OK) return st;
+    rb_ctx *m = new (std::nothrow) rb_ctx();
+    if (!m) return fail(RB_E_OOM, "host allocation failed");
+    m->multi = true;
+    m->device = device;
+    m->params = *params;
+    for (int32_t k = 0; k < n_codes; ++k) {
+        rb_ctx *s = nullptr;
+        st = rb_create(&s, codes[k].M, codes[k].N, codes[k].nnz, codes[k].rows, codes[k].cols, codes[k].prior_p,
+                       params, device);
+        if (st != RB_OK) {
+            const std::string msg = "code " + std::to_string(k) + ": " + g_last_error;
+            rb_destroy(m);
+            return fail(st, msg);
+        }
+        m->subs.push_back(s);
+        // cheapest tile of the mixed set that fits this code
+        int best = -1;
+        double best_cost = 0.0;
+        for (int v = 0; v < rb::num_variants(); ++v) {
+            if (rb::mixed_tile_of_variant(v) < 0 || !variant_fits(s, rb::variant_shape(v))) continue;
+            const double cost = variant_cost(rb::variant_shape(v));
+            if (best < 0 || cost < best_cost) {
+                best = v;
+                best_cost = cost;
+            }
+        }
+        if (best < 0) {
+            rb_destroy(m);
+            return fail(RB_E_UNSUPPORTED, "code " + std::to_string(k) + " fits no tile of the mixed launch");
+        }
+        if ((st = plan(s, best)) != RB_OK) {
+            rb_destroy(m);
+            return st;
+        }
+        m->m_max = std::max(m->m_max, s->M);
+        m->n_max = std::max(m->n_max, s->N);
+    }
+    m->num_cu = m->subs[0]->num_cu;
+    m->M = m->m_max;
+    m->N = m->n_max;
+    std::vector<int32_t> ms;
+    for (rb_ctx *s : m->subs) ms.push_back(s->M);
+    if ((st = upload(&m->d_code_m, ms, "upload code rows")) != RB_OK || (st = upload_codes(m)) != RB_OK) {
+        rb_destroy(m);
+        return st;
+    }
+    hipError_t e = hipMalloc(&m->d_queues, sizeof(unsigned long long) * (size_t)n_codes);
+    if (e != hipSuccess) {
+        rb_destroy(m);
+        return hip_fail(e, "hipMalloc(queues)");
+    }
+    *out = m;
+    return RB_OK;
+}
+
+rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn, uint8_t *d_corr,
+                          uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters, double *d_weight,
+                          float *d_final_llr, void *d_workspace, size_t workspace_bytes, void *stream) {
+    g_last_error.clear();
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (!c->multi) return fail(RB_E_INVALID_ARG, "not a mixed-code context");
+    if (B < 0) return fail(RB_E_INVALID_ARG, "B must be >= 0");
+    if (B == 0) return RB_OK;
+    if (B > INT32_MAX) return fail(RB_E_SHAPE, "B exceeds 2^31 - 1");
+    if (!d_code_id || !d_syn || !d_corr || !d_conv || !d_legs || !d_iters || !d_workspace)
+        return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
+    const int nc = (int)c->subs.size();
+    if (workspace_bytes < rb::shot_list_bytes(B, nc)) return fail(RB_E_WORKSPACE, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(rb::launch_shot_lists(B, d_syn, c->m_max, d_code_id, c->d_code_m, nc, d_workspace, c->d_queues, s),
+           "shot list kernels");
+    rb::MixedArgs m{};
+    m.run = base_args(c->subs[0], B, d_syn);
+    m.run.syn_stride = c->m_max;
+    m.run.corr_stride = c->n_max;
+    m.run.corr = d_corr;
+    m.run.conv = d_conv;
+    m.run.legs = d_legs;
+    m.run.iters = d_iters;
+    m.run.weight = d_weight;
+    m.run.final_llr = d_final_llr;
+    m.codes = c->d_codes;
+    m.ncodes = nc;
+    const int32_t *ws = (const int32_t *)d_workspace;
+    m.seg_start = ws + (size_t)nc * rb::kWeightBinsHost;
+    m.seg_count = m.seg_start + nc;
+    m.list = ws + (size_t)nc * (rb::kWeightBinsHost + 2) + (size_t)B;
+    m.queues = c->d_queues;
+    const int64_t full = (int64_t)c->blocks_per_cu[0] * c->num_cu;
+    const int grid = (int)std::max<int64_t>(1, full);
+    RB_HIP(rb::launch_mixed(c->params.anchor == RB_ANCHOR_PRIOR, m, grid, (size_t)c->lds_bytes, s),
+           "mixed kernel launch");
+    return RB_OK;
+}
+
+rb_status rb_autotune_multi(rb_ctx *c, const int64_t *sample_b, const uint8_t *const *d_samples, int32_t reps,
+                            int32_t *chosen_variants) {
+    g_last_error.clear();
+    if (!c || !c->multi) return fail(RB_E_INVALID_ARG, "not a mixed-code context");
+    if (!sample_b || !d_samples || reps < 1) return fail(RB_E_INVALID_ARG, "bad samples");
+    for (size_t k = 0; k < c->subs.size(); ++k) {
+        rb_ctx *s = c->subs[k];
+        if (sample_b[k] >= 1 && d_samples[k]) {
+            int best = -1;
+            float best_t = 0.0f;
+            for (int v = 0; v < rb::num_variants(); ++v) {
+                if (rb::mixed_tile_of_variant(v) < 0 || !variant_fits(s, rb::variant_shape(v))) continue;
+                rb_status st = rb_set_variant(s, v);
+                if (st != RB_OK) return st;
+                float ms = 0.0f;
+                st = time_variant(s, sample_b[k], d_samples[k], reps, &ms);
+                if (st != RB_OK) return st;
+                if (best < 0 || ms < best_t) {
+                    best = v;
+                    best_t = ms;
+                }
+            }
+            if (best >= 0) {
+                rb_status st = rb_set_variant(s, best);
+                if (st != RB_OK) return st;
+            }
+        }
+        if (chosen_variants) chosen_variants[k] = s->variant;
+    }
+    return upload_codes(c);
 }
 
 rb_status rb_sync_status(rb_ctx *c) {

@@ -13,13 +13,17 @@ namespace rb {
 // j = g + G*v (v < VPT); DC and DV bound the row and column degrees.
 struct TileShape {
     int G, CPT, DC, VPT, DV;
+    int waves;  // waves per SIMD the kernel's register budget targets
 };
 
 // Arguments of the group kernel (passed by value).
 struct GroupArgs {
     int32_t M, N;
+    int32_t syn_stride, corr_stride;  // bytes per syndrome row, entries per correction row
     int64_t B;
-    const uint8_t *syn;   // [B][M]
+    int64_t count;        // queue positions to decode
+    const int32_t *list;  // [count] shot of queue position k, or null (shot = k)
+    const uint8_t *syn;   // [B][syn_stride]
     uint8_t *corr;        // [B][N]
     uint8_t *conv;        // [B]
     int32_t *legs;        // [B]
@@ -28,12 +32,16 @@ struct GroupArgs {
     float *final_llr;     // [B][N] or null
     const float *w;       // [N] channel LLRs
     const float *gamma;   // [R][N] memory strengths, row r-1 = leg r
-    const uint32_t *lam_off;  // [G][CPT][DC] slot-relative byte offsets of Lambda gathers
-    const uint32_t *mu_off;   // [G][VPT][DV] slot-relative byte offsets of mu gathers
+    // per-lane gather tables, two 16-bit slot-relative LDS byte offsets per
+    // word: lane g's entries e = c*DC + k (Lambda of check edge) and
+    // e = v*DV + k (mu of fault edge) at word g*ceil(n/2) + e/2, half e%2
+    const uint32_t *lam_off;  // [G][ceil(CPT*DC/2)]
+    const uint32_t *mu_off;   // [G][ceil(VPT*DV/2)]
     unsigned long long *queue;  // next unclaimed shot
     int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
     float L;
-    uint32_t slot_bytes;   // LDS bytes per shot slot
+    // LDS offsets in interleaved form (slot word w -> byte 4 * w * NS; the
+    // kernel adds 4 * slot)
     uint32_t lampad_off;   // +inf cell: Lambda of padded check edges
     uint32_t mupad_off;    // -0 cell: mu of padded fault edges
     uint32_t mu0_off;      // start of the check-message rows
@@ -44,8 +52,82 @@ struct GroupArgs {
     float *trace;          // [B][T+1][N]
 };
 
+// Shape of a block-kernel configuration: TPB threads decode one syndrome;
+// thread t owns one check (degree <= DCMAX) and faults t + TPB*v, v < VPT
+// (degree <= DV).
+struct BlockShape {
+    int TPB, DCMAX, VPT, DV;
+    int waves;
+};
+
+struct BlockArgs {
+    int32_t M, N;
+    int64_t B;
+    const uint8_t *syn;
+    uint8_t *corr;
+    uint8_t *conv;
+    int32_t *legs;
+    int32_t *iters;
+    double *weight;
+    float *final_llr;
+    const float *w;
+    const float *gamma;
+    const uint32_t *chk_col;   // [DCMAX/2][TPB] two 16-bit Lambda byte addresses per word
+    const uint32_t *col_mu;    // [VPT*DV/2][TPB] two 16-bit message word indices per word
+    const int32_t *chk_row;    // [TPB] check owned by thread t, or -1
+    const int32_t *wave_deg;   // [TPB/64] row length (max degree) of wave w
+    const int32_t *wave_base;  // [TPB/64] first message word of wave w (relative to mu0)
+    unsigned long long *queue;
+    int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
+    float L;
+    uint32_t lampad_off, mupad_off, red_off, mu0_off;  // LDS byte offsets
+    const float *trace_gamma;
+    float scale;
+    int32_t trace_T;
+    float *trace;
+};
+
+// Largest static LDS of a variant's kernels.  The kernels address LDS by
+// absolute offsets from 0, which is only valid without static LDS; the host
+// refuses to plan a variant for which this is nonzero.
+hipError_t block_static_lds(int v, size_t *bytes);
+hipError_t variant_static_lds(int v, size_t *bytes);
+
+int num_block_variants();
+BlockShape block_variant_shape(int v);
+hipError_t block_variant_occupancy(int v, bool prior_anchor, bool trace, size_t lds, int *blocks);
+// Allows `lds` bytes of dynamic LDS for every instantiation of variant v.
+hipError_t block_prepare(int v, size_t lds);
+hipError_t launch_block(int v, bool prior_anchor, bool trace, const BlockArgs &a, int grid,
+                        size_t lds, hipStream_t s);
+
+// Per-code data of the mixed launch (device array).
+struct CodeStatic {
+    int32_t M, N;
+    int32_t tile;  // index into the mixed tile switch
+    const float *w;
+    const float *gamma;
+    const uint32_t *lam_off;
+    const uint32_t *mu_off;
+    uint32_t lampad_off, mupad_off, mu0_off;
+};
+
+struct MixedArgs {
+    GroupArgs run;  // outputs, strides (M_max, N_max), relay parameters
+    const CodeStatic *codes;
+    int32_t ncodes;
+    const int32_t *list;       // shot lists, all codes
+    const int32_t *seg_start;  // [ncodes] (device, written by the list kernels)
+    const int32_t *seg_count;  // [ncodes]
+    unsigned long long *queues;  // [ncodes]
+};
+
 int num_variants();
 TileShape variant_shape(int v);
+// Position of group variant v in the mixed launch's tile switch, or -1.
+int mixed_tile_of_variant(int v);
+hipError_t mixed_occupancy(bool prior_anchor, size_t lds, int *blocks);
+hipError_t launch_mixed(bool prior_anchor, const MixedArgs &m, int grid, size_t lds, hipStream_t s);
 // Blocks of the variant's kernel that fit on one CU with `lds` bytes of LDS per block.
 hipError_t variant_occupancy(int v, bool prior_anchor, bool trace, size_t lds, int *blocks);
 hipError_t launch_group(int v, bool prior_anchor, bool trace, const GroupArgs &a, int grid,
@@ -53,5 +135,41 @@ hipError_t launch_group(int v, bool prior_anchor, bool trace, const GroupArgs &a
 hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_first, float lo,
                               float hi, hipStream_t s);
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s);
+// Builds per-code shot lists in `workspace` (shot_list_bytes(B, ncodes) bytes):
+// positions sorted by (code, decreasing syndrome weight); the list of code c
+// starts at list + seg_start[c] and holds seg_count[c] shots.  Also zeroes the
+// per-code queue counters.  Layout: hist[ncodes*256], seg_start[ncodes],
+// seg_count[ncodes], key[B], list[B] (int32).
+hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
+                             const int32_t *code_m, int ncodes, void *workspace,
+                             unsigned long long *queues, hipStream_t s);
+size_t shot_list_bytes(int64_t B, int ncodes);
+constexpr int kWeightBinsHost = 256;              // weight bins of the shot-list sort
+constexpr int kListHeader = kWeightBinsHost + 2;  // int32 words before key[] for one code
+
+// Unrolled one-leg DMem-BP with learnable gamma_j and LLR scale, and its adjoint.
+struct TrainArgs {
+    int32_t M, N, E;
+    int64_t B;
+    const uint8_t *syn;     // [B][M]
+    const float *w;         // [N] channel LLRs
+    const float *gamma;     // [N] learnable memory strengths (device)
+    const float *scale;     // [1] learnable LLR scale s (device)
+    int32_t T, C;           // iterations, checkpoint interval
+    float L;
+    const int32_t *rowptr, *colidx, *colptr, *cedge;  // CSR / CSC (cedge: CSR edge id)
+    float *llr_out;         // [B][N] Lambda(T)
+    float *tape;            // [B][shot_floats]: w', checkpoints, segment tape
+    int64_t shot_floats;
+    const float *dllr;      // [B][N] dL/dLambda(T)
+    float *gamma_part;      // [B][N] per-shot dL/dgamma
+    float *scale_part;      // [B]
+    float *dgamma;          // [N] out
+    float *dscale;          // [1] out
+};
+
+size_t train_lds_bytes(int N, int E);
+hipError_t launch_train_forward(const TrainArgs &a, hipStream_t s);
+hipError_t launch_train_backward(const TrainArgs &a, hipStream_t s);
 
 }  // namespace rb

@@ -10,14 +10,20 @@
 // Leg r >= 2 restarts the check messages at zero from Lambda^{(r-1)}; the
 // memory anchor is clip(Lambda^{(r-1)}) (chain) or w (prior).
 //
-// Execution model.  One block is one wave64.  A wave holds 64/G shot slots;
-// the G lanes of a slot decode one syndrome together and pull the next one
-// from a global queue when it finishes, so the long tail of hard syndromes
-// never stalls the other slots of the wave.  Per-shot state lives in LDS
-// (marginals Lambda[N] and one row of DC check messages per check) and in
+// Execution model.  One block is one wave64.  A wave holds NS = 64/G shot
+// slots; the G lanes of a slot decode one syndrome together and pull the next
+// one from a global queue when it finishes, so the long tail of hard
+// syndromes never stalls the other slots of the wave.  Per-shot state lives in
+// LDS (marginals Lambda[N] and one row of check messages per check) and in
 // registers (the lane's faults: Lambda, lambda(0), gamma; its checks'
 // syndrome bits).  The graph is precompiled into per-lane LDS byte offsets
 // held in registers, so a gather is a single ds_read with no index load.
+//
+// LDS layout.  The NS slots of a wave are interleaved word by word: word w of
+// slot s sits at LDS word w*NS + s.  All slots run the same graph, so the
+// lanes of different slots that execute the same gather hit NS consecutive
+// banks; check-message rows have an odd stride (DC | 1 words) so that the
+// row accesses of the G lanes of a slot spread over the banks as well.
 //
 // Check update (min1 / min2 / sign parity): for one check the two smallest
 // |nu| are tracked with min/max only; edge k then receives m2 if |nu_k| == m1
@@ -42,7 +48,8 @@
 namespace rb {
 namespace {
 
-__device__ __forceinline__ float clipf(float x, float L) { return fminf(fmaxf(x, -L), L); }
+// clip(x) = min(max(x, -L), L) as one median-of-three (exact; no NaNs occur).
+__device__ __forceinline__ float clipf(float x, float L) { return __builtin_amdgcn_fmed3f(x, -L, L); }
 
 // ------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) for the memory strengths
@@ -91,9 +98,17 @@ __global__ void gamma_table_kernel(float *tab, int R, int N, uint64_t seed, floa
 
 __global__ void reset_queue_kernel(unsigned long long *q) { *q = 0ull; }
 
+// Makes `x` opaque to the optimiser for one loop trip (no instruction is
+// emitted).  Used on loop-invariant registers so that values derived from
+// them (unpacked gather addresses, per-column global pointers) are recomputed
+// where used instead of being hoisted out of the persistent loop and spilled.
+__device__ __forceinline__ void opaque(uint32_t &x) { asm volatile("" : "+v"(x)); }
+
+// LDS word at a byte address (the kernels use no static LDS, so the dynamic
+// LDS window starts at address 0).
 template <typename T>
-__device__ __forceinline__ T &lds_at(char *lds, uint32_t byte_addr) {
-    return *reinterpret_cast<T *>(lds + byte_addr);
+__device__ __forceinline__ __attribute__((address_space(3))) T &lds_at(char *, uint32_t byte_addr) {
+    return *(__attribute__((address_space(3))) T *)(size_t)byte_addr;
 }
 
 // Sum over the G lanes of a slot (xor butterfly; every lane gets the total).
@@ -107,33 +122,55 @@ __device__ __forceinline__ double group_sum(double x) {
 // ------------------------------------------------------------------------
 // The group kernel
 // ------------------------------------------------------------------------
+// Decodes the syndromes of one code: slots claim queue positions k < a.count
+// (shot = a.list[k], or k without a list) until the queue is exhausted, and
+// the function returns once every slot of the wave is idle.
 template <int G, int CPT, int DC, int VPT, int DV, bool PRIOR, bool TRACE>
-__global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
+__device__ __forceinline__ void group_loop(const GroupArgs a) {
     static_assert(64 % G == 0, "G must divide the wave");
     static_assert(CPT <= 32 && VPT <= 32, "per-lane bit masks are 32 bits");
-    extern __shared__ __align__(16) char lds[];
+    char *lds = nullptr;  // LDS is addressed by absolute byte offsets
+    constexpr int NS = 64 / G;                     // slots per wave
+    constexpr int RS = DC | 1;                     // words per check-message row (odd)
+    constexpr uint32_t WORD = 4u * NS;             // bytes between consecutive words of a slot
+    constexpr uint32_t ROW_STRIDE = WORD * G * RS; // bytes between the rows of checks c, c+1
 
-    const int lane = threadIdx.x;
+    uint32_t lane_rt = threadIdx.x;
+    opaque(lane_rt);  // keeps lane-derived constants inside this tile's code path
+    const int lane = (int)lane_rt;
     const int g = lane % G;
     const int slot = lane / G;
-    const uint32_t base = (uint32_t)slot * a.slot_bytes;
-    const uint32_t mu_row0 = base + a.mu0_off + (uint32_t)g * DC * 4u;  // row of check g
-    constexpr uint32_t ROW_STRIDE = (uint32_t)G * DC * 4u;               // bytes between c, c+1
+    uint32_t gl = (uint32_t)g;  // lane in slot, made opaque inside the loop
+    const uint32_t base = 4u * (uint32_t)slot;     // word 0 of this slot
+    const uint32_t mu_row0 = base + a.mu0_off + WORD * RS * (uint32_t)g;  // row of check g
+    const uint32_t lam_w0 = base + WORD * (uint32_t)g;                    // Lambda of fault g
     const unsigned long long gmask =
         (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (uint32_t)(slot * G));
     const float L = a.L;
 
-    // ---- per-lane gather tables (absolute LDS byte addresses)
-    uint32_t lam_addr[CPT][DC];
-    uint32_t mu_addr[VPT][DV];
+    // ---- per-lane gather tables: two 16-bit slot-relative LDS byte offsets
+    // per register.  Offsets are multiples of 4*NS and the slot base 4*slot is
+    // below 4*NS, so address = offset | base.
+    constexpr int NLP = (CPT * DC + 1) / 2;
+    constexpr int NMP = (VPT * DV + 1) / 2;
+    uint32_t lam_pk[NLP];
+    uint32_t mu_pk[NMP];
+    {
+        const uint32_t *lt = a.lam_off + (size_t)g * NLP;
+        const uint32_t *mt = a.mu_off + (size_t)g * NMP;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c)
+        for (int e = 0; e < NLP; ++e) lam_pk[e] = lt[e];
 #pragma unroll
-        for (int k = 0; k < DC; ++k) lam_addr[c][k] = base + a.lam_off[(g * CPT + c) * DC + k];
-#pragma unroll
-    for (int v = 0; v < VPT; ++v)
-#pragma unroll
-        for (int k = 0; k < DV; ++k) mu_addr[v][k] = base + a.mu_off[(g * VPT + v) * DV + k];
+        for (int e = 0; e < NMP; ++e) mu_pk[e] = mt[e];
+    }
+    auto lam_addr = [&](int c, int k) -> uint32_t {
+        const int e = c * DC + k;
+        return ((e & 1) ? (lam_pk[e >> 1] >> 16) : (lam_pk[e >> 1] & 0xffffu)) | base;
+    };
+    auto mu_addr = [&](int v, int k) -> uint32_t {
+        const int e = v * DV + k;
+        return ((e & 1) ? (mu_pk[e >> 1] >> 16) : (mu_pk[e >> 1] & 0xffffu)) | base;
+    };
 
     if (g == 0) {
         lds_at<float>(lds, base + a.lampad_off) = __int_as_float(0x7f800000);  // +inf
@@ -155,7 +192,7 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
 #pragma unroll
-            for (int k = 0; k < DC; ++k) lds_at<float>(lds, mu_row0 + c * ROW_STRIDE + 4u * k) = 0.0f;
+            for (int k = 0; k < DC; ++k) lds_at<float>(lds, mu_row0 + c * ROW_STRIDE + WORD * k) = 0.0f;
     };
 
     // claim the next syndrome for this slot and initialise leg 1
@@ -163,12 +200,12 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
         unsigned long long nxt = 0;
         if (g == 0) nxt = atomicAdd(a.queue, 1ull);
         nxt = __shfl(nxt, 0, G);
-        if (nxt >= (unsigned long long)a.B) {
+        if (nxt >= (unsigned long long)a.count) {
             active = false;
             return;
         }
         active = true;
-        shot = (long long)nxt;
+        shot = a.list ? (long long)a.list[nxt] : (long long)nxt;
         r = 1;
         t = 0;
         total = 0;
@@ -176,20 +213,20 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
         best_w = __longlong_as_double(0x7ff0000000000000ll);  // +inf
         best_mask = 0;
         sig = 0;
-        const uint8_t *s = a.syn + (size_t)shot * a.M;
+        const uint8_t *s = a.syn + (size_t)shot * a.syn_stride;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int i = g + G * c;
+            const int i = (int)gl + G * c;
             if (i < a.M && s[i]) sig |= 1u << c;
         }
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
-            const int j = g + G * v;
+            const int j = (int)gl + G * v;
             float wj = 0.0f, gj = 0.0f;
             if (j < a.N) {
                 wj = a.scale * a.w[j];
                 gj = TRACE ? a.trace_gamma[j] : a.gamma[j];
-                lds_at<float>(lds, base + 4u * j) = wj;
+                lds_at<float>(lds, base + WORD * j) = wj;
                 if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
             }
             Lr[v] = wj;
@@ -203,6 +240,11 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
     __syncthreads();
 
     while (__any(active)) {
+#pragma unroll
+        for (int e = 0; e < NLP; ++e) opaque(lam_pk[e]);
+#pragma unroll
+        for (int e = 0; e < NMP; ++e) opaque(mu_pk[e]);
+        opaque(gl);
         // ---------------- check pass: mu(t+1) from Lambda(t), mu(t); parity of F(t)
         bool mism = false;
         if (active) {
@@ -211,32 +253,39 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
                 const uint32_t row = mu_row0 + c * ROW_STRIDE;
                 float mo[DC], lv[DC];
 #pragma unroll
-                for (int k = 0; k < DC; ++k) mo[k] = lds_at<float>(lds, row + 4u * k);
+                for (int k = 0; k < DC; ++k) mo[k] = lds_at<float>(lds, row + WORD * k);
 #pragma unroll
-                for (int k = 0; k < DC; ++k) lv[k] = lds_at<float>(lds, lam_addr[c][k]);
-                const uint32_t sc = (sig >> c) & 1u;
-                uint32_t par = sc;
-#pragma unroll
-                for (int k = 0; k < DC; ++k) par ^= (lv[k] < 0.0f) ? 1u : 0u;
-                mism |= (par != 0u);
-                float nu[DC];
-                uint32_t sg = sc;
+                for (int k = 0; k < DC; ++k) lv[k] = lds_at<float>(lds, lam_addr(c, k));
+                const bool sc = (sig >> c) & 1u;
+                bool fpar = sc;  // sigma_i + parity of F(t) over the check
+                bool neg = sc;   // sigma_i + parity of the signs of nu
+                bool sk[DC];
+                float av[DC];
                 float m1 = L, m2 = L;
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
-                    nu[k] = clipf(lv[k] - mo[k], L);
-                    sg ^= (nu[k] < 0.0f) ? 1u : 0u;
-                    const float av = fabsf(nu[k]);
-                    m2 = fminf(m2, fmaxf(m1, av));
-                    m1 = fminf(m1, av);
+                    fpar ^= lv[k] < 0.0f;
+                    const float nu = clipf(lv[k] - mo[k], L);
+                    sk[k] = nu < 0.0f;
+                    neg ^= sk[k];
+                    av[k] = fabsf(nu);
+                    // two smallest magnitudes: with m1 <= m2, min(m2, max(m1, av)) is the
+                    // median of (m1, av, m2)
+                    m2 = __builtin_amdgcn_fmed3f(m1, av[k], m2);
+                    // min(m1, av) as med3(m1, av, -inf): one VOP3 op taking |nu| as a
+                    // source modifier
+                    m1 = __builtin_amdgcn_fmed3f(m1, av[k], -__builtin_inff());
                 }
+                mism |= fpar;
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
-                    const float av = fabsf(nu[k]);
-                    const float mag = (av == m1) ? m2 : m1;
-                    const uint32_t s = sg ^ ((nu[k] < 0.0f) ? 1u : 0u);
-                    lds_at<float>(lds, row + 4u * k) = s ? -mag : mag;
+                    const float mag = (av[k] == m1) ? m2 : m1;
+                    lds_at<float>(lds, row + WORD * k) = (neg ^ sk[k]) ? -mag : mag;
                 }
+                // keep the scheduler from hoisting the next check's gathers above
+                // this one: bounded live ranges keep the kernel inside its
+                // register budget
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         const unsigned long long bal = __ballot(mism);
@@ -256,7 +305,7 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
                     uint32_t fm = 0;
 #pragma unroll
                     for (int v = 0; v < VPT; ++v) {
-                        const int j = g + G * v;
+                        const int j = (int)gl + G * v;
                         if (j < a.N && Lr[v] < 0.0f) {
                             part += (double)a.w[j];
                             fm |= 1u << v;
@@ -279,7 +328,7 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
                 const float *gr = a.gamma + (size_t)(r - 1) * a.N;
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
-                    const int j = g + G * v;
+                    const int j = (int)gl + G * v;
                     if (j < a.N) {
                         gm[v] = gr[j];
                         l0[v] = PRIOR ? a.w[j] : clipf(Lr[v], L);
@@ -292,7 +341,7 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
                     double part = 0.0;
 #pragma unroll
                     for (int v = 0; v < VPT; ++v) {
-                        const int j = g + G * v;
+                        const int j = (int)gl + G * v;
                         if (j < a.N && Lr[v] < 0.0f) {
                             fm |= 1u << v;
                             part += (double)a.w[j];
@@ -302,10 +351,10 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
                     const uint32_t out = count > 0 ? best_mask : fm;
 #pragma unroll
                     for (int v = 0; v < VPT; ++v) {
-                        const int j = g + G * v;
+                        const int j = (int)gl + G * v;
                         if (j < a.N) {
-                            a.corr[(size_t)shot * a.N + j] = (uint8_t)((out >> v) & 1u);
-                            if (a.final_llr) a.final_llr[(size_t)shot * a.N + j] = Lr[v];
+                            a.corr[(size_t)shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
+                            if (a.final_llr) a.final_llr[(size_t)shot * a.corr_stride + j] = Lr[v];
                         }
                     }
                     if (g == 0) {
@@ -329,12 +378,15 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
                 const float y = gm[v] * clipf(Lr[v], L);
                 float acc = clipf(x + y, L);
 #pragma unroll
-                for (int k = 0; k < DV; ++k) acc += lds_at<float>(lds, mu_addr[v][k]);
+                for (int k = 0; k < DV; ++k) acc += lds_at<float>(lds, mu_addr(v, k));
                 Lr[v] = acc;
-                const int j = g + G * v;
-                if (j < a.N) {
-                    lds_at<float>(lds, base + 4u * j) = acc;
-                    if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + t + 1) * a.N + j] = acc;
+                // columns j >= N of the last row of lanes own spare words of the
+                // padded Lambda region, so the write needs no bound check
+                lds_at<float>(lds, lam_w0 + WORD * G * v) = acc;
+                if (v % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+                if (TRACE) {
+                    const int j = (int)gl + G * v;
+                    if (j < a.N) a.trace[((size_t)shot * (a.trace_T + 1) + t + 1) * a.N + j] = acc;
                 }
             }
             ++t;
@@ -342,6 +394,105 @@ __global__ __launch_bounds__(64) void relay_group_kernel(GroupArgs a) {
         }
         __syncthreads();
     }
+}
+
+template <int G, int CPT, int DC, int VPT, int DV, int WAVES, bool PRIOR, bool TRACE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES)))
+void relay_group_kernel(GroupArgs a) {
+    group_loop<G, CPT, DC, VPT, DV, PRIOR, TRACE>(a);
+}
+
+// ------------------------------------------------------------------------
+// Mixed-code launch: each wave decodes one code at a time with that code's
+// compiled tile, drains the code's queue, then moves on to the next code
+// (starting at blockIdx mod ncodes, so the codes are worked on concurrently).
+// Only tiles within a 128-VGPR budget take part, so mixing never lowers
+// occupancy below what the largest code needs on its own.
+// ------------------------------------------------------------------------
+template <bool PRIOR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+void relay_mixed_kernel(MixedArgs m) {
+    for (int q = 0; q < m.ncodes; ++q) {
+        const int c = (int)((blockIdx.x + (unsigned)q) % (unsigned)m.ncodes);
+        const CodeStatic cs = m.codes[c];
+        GroupArgs a = m.run;
+        a.M = cs.M;
+        a.N = cs.N;
+        a.w = cs.w;
+        a.gamma = cs.gamma;
+        a.lam_off = cs.lam_off;
+        a.mu_off = cs.mu_off;
+        a.lampad_off = cs.lampad_off;
+        a.mupad_off = cs.mupad_off;
+        a.mu0_off = cs.mu0_off;
+        a.list = m.list + m.seg_start[c];
+        a.count = m.seg_count[c];
+        a.queue = m.queues + c;
+        switch (cs.tile) {
+            case 0: group_loop<8, 5, 6, 9, 3, PRIOR, false>(a); break;
+            case 1: group_loop<16, 3, 6, 6, 3, PRIOR, false>(a); break;
+            case 2: group_loop<16, 5, 6, 9, 3, PRIOR, false>(a); break;
+            case 3: group_loop<32, 5, 6, 9, 3, PRIOR, false>(a); break;
+            default: break;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Shot lists: per code, positions sorted by decreasing syndrome weight (a
+// longest-first order, so the long-tailed hard syndromes start early and the
+// queue ends with short ones).  Counting sort over (code, weight bin).
+// ------------------------------------------------------------------------
+constexpr int kWeightBins = 256;
+
+__global__ void list_zero_kernel(int32_t *p, int n, unsigned long long *queues, int nq) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+    if (i < nq) queues[i] = 0ull;
+}
+
+__global__ void list_key_kernel(int64_t B, const uint8_t *syn, int32_t syn_stride,
+                                const int32_t *code_id, const int32_t *code_m, int ncodes,
+                                int32_t *key, int32_t *hist) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int c = code_id ? code_id[b] : 0;
+    if (c < 0 || c >= ncodes) {
+        key[b] = -1;  // invalid code id: the shot is skipped (outputs untouched)
+        return;
+    }
+    const int m = code_m[c];
+    const uint8_t *s = syn + (size_t)b * syn_stride;
+    int wgt = 0;
+    for (int i = 0; i < m; ++i) wgt += s[i] != 0;
+    const int bin = kWeightBins - 1 - min(wgt, kWeightBins - 1);
+    const int k = c * kWeightBins + bin;
+    key[b] = k;
+    atomicAdd(&hist[k], 1);
+}
+
+// single thread: exclusive scan of the histogram into positions; per-code
+// segment start and length
+__global__ void list_scan_kernel(int ncodes, int32_t *hist, int32_t *seg_start, int32_t *seg_count) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int32_t run = 0;
+    for (int c = 0; c < ncodes; ++c) {
+        seg_start[c] = run;
+        for (int k = 0; k < kWeightBins; ++k) {
+            const int32_t n = hist[c * kWeightBins + k];
+            hist[c * kWeightBins + k] = run;
+            run += n;
+        }
+        seg_count[c] = run - seg_start[c];
+    }
+}
+
+__global__ void list_scatter_kernel(int64_t B, const int32_t *key, int32_t *pos, int32_t *list) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int k = key[b];
+    if (k < 0) return;
+    list[atomicAdd(&pos[k], 1)] = (int32_t)b;
 }
 
 // ------------------------------------------------------------------------
@@ -352,31 +503,77 @@ struct Variant {
     const void *fn[2][2];  // [prior][trace]
 };
 
-#define RB_VARIANT(G, CPT, DC, VPT, DV)                                                     \
-    {{G, CPT, DC, VPT, DV},                                                                 \
-     {{(const void *)relay_group_kernel<G, CPT, DC, VPT, DV, false, false>,                 \
-       (const void *)relay_group_kernel<G, CPT, DC, VPT, DV, false, true>},                 \
-      {(const void *)relay_group_kernel<G, CPT, DC, VPT, DV, true, false>,                  \
-       (const void *)relay_group_kernel<G, CPT, DC, VPT, DV, true, true>}}}
+#define RB_VARIANT(G, CPT, DC, VPT, DV, W)                                                  \
+    {{G, CPT, DC, VPT, DV, W},                                                              \
+     {{(const void *)relay_group_kernel<G, CPT, DC, VPT, DV, W, false, false>,              \
+       (const void *)relay_group_kernel<G, CPT, DC, VPT, DV, W, false, true>},              \
+      {(const void *)relay_group_kernel<G, CPT, DC, VPT, DV, W, true, false>,               \
+       (const void *)relay_group_kernel<G, CPT, DC, VPT, DV, W, true, true>}}}
 
+// (G, CPT, DC, VPT, DV, waves per SIMD the register budget targets)
 const Variant kVariants[] = {
     // regular degree-(6, 3) graphs: bivariate-bicycle check matrices
-    RB_VARIANT(4, 9, 6, 18, 3),    // M <= 36,  N <= 72
-    RB_VARIANT(8, 6, 6, 12, 3),    // M <= 48,  N <= 96
-    RB_VARIANT(8, 9, 6, 18, 3),    // M <= 72,  N <= 144
-    RB_VARIANT(16, 5, 6, 9, 3),    // M <= 80,  N <= 144
-    RB_VARIANT(16, 9, 6, 18, 3),   // M <= 144, N <= 288
-    RB_VARIANT(32, 5, 6, 9, 3),    // M <= 160, N <= 288
+    RB_VARIANT(4, 9, 6, 18, 3, 2),    // M <= 36,  N <= 72
+    RB_VARIANT(8, 5, 6, 9, 3, 4),     // M <= 40,  N <= 72
+    RB_VARIANT(8, 6, 6, 12, 3, 3),    // M <= 48,  N <= 96
+    RB_VARIANT(16, 3, 6, 6, 3, 4),    // M <= 48,  N <= 96
+    RB_VARIANT(8, 9, 6, 18, 3, 2),    // M <= 72,  N <= 144
+    RB_VARIANT(16, 5, 6, 9, 3, 4),    // M <= 80,  N <= 144
+    RB_VARIANT(16, 5, 6, 9, 3, 3),    // M <= 80,  N <= 144
+    RB_VARIANT(16, 9, 6, 18, 3, 2),   // M <= 144, N <= 288
+    RB_VARIANT(32, 5, 6, 9, 3, 4),    // M <= 160, N <= 288
     // irregular small graphs
-    RB_VARIANT(16, 4, 16, 8, 8),   // M <= 64,  N <= 128
-    RB_VARIANT(64, 4, 16, 8, 8),   // M <= 256, N <= 512
+    RB_VARIANT(16, 4, 16, 8, 8, 2),   // M <= 64,  N <= 128
+    RB_VARIANT(64, 4, 16, 8, 8, 2),   // M <= 256, N <= 512
 };
 
 }  // namespace
 
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 
+// group variants usable in the mixed launch, in the order of its tile switch
+const int kMixedVariants[] = {1, 3, 5, 8};
+
+int mixed_tile_of_variant(int v) {
+    for (int t = 0; t < (int)(sizeof(kMixedVariants) / sizeof(kMixedVariants[0])); ++t)
+        if (kMixedVariants[t] == v) return t;
+    return -1;
+}
+
+hipError_t mixed_occupancy(bool prior_anchor, size_t lds, int *blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, prior_anchor ? (const void *)relay_mixed_kernel<true> : (const void *)relay_mixed_kernel<false>,
+        64, lds);
+}
+
+hipError_t launch_mixed(bool prior_anchor, const MixedArgs &m, int grid, size_t lds, hipStream_t s) {
+    const void *fn = prior_anchor ? (const void *)relay_mixed_kernel<true> : (const void *)relay_mixed_kernel<false>;
+    MixedArgs copy = m;
+    void *args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(grid), dim3(64), args, lds, s);
+}
+
 TileShape variant_shape(int v) { return kVariants[v].shape; }
+
+hipError_t variant_static_lds(int v, size_t *bytes) {
+    size_t mx = 0;
+    for (int p = 0; p < 2; ++p)
+        for (int tr = 0; tr < 2; ++tr) {
+            hipFuncAttributes attr;
+            const hipError_t e = hipFuncGetAttributes(&attr, kVariants[v].fn[p][tr]);
+            if (e != hipSuccess) return e;
+            if ((size_t)attr.sharedSizeBytes > mx) mx = (size_t)attr.sharedSizeBytes;
+        }
+    for (int p = 0; p < 2; ++p) {
+        hipFuncAttributes attr;
+        const hipError_t e = hipFuncGetAttributes(
+            &attr, p ? (const void *)relay_mixed_kernel<true> : (const void *)relay_mixed_kernel<false>);
+        if (e != hipSuccess) return e;
+        if ((size_t)attr.sharedSizeBytes > mx) mx = (size_t)attr.sharedSizeBytes;
+    }
+    *bytes = mx;
+    return hipSuccess;
+}
 
 hipError_t variant_occupancy(int v, bool prior_anchor, bool trace, size_t lds, int *blocks) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -399,6 +596,28 @@ hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_f
     hipLaunchKernelGGL(gamma_table_kernel, dim3(blocks), dim3(threads), 0, s, tab, R, N, seed,
                        g_first, lo, hi);
     return hipGetLastError();
+}
+
+hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
+                             const int32_t *code_m, int ncodes, void *workspace,
+                             unsigned long long *queues, hipStream_t s) {
+    int32_t *hist = (int32_t *)workspace;                       // ncodes * bins
+    int32_t *seg_start = hist + (size_t)ncodes * kWeightBins;   // ncodes
+    int32_t *seg_count = seg_start + ncodes;                    // ncodes
+    int32_t *key = seg_count + ncodes;                          // B
+    int32_t *list = key + B;                                    // B
+    const int nh = ncodes * kWeightBins;
+    hipLaunchKernelGGL(list_zero_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, hist, nh, queues, ncodes);
+    const int blocks = (int)((B + 255) / 256);
+    hipLaunchKernelGGL(list_key_kernel, dim3(blocks), dim3(256), 0, s, B, syn, syn_stride, code_id, code_m,
+                       ncodes, key, hist);
+    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, ncodes, hist, seg_start, seg_count);
+    hipLaunchKernelGGL(list_scatter_kernel, dim3(blocks), dim3(256), 0, s, B, key, hist, list);
+    return hipGetLastError();
+}
+
+size_t shot_list_bytes(int64_t B, int ncodes) {
+    return sizeof(int32_t) * ((size_t)ncodes * (kWeightBins + 2) + 2 * (size_t)B);
 }
 
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s) {

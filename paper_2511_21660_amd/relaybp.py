@@ -52,7 +52,13 @@ class RBInfo(ctypes.Structure):
         (n, ctypes.c_int32) for n in (
             "max_row_degree", "max_col_degree", "variant", "lanes_per_shot", "checks_per_lane",
             "row_slots", "cols_per_lane", "col_slots", "shots_per_block", "threads_per_block",
-            "lds_bytes_per_block", "blocks_per_cu", "grid_blocks", "num_variants")]
+            "waves_per_simd_target", "lds_bytes_per_block", "blocks_per_cu", "grid_blocks",
+            "num_variants")]
+
+
+class RBCodeDesc(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("rows", ctypes.c_void_p), ("cols", ctypes.c_void_p), ("prior_p", ctypes.c_void_p)]
 
 
 _lib = None
@@ -78,12 +84,27 @@ def load_library():
     L.rb_get_info.argtypes = [P, ctypes.POINTER(RBInfo)]
     L.rb_set_variant.argtypes = [P, i32]
     L.rb_sync_status.argtypes = [P]
+    L.rb_autotune.argtypes = [P, i64, P, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+    L.rb_reserve.argtypes = [P, i64]
+    L.rb_workspace_size.argtypes = [P, i64]
+    L.rb_workspace_size.restype = ctypes.c_size_t
+    L.rb_create_multi.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(RBCodeDesc),
+                                  ctypes.POINTER(RBParams), i32]
+    L.rb_decode_multi.argtypes = [P, i64, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+    L.rb_autotune_multi.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(P), i32,
+                                    ctypes.POINTER(i32)]
+    L.rb_train_tape_size.argtypes = [P, i64, i32, i32]
+    L.rb_train_tape_size.restype = ctypes.c_size_t
+    L.rb_forward_train.argtypes = [P, i64, P, P, P, i32, i32, P, P, ctypes.c_size_t, P]
+    L.rb_backward.argtypes = [P, i64, P, P, P, i32, i32, P, ctypes.c_size_t, P, P, P, P]
     L.rb_status_string.argtypes = [ctypes.c_int]
     L.rb_status_string.restype = ctypes.c_char_p
     L.rb_last_error_message.argtypes = []
     L.rb_last_error_message.restype = ctypes.c_char_p
     for name in ("rb_params_default", "rb_create", "rb_decode", "rb_trace", "rb_get_llr",
-                 "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status"):
+                 "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status",
+                 "rb_autotune", "rb_reserve", "rb_create_multi", "rb_decode_multi",
+                 "rb_autotune_multi", "rb_forward_train", "rb_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -222,5 +243,127 @@ class Decoder:
     def set_variant(self, v: int):
         _check(load_library().rb_set_variant(self._h, int(v)))
 
+    def tape_bytes(self, b: int, t_iters: int, ckpt_every: int) -> int:
+        return int(load_library().rb_train_tape_size(self._h, int(b), int(t_iters), int(ckpt_every)))
+
+    def forward_train(self, syndromes, gamma, scale, t_iters, ckpt_every, tape, llr_out):
+        _check(load_library().rb_forward_train(
+            self._h, syndromes.shape[0], _ptr(syndromes), _ptr(gamma), _ptr(scale), int(t_iters),
+            int(ckpt_every), _ptr(llr_out), _ptr(tape), tape.numel(), _stream(syndromes.device)))
+
+    def backward_train(self, syndromes, gamma, scale, t_iters, ckpt_every, tape, dllr, dgamma,
+                       dscale):
+        _check(load_library().rb_backward(
+            self._h, syndromes.shape[0], _ptr(syndromes), _ptr(gamma), _ptr(scale), int(t_iters),
+            int(ckpt_every), _ptr(tape), tape.numel(), _ptr(dllr), _ptr(dgamma), _ptr(dscale),
+            _stream(syndromes.device)))
+
+    def reserve(self, max_batch: int):
+        """Enables longest-first scheduling for batches of up to max_batch syndromes
+        (allocates a device workspace once; synchronises the device)."""
+        _check(load_library().rb_reserve(self._h, int(max_batch)))
+
+    def autotune(self, syndromes, reps: int = 3):
+        """Times every fitting kernel configuration on these syndromes and keeps
+        the fastest; returns (variant, ms per decode).  Synchronises the device."""
+        syndromes = syndromes.contiguous()
+        v = ctypes.c_int32()
+        ms = ctypes.c_float()
+        _check(load_library().rb_autotune(self._h, syndromes.shape[0], _ptr(syndromes), int(reps),
+                                          ctypes.byref(v), ctypes.byref(ms)))
+        return v.value, ms.value
+
     def sync(self):
         _check(load_library().rb_sync_status(self._h))
+
+
+class MultiDecoder:
+    """One persistent launch over syndromes of several codes (rb_decode_multi)."""
+
+    def __init__(self, problems, params=None, device=0, **overrides):
+        L = load_library()
+        self.device = int(device)
+        if params is None:
+            params = default_params(**overrides)
+        elif isinstance(params, dict):
+            params = default_params(**params, **overrides)
+        self.params = params
+        self.ms = [int(p.m) for p in problems]
+        self.ns = [int(p.n) for p in problems]
+        self.m_max, self.n_max = max(self.ms), max(self.ns)
+        keep = []
+        descs = (RBCodeDesc * len(problems))()
+        for k, p in enumerate(problems):
+            rows = np.ascontiguousarray(p.rows, dtype=np.int32)
+            cols = np.ascontiguousarray(p.cols, dtype=np.int32)
+            prior = np.ascontiguousarray(np.broadcast_to(np.asarray(p.prior, np.float64), (p.n,)))
+            keep += [rows, cols, prior]
+            descs[k] = RBCodeDesc(p.m, p.n, rows.size, rows.ctypes.data_as(ctypes.c_void_p),
+                                  cols.ctypes.data_as(ctypes.c_void_p),
+                                  prior.ctypes.data_as(ctypes.c_void_p))
+        h = ctypes.c_void_p()
+        _check(L.rb_create_multi(ctypes.byref(h), len(problems), descs, ctypes.byref(params),
+                                 self.device))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().rb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, b: int) -> int:
+        return int(load_library().rb_workspace_size(self._h, int(b)))
+
+    def alloc(self, b: int, want_weight=True, want_llr=False):
+        """Output buffers and workspace for a batch of b syndromes (reusable, e.g.
+        across hipGraph replays)."""
+        import torch
+
+        dev = torch.device("cuda", self.device)
+        out = {
+            "corr": torch.empty((b, self.n_max), dtype=torch.uint8, device=dev),
+            "conv": torch.empty(b, dtype=torch.uint8, device=dev),
+            "legs": torch.empty(b, dtype=torch.int32, device=dev),
+            "iters": torch.empty(b, dtype=torch.int32, device=dev),
+            "workspace": torch.empty(max(1, self.workspace_bytes(b)), dtype=torch.uint8,
+                                     device=dev),
+        }
+        if want_weight:
+            out["weight"] = torch.empty(b, dtype=torch.float64, device=dev)
+        if want_llr:
+            out["llr"] = torch.empty((b, self.n_max), dtype=torch.float32, device=dev)
+        return out
+
+    def decode(self, code_id, syndromes, out=None, want_weight=True, want_llr=False):
+        """code_id int32 [B], syndromes uint8 [B, M_max] (CUDA).  Enqueues on the
+        current stream; returns the dict of output tensors."""
+        import torch
+
+        if syndromes.dtype != torch.uint8 or syndromes.shape[1] != self.m_max:
+            raise ValueError(f"syndromes must be uint8 [B, {self.m_max}]")
+        if code_id.dtype != torch.int32 or code_id.shape[0] != syndromes.shape[0]:
+            raise ValueError("code_id must be int32 [B]")
+        b = syndromes.shape[0]
+        if out is None:
+            out = self.alloc(b, want_weight, want_llr)
+        ws = out["workspace"]
+        _check(load_library().rb_decode_multi(
+            self._h, b, _ptr(code_id), _ptr(syndromes), _ptr(out["corr"]), _ptr(out["conv"]),
+            _ptr(out["legs"]), _ptr(out["iters"]), _ptr(out.get("weight")), _ptr(out.get("llr")),
+            _ptr(ws), ws.numel(), _stream(syndromes.device)))
+        return out
+
+    def autotune(self, samples, reps: int = 3):
+        """samples: list (one per code) of uint8 CUDA tensors [b_k, M_k] (or None)."""
+        k = len(self.ms)
+        bs = (ctypes.c_int64 * k)(*[0 if s is None else s.shape[0] for s in samples])
+        ptrs = (ctypes.c_void_p * k)(*[None if s is None else s.data_ptr() for s in samples])
+        chosen = (ctypes.c_int32 * k)()
+        _check(load_library().rb_autotune_multi(self._h, bs, ptrs, int(reps), chosen))
+        return list(chosen)

@@ -226,3 +226,159 @@ def test_cfg2_full_size_sampled_parity(rb):
     sub = {k: gpu[k][idx] for k in KEYS}
     sub["info"] = gpu["info"]
     assert_parity(sub, ref, syn[idx], prob, "cfg2 full-size sample")
+
+
+@pytest.fixture(scope="module")
+def dem():
+    return codes.dem_problem()
+
+
+def test_dem_block_kernel_parity(rb, dem):
+    """DEM-shaped 936 x 8785 matrix (E = 27,617, row degree up to 63): the
+    block kernel against the oracle on 200 shots, T = 80/60, R = 20, S = 1."""
+    _, syn = sampling.sample_batch(dem, 3 << 32, 0, 200)
+    gpu = gpu_decode(rb, dem, RELAY_DEFAULT, syn)
+    assert gpu["info"]["threads_per_block"] >= 512
+    ref = oracle.decode(dem.m, dem.n, dem.rows, dem.cols, dem.prior, RELAY_DEFAULT, syn,
+                        want_llr=True)
+    assert_parity(gpu, ref, syn, dem, "dem block")
+
+
+def test_dem_trace_bit_exact(rb, dem):
+    _, syn = sampling.sample_batch(dem, 17, 0, 4)
+    gamma = np.random.default_rng(9).uniform(-0.24, 0.66, dem.n).astype(np.float32)
+    dec = rb.Decoder.from_problem(dem, **RELAY_DEFAULT)
+    tr = dec.trace(torch.from_numpy(syn).cuda(), torch.from_numpy(gamma).cuda(), 25).cpu().numpy()
+    ref = oracle.trace(dem.m, dem.n, dem.rows, dem.cols, dem.prior, gamma, 25, syn)
+    np.testing.assert_array_equal(tr, ref)
+
+
+def test_dem_prior_anchor_and_solutions(rb, dem):
+    _, syn = sampling.sample_batch(dem, 5 << 32, 0, 120)
+    prm = dict(RELAY_DEFAULT, anchor=1, num_solutions=3, num_legs=8, max_total_iters=300)
+    gpu = gpu_decode(rb, dem, prm, syn)
+    ref = oracle.decode(dem.m, dem.n, dem.rows, dem.cols, dem.prior, prm, syn, want_llr=True)
+    assert_parity(gpu, ref, syn, dem, "dem prior anchor S=3")
+
+
+# ----------------------------------------------------------- mixed batches
+
+MIX_CODES = ("bb72", "bb90", "bb144", "bb288")
+MIX_PATTERN = np.array([0, 1, 2, 0, 3, 1, 0, 2, 1, 0], np.int32)  # 4:3:2:1 interleave
+
+
+def _mixed_inputs(b, p=0.04, key=4 << 32):
+    probs = [codes.bb_problem(n, p) for n in MIX_CODES]
+    code_id = np.resize(MIX_PATTERN, b).astype(np.int32)
+    m_max = max(pr.m for pr in probs)
+    syn = np.zeros((b, m_max), np.uint8)
+    per_code = {}
+    for k, pr in enumerate(probs):
+        idx = np.nonzero(code_id == k)[0]
+        _, s = sampling.sample_batch(pr, key | k, 0, idx.size)
+        syn[idx, :pr.m] = s
+        per_code[k] = (idx, s)
+    return probs, code_id, syn, per_code
+
+
+def test_mixed_batch_parity(rb):
+    """Four BB codes interleaved 4:3:2:1 in one launch: every shot equals the
+    oracle's decode of its own code."""
+    b = 1200
+    probs, code_id, syn, per_code = _mixed_inputs(b)
+    dec = rb.MultiDecoder(probs, **RELAY_DEFAULT)
+    out = dec.decode(torch.from_numpy(code_id).cuda(), torch.from_numpy(syn).cuda(), want_llr=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items() if k != "workspace"}
+    for k, pr in enumerate(probs):
+        idx, s = per_code[k]
+        ref = oracle.decode(pr.m, pr.n, pr.rows, pr.cols, pr.prior, RELAY_DEFAULT, s, want_llr=True)
+        sub = {"corr": g["corr"][idx, :pr.n], "conv": g["conv"][idx], "legs": g["legs"][idx],
+               "iters": g["iters"][idx], "weight": g["weight"][idx], "llr": g["llr"][idx, :pr.n],
+               "info": {"variant": "mixed"}}
+        assert_parity(sub, ref, s, pr, f"mixed code {MIX_CODES[k]}")
+    dec.close()
+
+
+def _defined(out, code_id, ns):
+    """Outputs with the padding of each row (entries >= N of its code) zeroed."""
+    cid = torch.as_tensor(code_id, device="cuda").long()
+    n_of = torch.as_tensor(ns, device="cuda")[cid]
+    res = {}
+    for k, v in out.items():
+        if k == "workspace":
+            continue
+        if v.dim() == 2:
+            mask = torch.arange(v.shape[1], device="cuda")[None, :] < n_of[:, None]
+            v = torch.where(mask, v, torch.zeros_like(v))
+        res[k] = v.clone()
+    return res
+
+
+def test_mixed_autotune_keeps_results(rb):
+    b = 600
+    probs, code_id, syn, per_code = _mixed_inputs(b, key=7 << 32)
+    dec = rb.MultiDecoder(probs, **RELAY_DEFAULT)
+    d_code, d_syn = torch.from_numpy(code_id).cuda(), torch.from_numpy(syn).cuda()
+    ns = [pr.n for pr in probs]
+    before = _defined(dec.decode(d_code, d_syn, want_llr=True), code_id, ns)
+    samples = [torch.from_numpy(per_code[k][1]).cuda() for k in range(len(probs))]
+    chosen = dec.autotune(samples, reps=1)
+    assert len(chosen) == len(probs)
+    after = _defined(dec.decode(d_code, d_syn, want_llr=True), code_id, ns)
+    torch.cuda.synchronize()
+    for k in before:
+        assert torch.equal(before[k], after[k]), k
+
+
+def test_mixed_hipgraph_replays(rb):
+    """rb_decode_multi captured in a hipGraph (through torch.cuda.CUDAGraph) and
+    replayed several times, with eager work and synchronisation in between:
+    every replay equals the eager result."""
+    b = 800
+    probs, code_id, syn, _ = _mixed_inputs(b, key=9 << 32)
+    dec = rb.MultiDecoder(probs, **RELAY_DEFAULT)
+    d_code, d_syn = torch.from_numpy(code_id).cuda(), torch.from_numpy(syn).cuda()
+    ns = [pr.n for pr in probs]
+    eager = _defined(dec.decode(d_code, d_syn), code_id, ns)
+    torch.cuda.synchronize()
+    out = dec.alloc(b)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        dec.decode(d_code, d_syn, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dec.decode(d_code, d_syn, out=out)
+    for rep in range(3):
+        for v in out.values():
+            v.fill_(0x5A if v.dtype == torch.uint8 else 7)  # poison between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = _defined(out, code_id, ns)
+        for k in eager:
+            assert torch.equal(got[k], eager[k]), f"replay {rep}: {k}"
+        del junk
+
+
+def test_longest_first_schedule_keeps_results(rb):
+    """rb_reserve switches rb_decode to a shot list sorted by syndrome weight;
+    every shot's result is unchanged."""
+    prob = codes.bb_problem("bb144", 0.07)
+    _, syn = sampling.sample_batch(prob, 31, 0, 3000)
+    prm = dict(RELAY_DEFAULT, num_legs=60, num_solutions=2)
+    dec = rb.Decoder.from_problem(prob, **prm)
+    d_syn = torch.from_numpy(syn).cuda()
+    plain = {k: v.cpu().numpy() for k, v in dec.decode(d_syn, want_llr=True).items()}
+    dec.reserve(4000)
+    lpt = {k: v.cpu().numpy() for k, v in dec.decode(d_syn, want_llr=True).items()}
+    for k in plain:
+        np.testing.assert_array_equal(plain[k], lpt[k])
+    ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, prm, syn[:500],
+                        want_llr=True)
+    sub = {k: lpt[k][:500] for k in KEYS}
+    sub["info"] = dec.info()
+    assert_parity(sub, ref, syn[:500], prob, "longest-first")
