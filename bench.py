@@ -70,6 +70,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100000, help="oracle shots per p")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--schedule", choices=["per-p", "per-p-lpt", "mixed"], default="mixed",
+                    help="per-p: one launch per p in input order; per-p-lpt: one launch per p, "
+                         "shots longest-first; mixed: all four p in one launch (one code "
+                         "context per p), longest-first per p")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy kernel of MB MiB (int32 "
                          "bitwise_not: reads and writes MB MiB) to scale HBM counters")
@@ -98,30 +102,59 @@ def main():
         faults.append(f)
         syns.append(s)
     E = probs[0].nnz
-    decs = [rb.Decoder.from_problem(pr, device=0, **RELAY) for pr in probs]
-    if args.variant is not None:
-        for d in decs:
-            d.set_variant(args.variant)
-    d_syn = [torch.from_numpy(s).to(dev) for s in syns]
-    outs = []
-    for s in syns:
-        b = s.shape[0]
-        outs.append({
-            "corr": torch.empty((b, 144), dtype=torch.uint8, device=dev),
-            "conv": torch.empty(b, dtype=torch.uint8, device=dev),
-            "legs": torch.empty(b, dtype=torch.int32, device=dev),
-            "iters": torch.empty(b, dtype=torch.int32, device=dev),
-            "weight": torch.empty(b, dtype=torch.float64, device=dev),
-        })
     stream = torch.cuda.current_stream(dev)
+    if args.schedule == "mixed":
+        mdec = rb.MultiDecoder(probs, device=0, **RELAY)
+        code_id = torch.cat([torch.full((s.shape[0],), q, dtype=torch.int32)
+                             for q, s in enumerate(syns)]).to(dev)
+        d_all = torch.from_numpy(np.concatenate(syns)).to(dev)
+        mout = mdec.alloc(d_all.shape[0])
+        decs = None
+        offs = np.cumsum([0] + [s.shape[0] for s in syns])
 
-    def step(events=None):
-        for q in range(len(ps)):
+        def step(events=None):
             if events is not None:
-                events[q][0].record(stream)
-            decs[q].decode(d_syn[q], out=outs[q])
+                events[0][0].record(stream)
+            mdec.decode(code_id, d_all, out=mout)
             if events is not None:
-                events[q][1].record(stream)
+                events[0][1].record(stream)
+
+        n_launch = 1
+
+        def results():
+            host = {k: v.cpu().numpy() for k, v in mout.items() if k != "workspace"}
+            return [{k: v[offs[q]:offs[q + 1]] for k, v in host.items()} for q in range(len(ps))]
+    else:
+        decs = [rb.Decoder.from_problem(pr, device=0, **RELAY) for pr in probs]
+        for d in decs:
+            if args.variant is not None:
+                d.set_variant(args.variant)
+            if args.schedule == "per-p-lpt":
+                d.reserve(args.shots)
+        d_syn = [torch.from_numpy(s).to(dev) for s in syns]
+        outs = []
+        for s in syns:
+            b = s.shape[0]
+            outs.append({
+                "corr": torch.empty((b, 144), dtype=torch.uint8, device=dev),
+                "conv": torch.empty(b, dtype=torch.uint8, device=dev),
+                "legs": torch.empty(b, dtype=torch.int32, device=dev),
+                "iters": torch.empty(b, dtype=torch.int32, device=dev),
+                "weight": torch.empty(b, dtype=torch.float64, device=dev),
+            })
+
+        def step(events=None):
+            for q in range(len(ps)):
+                if events is not None:
+                    events[q][0].record(stream)
+                decs[q].decode(d_syn[q], out=outs[q])
+                if events is not None:
+                    events[q][1].record(stream)
+
+        n_launch = len(ps)
+
+        def results():
+            return [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
 
     for _ in range(args.warmup):
         step()
@@ -130,7 +163,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in ps]
+              for _ in range(n_launch)]
         step(ev)
         launch_ms.append(ev)
     torch.cuda.synchronize()
@@ -138,7 +171,7 @@ def main():
     per_launch = [[e[0].elapsed_time(e[1]) for e in evs] for evs in launch_ms]
     kernel_ms = float(np.mean(per_launch))
 
-    res = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+    res = results()
     n_shots = sum(s.shape[0] for s in syns)
     iters_total = sum(int(r["iters"].astype(np.int64).sum()) for r in res)
     edge_updates_step = iters_total * E
@@ -147,6 +180,8 @@ def main():
 
     # roofline of the decode kernel: algorithmic ops per launch / mean launch time
     per_launch_eu = [int(r["iters"].astype(np.int64).sum()) * E for r in res]
+    if n_launch == 1:
+        per_launch_eu = [sum(per_launch_eu)]
     ops_per_iter = OPS_PER_EDGE * E + OPS_PER_FAULT * 144 + OPS_PER_CHECK * 72
     ops_launch = np.mean([eu / E * ops_per_iter for eu in per_launch_eu])
     achieved_tops = ops_launch / (kernel_ms * 1e-3) / 1e12
@@ -191,7 +226,19 @@ def main():
         torch.cuda.synchronize()
         copy_bytes = n_el * 4
 
-    info = decs[0].info()
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "relay_mixed_kernel_bb144_hbm_traffic.txt")
+    if args.schedule == "mixed" and os.path.exists(tpath):
+        from paper_2511_21660_amd import profiling
+
+        rec = json.load(open(tpath))
+        if rec.get("source_hash") == profiling.source_hash():
+            traffic = rec["traffic_bytes_per_launch"]
+
+    info = decs[0].info() if decs else {"variant": "mixed", "lanes_per_shot": None,
+                                         "checks_per_lane": None, "cols_per_lane": None,
+                                         "shots_per_block": None, "lds_bytes_per_block": None,
+                                         "blocks_per_cu": None, "grid_blocks": None}
     line = {
         "metric": "syndromes decoded/s at matched LER; edge-updates/s and % HBM/LDS roofline",
         "value": value,
@@ -210,13 +257,14 @@ def main():
                    "p": ps, "syndromes_per_p": args.shots, "syndromes_per_step": n_shots,
                    "T_first": 80, "T_leg": 60, "legs": 301, "solutions": 5,
                    "gamma_first": 0.125, "gamma_range": [-0.24, 0.66], "anchor": "chain",
-                   "parallelism": "single_gpu"},
+                   "schedule": args.schedule, "parallelism": "single_gpu"},
         "edge_updates_per_s": eu_per_s,
-        "launch_ms_by_p": {str(p): float(np.mean([pl[q] for pl in per_launch]))
-                           for q, p in enumerate(ps)},
+        "launch_ms": [float(np.mean([pl[q] for pl in per_launch])) for q in range(n_launch)],
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS,
-                     "unit": "Tops/s", "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": None,
-                     "kernel": "relay_group_kernel", "kernel_ms_per_launch": kernel_ms,
+                     "unit": "Tops/s", "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,
+                     "kernel": ("relay_mixed_kernel" if args.schedule == "mixed"
+                                else "relay_group_kernel"),
+                     "kernel_ms_per_launch": kernel_ms,
                      "ops_per_edge_update": ops_per_iter / E},
         "lds_roofline": {"achieved": lds_tbs, "peak": PEAK_LDS_TBS, "unit": "TB/s",
                          "frac": lds_tbs / PEAK_LDS_TBS, "bytes_per_edge_update": b_alg},

@@ -451,24 +451,41 @@ __global__ void list_zero_kernel(int32_t *p, int n, unsigned long long *queues, 
     if (i < nq) queues[i] = 0ull;
 }
 
-__global__ void list_key_kernel(int64_t B, const uint8_t *syn, int32_t syn_stride,
-                                const int32_t *code_id, const int32_t *code_m, int ncodes,
-                                int32_t *key, int32_t *hist) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+constexpr int kListThreads = 256;
+
+// Key of shot b: code-major, then decreasing syndrome weight (bin), or -1.
+__device__ __forceinline__ int shot_key(int64_t b, const uint8_t *syn, int32_t syn_stride,
+                                        const int32_t *code_id, const int32_t *code_m, int ncodes) {
     const int c = code_id ? code_id[b] : 0;
-    if (c < 0 || c >= ncodes) {
-        key[b] = -1;  // invalid code id: the shot is skipped (outputs untouched)
-        return;
-    }
+    if (c < 0 || c >= ncodes) return -1;  // invalid code id: shot skipped, outputs untouched
     const int m = code_m[c];
     const uint8_t *s = syn + (size_t)b * syn_stride;
     int wgt = 0;
     for (int i = 0; i < m; ++i) wgt += s[i] != 0;
-    const int bin = kWeightBins - 1 - min(wgt, kWeightBins - 1);
-    const int k = c * kWeightBins + bin;
-    key[b] = k;
-    atomicAdd(&hist[k], 1);
+    return c * kWeightBins + (kWeightBins - 1 - min(wgt, kWeightBins - 1));
+}
+
+// Block-local histogram in LDS (dynamic LDS: nbins words), then one global
+// atomic per nonzero (block, bin).
+__global__ __launch_bounds__(kListThreads) void list_key_kernel(
+        int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
+        const int32_t *code_m, int ncodes, int32_t *key, int32_t *hist) {
+    const int nb = ncodes * kWeightBins;
+    for (int k = threadIdx.x; k < nb; k += kListThreads) *(__attribute__((address_space(3))) int32_t *)(size_t)(4u * k) = 0;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * kListThreads + threadIdx.x;
+    if (b < B) {
+        const int k = shot_key(b, syn, syn_stride, code_id, code_m, ncodes);
+        key[b] = k;
+        if (k >= 0)
+            __hip_atomic_fetch_add((__attribute__((address_space(3))) int32_t *)(size_t)(4u * k), 1,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += kListThreads) {
+        const int n = *(__attribute__((address_space(3))) int32_t *)(size_t)(4u * k);
+        if (n) atomicAdd(&hist[k], n);
+    }
 }
 
 // single thread: exclusive scan of the histogram into positions; per-code
@@ -487,12 +504,30 @@ __global__ void list_scan_kernel(int ncodes, int32_t *hist, int32_t *seg_start, 
     }
 }
 
-__global__ void list_scatter_kernel(int64_t B, const int32_t *key, int32_t *pos, int32_t *list) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const int k = key[b];
-    if (k < 0) return;
-    list[atomicAdd(&pos[k], 1)] = (int32_t)b;
+// Each block reserves one contiguous range per nonzero (block, bin) and
+// places its shots inside it (order within a bin is irrelevant: every shot's
+// result depends on its own syndrome only).
+__global__ __launch_bounds__(kListThreads) void list_scatter_kernel(int64_t B, int nb, const int32_t *key,
+                                                                    int32_t *pos, int32_t *list) {
+    // LDS: count[nb], then base[nb]
+    const uint32_t cnt0 = 0u, base0 = 4u * (uint32_t)nb;
+    for (int k = threadIdx.x; k < nb; k += kListThreads) *(__attribute__((address_space(3))) int32_t *)(size_t)(cnt0 + 4u * k) = 0;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * kListThreads + threadIdx.x;
+    int k = -1, local = 0;
+    if (b < B) {
+        k = key[b];
+        if (k >= 0)
+            local = __hip_atomic_fetch_add((__attribute__((address_space(3))) int32_t *)(size_t)(cnt0 + 4u * k), 1,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb; q += kListThreads) {
+        const int n = *(__attribute__((address_space(3))) int32_t *)(size_t)(cnt0 + 4u * q);
+        *(__attribute__((address_space(3))) int32_t *)(size_t)(base0 + 4u * q) = n ? atomicAdd(&pos[q], n) : 0;
+    }
+    __syncthreads();
+    if (k >= 0) list[*(__attribute__((address_space(3))) int32_t *)(size_t)(base0 + 4u * k) + local] = (int32_t)b;
 }
 
 // ------------------------------------------------------------------------
@@ -608,11 +643,12 @@ hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, 
     int32_t *list = key + B;                                    // B
     const int nh = ncodes * kWeightBins;
     hipLaunchKernelGGL(list_zero_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, hist, nh, queues, ncodes);
-    const int blocks = (int)((B + 255) / 256);
-    hipLaunchKernelGGL(list_key_kernel, dim3(blocks), dim3(256), 0, s, B, syn, syn_stride, code_id, code_m,
-                       ncodes, key, hist);
+    const int blocks = (int)((B + kListThreads - 1) / kListThreads);
+    hipLaunchKernelGGL(list_key_kernel, dim3(blocks), dim3(kListThreads), 4u * (size_t)nh, s, B, syn, syn_stride,
+                       code_id, code_m, ncodes, key, hist);
     hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, ncodes, hist, seg_start, seg_count);
-    hipLaunchKernelGGL(list_scatter_kernel, dim3(blocks), dim3(256), 0, s, B, key, hist, list);
+    hipLaunchKernelGGL(list_scatter_kernel, dim3(blocks), dim3(kListThreads), 8u * (size_t)nh, s, B, nh, key, hist,
+                       list);
     return hipGetLastError();
 }
 

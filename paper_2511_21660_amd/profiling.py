@@ -1,0 +1,99 @@
+"""Summaries of rocprofv3 output for the decoding kernels.
+
+* ``stats``   : markdown table of a ``--kernel-trace --stats`` kernel_stats.csv.
+* ``traffic`` : HBM bytes per launch of a kernel from two ``--pmc`` runs
+  (FETCH_SIZE, WRITE_SIZE, both in KiB per dispatch), each scaled by what the
+  same counter reads for a plain copy kernel that moves a known number of
+  bytes each way; stamped with a hash of the kernel sources so that a stale
+  figure is recognised after the kernels change.
+
+Usage (after the rocprofv3 runs):
+    python -m paper_2511_21660_amd.profiling stats KERNEL_STATS_CSV
+    python -m paper_2511_21660_amd.profiling traffic --fetch FETCH_CSV --write WRITE_CSV \
+        --kernel relay_mixed_kernel --copy-kernel elementwise --copy-bytes N --out OUT_JSON
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    """SHA-256 over the library's kernel and host sources."""
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(_HERE, "csrc", "*"))):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stats_table(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def _counter_means(path: str, counter: str):
+    sums = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        sums.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in sums.items()}
+
+
+def _pick(means: dict, substr: str) -> float:
+    hits = [v for k, v in means.items() if substr in k]
+    if not hits:
+        raise SystemExit(f"no kernel matching {substr!r} in counter output")
+    return max(hits)
+
+
+def traffic(fetch_csv, write_csv, kernel, copy_kernel, copy_bytes):
+    f = _counter_means(fetch_csv, "FETCH_SIZE")
+    w = _counter_means(write_csv, "WRITE_SIZE")
+    fetch_scale = copy_bytes / (_pick(f, copy_kernel) * 1024.0)
+    write_scale = copy_bytes / (_pick(w, copy_kernel) * 1024.0)
+    fb = _pick(f, kernel) * 1024.0 * fetch_scale
+    wb = _pick(w, kernel) * 1024.0 * write_scale
+    return {"kernel": kernel, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+            "traffic_bytes_per_launch": fb + wb, "fetch_scale": fetch_scale,
+            "write_scale": write_scale, "source_hash": source_hash()}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-kernel", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print(stats_table(a.csv))
+    else:
+        res = traffic(a.fetch, a.write, a.kernel, a.copy_kernel, a.copy_bytes)
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
