@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Relay-BP decoding throughput on one MI355X.
 
-Default workload: plain Relay-BP FP32 on the [[144,12,12]] bivariate-bicycle
-code (HX 72 x 144, E = 432 edges), i.i.d. code-capacity faults at
-p in {0.02, 0.04, 0.06, 0.08}, 10^5 syndromes per p, T_1 = 80, T_r = 60,
-R = 301 legs in total, S = 5 solutions kept (lowest weight output).
-One step = decoding all 4 x 10^5 syndromes (four launches, one decoder per p),
-syndromes already resident in HBM.
+Default workload (--workload bb144): plain Relay-BP FP32 on the [[144,12,12]]
+bivariate-bicycle code (HX 72 x 144, E = 432 edges), i.i.d. code-capacity
+faults at p in {0.02, 0.04, 0.06, 0.08}, 10^5 syndromes per p, T_1 = 80,
+T_r = 60, R = 301 legs in total, S = 5 solutions kept (lowest weight output).
+One step decodes all 4 x 10^5 syndromes, already resident in HBM.
 
-Prints one JSON line: syndromes/s (the headline), edge-updates/s, the roofline
-of the decode kernel measured with HIP events on the launch stream, and the
-CPU oracle timed on a bounded sample of the same workload on the host cores.
+Other workloads:
+  --workload dem          DEM-shaped 936 x 8785 matrix, 10^6 shots, R = 20, S = 1
+  --workload mixed-codes  [[72,12,6]], [[90,8,10]], [[144,12,12]], [[288,12,18]]
+                          interleaved 4:3:2:1, 4 x 10^5 shots at p = 0.04, R = 20,
+                          S = 1: one autotuned mixed launch (eager and replayed from
+                          a hipGraph) against four per-code launches
+
+Prints one JSON line: syndromes/s (the headline), edge-updates/s, the ALU
+roofline of the decode kernel from HIP events on the launch stream, the LDS
+roofline, the logical error rate with 95 % Wilson intervals, and the CPU
+oracle timed on a bounded sample of the same syndromes on the host cores.
 """
 from __future__ import annotations
 
@@ -29,11 +36,13 @@ sys.path.insert(0, ROOT)
 # MI355X peaks (published): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3 T lane-ops/s (non-packed FP32 / int)
 PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 78.6 TB/s at 128 B/clk/CU
-PEAK_HBM_GBS = 8000.0
 
+# Relay parameters of the paper's appendix on Relay resources (T = 80, then
+# 60; gamma_0 = 0.125, gamma ~ U[-0.24, 0.66]); R counts every leg.
 RELAY = dict(num_legs=301, iters_first=80, iters_leg=60, num_solutions=5, gamma_first=0.125,
              gamma_lo=-0.24, gamma_hi=0.66, llr_clip=2.0 ** 64, seed=0x52454C4159, anchor=0,
              max_total_iters=0)
+RELAY_R20 = dict(RELAY, num_legs=20, num_solutions=1)
 
 # Algorithmic work per edge-update (one edge in one iteration), from the
 # update rules: check side nu = clip(Lambda - mu) (2), sign parity (1),
@@ -43,6 +52,19 @@ RELAY = dict(num_legs=301, iters_first=80, iters_leg=60, num_solutions=5, gamma_
 OPS_PER_EDGE = 11.0
 OPS_PER_FAULT = 7.0
 OPS_PER_CHECK = 3.0
+
+DEFAULT_STEPS = {"bb144": 20, "dem": 5, "mixed-codes": 10}
+
+
+def ops_per_iteration(m, n, e):
+    return OPS_PER_EDGE * e + OPS_PER_FAULT * n + OPS_PER_CHECK * m
+
+
+def lds_bytes_per_edge_update(m, n, e):
+    """Algorithmic LDS bytes per edge-update: one nu to its check and one mu
+    back (8 B), plus Lambda / lambda per fault (8 B) and the check state
+    (12 B) per check, spread over the edges."""
+    return 8.0 + (8.0 * n + 12.0 * m) / e
 
 
 def wilson(k, n, z=1.96):
@@ -61,23 +83,403 @@ def logical_failures(prob, faults, corr, conv):
     return (~conv.astype(bool)) | bad
 
 
+def timed(torch, step, n_launch, steps, warmup):
+    """warmup untimed steps, then `steps` steps bracketed by device
+    synchronisation.  step(ev) records ev[k] = (start, end) HIP events on the
+    launch stream around launch k (ev is None during warm-up)."""
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n_launch)]
+        step(ev)
+        evs.append(ev)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    per_launch = [[e[0].elapsed_time(e[1]) for e in ev] for ev in evs]
+    return elapsed, per_launch
+
+
+def launch_means(per_launch):
+    return [float(np.mean([pl[k] for pl in per_launch])) for k in range(len(per_launch[0]))]
+
+
+def roofline(kernel, kernel_ms, ops_launch, eu_launch, lds_b_per_eu, traffic):
+    achieved = ops_launch / (kernel_ms * 1e-3) / 1e12
+    lds = eu_launch * lds_b_per_eu / (kernel_ms * 1e-3) / 1e12
+    return ({"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+             "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic, "kernel": kernel,
+             "kernel_ms_per_launch": kernel_ms, "ops_per_edge_update": ops_launch / eu_launch},
+            {"achieved": lds, "peak": PEAK_LDS_TBS, "unit": "TB/s", "frac": lds / PEAK_LDS_TBS,
+             "bytes_per_edge_update": lds_b_per_eu})
+
+
+def stored_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 summary, if it was taken
+    with the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    from paper_2511_21660_amd import profiling
+
+    rec = json.load(open(path))
+    if rec.get("source_hash") != profiling.source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def head(args, value, elapsed, config):
+    return {
+        "metric": "syndromes decoded/s at matched LER; edge-updates/s and % HBM/LDS roofline",
+        "value": value,
+        "unit": "syndromes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": config,
+    }
+
+
+def oracle_threads():
+    return min(16, os.cpu_count() or 1)
+
+
+# --------------------------------------------------------------------------
+# [[144,12,12]] at four p values, S = 5 (the headline)
+# --------------------------------------------------------------------------
+
+
+def run_bb144(args, torch, rb, codes, sampling):
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    ps = [0.02, 0.04, 0.06, 0.08]
+    shots = args.shots or 100000
+    probs, faults, syns = [], [], []
+    for q, p in enumerate(ps):
+        prob = codes.bb_problem("bb144", p)
+        f, s = sampling.sample_batch(prob, (2 << 32) | q, 0, shots)
+        probs.append(prob)
+        faults.append(f)
+        syns.append(s)
+    M, N, E = probs[0].m, probs[0].n, probs[0].nnz
+    if args.schedule == "mixed":
+        mdec = rb.MultiDecoder(probs, device=0, **RELAY)
+        code_id = torch.cat([torch.full((s.shape[0],), q, dtype=torch.int32)
+                             for q, s in enumerate(syns)]).to(dev)
+        d_all = torch.from_numpy(np.concatenate(syns)).to(dev)
+        mout = mdec.alloc(d_all.shape[0])
+        offs = np.cumsum([0] + [s.shape[0] for s in syns])
+
+        def step(ev):
+            if ev is not None:
+                ev[0][0].record(stream)
+            mdec.decode(code_id, d_all, out=mout)
+            if ev is not None:
+                ev[0][1].record(stream)
+
+        n_launch, kernel, info = 1, "relay_mixed_kernel", {"variant": "mixed"}
+
+        def results():
+            host = {k: v.cpu().numpy() for k, v in mout.items() if k != "workspace"}
+            return [{k: v[offs[q]:offs[q + 1]] for k, v in host.items()} for q in range(len(ps))]
+    else:
+        decs = [rb.Decoder.from_problem(pr, device=0, **RELAY) for pr in probs]
+        for d in decs:
+            if args.variant is not None:
+                d.set_variant(args.variant)
+            if args.schedule == "per-p-lpt":
+                d.reserve(shots)
+        d_syn = [torch.from_numpy(s).to(dev) for s in syns]
+        outs = [decs[q].decode(d_syn[q]) for q in range(len(ps))]
+
+        def step(ev):
+            for q in range(len(ps)):
+                if ev is not None:
+                    ev[q][0].record(stream)
+                decs[q].decode(d_syn[q], out=outs[q])
+                if ev is not None:
+                    ev[q][1].record(stream)
+
+        n_launch, kernel = len(ps), "relay_group_kernel"
+        info = decs[0].info()
+
+        def results():
+            return [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+
+    elapsed, per_launch = timed(torch, step, n_launch, args.steps, args.warmup)
+    kernel_ms = float(np.mean(per_launch))
+    res = results()
+    n_shots = sum(s.shape[0] for s in syns)
+    iters_step = sum(int(r["iters"].astype(np.int64).sum()) for r in res)
+    eu_launch = iters_step * E / n_launch
+    traffic = stored_traffic("relay_mixed_kernel_bb144_hbm_traffic.txt") if n_launch == 1 else None
+    roof, lds = roofline(kernel, kernel_ms, eu_launch / E * ops_per_iteration(M, N, E), eu_launch,
+                         lds_bytes_per_edge_update(M, N, E), traffic)
+    ler = {}
+    for q, p in enumerate(ps):
+        fail = logical_failures(probs[q], faults[q], res[q]["corr"][:, :N], res[q]["conv"])
+        k = int(fail.sum())
+        ler[str(p)] = {"ler": k / len(fail), "wilson95": wilson(k, len(fail)),
+                       "conv": float(res[q]["conv"].mean()),
+                       "mean_iters": float(res[q]["iters"].mean()),
+                       "max_iters": int(res[q]["iters"].max())}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = oracle_threads()
+        n_cpu = min(args.cpu_sample or shots, shots)
+        t1 = time.perf_counter()
+        agree = True
+        for q in range(len(ps)):
+            ref = oracle.decode(probs[q].m, probs[q].n, probs[q].rows, probs[q].cols,
+                                probs[q].prior, RELAY, syns[q][:n_cpu], threads=threads)
+            agree &= bool(np.array_equal(ref["corr"], res[q]["corr"][:n_cpu, :N])
+                          and np.array_equal(ref["iters"], res[q]["iters"][:n_cpu]))
+        tc = time.perf_counter() - t1
+        cpu = {"value": len(ps) * n_cpu / tc, "unit": "syndromes/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {n_cpu} syndromes of each of the 4 p values "
+                         f"({len(ps) * n_cpu} of {n_shots}), same inputs, {tc:.1f} s",
+               "paired_with_gpu_bit_exact": agree}
+    line = head(args, n_shots * args.steps / elapsed, elapsed, {
+        "workload": "relay_bp_bb144_code_capacity", "code": "[[144,12,12]] HX 72x144",
+        "edges": E, "p": ps, "syndromes_per_p": shots, "syndromes_per_step": n_shots,
+        "T_first": 80, "T_leg": 60, "legs": 301, "solutions": 5, "gamma_first": 0.125,
+        "gamma_range": [-0.24, 0.66], "anchor": "chain", "schedule": args.schedule,
+        "parallelism": "single_gpu"})
+    line.update({"edge_updates_per_s": iters_step * E * args.steps / elapsed,
+                 "launch_ms": launch_means(per_launch), "roofline": roof, "lds_roofline": lds,
+                 "ler": ler, "kernel_config": info, "cpu_baseline": cpu})
+    return line
+
+
+# --------------------------------------------------------------------------
+# DEM-shaped 936 x 8785 matrix, 10^6 shots, R = 20, S = 1
+# --------------------------------------------------------------------------
+
+
+def run_dem(args, torch, rb, codes, sampling):
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    prob = codes.dem_problem()
+    M, N, E = prob.m, prob.n, prob.nnz
+    shots = args.shots or 1000000
+    t_in = time.perf_counter()
+    syn_np, (f_shots, f_cols) = sampling.sample_syndromes_sparse(prob, 0xDE3, shots)
+    print(f"# dem inputs: {shots} shots, {f_shots.size} faults, "
+          f"{time.perf_counter() - t_in:.1f} s", file=sys.stderr, flush=True)
+    dec = rb.Decoder.from_problem(prob, device=0, **RELAY_R20)
+    if args.variant is not None:
+        dec.set_variant(args.variant)
+    d_syn = torch.from_numpy(syn_np).to(dev)
+    out = dec.decode(d_syn)
+
+    def step(ev):
+        if ev is not None:
+            ev[0][0].record(stream)
+        dec.decode(d_syn, out=out)
+        if ev is not None:
+            ev[0][1].record(stream)
+
+    elapsed, per_launch = timed(torch, step, 1, args.steps, args.warmup)
+    kernel_ms = float(np.mean(per_launch))
+    iters = out["iters"].cpu().numpy()
+    conv = out["conv"].cpu().numpy()
+    iters_launch = int(iters.astype(np.int64).sum())
+    roof, lds = roofline("relay_block_kernel", kernel_ms, iters_launch * ops_per_iteration(M, N, E),
+                         iters_launch * E, lds_bytes_per_edge_update(M, N, E),
+                         stored_traffic("relay_block_kernel_dem936x8785_hbm_traffic.txt"))
+    # logical failures on the GPU, so that the 8.8 GB correction array stays in
+    # HBM: A (F xor F_hat) = A F xor A F_hat over GF(2).
+    a = torch.from_numpy(prob.logical.astype(np.float32)).to(dev)
+    af = torch.zeros((shots, a.shape[0]), dtype=torch.int32, device=dev)
+    d_fs = torch.from_numpy(f_shots).to(dev)
+    d_fc = torch.from_numpy(f_cols).to(dev)
+    for c0 in range(0, d_fs.numel(), 1 << 22):
+        af.index_add_(0, d_fs[c0:c0 + (1 << 22)],
+                      a[:, d_fc[c0:c0 + (1 << 22)]].T.contiguous().to(torch.int32))
+    fail = torch.zeros(shots, dtype=torch.bool, device=dev)
+    chunk = 50000
+    for s0 in range(0, shots, chunk):
+        ah = torch.round(out["corr"][s0:s0 + chunk].float() @ a.T).to(torch.int32)
+        fail[s0:s0 + chunk] = ((ah + af[s0:s0 + chunk]) % 2).any(1)
+    fail |= out["conv"] == 0
+    k = int(fail.sum().item())
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = oracle_threads()
+        n_cpu = min(args.cpu_sample or 4000, shots)
+        t1 = time.perf_counter()
+        ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n_cpu],
+                            threads=threads)
+        tc = time.perf_counter() - t1
+        agree = bool(np.array_equal(ref["corr"], out["corr"][:n_cpu].cpu().numpy())
+                     and np.array_equal(ref["iters"], iters[:n_cpu])
+                     and np.array_equal(ref["conv"], conv[:n_cpu]))
+        cpu = {"value": n_cpu / tc, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n_cpu} of {shots} syndromes, same inputs, {tc:.1f} s",
+               "paired_with_gpu_bit_exact": agree}
+    line = head(args, shots * args.steps / elapsed, elapsed, {
+        "workload": "relay_bp_dem_936x8785", "matrix": "DEM-shaped synthetic 936x8785",
+        "edges": E, "shots": shots, "T_first": 80, "T_leg": 60, "legs": 20, "solutions": 1,
+        "gamma_first": 0.125, "gamma_range": [-0.24, 0.66], "anchor": "chain",
+        "parallelism": "single_gpu"})
+    line.update({"edge_updates_per_s": iters_launch * E * args.steps / elapsed,
+                 "launch_ms": [kernel_ms], "roofline": roof, "lds_roofline": lds,
+                 "ler": {"ler": k / shots, "wilson95": wilson(k, shots),
+                         "conv": float(conv.mean()), "mean_iters": float(iters.mean()),
+                         "max_iters": int(iters.max()), "faults_per_shot": f_shots.size / shots},
+                 "kernel_config": dec.info(), "cpu_baseline": cpu})
+    return line
+
+
+# --------------------------------------------------------------------------
+# four BB codes interleaved 4:3:2:1: one mixed launch vs four per-code launches
+# --------------------------------------------------------------------------
+
+
+def run_mixed_codes(args, torch, rb, codes, sampling):
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    names = ("bb72", "bb90", "bb144", "bb288")
+    pattern = np.array([0, 1, 2, 0, 3, 1, 0, 2, 1, 0], np.int32)  # 4:3:2:1
+    shots = args.shots or 400000
+    probs = [codes.bb_problem(nm, 0.04) for nm in names]
+    code_id = np.resize(pattern, shots).astype(np.int32)
+    m_max = max(p.m for p in probs)
+    syn = np.zeros((shots, m_max), np.uint8)
+    per = []
+    for k, pr in enumerate(probs):
+        idx = np.nonzero(code_id == k)[0]
+        f, s = sampling.sample_batch(pr, (4 << 32) | k, 0, idx.size)
+        syn[idx, :pr.m] = s
+        per.append((idx, f, s))
+    mdec = rb.MultiDecoder(probs, device=0, **RELAY_R20)
+    d_code = torch.from_numpy(code_id).to(dev)
+    d_syn = torch.from_numpy(syn).to(dev)
+    mout = mdec.alloc(shots)
+    samples = [torch.from_numpy(per[k][2][:20000]).to(dev) for k in range(len(probs))]
+    chosen = mdec.autotune(samples, reps=2)
+
+    def step_mixed(ev):
+        if ev is not None:
+            ev[0][0].record(stream)
+        mdec.decode(d_code, d_syn, out=mout)
+        if ev is not None:
+            ev[0][1].record(stream)
+
+    el_mixed, pl_mixed = timed(torch, step_mixed, 1, args.steps, args.warmup)
+    host = {k: v.cpu().numpy() for k, v in mout.items() if k != "workspace"}
+    # the same launch captured in a hipGraph and replayed
+    gout = mdec.alloc(shots)
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        mdec.decode(d_code, d_syn, out=gout)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        mdec.decode(d_code, d_syn, out=gout)
+
+    def step_graph(ev):
+        if ev is not None:
+            ev[0][0].record(stream)
+        graph.replay()
+        if ev is not None:
+            ev[0][1].record(stream)
+
+    el_graph, pl_graph = timed(torch, step_graph, 1, args.steps, args.warmup)
+    graph_same = all(np.array_equal(gout[k].cpu().numpy(), host[k]) for k in host)
+    del graph
+    # four per-code launches, each code's syndromes contiguous, autotuned per code
+    decs, d_per, outs = [], [], []
+    for k, pr in enumerate(probs):
+        d = rb.Decoder.from_problem(pr, device=0, **RELAY_R20)
+        d.autotune(samples[k], reps=2)
+        decs.append(d)
+        d_per.append(torch.from_numpy(per[k][2]).to(dev))
+        outs.append(d.decode(d_per[-1]))
+
+    def step_per(ev):
+        for k in range(len(probs)):
+            if ev is not None:
+                ev[k][0].record(stream)
+            decs[k].decode(d_per[k], out=outs[k])
+            if ev is not None:
+                ev[k][1].record(stream)
+
+    el_per, pl_per = timed(torch, step_per, len(probs), args.steps, args.warmup)
+    ler, same = {}, True
+    eu_launch, ops_launch = 0, 0.0
+    for k, pr in enumerate(probs):
+        idx, f, s = per[k]
+        fail = logical_failures(pr, f, host["corr"][idx, :pr.n], host["conv"][idx])
+        n_fail = int(fail.sum())
+        it = int(host["iters"][idx].astype(np.int64).sum())
+        ler[names[k]] = {"shots": int(idx.size), "ler": n_fail / idx.size,
+                         "wilson95": wilson(n_fail, idx.size),
+                         "mean_iters": float(host["iters"][idx].mean())}
+        same &= bool(np.array_equal(outs[k]["corr"].cpu().numpy(), host["corr"][idx, :pr.n])
+                     and np.array_equal(outs[k]["iters"].cpu().numpy(), host["iters"][idx]))
+        eu_launch += it * pr.nnz
+        ops_launch += it * ops_per_iteration(pr.m, pr.n, pr.nnz)
+    kernel_ms = float(np.mean(pl_mixed))
+    lds_b = sum(int(host["iters"][per[k][0]].astype(np.int64).sum()) * pr.nnz *
+                lds_bytes_per_edge_update(pr.m, pr.n, pr.nnz)
+                for k, pr in enumerate(probs)) / eu_launch
+    roof, lds = roofline("relay_mixed_kernel", kernel_ms, ops_launch, eu_launch, lds_b, None)
+    line = head(args, shots * args.steps / el_mixed, el_mixed, {
+        "workload": "relay_bp_mixed_bb_codes", "codes": list(names), "proportions": "4:3:2:1",
+        "shots": shots, "p": 0.04, "legs": 20, "solutions": 1, "schedule": "mixed",
+        "parallelism": "single_gpu"})
+    line.update({
+        "edge_updates_per_s": eu_launch * args.steps / el_mixed,
+        "launch_ms": [kernel_ms], "roofline": roof, "lds_roofline": lds,
+        "hipgraph_replay": {"value": shots * args.steps / el_graph,
+                            "launch_ms": float(np.mean(pl_graph)),
+                            "results_identical": graph_same},
+        "per_code_launches": {"value": shots * args.steps / el_per,
+                              "launch_ms": launch_means(pl_per),
+                              "results_identical": same},
+        "tiles_chosen": chosen, "ler": ler, "cpu_baseline": None})
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--shots", type=int, default=100000, help="syndromes per p")
-    ap.add_argument("--cpu-sample", type=int, default=100000, help="oracle shots per p")
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (default per workload)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["bb144", "dem", "mixed-codes"], default="bb144")
+    ap.add_argument("--shots", type=int, default=0,
+                    help="syndromes per p (bb144) or in total (default per workload)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle sample: syndromes per p (bb144) or in total (dem)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--schedule", choices=["per-p", "per-p-lpt", "mixed"], default="mixed",
-                    help="per-p: one launch per p in input order; per-p-lpt: one launch per p, "
-                         "shots longest-first; mixed: all four p in one launch (one code "
-                         "context per p), longest-first per p")
+                    help="bb144 only.  per-p: one launch per p in input order; per-p-lpt: one "
+                         "launch per p, shots longest-first; mixed: all four p in one launch "
+                         "(one code context per p)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy kernel of MB MiB (int32 "
                          "bitwise_not: reads and writes MB MiB) to scale HBM counters")
     args = ap.parse_args()
+    if args.steps <= 0:
+        args.steps = DEFAULT_STEPS[args.workload]
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -92,191 +494,16 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
-    dev = torch.device("cuda", 0)
-    ps = [0.02, 0.04, 0.06, 0.08]
-    probs, faults, syns = [], [], []
-    for q, p in enumerate(ps):
-        prob = codes.bb_problem("bb144", p)
-        f, s = sampling.sample_batch(prob, (2 << 32) | q, 0, args.shots)
-        probs.append(prob)
-        faults.append(f)
-        syns.append(s)
-    E = probs[0].nnz
-    stream = torch.cuda.current_stream(dev)
-    if args.schedule == "mixed":
-        mdec = rb.MultiDecoder(probs, device=0, **RELAY)
-        code_id = torch.cat([torch.full((s.shape[0],), q, dtype=torch.int32)
-                             for q, s in enumerate(syns)]).to(dev)
-        d_all = torch.from_numpy(np.concatenate(syns)).to(dev)
-        mout = mdec.alloc(d_all.shape[0])
-        decs = None
-        offs = np.cumsum([0] + [s.shape[0] for s in syns])
-
-        def step(events=None):
-            if events is not None:
-                events[0][0].record(stream)
-            mdec.decode(code_id, d_all, out=mout)
-            if events is not None:
-                events[0][1].record(stream)
-
-        n_launch = 1
-
-        def results():
-            host = {k: v.cpu().numpy() for k, v in mout.items() if k != "workspace"}
-            return [{k: v[offs[q]:offs[q + 1]] for k, v in host.items()} for q in range(len(ps))]
-    else:
-        decs = [rb.Decoder.from_problem(pr, device=0, **RELAY) for pr in probs]
-        for d in decs:
-            if args.variant is not None:
-                d.set_variant(args.variant)
-            if args.schedule == "per-p-lpt":
-                d.reserve(args.shots)
-        d_syn = [torch.from_numpy(s).to(dev) for s in syns]
-        outs = []
-        for s in syns:
-            b = s.shape[0]
-            outs.append({
-                "corr": torch.empty((b, 144), dtype=torch.uint8, device=dev),
-                "conv": torch.empty(b, dtype=torch.uint8, device=dev),
-                "legs": torch.empty(b, dtype=torch.int32, device=dev),
-                "iters": torch.empty(b, dtype=torch.int32, device=dev),
-                "weight": torch.empty(b, dtype=torch.float64, device=dev),
-            })
-
-        def step(events=None):
-            for q in range(len(ps)):
-                if events is not None:
-                    events[q][0].record(stream)
-                decs[q].decode(d_syn[q], out=outs[q])
-                if events is not None:
-                    events[q][1].record(stream)
-
-        n_launch = len(ps)
-
-        def results():
-            return [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    launch_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(n_launch)]
-        step(ev)
-        launch_ms.append(ev)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    per_launch = [[e[0].elapsed_time(e[1]) for e in evs] for evs in launch_ms]
-    kernel_ms = float(np.mean(per_launch))
-
-    res = results()
-    n_shots = sum(s.shape[0] for s in syns)
-    iters_total = sum(int(r["iters"].astype(np.int64).sum()) for r in res)
-    edge_updates_step = iters_total * E
-    value = n_shots * args.steps / elapsed
-    eu_per_s = edge_updates_step * args.steps / elapsed
-
-    # roofline of the decode kernel: algorithmic ops per launch / mean launch time
-    per_launch_eu = [int(r["iters"].astype(np.int64).sum()) * E for r in res]
-    if n_launch == 1:
-        per_launch_eu = [sum(per_launch_eu)]
-    ops_per_iter = OPS_PER_EDGE * E + OPS_PER_FAULT * 144 + OPS_PER_CHECK * 72
-    ops_launch = np.mean([eu / E * ops_per_iter for eu in per_launch_eu])
-    achieved_tops = ops_launch / (kernel_ms * 1e-3) / 1e12
-    b_alg = 8.0 + (8.0 * 144 + 12.0 * 72) / E
-    lds_tbs = np.mean(per_launch_eu) * b_alg / (kernel_ms * 1e-3) / 1e12
-
-    ler = {}
-    for q, p in enumerate(ps):
-        fail = logical_failures(probs[q], faults[q], res[q]["corr"], res[q]["conv"])
-        k = int(fail.sum())
-        ler[str(p)] = {"ler": k / len(fail), "wilson95": wilson(k, len(fail)),
-                       "conv": float(res[q]["conv"].mean()),
-                       "mean_iters": float(res[q]["iters"].mean()),
-                       "max_iters": int(res[q]["iters"].max())}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        threads = min(16, os.cpu_count() or 1)
-        n_cpu = min(args.cpu_sample, args.shots)
-        t1 = time.perf_counter()
-        agree = True
-        for q in range(len(ps)):
-            ref = oracle.decode(probs[q].m, probs[q].n, probs[q].rows, probs[q].cols,
-                                probs[q].prior, RELAY, syns[q][:n_cpu], threads=threads)
-            agree &= bool(np.array_equal(ref["corr"], res[q]["corr"][:n_cpu])
-                          and np.array_equal(ref["iters"], res[q]["iters"][:n_cpu]))
-        tc = time.perf_counter() - t1
-        cpu = {"value": 4 * n_cpu / tc, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {n_cpu} syndromes of each of the 4 p values "
-                         f"({4 * n_cpu} of {n_shots}), same inputs, {tc:.1f} s",
-               "paired_with_gpu_bit_exact": agree}
-
-    copy_bytes = 0
+    run = {"bb144": run_bb144, "dem": run_dem, "mixed-codes": run_mixed_codes}[args.workload]
+    line = run(args, torch, rb, codes, sampling)
     if args.calibrate_copy > 0:
         n_el = args.calibrate_copy * (1 << 20) // 4
-        src = torch.arange(n_el, dtype=torch.int32, device=dev)
+        src = torch.arange(n_el, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
-        copy_bytes = n_el * 4
-
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "relay_mixed_kernel_bb144_hbm_traffic.txt")
-    if args.schedule == "mixed" and os.path.exists(tpath):
-        from paper_2511_21660_amd import profiling
-
-        rec = json.load(open(tpath))
-        if rec.get("source_hash") == profiling.source_hash():
-            traffic = rec["traffic_bytes_per_launch"]
-
-    info = decs[0].info() if decs else {"variant": "mixed", "lanes_per_shot": None,
-                                         "checks_per_lane": None, "cols_per_lane": None,
-                                         "shots_per_block": None, "lds_bytes_per_block": None,
-                                         "blocks_per_cu": None, "grid_blocks": None}
-    line = {
-        "metric": "syndromes decoded/s at matched LER; edge-updates/s and % HBM/LDS roofline",
-        "value": value,
-        "unit": "syndromes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "relay_bp_bb144_code_capacity",
-                   "code": "[[144,12,12]] HX 72x144", "edges": E,
-                   "p": ps, "syndromes_per_p": args.shots, "syndromes_per_step": n_shots,
-                   "T_first": 80, "T_leg": 60, "legs": 301, "solutions": 5,
-                   "gamma_first": 0.125, "gamma_range": [-0.24, 0.66], "anchor": "chain",
-                   "schedule": args.schedule, "parallelism": "single_gpu"},
-        "edge_updates_per_s": eu_per_s,
-        "launch_ms": [float(np.mean([pl[q] for pl in per_launch])) for q in range(n_launch)],
-        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS,
-                     "unit": "Tops/s", "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,
-                     "kernel": ("relay_mixed_kernel" if args.schedule == "mixed"
-                                else "relay_group_kernel"),
-                     "kernel_ms_per_launch": kernel_ms,
-                     "ops_per_edge_update": ops_per_iter / E},
-        "lds_roofline": {"achieved": lds_tbs, "peak": PEAK_LDS_TBS, "unit": "TB/s",
-                         "frac": lds_tbs / PEAK_LDS_TBS, "bytes_per_edge_update": b_alg},
-        "ler": ler,
-        "kernel_config": {k: info[k] for k in ("variant", "lanes_per_shot", "checks_per_lane",
-                                               "cols_per_lane", "shots_per_block",
-                                               "lds_bytes_per_block", "blocks_per_cu",
-                                               "grid_blocks")},
-        "cpu_baseline": cpu,
-    }
-    if copy_bytes:
-        line["copy_calibration_bytes_each_way"] = copy_bytes
+        line["copy_calibration_bytes_each_way"] = n_el * 4
     print(json.dumps(line), flush=True)
 
 

@@ -66,8 +66,9 @@ struct rb_ctx {
     bool block = false;
     rb::TileShape shape{};
     rb::BlockShape bshape{};
-    uint32_t red_off = 0;
+    uint32_t red_off = 0, slack_off = 0;
     int32_t *d_chk_row = nullptr, *d_wave_deg = nullptr, *d_wave_base = nullptr;
+    int32_t *d_slot_col = nullptr;
     // longest-first shot lists for single-code decodes (rb_reserve)
     void *d_ws = nullptr;
     int64_t ws_capacity = 0;
@@ -195,7 +196,7 @@ rb_status build_plan(rb_ctx *c, int v) {
 int total_variants() { return rb::num_variants() + rb::num_block_variants(); }
 
 struct BlockLayout {
-    uint32_t lampad_off, mupad_off, red_off, mu0_off;
+    uint32_t lampad_off, mupad_off, red_off, mu0_off, slack_off;
     int lds_bytes;
     int npad;
 };
@@ -208,26 +209,53 @@ BlockLayout block_layout(const rb::BlockShape &s, int64_t msg_words) {
     l.lampad_off = 4u * (uint32_t)l.npad;
     l.mupad_off = l.lampad_off + 4u;
     l.red_off = (l.mupad_off + 4u + 7u) & ~7u;
-    l.mu0_off = (l.red_off + 8u * (uint32_t)(s.TPB / 64) + 8u + 15u) & ~15u;
-    const int64_t bytes = (int64_t)l.mu0_off + 4 * msg_words;
+    // scratch: TPB/64 doubles (block sums), TPB/64 words (block OR), shot index
+    l.mu0_off = (l.red_off + 12u * (uint32_t)(s.TPB / 64) + 8u + 15u) & ~15u;
+    l.slack_off = l.mu0_off + 4u * (uint32_t)msg_words;
+    const int64_t bytes = (int64_t)l.mu0_off + 4 * (msg_words + (rb::kBlockChunk - 1) * 64);
     l.lds_bytes = bytes > (1 << 30) ? (1 << 30) : (int)bytes;
     return l;
 }
 
-// checks sorted by decreasing degree (stable); wave-ELL row counts
+// Check placement: checks sorted by decreasing degree (stable) form groups of
+// 64 rows of nearly equal length; the groups are placed on waves so that the
+// four SIMDs of a CU (wave w runs on SIMD w % 4) get about the same number of
+// row chunks (kBlockChunk edges each), largest group first onto the least
+// loaded SIMD.  order[t] is the check of thread t or -1; wave-ELL row counts
+// and first message words per wave.
 void block_order(const rb_ctx *c, const rb::BlockShape &s, std::vector<int32_t> &order,
                  std::vector<int32_t> &wdeg, std::vector<int32_t> &wbase, int64_t &words) {
-    order.resize((size_t)c->M);
-    for (int32_t i = 0; i < c->M; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    std::vector<int32_t> sorted((size_t)c->M);
+    for (int32_t i = 0; i < c->M; ++i) sorted[i] = i;
+    std::stable_sort(sorted.begin(), sorted.end(), [&](int32_t x, int32_t y) {
         return (c->rowptr[x + 1] - c->rowptr[x]) > (c->rowptr[y + 1] - c->rowptr[y]);
     });
-    const int nw = s.TPB / 64;
+    const int nw = s.TPB / 64, ng = ceil_div(c->M, 64);
+    std::vector<int32_t> gdeg((size_t)ng, 0);
+    for (int32_t q = 0; q < c->M; ++q) {
+        const int32_t i = sorted[q];
+        gdeg[q / 64] = std::max<int32_t>(gdeg[q / 64], (int32_t)(c->rowptr[i + 1] - c->rowptr[i]));
+    }
+    // groups are already in decreasing length: greedy placement
+    std::vector<int> group_of_wave((size_t)nw, -1);
+    int64_t load[4] = {0, 0, 0, 0};
+    int used[4] = {0, 0, 0, 0};
+    for (int g = 0; g < ng; ++g) {
+        int best = -1;
+        for (int q = 0; q < 4; ++q)
+            if (used[q] < nw / 4 && (best < 0 || load[q] < load[best])) best = q;
+        group_of_wave[(size_t)(best + 4 * used[best])] = g;
+        load[best] += ceil_div(gdeg[g], rb::kBlockChunk);
+        ++used[best];
+    }
+    order.assign((size_t)s.TPB, -1);
     wdeg.assign((size_t)nw, 0);
     wbase.assign((size_t)nw, 0);
-    for (int32_t t = 0; t < c->M; ++t) {
-        const int32_t i = order[t];
-        wdeg[t / 64] = std::max<int32_t>(wdeg[t / 64], (int32_t)(c->rowptr[i + 1] - c->rowptr[i]));
+    for (int w = 0; w < nw; ++w) {
+        const int g = group_of_wave[w];
+        if (g < 0) continue;
+        wdeg[w] = gdeg[g];
+        for (int l = 0; l < 64 && 64 * g + l < c->M; ++l) order[(size_t)(64 * w + l)] = sorted[64 * g + l];
     }
     words = 0;
     for (int w = 0; w < nw; ++w) {
@@ -236,9 +264,27 @@ void block_order(const rb_ctx *c, const rb::BlockShape &s, std::vector<int32_t> 
     }
 }
 
+// faults in the order of decreasing column degree (stable): slot s holds order[s]
+std::vector<int32_t> fault_order(const rb_ctx *c) {
+    std::vector<int32_t> order((size_t)c->N);
+    for (int32_t j = 0; j < c->N; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return (c->colptr[x + 1] - c->colptr[x]) > (c->colptr[y + 1] - c->colptr[y]);
+    });
+    return order;
+}
+
 bool block_fits(const rb_ctx *c, const rb::BlockShape &s) {
-    if (c->M > s.TPB || ceil_div(c->N, s.TPB) > s.VPT) return false;
-    if (c->max_row > s.DCMAX || c->max_col > s.DV) return false;
+    if (c->M > s.TPB || ceil_div(c->N, s.TPB) > s.VPT || s.VPT > 16) return false;
+    if (c->max_row > s.DCMAX) return false;
+    {
+        // the first (largest-degree) fault of every band within the band's cap
+        const std::vector<int32_t> fo = fault_order(c);
+        for (int v = 0; v < s.VPT && (int64_t)v * s.TPB < c->N; ++v) {
+            const int32_t j = fo[(size_t)v * s.TPB];
+            if (c->colptr[j + 1] - c->colptr[j] > rb::prof_dv(s.prof, v)) return false;
+        }
+    }
     std::vector<int32_t> order, wdeg, wbase;
     int64_t words = 0;
     block_order(c, s, order, wdeg, wbase, words);
@@ -269,44 +315,60 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
     block_order(c, s, order, wdeg, wbase, words);
     const BlockLayout lay = block_layout(s, words);
     std::vector<int32_t> rank((size_t)c->M), chk_row((size_t)s.TPB, -1);
-    for (int32_t t = 0; t < c->M; ++t) {
+    for (int32_t t = 0; t < s.TPB; ++t) {
+        if (order[t] < 0) continue;
         rank[order[t]] = t;
         chk_row[t] = order[t];
     }
-    const int ncp = s.DCMAX / 2, nmp = s.VPT * s.DV / 2;
+    // fault slots by decreasing column degree
+    const std::vector<int32_t> fo = fault_order(c);
+    std::vector<int32_t> slot_col((size_t)s.TPB * s.VPT, -1), slot_of((size_t)c->N);
+    for (int32_t q = 0; q < c->N; ++q) {
+        slot_col[q] = fo[q];
+        slot_of[fo[q]] = q;
+    }
+    const int nmu = rb::prof_pre(s.prof, s.VPT);
+    const int ncp = s.DCMAX / 2, nmp = (nmu + 1) / 2;
     std::vector<uint16_t> col16((size_t)s.TPB * s.DCMAX, (uint16_t)lay.lampad_off);
-    std::vector<uint16_t> mu16((size_t)s.TPB * s.VPT * s.DV, (uint16_t)(lay.mupad_off / 4u));
-    for (int32_t t = 0; t < c->M; ++t) {
+    std::vector<uint16_t> mu16((size_t)s.TPB * nmp * 2, (uint16_t)(lay.mupad_off / 4u));
+    for (int32_t t = 0; t < s.TPB; ++t) {
         const int32_t i = order[t];
+        if (i < 0) continue;
         for (int64_t k = 0; k < c->rowptr[i + 1] - c->rowptr[i]; ++k)
-            col16[(size_t)t * s.DCMAX + k] = (uint16_t)(4u * (uint32_t)c->colidx[c->rowptr[i] + k]);
+            col16[(size_t)t * s.DCMAX + k] =
+                (uint16_t)(4u * (uint32_t)slot_of[c->colidx[c->rowptr[i] + k]]);
     }
     for (int32_t t = 0; t < s.TPB; ++t)
         for (int v = 0; v < s.VPT; ++v) {
-            const int64_t j = (int64_t)t + (int64_t)s.TPB * v;
-            if (j >= c->N) continue;
+            const int32_t j = slot_col[(size_t)t + (size_t)s.TPB * v];
+            if (j < 0) continue;
             for (int64_t k = 0; k < c->colptr[j + 1] - c->colptr[j]; ++k) {
                 const int32_t i = c->rowidx[c->colptr[j] + k];
                 const int32_t ti = rank[i];
                 const int64_t word = (int64_t)(lay.mu0_off / 4u) + wbase[ti / 64] +
                                      (int64_t)c->cpos[c->colptr[j] + k] * 64 + (ti % 64);
-                mu16[((size_t)t * s.VPT + v) * s.DV + k] = (uint16_t)word;
+                mu16[(size_t)t * nmp * 2 + rb::prof_pre(s.prof, v) + k] = (uint16_t)word;
             }
         }
-    // transpose to [pair][thread] so a load of one pair index is coalesced
+    // check table as [chunk][thread][4 words] (one 16-byte load per thread and
+    // chunk of 8 edges, coalesced over a wave); fault table as [pair][thread]
     std::vector<uint32_t> col_pk((size_t)ncp * s.TPB), mu_pk((size_t)nmp * s.TPB);
     for (int32_t t = 0; t < s.TPB; ++t) {
-        for (int e = 0; e < ncp; ++e)
-            col_pk[(size_t)e * s.TPB + t] = (uint32_t)col16[(size_t)t * s.DCMAX + 2 * e] |
-                                           ((uint32_t)col16[(size_t)t * s.DCMAX + 2 * e + 1] << 16);
+        for (int e = 0; e < ncp; ++e) {
+            const int ch = e / 4, d = e % 4;
+            col_pk[((size_t)ch * s.TPB + t) * 4 + d] =
+                (uint32_t)col16[(size_t)t * s.DCMAX + 2 * e] |
+                ((uint32_t)col16[(size_t)t * s.DCMAX + 2 * e + 1] << 16);
+        }
         for (int e = 0; e < nmp; ++e)
-            mu_pk[(size_t)e * s.TPB + t] = (uint32_t)mu16[(size_t)t * s.VPT * s.DV + 2 * e] |
-                                          ((uint32_t)mu16[(size_t)t * s.VPT * s.DV + 2 * e + 1] << 16);
+            mu_pk[(size_t)e * s.TPB + t] = (uint32_t)mu16[(size_t)t * nmp * 2 + 2 * e] |
+                                          ((uint32_t)mu16[(size_t)t * nmp * 2 + 2 * e + 1] << 16);
     }
     rb_status st;
     if ((st = upload(&c->d_lam_off, col_pk, "upload check table")) != RB_OK) return st;
     if ((st = upload(&c->d_mu_off, mu_pk, "upload fault table")) != RB_OK) return st;
     if ((st = upload(&c->d_chk_row, chk_row, "upload row map")) != RB_OK) return st;
+    if ((st = upload(&c->d_slot_col, slot_col, "upload slot map")) != RB_OK) return st;
     if ((st = upload(&c->d_wave_deg, wdeg, "upload wave degrees")) != RB_OK) return st;
     if ((st = upload(&c->d_wave_base, wbase, "upload wave bases")) != RB_OK) return st;
     {
@@ -321,6 +383,7 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
     c->lampad_off = lay.lampad_off;
     c->mupad_off = lay.mupad_off;
     c->red_off = lay.red_off;
+    c->slack_off = lay.slack_off;
     c->mu0_off = lay.mu0_off;
     c->lds_bytes = lay.lds_bytes;
     const bool prior = c->params.anchor == RB_ANCHOR_PRIOR;
@@ -538,6 +601,7 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_chk_row);
         (void)hipFree(c->d_wave_deg);
         (void)hipFree(c->d_wave_base);
+        (void)hipFree(c->d_slot_col);
     }
     if (c->d_rowptr || c->d_colidx || c->d_colptr || c->d_cedge) {
         (void)hipSetDevice(c->device);
@@ -604,6 +668,7 @@ static rb::BlockArgs block_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.chk_col = c->d_lam_off;
     b.col_mu = c->d_mu_off;
     b.chk_row = c->d_chk_row;
+    b.slot_col = c->d_slot_col;
     b.wave_deg = c->d_wave_deg;
     b.wave_base = c->d_wave_base;
     b.queue = g.queue;
@@ -617,6 +682,7 @@ static rb::BlockArgs block_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.mupad_off = c->mupad_off;
     b.red_off = c->red_off;
     b.mu0_off = c->mu0_off;
+    b.slack_off = c->slack_off;
     b.trace_gamma = g.trace_gamma;
     b.scale = g.scale;
     b.trace_T = g.trace_T;
@@ -729,7 +795,7 @@ rb_status rb_get_info(const rb_ctx *c, rb_info *info) {
         info->checks_per_lane = 1;
         info->row_slots = c->bshape.DCMAX;
         info->cols_per_lane = c->bshape.VPT;
-        info->col_slots = c->bshape.DV;
+        info->col_slots = rb::prof_max(c->bshape.prof, c->bshape.VPT);
         info->shots_per_block = 1;
         info->threads_per_block = c->bshape.TPB;
         info->waves_per_simd_target = c->bshape.waves;

@@ -7,22 +7,33 @@
 // one syndrome at a time and pulls the next one from a global queue.
 //
 // Roles.  Thread t owns the check of rank t in the order of decreasing degree
-// (so the 64 rows a wave handles have nearly the same length) and the faults
-// j = t + TPB*v, v < VPT.
+// (so the 64 rows a wave handles have nearly the same length) and the fault
+// slots s = t + TPB*v, v < VPT; slot s holds the fault of rank s in the order
+// of decreasing column degree (slot_col), so each band v of slots has a
+// small fixed degree cap and the thread gathers only that many messages.
 //
-// LDS.  Lambda[N_pad] (N_pad = TPB*VPT; faults >= N are spare words), a +inf
-// cell and a -0 cell, then the check-to-fault messages in "wave-ELL" order:
-// wave w owns maxdeg(w) rows of 64 words, word (k, lane) holding edge k of the
-// lane's check, so a thread's k-th message is at a fixed stride from its base
-// and the 64 lanes of a wave access 64 consecutive words (conflict-free).
-// Between the two passes over a row the thread parks nu in its message words.
-// Fault-side gathers read messages through per-thread 16-bit word indices.
+// LDS.  Lambda[N_pad] by slot (N_pad = TPB*VPT; slots >= N are spare), a +inf
+// cell and a -0 cell, reduction scratch, then the check-to-fault messages in
+// "wave-ELL" order: wave w owns maxdeg(w) rows of 64 words, word (k, lane)
+// holding edge k of the lane's check, so a thread's k-th message is at a
+// fixed stride from its base and the 64 lanes of a wave access 64
+// consecutive words (conflict-free).  Fault-side gathers read messages
+// through per-thread 16-bit word indices.
+//
+// Check pass.  Edges are read in chunks of kBlockChunk: all loads of a chunk
+// are issued before the first is used, so one LDS round trip is exposed per
+// chunk rather than per edge.  Reads past the end of a wave's rows (the last
+// chunk) return finite messages of other rows or zeroed slack words, paired
+// with the +inf Lambda of a padded edge, so they change nothing.  The signs
+// of nu and the position of the minimum stay in registers, so the second
+// pass over the row only writes messages.
 //
 // The syndrome test is fused into the check pass (parity of F(t) over each
-// row) and reduced with one __syncthreads_or; leg and shot events are
-// block-uniform, so the scheduler never diverges.
+// row) and reduced with one barrier; leg and shot events are block-uniform,
+// so the scheduler never diverges.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "relay_internal.h"
 
@@ -55,7 +66,9 @@ __device__ __forceinline__ double block_sum(double x, uint32_t red) {
 }
 
 // OR of a predicate over the block (every thread gets the result); `flags` is
-// the byte address of TPB/64 words of LDS scratch.  (The library's kernels
+// the byte address of TPB/64 words of LDS scratch.  One barrier: the caller
+// guarantees another barrier before the next call, so no wave can overwrite
+// a flag that another wave has still to read.  (The library's kernels
 // address LDS absolutely from 0 and must not use static LDS, so the runtime's
 // __syncthreads_or, which keeps its scratch in static LDS, is not used.)
 template <int TPB>
@@ -67,29 +80,33 @@ __device__ __forceinline__ bool block_or(bool pred, uint32_t flags) {
     uint32_t acc = 0;
 #pragma unroll
     for (int w = 0; w < TPB / 64; ++w) acc |= lds_b<uint32_t>(flags + 4u * w);
-    __syncthreads();
     return acc != 0;
 }
 
-template <int TPB, int DCMAX, int VPT, int DV, int WAVES, bool PRIOR, bool TRACE>
+template <int TPB, int DCMAX, int VPT, uint64_t PROF, int WAVES, bool PRIOR, bool TRACE>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void relay_block_kernel(BlockArgs a) {
-    static_assert(TPB % 64 == 0 && DCMAX % 2 == 0 && (VPT * DV) % 2 == 0, "shape");
-    const uint32_t red = a.red_off;                 // TPB/64 doubles of scratch
-    const uint32_t shot_sh = a.red_off + 8u * (TPB / 64);  // claimed shot index
+    constexpr int CH = kBlockChunk;
+    constexpr int NMU = prof_pre(PROF, VPT);  // fault-side gather entries per thread
+    constexpr int DV = prof_max(PROF, VPT);
+    static_assert(TPB % 128 == 0 && CH == 8 && DCMAX % CH == 0 && DCMAX <= 64 && DV >= 1, "shape");
+    const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
+    const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 words (block OR)
+    const uint32_t shot_sh = flags + 4u * (TPB / 64);     // claimed shot index
     const int t = threadIdx.x;
     const int wave = t >> 6;
     const float L = a.L;
     uint32_t tl = (uint32_t)t;  // thread index, opaque inside the loop
 
-    // check side: column byte addresses (16-bit, Lambda region < 64 KiB)
-    uint32_t col_pk[DCMAX / 2];
+    // check side: Lambda byte addresses (16-bit, Lambda region < 64 KiB) of
+    // the row's edges, kBlockChunk per uint4.  Chunk 0 stays in registers; the
+    // others stream from the (L2-resident) table one chunk ahead of use.
+    const uint4 *ctab = reinterpret_cast<const uint4 *>(a.chk_col);  // [DCMAX/CH][TPB]
+    uint4 col0 = ctab[t];
     // fault side: message word indices (16-bit)
-    uint32_t mu_pk[VPT * DV / 2];
+    uint32_t mu_pk[(NMU + 1) / 2];
 #pragma unroll
-    for (int e = 0; e < DCMAX / 2; ++e) col_pk[e] = a.chk_col[(size_t)e * TPB + t];
-#pragma unroll
-    for (int e = 0; e < VPT * DV / 2; ++e) mu_pk[e] = a.col_mu[(size_t)e * TPB + t];
+    for (int e = 0; e < (NMU + 1) / 2; ++e) mu_pk[e] = a.col_mu[(size_t)e * TPB + t];
     const int myrow = a.chk_row[t];           // check index or -1
     // row length of this wave (uniform: read back as a scalar)
     const int wdeg = __builtin_amdgcn_readfirstlane(a.wave_deg[wave]);
@@ -99,8 +116,12 @@ void relay_block_kernel(BlockArgs a) {
         lds_b<float>(a.lampad_off) = __int_as_float(0x7f800000);
         lds_b<float>(a.mupad_off) = __int_as_float(0x80000000);
     }
+    for (int q = t; q < (CH - 1) * 64; q += TPB) lds_b<float>(a.slack_off + 4u * q) = 0.0f;
 
-    float Lr[VPT], l0[VPT], gm[VPT];
+    // Lambda of the thread's faults lives only in LDS (word j); it is read back
+    // where needed, which keeps the register budget for the gather tables.
+    // xl = (1 - gamma) * lambda(0) is constant within a leg and kept as such
+    float xl[VPT], gm[VPT];
     bool sig = false;
     uint32_t best_mask = 0;
     double best_w = 0.0;
@@ -127,17 +148,17 @@ void relay_block_kernel(BlockArgs a) {
         sig = myrow >= 0 && a.syn[(size_t)shot * a.M + myrow] != 0;
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
-            const int j = (int)tl + TPB * v;
+            const uint32_t sl = tl + TPB * v;
+            const int j = a.slot_col[sl];
             float wj = 0.0f, gj = 0.0f;
-            if (j < a.N) {
+            if (j >= 0) {
                 wj = a.scale * a.w[j];
                 gj = TRACE ? a.trace_gamma[j] : a.gamma[j];
                 if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
             }
-            Lr[v] = wj;
-            l0[v] = wj;
+            xl[v] = (1.0f - gj) * wj;
             gm[v] = gj;
-            lds_b<float>(4u * (uint32_t)j) = wj;
+            lds_b<float>(4u * sl) = wj;
         }
         zero_row();
         return true;
@@ -147,37 +168,83 @@ void relay_block_kernel(BlockArgs a) {
     __syncthreads();
 
     while (active) {
+        opaque_b(col0.x);
+        opaque_b(col0.y);
+        opaque_b(col0.z);
+        opaque_b(col0.w);
 #pragma unroll
-        for (int e = 0; e < DCMAX / 2; ++e) opaque_b(col_pk[e]);
-#pragma unroll
-        for (int e = 0; e < VPT * DV / 2; ++e) opaque_b(mu_pk[e]);
+        for (int e = 0; e < (NMU + 1) / 2; ++e) opaque_b(mu_pk[e]);
         opaque_b(tl);
 
-        // ---------------- check pass (two passes over the thread's row)
+        // ---------------- check pass
+        // pass 1: nu = clip(Lambda - mu_old) per edge; min1, min2 and the
+        // first position of the minimum, the signs of nu (bit k of sg) and
+        // their parity; parity of F over the row.  Pass 2 only writes.
         bool fpar = sig, neg = sig;
         float m1 = L, m2 = L;
+        int amin = 0;
+        uint32_t sg_lo = 0, sg_hi = 0;  // bit k: nu_k < 0
+        uint4 cur = col0;
 #pragma unroll
-        for (int k = 0; k < DCMAX; ++k) {
-            if (k >= wdeg) break;  // wave-uniform row length
-            const uint32_t ca = (k & 1) ? (col_pk[k >> 1] >> 16) : (col_pk[k >> 1] & 0xffffu);
-            const float lv = lds_b<float>(ca);
-            const float mo = lds_b<float>(mrow + 256u * k);
-            fpar ^= lv < 0.0f;
-            const float nu = clipb(lv - mo, L);
-            neg ^= nu < 0.0f;
-            const float av = fabsf(nu);
-            m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
-            m1 = fminf(m1, av);
-            lds_b<float>(mrow + 256u * k) = nu;  // park nu
-        }
+        for (int c = 0; c < DCMAX; c += CH) {
+            if (c >= wdeg) break;  // wave-uniform row length
+            uint4 nxt = cur;
+            if (c + CH < DCMAX && c + CH < wdeg) nxt = ctab[(size_t)(c / CH + 1) * TPB + tl];
+            const uint32_t pk[4] = {cur.x, cur.y, cur.z, cur.w};
+            float lv[CH], mo[CH];
 #pragma unroll
-        for (int k = 0; k < DCMAX; ++k) {
-            if (k >= wdeg) break;
-            const float nu = lds_b<float>(mrow + 256u * k);
-            const float mag = (fabsf(nu) == m1) ? m2 : m1;
-            lds_b<float>(mrow + 256u * k) = (neg ^ (nu < 0.0f)) ? -mag : mag;
+            for (int q = 0; q < CH; ++q) {
+                const uint32_t ca = (q & 1) ? (pk[q >> 1] >> 16) : (pk[q >> 1] & 0xffffu);
+                lv[q] = lds_b<float>(ca);
+                mo[q] = lds_b<float>(mrow + 256u * (c + q));
+            }
+            cur = nxt;
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int k = c + q;
+                fpar ^= lv[q] < 0.0f;
+                const float nu = clipb(lv[q] - mo[q], L);
+                const bool sn = nu < 0.0f;
+                neg ^= sn;
+                if (k < 32)
+                    sg_lo |= sn ? (1u << k) : 0u;
+                else
+                    sg_hi |= sn ? (1u << (k - 32)) : 0u;
+                const float av = fabsf(nu);
+                amin = av < m1 ? k : amin;
+                m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
+                m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
+            }
         }
-        const bool unsat = block_or<TPB>(fpar, red);
+        // pass 2: mu = +-m1 on every edge (sign of nu times the row parity),
+        // then +-m2 at the minimum's position (m1, m2 >= +0)
+        {
+            const uint32_t flip = neg ? 0xffffffffu : 0u;
+            const uint32_t s_lo = sg_lo ^ flip, s_hi = sg_hi ^ flip;
+            const uint32_t b1 = __float_as_uint(m1);
+            auto pass2 = [&](auto full_tag, int c) {
+                constexpr bool FULL = decltype(full_tag)::value;
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    const int k = c + q;
+                    const uint32_t sb = k < 32 ? (s_lo << (31 - k)) : (s_hi << (63 - k));
+                    if (FULL || k < wdeg) lds_b<uint32_t>(mrow + 256u * k) = (sb & 0x80000000u) | b1;
+                }
+            };
+#pragma unroll
+            for (int c = 0; c < DCMAX; c += CH) {
+                if (c >= wdeg) break;
+                if (c + CH <= wdeg)
+                    pass2(std::true_type{}, c);
+                else
+                    pass2(std::false_type{}, c);
+            }
+            if (wdeg > 0) {
+                const uint32_t sa = amin < 32 ? (s_lo >> amin) : (s_hi >> (amin - 32));
+                lds_b<uint32_t>(mrow + 256u * (uint32_t)amin) = (sa << 31) | __float_as_uint(m2);
+            }
+        }
+        const bool unsat = block_or<TPB>(fpar, flags);
 
         // ---------------- leg scheduler (block-uniform)
         const bool cut = a.max_total_iters > 0 && total >= a.max_total_iters;
@@ -191,8 +258,9 @@ void relay_block_kernel(BlockArgs a) {
                 double part = 0.0;
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
-                    const int j = (int)tl + TPB * v;
-                    if (j < a.N && Lr[v] < 0.0f) {
+                    const uint32_t sl = tl + TPB * v;
+                    const int j = a.slot_col[sl];
+                    if (j >= 0 && lds_b<float>(4u * sl) < 0.0f) {
                         fm |= 1u << v;
                         part += (double)a.w[j];
                     }
@@ -212,10 +280,12 @@ void relay_block_kernel(BlockArgs a) {
                     const uint32_t out = count > 0 ? best_mask : fm;
 #pragma unroll
                     for (int v = 0; v < VPT; ++v) {
-                        const int j = (int)tl + TPB * v;
-                        if (j < a.N) {
+                        const uint32_t sl = tl + TPB * v;
+                        const int j = a.slot_col[sl];
+                        if (j >= 0) {
                             a.corr[(size_t)shot * a.N + j] = (uint8_t)((out >> v) & 1u);
-                            if (a.final_llr) a.final_llr[(size_t)shot * a.N + j] = Lr[v];
+                            if (a.final_llr)
+                                a.final_llr[(size_t)shot * a.N + j] = lds_b<float>(4u * sl);
                         }
                     }
                     if (t == 0) {
@@ -232,10 +302,13 @@ void relay_block_kernel(BlockArgs a) {
                 const float *gr = a.gamma + (size_t)(r - 1) * a.N;
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
-                    const int j = (int)tl + TPB * v;
-                    if (j < a.N) {
-                        gm[v] = gr[j];
-                        l0[v] = PRIOR ? a.w[j] : clipb(Lr[v], L);
+                    const uint32_t sl = tl + TPB * v;
+                    const int j = a.slot_col[sl];
+                    if (j >= 0) {
+                        const float g = gr[j];
+                        const float l0 = PRIOR ? a.w[j] : clipb(lds_b<float>(4u * sl), L);
+                        gm[v] = g;
+                        xl[v] = (1.0f - g) * l0;
                     }
                 }
                 zero_row();
@@ -247,23 +320,37 @@ void relay_block_kernel(BlockArgs a) {
         }
 
         // ---------------- fault pass
+        // Software-pipelined by one fault: the gathers of slot v+1 are issued
+        // before slot v's sum is stored (the stores go to the Lambda words,
+        // which no gather reads).  Band v gathers prof_dv(PROF, v) messages;
+        // a fault of smaller degree reads the -0 cell for the rest.
+        auto mu_word = [&](int e) -> uint32_t {
+            return ((e & 1) ? (mu_pk[e >> 1] >> 16) : (mu_pk[e >> 1] & 0xffffu)) << 2;
+        };
+        float nv[DV], lam_n;
+#pragma unroll
+        for (int k = 0; k < prof_dv(PROF, 0); ++k) nv[k] = lds_b<float>(mu_word(k));
+        lam_n = lds_b<float>(4u * tl);
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
-            const float om = 1.0f - gm[v];
-            const float x = om * l0[v];
-            const float y = gm[v] * clipb(Lr[v], L);
-            float acc = clipb(x + y, L);
+            float mv[DV];
 #pragma unroll
-            for (int k = 0; k < DV; ++k) {
-                const int e = v * DV + k;
-                const uint32_t wi = (e & 1) ? (mu_pk[e >> 1] >> 16) : (mu_pk[e >> 1] & 0xffffu);
-                acc += lds_b<float>(wi << 2);
+            for (int k = 0; k < prof_dv(PROF, v); ++k) mv[k] = nv[k];
+            const float lam = lam_n;
+            if (v + 1 < VPT) {
+#pragma unroll
+                for (int k = 0; k < prof_dv(PROF, v + 1); ++k)
+                    nv[k] = lds_b<float>(mu_word(prof_pre(PROF, v + 1) + k));
+                lam_n = lds_b<float>(4u * (tl + TPB * (v + 1)));
             }
-            Lr[v] = acc;
+            const float y = gm[v] * clipb(lam, L);
+            float acc = clipb(xl[v] + y, L);
+#pragma unroll
+            for (int k = 0; k < prof_dv(PROF, v); ++k) acc += mv[k];
             lds_b<float>(4u * (tl + TPB * v)) = acc;
             if (TRACE) {
-                const int j = (int)tl + TPB * v;
-                if (j < a.N) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * a.N + j] = acc;
+                const int j = a.slot_col[tl + TPB * v];
+                if (j >= 0) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * a.N + j] = acc;
             }
         }
         ++tt;
@@ -277,18 +364,23 @@ struct BlockVariant {
     const void *fn[2][2];
 };
 
-#define RB_BVARIANT(TPB, DCMAX, VPT, DV, W)                                                   \
-    {{TPB, DCMAX, VPT, DV, W},                                                                \
-     {{(const void *)relay_block_kernel<TPB, DCMAX, VPT, DV, W, false, false>,                \
-       (const void *)relay_block_kernel<TPB, DCMAX, VPT, DV, W, false, true>},                \
-      {(const void *)relay_block_kernel<TPB, DCMAX, VPT, DV, W, true, false>,                 \
-       (const void *)relay_block_kernel<TPB, DCMAX, VPT, DV, W, true, true>}}}
+#define RB_BVARIANT(TPB, DCMAX, VPT, PROF, W)                                                 \
+    {{TPB, DCMAX, VPT, PROF, W},                                                              \
+     {{(const void *)relay_block_kernel<TPB, DCMAX, VPT, PROF, W, false, false>,              \
+       (const void *)relay_block_kernel<TPB, DCMAX, VPT, PROF, W, false, true>},              \
+      {(const void *)relay_block_kernel<TPB, DCMAX, VPT, PROF, W, true, false>,               \
+       (const void *)relay_block_kernel<TPB, DCMAX, VPT, PROF, W, true, true>}}}
 
-// (threads, max row degree, faults per thread, max column degree, waves/SIMD)
+// (threads, max row degree, fault slots per thread, column-degree caps of the
+// slot bands (band 0 in the low nibble), waves/SIMD); the planner takes the
+// first that fits.
 const BlockVariant kBlockVariants[] = {
-    RB_BVARIANT(1024, 64, 9, 6, 4),   // M <= 1024, N <= 9216 (DEM-shaped 936 x 8785)
-    RB_BVARIANT(1024, 32, 4, 8, 4),   // M <= 1024, N <= 4096
-    RB_BVARIANT(512, 32, 4, 8, 2),    // M <= 512,  N <= 2048
+    // M <= 1024, N <= 9216, degrees sorted like a circuit-level DEM (weights
+    // 2..6, mostly 2 and 3), e.g. 936 x 8785: caps 6,6,5,4,3,3,3,2,2
+    RB_BVARIANT(1024, 64, 9, 0x223334566ull, 4),
+    RB_BVARIANT(1024, 64, 9, 0x666666666ull, 4),  // M <= 1024, N <= 9216, degree <= 6
+    RB_BVARIANT(1024, 32, 4, 0x8888ull, 4),       // M <= 1024, N <= 4096, degree <= 8
+    RB_BVARIANT(512, 32, 4, 0x8888ull, 2),        // M <= 512,  N <= 2048, degree <= 8
 };
 
 }  // namespace

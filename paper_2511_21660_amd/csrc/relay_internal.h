@@ -55,10 +55,36 @@ struct GroupArgs {
 // Shape of a block-kernel configuration: TPB threads decode one syndrome;
 // thread t owns one check (degree <= DCMAX) and faults t + TPB*v, v < VPT
 // (degree <= DV).
+//
+// Faults are assigned to slots s = t + TPB*v in the order of decreasing
+// column degree, so band v (slots TPB*v .. TPB*(v+1)-1) holds faults of
+// nearly equal degree; `prof` caps the degree of each band (4 bits per band,
+// band 0 in the low bits) and sizes the thread's fault-side gather table.
 struct BlockShape {
-    int TPB, DCMAX, VPT, DV;
+    int TPB, DCMAX, VPT;
+    uint64_t prof;
     int waves;
 };
+
+__host__ __device__ constexpr int prof_dv(uint64_t prof, int v) { return (int)((prof >> (4 * v)) & 15u); }
+
+// gather-table entries of bands 0 .. v-1
+__host__ __device__ constexpr int prof_pre(uint64_t prof, int v) {
+    int s = 0;
+    for (int u = 0; u < v; ++u) s += prof_dv(prof, u);
+    return s;
+}
+
+__host__ __device__ constexpr int prof_max(uint64_t prof, int vpt) {
+    int m = 0;
+    for (int u = 0; u < vpt; ++u) m = prof_dv(prof, u) > m ? prof_dv(prof, u) : m;
+    return m;
+}
+
+// The block kernel reads check rows in chunks of this many edges; reads past
+// a wave's last row land in the next wave's rows or in the zeroed slack words
+// after the message region ((kBlockChunk - 1) rows of 64 words).
+constexpr int kBlockChunk = 8;
 
 struct BlockArgs {
     int32_t M, N;
@@ -72,8 +98,9 @@ struct BlockArgs {
     float *final_llr;
     const float *w;
     const float *gamma;
-    const uint32_t *chk_col;   // [DCMAX/2][TPB] two 16-bit Lambda byte addresses per word
-    const uint32_t *col_mu;    // [VPT*DV/2][TPB] two 16-bit message word indices per word
+    const uint32_t *chk_col;   // [DCMAX/8][TPB][4] 16-bit Lambda byte addresses, 8 per chunk
+    const uint32_t *col_mu;    // [ceil(prof_pre(VPT)/2)][TPB] two 16-bit message word indices
+    const int32_t *slot_col;   // [TPB*VPT] fault held by slot s, or -1
     const int32_t *chk_row;    // [TPB] check owned by thread t, or -1
     const int32_t *wave_deg;   // [TPB/64] row length (max degree) of wave w
     const int32_t *wave_base;  // [TPB/64] first message word of wave w (relative to mu0)
@@ -81,6 +108,7 @@ struct BlockArgs {
     int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
     float L;
     uint32_t lampad_off, mupad_off, red_off, mu0_off;  // LDS byte offsets
+    uint32_t slack_off;  // first of the (kBlockChunk - 1) * 64 slack words
     const float *trace_gamma;
     float scale;
     int32_t trace_T;

@@ -170,6 +170,28 @@ def test_irregular_graph_edge_cases(rb, seed, anchor):
         assert_parity(gpu, ref, syn, prob, f"irregular seed={seed} anchor={anchor}")
 
 
+def test_irregular_graph_every_variant(rb):
+    """Irregular graph (empty rows and columns, a degree-1 check, erasures) on
+    every kernel configuration that fits it, group tiles and block shapes."""
+    prob = _irregular_problem(3)
+    _, syn = sampling.sample_batch(prob, 77, 0, 250)
+    syn[:4] = 1
+    prm = dict(RELAY_DEFAULT, num_solutions=2, num_legs=10)
+    ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, prm, syn,
+                        want_llr=True)
+    nvar = gpu_decode(rb, prob, prm, syn[:1])["info"]["num_variants"]
+    tested = []
+    for v in range(nvar):
+        try:
+            gpu = gpu_decode(rb, prob, prm, syn, variant=v)
+        except rb.RelayError as e:
+            assert e.status == 8
+            continue
+        assert_parity(gpu, ref, syn, prob, f"variant {v}")
+        tested.append(gpu["info"]["threads_per_block"])
+    assert len(tested) >= 3 and max(tested) >= 512  # block shapes included
+
+
 def test_unsatisfiable_syndrome_runs_full_budget(rb):
     code = codes.bb_code("bb72")
     h = np.vstack([code.hx, np.zeros((1, 72), np.uint8)])
