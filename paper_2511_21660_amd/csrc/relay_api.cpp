@@ -68,7 +68,9 @@ struct rb_ctx {
     rb::BlockShape bshape{};
     uint32_t red_off = 0, slack_off = 0;
     int32_t *d_chk_row = nullptr, *d_wave_deg = nullptr, *d_wave_base = nullptr;
-    int32_t *d_slot_col = nullptr;
+    int32_t *d_slot_col = nullptr, *d_chk_split = nullptr;
+    float *d_w_slot = nullptr;      // [TPB*VPT] w by fault slot (block kernel)
+    float *d_gamma_slot = nullptr;  // [R][TPB*VPT] gamma by fault slot (block kernel)
     // longest-first shot lists for single-code decodes (rb_reserve)
     void *d_ws = nullptr;
     int64_t ws_capacity = 0;
@@ -217,45 +219,85 @@ BlockLayout block_layout(const rb::BlockShape &s, int64_t msg_words) {
     return l;
 }
 
-// Check placement: checks sorted by decreasing degree (stable) form groups of
-// 64 rows of nearly equal length; the groups are placed on waves so that the
-// four SIMDs of a CU (wave w runs on SIMD w % 4) get about the same number of
-// row chunks (kBlockChunk edges each), largest group first onto the least
-// loaded SIMD.  order[t] is the check of thread t or -1; wave-ELL row counts
-// and first message words per wave.
-void block_order(const rb_ctx *c, const rb::BlockShape &s, std::vector<int32_t> &order,
+// One thread's share of a check: edges rowptr[row] + b .. rowptr[row] + e.
+// A long check may be split over two adjacent lanes (2p, 2p+1) of a wave,
+// which combine their partial minima and parities.
+struct LaneSeg {
+    int32_t row = -1, b = 0, e = 0;
+    bool split = false, first = true;
+};
+
+// Rows longer than this are split in two while spare lanes remain (longest
+// first), so that no wave is held up by a few very long rows.
+constexpr int kSplitRowDegree = 32;
+
+// Check placement: segments sorted by decreasing length (stable) form groups
+// of 64 lanes of nearly equal length; the groups are placed on waves so that
+// the four SIMDs of a CU (wave w runs on SIMD w % 4) get about the same number
+// of row chunks (kBlockChunk edges each), largest group first onto the least
+// loaded SIMD.  lanes[t] is thread t's segment (row -1: none); wave-ELL row
+// counts and first message words per wave.
+void block_order(const rb_ctx *c, const rb::BlockShape &s, std::vector<LaneSeg> &lanes,
                  std::vector<int32_t> &wdeg, std::vector<int32_t> &wbase, int64_t &words) {
+    auto deg = [&](int32_t i) { return (int32_t)(c->rowptr[i + 1] - c->rowptr[i]); };
     std::vector<int32_t> sorted((size_t)c->M);
     for (int32_t i = 0; i < c->M; ++i) sorted[i] = i;
-    std::stable_sort(sorted.begin(), sorted.end(), [&](int32_t x, int32_t y) {
-        return (c->rowptr[x + 1] - c->rowptr[x]) > (c->rowptr[y + 1] - c->rowptr[y]);
-    });
-    const int nw = s.TPB / 64, ng = ceil_div(c->M, 64);
-    std::vector<int32_t> gdeg((size_t)ng, 0);
-    for (int32_t q = 0; q < c->M; ++q) {
-        const int32_t i = sorted[q];
-        gdeg[q / 64] = std::max<int32_t>(gdeg[q / 64], (int32_t)(c->rowptr[i + 1] - c->rowptr[i]));
+    std::stable_sort(sorted.begin(), sorted.end(), [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
+    int spare = s.TPB - c->M - 1;  // one lane kept free for pair alignment
+    std::vector<LaneSeg> pairs, singles;  // pairs: first half of each split row
+    for (int32_t i : sorted) {
+        const int32_t d = deg(i);
+        if (spare > 0 && d > kSplitRowDegree) {
+            --spare;
+            pairs.push_back({i, 0, (d + 1) / 2, true, true});
+        } else {
+            singles.push_back({i, 0, d, false, true});
+        }
     }
-    // groups are already in decreasing length: greedy placement
+    // merge by decreasing length; a pair starts on an even lane
+    std::vector<LaneSeg> seq;
+    size_t pi = 0, si = 0;
+    while (pi < pairs.size() || si < singles.size()) {
+        const bool take_pair = pi < pairs.size() &&
+                               (si >= singles.size() || pairs[pi].e >= singles[si].e - singles[si].b);
+        if (take_pair && (seq.size() % 2 == 0 || si >= singles.size())) {
+            if (seq.size() % 2 == 1) seq.push_back(LaneSeg{});  // idle lane keeps pairs aligned
+            const LaneSeg f = pairs[pi++];
+            seq.push_back(f);
+            seq.push_back({f.row, f.e, deg(f.row), true, false});
+        } else {
+            seq.push_back(singles[si++]);
+        }
+    }
+    const int nw = s.TPB / 64;
+    const int ng = ceil_div((int)seq.size(), 64);
+    std::vector<int32_t> gdeg((size_t)ng, 0);
+    for (size_t q = 0; q < seq.size(); ++q) gdeg[q / 64] = std::max(gdeg[q / 64], seq[q].e - seq[q].b);
+    // greedy placement of the groups (largest first) on the least loaded SIMD
+    std::vector<int> gorder((size_t)ng);
+    for (int g = 0; g < ng; ++g) gorder[g] = g;
+    std::stable_sort(gorder.begin(), gorder.end(), [&](int x, int y) { return gdeg[x] > gdeg[y]; });
     std::vector<int> group_of_wave((size_t)nw, -1);
     int64_t load[4] = {0, 0, 0, 0};
     int used[4] = {0, 0, 0, 0};
-    for (int g = 0; g < ng; ++g) {
+    for (int g : gorder) {
         int best = -1;
         for (int q = 0; q < 4; ++q)
             if (used[q] < nw / 4 && (best < 0 || load[q] < load[best])) best = q;
+        if (best < 0) break;  // more groups than waves: caller rejects (words stays small)
         group_of_wave[(size_t)(best + 4 * used[best])] = g;
         load[best] += ceil_div(gdeg[g], rb::kBlockChunk);
         ++used[best];
     }
-    order.assign((size_t)s.TPB, -1);
+    lanes.assign((size_t)s.TPB, LaneSeg{});
     wdeg.assign((size_t)nw, 0);
     wbase.assign((size_t)nw, 0);
     for (int w = 0; w < nw; ++w) {
         const int g = group_of_wave[w];
         if (g < 0) continue;
         wdeg[w] = gdeg[g];
-        for (int l = 0; l < 64 && 64 * g + l < c->M; ++l) order[(size_t)(64 * w + l)] = sorted[64 * g + l];
+        for (int l = 0; l < 64 && (size_t)(64 * g + l) < seq.size(); ++l)
+            lanes[(size_t)(64 * w + l)] = seq[(size_t)(64 * g + l)];
     }
     words = 0;
     for (int w = 0; w < nw; ++w) {
@@ -276,7 +318,6 @@ std::vector<int32_t> fault_order(const rb_ctx *c) {
 
 bool block_fits(const rb_ctx *c, const rb::BlockShape &s) {
     if (c->M > s.TPB || ceil_div(c->N, s.TPB) > s.VPT || s.VPT > 16) return false;
-    if (c->max_row > s.DCMAX) return false;
     {
         // the first (largest-degree) fault of every band within the band's cap
         const std::vector<int32_t> fo = fault_order(c);
@@ -285,9 +326,19 @@ bool block_fits(const rb_ctx *c, const rb::BlockShape &s) {
             if (c->colptr[j + 1] - c->colptr[j] > rb::prof_dv(s.prof, v)) return false;
         }
     }
-    std::vector<int32_t> order, wdeg, wbase;
+    std::vector<LaneSeg> lanes;
+    std::vector<int32_t> wdeg, wbase;
     int64_t words = 0;
-    block_order(c, s, order, wdeg, wbase, words);
+    block_order(c, s, lanes, wdeg, wbase, words);
+    for (const LaneSeg &g : lanes)
+        if (g.e - g.b > s.DCMAX) return false;
+    {
+        // every segment placed
+        int64_t placed = 0;
+        for (const LaneSeg &g : lanes)
+            if (g.row >= 0) placed += g.e - g.b;
+        if (placed != c->E) return false;
+    }
     const BlockLayout l = block_layout(s, words);
     if (l.lampad_off + 8u > 65535u) return false;                   // 16-bit Lambda addresses
     if ((int64_t)(l.mu0_off / 4u) + words > 65535) return false;    // 16-bit message indices
@@ -310,15 +361,21 @@ rb_status upload(T **dst, const std::vector<T> &src, const char *what) {
 
 rb_status build_block_plan(rb_ctx *c, int bv) {
     const rb::BlockShape s = rb::block_variant_shape(bv);
-    std::vector<int32_t> order, wdeg, wbase;
+    std::vector<LaneSeg> lanes;
+    std::vector<int32_t> wdeg, wbase;
     int64_t words = 0;
-    block_order(c, s, order, wdeg, wbase, words);
+    block_order(c, s, lanes, wdeg, wbase, words);
     const BlockLayout lay = block_layout(s, words);
-    std::vector<int32_t> rank((size_t)c->M), chk_row((size_t)s.TPB, -1);
+    // chk_row: the check whose syndrome bit thread t adds (first segment only);
+    // chk_split: thread t shares its check with thread t ^ 1
+    std::vector<int32_t> chk_row((size_t)s.TPB, -1), chk_split((size_t)s.TPB, 0);
+    std::vector<int32_t> lane_of_edge((size_t)c->E, -1);
     for (int32_t t = 0; t < s.TPB; ++t) {
-        if (order[t] < 0) continue;
-        rank[order[t]] = t;
-        chk_row[t] = order[t];
+        const LaneSeg &g = lanes[(size_t)t];
+        if (g.row < 0) continue;
+        if (g.first) chk_row[t] = g.row;
+        chk_split[t] = g.split ? 1 : 0;
+        for (int32_t q = g.b; q < g.e; ++q) lane_of_edge[(size_t)(c->rowptr[g.row] + q)] = t;
     }
     // fault slots by decreasing column degree
     const std::vector<int32_t> fo = fault_order(c);
@@ -331,12 +388,42 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
     const int ncp = s.DCMAX / 2, nmp = (nmu + 1) / 2;
     std::vector<uint16_t> col16((size_t)s.TPB * s.DCMAX, (uint16_t)lay.lampad_off);
     std::vector<uint16_t> mu16((size_t)s.TPB * nmp * 2, (uint16_t)(lay.mupad_off / 4u));
-    for (int32_t t = 0; t < s.TPB; ++t) {
-        const int32_t i = order[t];
-        if (i < 0) continue;
-        for (int64_t k = 0; k < c->rowptr[i + 1] - c->rowptr[i]; ++k)
-            col16[(size_t)t * s.DCMAX + k] =
-                (uint16_t)(4u * (uint32_t)slot_of[c->colidx[c->rowptr[i] + k]]);
+    // Edge order within each row (free: the check update does not depend on
+    // it).  Step k of a wave gathers Lambda of edge k of 64 rows at once; the
+    // edges are ordered greedily so that the 32 lanes of each half-wave hit
+    // distinct LDS banks (word address mod 32) as far as possible.
+    std::vector<int32_t> epos((size_t)c->E, 0);  // CSR edge -> message row k
+    {
+        const int nw = s.TPB / 64;
+        for (int w = 0; w < nw; ++w) {
+            std::vector<std::vector<int64_t>> left(64);
+            for (int l = 0; l < 64; ++l) {
+                const LaneSeg &g = lanes[(size_t)(64 * w + l)];
+                if (g.row < 0) continue;
+                for (int32_t q = g.b; q < g.e; ++q) left[l].push_back(c->rowptr[g.row] + q);
+            }
+            for (int k = 0; k < wdeg[w]; ++k)
+                for (int h = 0; h < 2; ++h) {
+                    int cnt[32] = {0};
+                    // lanes with the fewest edges left choose first
+                    int lanes[32];
+                    for (int q = 0; q < 32; ++q) lanes[q] = 32 * h + q;
+                    std::stable_sort(lanes, lanes + 32, [&](int x, int y) { return left[x].size() < left[y].size(); });
+                    for (int q = 0; q < 32; ++q) {
+                        const int l = lanes[q];
+                        if (left[l].empty()) continue;
+                        size_t best = 0;
+                        for (size_t u = 1; u < left[l].size(); ++u)
+                            if (cnt[slot_of[c->colidx[left[l][u]]] & 31] < cnt[slot_of[c->colidx[left[l][best]]] & 31])
+                                best = u;
+                        const int64_t e = left[l][best];
+                        left[l].erase(left[l].begin() + (std::ptrdiff_t)best);
+                        ++cnt[slot_of[c->colidx[e]] & 31];
+                        epos[(size_t)e] = k;
+                        col16[(size_t)(64 * w + l) * s.DCMAX + k] = (uint16_t)(4u * (uint32_t)slot_of[c->colidx[e]]);
+                    }
+                }
+        }
     }
     for (int32_t t = 0; t < s.TPB; ++t)
         for (int v = 0; v < s.VPT; ++v) {
@@ -344,9 +431,9 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
             if (j < 0) continue;
             for (int64_t k = 0; k < c->colptr[j + 1] - c->colptr[j]; ++k) {
                 const int32_t i = c->rowidx[c->colptr[j] + k];
-                const int32_t ti = rank[i];
-                const int64_t word = (int64_t)(lay.mu0_off / 4u) + wbase[ti / 64] +
-                                     (int64_t)c->cpos[c->colptr[j] + k] * 64 + (ti % 64);
+                const size_t e = (size_t)(c->rowptr[i] + c->cpos[c->colptr[j] + k]);
+                const int32_t ti = lane_of_edge[e];
+                const int64_t word = (int64_t)(lay.mu0_off / 4u) + wbase[ti / 64] + (int64_t)epos[e] * 64 + (ti % 64);
                 mu16[(size_t)t * nmp * 2 + rb::prof_pre(s.prof, v) + k] = (uint16_t)word;
             }
         }
@@ -368,7 +455,20 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
     if ((st = upload(&c->d_lam_off, col_pk, "upload check table")) != RB_OK) return st;
     if ((st = upload(&c->d_mu_off, mu_pk, "upload fault table")) != RB_OK) return st;
     if ((st = upload(&c->d_chk_row, chk_row, "upload row map")) != RB_OK) return st;
+    if ((st = upload(&c->d_chk_split, chk_split, "upload split map")) != RB_OK) return st;
     if ((st = upload(&c->d_slot_col, slot_col, "upload slot map")) != RB_OK) return st;
+    {
+        const int npad = s.TPB * s.VPT, R = c->params.num_legs;
+        std::vector<float> w_slot((size_t)npad, 0.0f);
+        for (int32_t q = 0; q < c->N; ++q) w_slot[q] = c->w[(size_t)slot_col[q]];
+        if ((st = upload(&c->d_w_slot, w_slot, "upload w by slot")) != RB_OK) return st;
+        (void)hipFree(c->d_gamma_slot);
+        c->d_gamma_slot = nullptr;
+        RB_HIP(hipMalloc(&c->d_gamma_slot, sizeof(float) * (size_t)npad * (size_t)R), "hipMalloc(gamma by slot)");
+        RB_HIP(rb::launch_gather_slots(c->d_gamma, c->N, c->d_slot_col, npad, R, c->d_gamma_slot, nullptr),
+               "gamma by slot");
+        RB_HIP(hipDeviceSynchronize(), "gamma by slot");
+    }
     if ((st = upload(&c->d_wave_deg, wdeg, "upload wave degrees")) != RB_OK) return st;
     if ((st = upload(&c->d_wave_base, wbase, "upload wave bases")) != RB_OK) return st;
     {
@@ -602,6 +702,9 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_wave_deg);
         (void)hipFree(c->d_wave_base);
         (void)hipFree(c->d_slot_col);
+        (void)hipFree(c->d_chk_split);
+        (void)hipFree(c->d_w_slot);
+        (void)hipFree(c->d_gamma_slot);
     }
     if (c->d_rowptr || c->d_colidx || c->d_colptr || c->d_cedge) {
         (void)hipSetDevice(c->device);
@@ -668,6 +771,9 @@ static rb::BlockArgs block_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.chk_col = c->d_lam_off;
     b.col_mu = c->d_mu_off;
     b.chk_row = c->d_chk_row;
+    b.chk_split = c->d_chk_split;
+    b.w_slot = c->d_w_slot;
+    b.gamma_slot = c->d_gamma_slot;
     b.slot_col = c->d_slot_col;
     b.wave_deg = c->d_wave_deg;
     b.wave_base = c->d_wave_base;

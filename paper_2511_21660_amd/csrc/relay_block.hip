@@ -6,8 +6,9 @@
 // faults and rows of degree up to 64.  One workgroup of TPB threads decodes
 // one syndrome at a time and pulls the next one from a global queue.
 //
-// Roles.  Thread t owns the check of rank t in the order of decreasing degree
-// (so the 64 rows a wave handles have nearly the same length) and the fault
+// Roles.  Thread t owns a check, or half of a long check shared with thread
+// t ^ 1, placed so that the 64 rows a wave handles have nearly the same length
+// and the four SIMDs get about the same work; and thread t owns the fault
 // slots s = t + TPB*v, v < VPT; slot s holds the fault of rank s in the order
 // of decreasing column degree (slot_col), so each band v of slots has a
 // small fixed degree cap and the thread gathers only that many messages.
@@ -43,6 +44,9 @@ namespace {
 __device__ __forceinline__ float clipb(float x, float L) { return __builtin_amdgcn_fmed3f(x, -L, L); }
 
 __device__ __forceinline__ void opaque_b(uint32_t &x) { asm volatile("" : "+v"(x)); }
+
+// value of lane l ^ 1 (DPP quad permutation 1,0,3,2; the whole wave is active)
+__device__ __forceinline__ int swap_pair(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
 
 template <typename T>
 __device__ __forceinline__ __attribute__((address_space(3))) T &lds_b(uint32_t byte_addr) {
@@ -107,7 +111,9 @@ void relay_block_kernel(BlockArgs a) {
     uint32_t mu_pk[(NMU + 1) / 2];
 #pragma unroll
     for (int e = 0; e < (NMU + 1) / 2; ++e) mu_pk[e] = a.col_mu[(size_t)e * TPB + t];
-    const int myrow = a.chk_row[t];           // check index or -1
+    const int myrow = a.chk_row[t];           // check whose syndrome bit this thread adds, or -1
+    const bool split = a.chk_split[t] != 0;   // shares its check with thread t ^ 1
+    const bool first_half = (t & 1) == 0;
     // row length of this wave (uniform: read back as a scalar)
     const int wdeg = __builtin_amdgcn_readfirstlane(a.wave_deg[wave]);
     const uint32_t mrow = a.mu0_off + 4u * ((uint32_t)a.wave_base[wave] + (uint32_t)(t & 63));
@@ -149,12 +155,12 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const uint32_t sl = tl + TPB * v;
-            const int j = a.slot_col[sl];
-            float wj = 0.0f, gj = 0.0f;
-            if (j >= 0) {
-                wj = a.scale * a.w[j];
-                gj = TRACE ? a.trace_gamma[j] : a.gamma[j];
-                if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
+            const float wj = a.scale * a.w_slot[sl];  // 0 for spare slots
+            float gj = a.gamma_slot[sl];
+            if (TRACE) {
+                const int j = a.slot_col[sl];
+                gj = j >= 0 ? a.trace_gamma[j] : 0.0f;
+                if (j >= 0) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
             }
             xl[v] = (1.0f - gj) * wj;
             gm[v] = gj;
@@ -184,23 +190,19 @@ void relay_block_kernel(BlockArgs a) {
         float m1 = L, m2 = L;
         int amin = 0;
         uint32_t sg_lo = 0, sg_hi = 0;  // bit k: nu_k < 0
-        uint4 cur = col0;
+        // one chunk of W edges (W = CH, or 4 for a short last chunk)
+        auto chunk = [&](auto w_tag, int c, const uint4 &tb) {
+            constexpr int W = decltype(w_tag)::value;
+            const uint32_t pk[4] = {tb.x, tb.y, tb.z, tb.w};
+            float lv[W], mo[W];
 #pragma unroll
-        for (int c = 0; c < DCMAX; c += CH) {
-            if (c >= wdeg) break;  // wave-uniform row length
-            uint4 nxt = cur;
-            if (c + CH < DCMAX && c + CH < wdeg) nxt = ctab[(size_t)(c / CH + 1) * TPB + tl];
-            const uint32_t pk[4] = {cur.x, cur.y, cur.z, cur.w};
-            float lv[CH], mo[CH];
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
+            for (int q = 0; q < W; ++q) {
                 const uint32_t ca = (q & 1) ? (pk[q >> 1] >> 16) : (pk[q >> 1] & 0xffffu);
                 lv[q] = lds_b<float>(ca);
                 mo[q] = lds_b<float>(mrow + 256u * (c + q));
             }
-            cur = nxt;
 #pragma unroll
-            for (int q = 0; q < CH; ++q) {
+            for (int q = 0; q < W; ++q) {
                 const int k = c + q;
                 fpar ^= lv[q] < 0.0f;
                 const float nu = clipb(lv[q] - mo[q], L);
@@ -214,6 +216,34 @@ void relay_block_kernel(BlockArgs a) {
                 amin = av < m1 ? k : amin;
                 m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
                 m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
+            }
+        };
+        uint4 cur = col0;
+#pragma unroll
+        for (int c = 0; c < DCMAX; c += CH) {
+            if (c >= wdeg) break;  // wave-uniform row length
+            uint4 nxt = cur;
+            if (c + CH < DCMAX && c + CH < wdeg) nxt = ctab[(size_t)(c / CH + 1) * TPB + tl];
+            if (c + CH / 2 >= wdeg)
+                chunk(std::integral_constant<int, CH / 2>{}, c, cur);
+            else
+                chunk(std::integral_constant<int, CH>{}, c, cur);
+            cur = nxt;
+        }
+        // a check split over threads t and t ^ 1: combine the two halves'
+        // minima and parities (the first half holds the earlier edges, so it
+        // keeps the minimum's position on a tie)
+        bool owns_min = true;
+        {
+            const float m1o = __int_as_float(swap_pair(__float_as_int(m1)));
+            const float m2o = __int_as_float(swap_pair(__float_as_int(m2)));
+            const int bo = swap_pair((neg ? 1 : 0) | (fpar ? 2 : 0));
+            if (split) {
+                owns_min = first_half ? (m1 <= m1o) : (m1 < m1o);
+                m2 = fminf(fmaxf(m1, m1o), fminf(m2, m2o));
+                m1 = fminf(m1, m1o);
+                neg ^= (bo & 1) != 0;
+                fpar ^= (bo & 2) != 0;
             }
         }
         // pass 2: mu = +-m1 on every edge (sign of nu times the row parity),
@@ -239,7 +269,7 @@ void relay_block_kernel(BlockArgs a) {
                 else
                     pass2(std::false_type{}, c);
             }
-            if (wdeg > 0) {
+            if (wdeg > 0 && owns_min) {
                 const uint32_t sa = amin < 32 ? (s_lo >> amin) : (s_hi >> (amin - 32));
                 lds_b<uint32_t>(mrow + 256u * (uint32_t)amin) = (sa << 31) | __float_as_uint(m2);
             }
@@ -259,10 +289,9 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
                     const uint32_t sl = tl + TPB * v;
-                    const int j = a.slot_col[sl];
-                    if (j >= 0 && lds_b<float>(4u * sl) < 0.0f) {
+                    if (sl < (uint32_t)a.N && lds_b<float>(4u * sl) < 0.0f) {
                         fm |= 1u << v;
-                        part += (double)a.w[j];
+                        part += (double)a.w_slot[sl];
                     }
                 }
                 const double W = block_sum<TPB>(part, red);
@@ -299,14 +328,13 @@ void relay_block_kernel(BlockArgs a) {
             if (!done) {
                 ++r;
                 tt = 0;
-                const float *gr = a.gamma + (size_t)(r - 1) * a.N;
+                const float *gr = a.gamma_slot + (size_t)(r - 1) * (TPB * VPT);
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
                     const uint32_t sl = tl + TPB * v;
-                    const int j = a.slot_col[sl];
-                    if (j >= 0) {
-                        const float g = gr[j];
-                        const float l0 = PRIOR ? a.w[j] : clipb(lds_b<float>(4u * sl), L);
+                    if (sl < (uint32_t)a.N) {
+                        const float g = gr[sl];
+                        const float l0 = PRIOR ? a.w_slot[sl] : clipb(lds_b<float>(4u * sl), L);
                         gm[v] = g;
                         xl[v] = (1.0f - g) * l0;
                     }
@@ -357,6 +385,15 @@ void relay_block_kernel(BlockArgs a) {
         ++total;
         __syncthreads();
     }
+}
+
+__global__ void gather_slots_kernel(const float *src, int64_t src_stride, const int32_t *slot_col,
+                                    int npad, int rows, float *dst) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)rows * npad) return;
+    const int64_t r = idx / npad;
+    const int j = slot_col[idx % npad];
+    dst[idx] = j >= 0 ? src[r * src_stride + j] : 0.0f;
 }
 
 struct BlockVariant {
@@ -416,6 +453,16 @@ hipError_t block_prepare(int v, size_t lds) {
             if (e != hipSuccess) return e;
         }
     return hipSuccess;
+}
+
+hipError_t launch_gather_slots(const float *src, int64_t src_stride, const int32_t *slot_col, int npad,
+                               int rows, float *dst, hipStream_t s) {
+    const int64_t n = (int64_t)rows * npad;
+    if (n == 0) return hipSuccess;
+    const int threads = 256;
+    hipLaunchKernelGGL(gather_slots_kernel, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
+                       s, src, src_stride, slot_col, npad, rows, dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_block(int v, bool prior_anchor, bool trace, const BlockArgs &a, int grid,

@@ -100,8 +100,11 @@ struct BlockArgs {
     const float *gamma;
     const uint32_t *chk_col;   // [DCMAX/8][TPB][4] 16-bit Lambda byte addresses, 8 per chunk
     const uint32_t *col_mu;    // [ceil(prof_pre(VPT)/2)][TPB] two 16-bit message word indices
-    const int32_t *slot_col;   // [TPB*VPT] fault held by slot s, or -1
-    const int32_t *chk_row;    // [TPB] check owned by thread t, or -1
+    const int32_t *slot_col;   // [TPB*VPT] fault held by slot s, or -1 (slots >= N)
+    const float *w_slot;       // [TPB*VPT] channel LLR by slot (0 for spare slots)
+    const float *gamma_slot;   // [R][TPB*VPT] memory strengths by slot
+    const int32_t *chk_row;    // [TPB] check whose syndrome bit thread t adds, or -1
+    const int32_t *chk_split;  // [TPB] 1: thread t holds part of a check shared with thread t ^ 1
     const int32_t *wave_deg;   // [TPB/64] row length (max degree) of wave w
     const int32_t *wave_base;  // [TPB/64] first message word of wave w (relative to mu0)
     unsigned long long *queue;
@@ -126,6 +129,9 @@ BlockShape block_variant_shape(int v);
 hipError_t block_variant_occupancy(int v, bool prior_anchor, bool trace, size_t lds, int *blocks);
 // Allows `lds` bytes of dynamic LDS for every instantiation of variant v.
 hipError_t block_prepare(int v, size_t lds);
+// dst[r][s] = src[r][slot_col[s]] (0 for spare slots), r < rows
+hipError_t launch_gather_slots(const float *src, int64_t src_stride, const int32_t *slot_col, int npad,
+                               int rows, float *dst, hipStream_t s);
 hipError_t launch_block(int v, bool prior_anchor, bool trace, const BlockArgs &a, int grid,
                         size_t lds, hipStream_t s);
 

@@ -192,6 +192,26 @@ def test_irregular_graph_every_variant(rb):
     assert len(tested) >= 3 and max(tested) >= 512  # block shapes included
 
 
+def test_long_rows_split_over_two_lanes(rb):
+    """Rows longer than 32 are split over two lanes of the block kernel, which
+    merge min1/min2, the minimum's position and the parities.  Uniform priors
+    make every |nu| equal at the first iteration, so ties between the two
+    halves occur; rows of degree 33..90 and short rows side by side."""
+    rng = np.random.default_rng(11)
+    m, n = 24, 400
+    h = np.zeros((m, n), np.uint8)
+    for i, d in enumerate([90, 77, 64, 50, 41, 33] + [int(x) for x in rng.integers(3, 12, m - 6)]):
+        h[i, rng.choice(n, d, replace=False)] = 1
+    prior = np.full(n, 0.05)
+    prob = codes.problem_from_dense("long_rows", h, prior, np.zeros((1, n), np.uint8))
+    _, syn = sampling.sample_batch(prob, 1234, 0, 300)
+    prm = dict(RELAY_DEFAULT, num_legs=6, num_solutions=2)
+    ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, prm, syn, want_llr=True)
+    gpu = gpu_decode(rb, prob, prm, syn)
+    assert gpu["info"]["threads_per_block"] >= 512
+    assert_parity(gpu, ref, syn, prob, "long rows")
+
+
 def test_unsatisfiable_syndrome_runs_full_budget(rb):
     code = codes.bb_code("bb72")
     h = np.vstack([code.hx, np.zeros((1, 72), np.uint8)])
