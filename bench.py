@@ -320,7 +320,7 @@ def run_dem(args, torch, rb, codes, sampling):
         import oracle
 
         threads = oracle_threads()
-        n_cpu = min(args.cpu_sample or 4000, shots)
+        n_cpu = min(args.cpu_sample or 20000, shots)
         t1 = time.perf_counter()
         ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n_cpu],
                             threads=threads)
@@ -441,6 +441,25 @@ def run_mixed_codes(args, torch, rb, codes, sampling):
                 lds_bytes_per_edge_update(pr.m, pr.n, pr.nnz)
                 for k, pr in enumerate(probs)) / eu_launch
     roof, lds = roofline("relay_mixed_kernel", kernel_ms, ops_launch, eu_launch, lds_b, None)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = oracle_threads()
+        n_cpu = min(args.cpu_sample or 100000, shots)
+        t1 = time.perf_counter()
+        agree = True
+        for k, pr in enumerate(probs):
+            idx = per[k][0]
+            sel = idx[idx < n_cpu]
+            ref = oracle.decode(pr.m, pr.n, pr.rows, pr.cols, pr.prior, RELAY_R20, syn[sel, :pr.m],
+                                threads=threads)
+            agree &= bool(np.array_equal(ref["corr"], host["corr"][sel, :pr.n])
+                          and np.array_equal(ref["iters"], host["iters"][sel]))
+        tc = time.perf_counter() - t1
+        cpu = {"value": n_cpu / tc, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n_cpu} of {shots} interleaved syndromes, same inputs, {tc:.1f} s",
+               "paired_with_gpu_bit_exact": agree}
     line = head(args, shots * args.steps / el_mixed, el_mixed, {
         "workload": "relay_bp_mixed_bb_codes", "codes": list(names), "proportions": "4:3:2:1",
         "shots": shots, "p": 0.04, "legs": 20, "solutions": 1, "schedule": "mixed",
@@ -454,7 +473,7 @@ def run_mixed_codes(args, torch, rb, codes, sampling):
         "per_code_launches": {"value": shots * args.steps / el_per,
                               "launch_ms": launch_means(pl_per),
                               "results_identical": same},
-        "tiles_chosen": chosen, "ler": ler, "cpu_baseline": None})
+        "tiles_chosen": chosen, "ler": ler, "cpu_baseline": cpu})
     return line
 
 
