@@ -13,6 +13,12 @@ Other workloads:
                           interleaved 4:3:2:1, 4 x 10^5 shots at p = 0.04, R = 20,
                           S = 1: one autotuned mixed launch (eager and replayed from
                           a hipGraph) against four per-code launches
+  --workload learned      [[144,12,12]] at p = 0.04: learn gamma_j and the prior
+                          scale through 60 unrolled iterations (2000 Adam steps,
+                          batch 4096; lr 1e-2 with the loss at T = 60, and lr 1e-3
+                          with the loss averaged over T = 5..60), then decode 10^6
+                          held-out shots with Relay (R = 20, S = 1) and one DMem-BP
+                          leg (T = 60), with and without the learned first leg
 
 Prints one JSON line: syndromes/s (the headline), edge-updates/s, the ALU
 roofline of the decode kernel from HIP events on the launch stream, the LDS
@@ -53,7 +59,7 @@ OPS_PER_EDGE = 11.0
 OPS_PER_FAULT = 7.0
 OPS_PER_CHECK = 3.0
 
-DEFAULT_STEPS = {"bb144": 20, "dem": 5, "mixed-codes": 10}
+DEFAULT_STEPS = {"bb144": 20, "dem": 5, "mixed-codes": 10, "learned": 3}
 
 
 def ops_per_iteration(m, n, e):
@@ -477,12 +483,85 @@ def run_mixed_codes(args, torch, rb, codes, sampling):
     return line
 
 
+# --------------------------------------------------------------------------
+# learned first leg on [[144,12,12]] at p = 0.04
+# --------------------------------------------------------------------------
+
+
+def run_learned(args, torch, rb, codes, sampling):
+    """Trains gamma_j and the prior scale through the unrolled first leg (batch
+    4096 of fresh errors per step, checkpoints every 10 iterations, Adam), then
+    decodes held-out shots with and without the learned first leg.  Two
+    trainings: as configured (lr 1e-2, loss at T = 60) and with a smaller step
+    and the loss averaged over depths 5, 10, 20, 40, 60."""
+    from paper_2511_21660_amd import learn
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    prob = codes.bb_problem("bb144", 0.04)
+    steps_train = args.train_steps or 2000
+    batch = 4096
+    tdec = rb.Decoder.from_problem(prob, device=0, **RELAY_R20)
+    trainings = {"lr1e-2_T60": dict(lr=1e-2, t_iters=60),
+                 "lr1e-3_T5-60": dict(lr=1e-3, t_iters=(5, 10, 20, 40, 60))}
+    learned, train_info = {}, {}
+    for tag, kw in trainings.items():
+        t0 = time.perf_counter()
+        gamma, scale, hist = learn.train_first_leg(
+            tdec, prob, lambda k: sampling.sample_batch(prob, (7 << 32) | k, 0, batch), steps=steps_train,
+            ckpt_every=10, log_every=max(1, steps_train // 10),
+            log=lambda m, tag=tag: print(f"# {tag} {m}", file=sys.stderr, flush=True), **kw)
+        torch.cuda.synchronize()
+        learned[tag] = (gamma, scale)
+        train_info[tag] = {"seconds": time.perf_counter() - t0, "loss_first": hist[0][1],
+                           "loss_last": hist[-1][1], "scale": scale, "gamma_mean": float(gamma.mean()),
+                           "gamma_min": float(gamma.min()), "gamma_max": float(gamma.max())}
+    shots = args.shots or 1000000
+    f_ev, s_ev = sampling.sample_batch(prob, 0xE7A1, 0, shots)
+    d_syn = torch.from_numpy(s_ev).to(dev)
+    forms = {"relay": dict(RELAY_R20), "dmem_leg": dict(RELAY_R20, num_legs=1, iters_first=60)}
+    res = {}
+    for form, prm in forms.items():
+        for tag in [None] + list(learned):
+            dec = rb.Decoder.from_problem(prob, device=0, **prm)
+            if tag is not None:
+                dec.set_leg_gamma(1, learned[tag][0])
+                dec.set_prior_scale(learned[tag][1])
+            out = dec.decode(d_syn)
+
+            def step(ev, dec=dec, out=out):
+                if ev is not None:
+                    ev[0][0].record(stream)
+                dec.decode(d_syn, out=out)
+                if ev is not None:
+                    ev[0][1].record(stream)
+
+            el, pl = timed(torch, step, 1, args.steps, args.warmup)
+            conv = out["conv"].cpu().numpy()
+            fail = logical_failures(prob, f_ev, out["corr"].cpu().numpy(), conv)
+            k = int(fail.sum())
+            res[f"{form}/{tag or 'gamma0=0.125'}"] = {
+                "syndromes_per_s": shots * args.steps / el, "launch_ms": float(np.mean(pl)),
+                "ler": k / shots, "wilson95": wilson(k, shots), "conv": float(conv.mean()),
+                "mean_iters": float(out["iters"].float().mean().item())}
+            dec.close()
+    best = res["relay/lr1e-3_T5-60"]
+    line = head(args, best["syndromes_per_s"], shots * args.steps / best["syndromes_per_s"], {
+        "workload": "relay_bp_bb144_learned_first_leg", "code": "[[144,12,12]] HX 72x144", "p": 0.04,
+        "train_steps": steps_train, "batch": batch, "unrolled_iters": 60, "ckpt_every": 10,
+        "optimizer": "adam", "eval_shots": shots, "legs": 20, "solutions": 1,
+        "parallelism": "single_gpu"})
+    line.update({"decoders": res, "training": train_info, "cpu_baseline": None})
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["bb144", "dem", "mixed-codes"], default="bb144")
+    ap.add_argument("--workload", choices=["bb144", "dem", "mixed-codes", "learned"], default="bb144")
+    ap.add_argument("--train-steps", type=int, default=0, help="learned: Adam steps (default 2000)")
     ap.add_argument("--shots", type=int, default=0,
                     help="syndromes per p (bb144) or in total (default per workload)")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -513,7 +592,8 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
-    run = {"bb144": run_bb144, "dem": run_dem, "mixed-codes": run_mixed_codes}[args.workload]
+    run = {"bb144": run_bb144, "dem": run_dem, "mixed-codes": run_mixed_codes,
+           "learned": run_learned}[args.workload]
     line = run(args, torch, rb, codes, sampling)
     if args.calibrate_copy > 0:
         n_el = args.calibrate_copy * (1 << 20) // 4

@@ -177,6 +177,20 @@ rb_status rb_get_llr(const rb_ctx *ctx, float *host_w);
  * Gamma_r) -- test hook for the counter-based generator. */
 rb_status rb_get_gamma_table(const rb_ctx *ctx, float *host_gamma);
 
+/* Learned first leg (the differentiable decoder's output, not part of the
+ * paper's decoder): rb_set_leg_gamma replaces row `leg` - 1 of the memory
+ * strength table (leg 1 = the first leg; host float[N], copied) for every
+ * later decode on this context, so a first leg trained with rb_forward_train /
+ * rb_backward can be run inside Relay.  rb_set_prior_scale sets s in
+ * Lambda(0) = lambda(0) = s * w_j (and lambda(0) = s * w_j under the prior
+ * anchor) for later decodes; the solution weight W keeps the unscaled w_j.
+ * Defaults: the generated table and s = 1 (the paper's decoder).  Both copy
+ * and synchronise the device; single-code contexts only (RB_E_INVALID_ARG for
+ * a mixed-code context); RB_E_NONFINITE for a non-finite value,
+ * RB_E_INVALID_ARG for a leg outside 1..R. */
+rb_status rb_set_leg_gamma(rb_ctx *ctx, int32_t leg, const float *host_gamma);
+rb_status rb_set_prior_scale(rb_ctx *ctx, float scale);
+
 /* Fills *info with the context's kernel configuration. */
 rb_status rb_get_info(const rb_ctx *ctx, rb_info *info);
 

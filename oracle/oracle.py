@@ -62,8 +62,8 @@ def lib():
         L.ro_gamma_f32.restype = ctypes.c_float
         for sfx in ("f32", "f64"):
             f = getattr(L, f"ro_decode_{sfx}")
-            f.argtypes = [i32, i32, i64, P, P, P, ctypes.POINTER(OracleParams), i64, P, P, P, P, P, P,
-                          P]
+            f.argtypes = [i32, i32, i64, P, P, P, ctypes.POINTER(OracleParams), P, ctypes.c_double,
+                          i64, P, P, P, P, P, P, P]
             f.restype = i32
             f = getattr(L, f"ro_trace_{sfx}")
             f.argtypes = [i32, i32, i64, P, P, P, ctypes.c_double, P, i32, ctypes.c_double, i64, P, P]
@@ -98,9 +98,12 @@ def _coo(rows, cols):
 
 
 def decode(m, n, rows, cols, prior, params: dict, syn, precision="f32", threads=None,
-           chunk=None, want_llr=False):
+           chunk=None, want_llr=False, gamma1=None, scale=1.0):
     """Relay-decode syndromes [B, M]; returns dict of corr/conv/legs/iters/weight
-    (and final marginals ``llr`` [B, N] when ``want_llr``)."""
+    (and final marginals ``llr`` [B, N] when ``want_llr``).  ``gamma1`` [N]
+    replaces leg 1's uniform memory strength per column and ``scale``
+    multiplies the initial channel LLRs (a learned first leg); the defaults are
+    the paper's decoder."""
     rows, cols = _coo(rows, cols)
     prior = np.ascontiguousarray(prior, dtype=np.float64)
     syn = np.ascontiguousarray(syn, dtype=np.uint8)
@@ -113,12 +116,18 @@ def decode(m, n, rows, cols, prior, params: dict, syn, precision="f32", threads=
     weight = np.zeros(b, np.float64)
     llr = np.zeros((b, n), np.float32 if precision == "f32" else np.float64) if want_llr else None
     fn = getattr(lib(), f"ro_decode_{precision}")
+    g1 = None
+    if gamma1 is not None:
+        g1 = np.ascontiguousarray(gamma1, dtype=np.float32 if precision == "f32" else np.float64)
+        if g1.shape != (n,):
+            raise ValueError("gamma1 must have one entry per column")
     threads = threads or os.cpu_count() or 1
     chunk = chunk or max(1, min(256, (b + threads - 1) // max(threads, 1)))
 
     def run(s0):
         s1 = min(b, s0 + chunk)
-        rc = fn(m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(prior), ctypes.byref(p), s1 - s0,
+        rc = fn(m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(prior), ctypes.byref(p),
+                _ptr(g1) if g1 is not None else None, float(scale), s1 - s0,
                 _ptr(syn[s0:s1]), _ptr(corr[s0:s1]), _ptr(conv[s0:s1]), _ptr(legs[s0:s1]),
                 _ptr(iters[s0:s1]), _ptr(weight[s0:s1]),
                 _ptr(llr[s0:s1]) if want_llr else None)

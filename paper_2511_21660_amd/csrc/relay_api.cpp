@@ -71,6 +71,7 @@ struct rb_ctx {
     int32_t *d_slot_col = nullptr, *d_chk_split = nullptr;
     float *d_w_slot = nullptr;      // [TPB*VPT] w by fault slot (block kernel)
     float *d_gamma_slot = nullptr;  // [R][TPB*VPT] gamma by fault slot (block kernel)
+    float prior_scale = 1.0f;       // s in Lambda(0) = s * w (rb_set_prior_scale)
     // longest-first shot lists for single-code decodes (rb_reserve)
     void *d_ws = nullptr;
     int64_t ws_capacity = 0;
@@ -750,7 +751,7 @@ static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     a.lampad_off = c->lampad_off;
     a.mupad_off = c->mupad_off;
     a.mu0_off = c->mu0_off;
-    a.scale = 1.0f;
+    a.scale = c->prior_scale;
     return a;
 }
 
@@ -868,6 +869,39 @@ rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_ga
     a.trace_T = T;
     a.trace = d_trace;
     return launch(c, a, true, (hipStream_t)stream);
+}
+
+rb_status rb_set_leg_gamma(rb_ctx *c, int32_t leg, const float *host_gamma) {
+    g_last_error.clear();
+    if (!c || !host_gamma) return fail(RB_E_INVALID_ARG, "NULL argument");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: set the gamma of a single-code context");
+    if (leg < 1 || leg > c->params.num_legs) return fail(RB_E_INVALID_ARG, "leg must be in 1..R");
+    for (int32_t j = 0; j < c->N; ++j)
+        if (!std::isfinite(host_gamma[j])) return fail(RB_E_NONFINITE, "gamma must be finite");
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(hipDeviceSynchronize(), "synchronise before gamma update");
+    RB_HIP(hipMemcpy(c->d_gamma + (size_t)(leg - 1) * c->N, host_gamma, sizeof(float) * (size_t)c->N,
+                     hipMemcpyHostToDevice),
+           "copy gamma row");
+    if (c->block) {
+        const int npad = c->bshape.TPB * c->bshape.VPT;
+        RB_HIP(rb::launch_gather_slots(c->d_gamma + (size_t)(leg - 1) * c->N, c->N, c->d_slot_col, npad, 1,
+                                       c->d_gamma_slot + (size_t)(leg - 1) * npad, nullptr),
+               "gamma by slot");
+        RB_HIP(hipDeviceSynchronize(), "gamma by slot");
+    }
+    return RB_OK;
+}
+
+rb_status rb_set_prior_scale(rb_ctx *c, float scale) {
+    g_last_error.clear();
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: set the scale of a single-code context");
+    if (!std::isfinite(scale)) return fail(RB_E_NONFINITE, "scale must be finite");
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(hipDeviceSynchronize(), "synchronise before scale update");
+    c->prior_scale = scale;
+    return RB_OK;
 }
 
 rb_status rb_get_llr(const rb_ctx *c, float *host_w) {

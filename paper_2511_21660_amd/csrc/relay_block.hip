@@ -334,7 +334,7 @@ void relay_block_kernel(BlockArgs a) {
                     const uint32_t sl = tl + TPB * v;
                     if (sl < (uint32_t)a.N) {
                         const float g = gr[sl];
-                        const float l0 = PRIOR ? a.w_slot[sl] : clipb(lds_b<float>(4u * sl), L);
+                        const float l0 = PRIOR ? a.scale * a.w_slot[sl] : clipb(lds_b<float>(4u * sl), L);
                         gm[v] = g;
                         xl[v] = (1.0f - g) * l0;
                     }

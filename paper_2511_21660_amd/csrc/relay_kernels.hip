@@ -331,7 +331,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                     const int j = (int)gl + G * v;
                     if (j < a.N) {
                         gm[v] = gr[j];
-                        l0[v] = PRIOR ? a.w[j] : clipf(Lr[v], L);
+                        l0[v] = PRIOR ? a.scale * a.w[j] : clipf(Lr[v], L);
                     }
                 }
                 zero_rows();

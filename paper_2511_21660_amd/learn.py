@@ -99,3 +99,40 @@ def soft_decoding_loss_np(llr, syndromes, faults, h, logical, eps=1e-7):
     prod = np.exp(ay @ lp.T) * (1.0 - 2.0 * np.mod(negy @ lp.T, 2.0))
     p_log = np.clip(0.5 * (1.0 - prod), eps, 1 - eps)
     return bce_syn.mean() + (-np.log(1 - p_log)).mean()
+
+
+def train_first_leg(decoder, problem, sample, steps=2000, t_iters=60, ckpt_every=10, lr=1e-2,
+                    gamma_init=0.125, scale_init=1.0, log_every=100, log=None):
+    """Adam on (gamma_j, s) through the unrolled first leg.
+
+    decoder: a relaybp.Decoder for `problem`; sample(step) -> (faults, syndromes)
+    uint8 numpy arrays [B, N], [B, M] of freshly drawn errors.  t_iters: the
+    unrolled depth, or a tuple of depths whose losses are averaged (each depth
+    is one forward / adjoint pass from the initial LLRs).  Returns (gamma
+    float32 [N], scale float, history list of (step, loss)).
+    """
+    depths = (t_iters,) if isinstance(t_iters, int) else tuple(t_iters)
+    dev = torch.device("cuda", decoder.device)
+    gamma = torch.full((problem.n,), gamma_init, dtype=torch.float32, device=dev, requires_grad=True)
+    scale = torch.tensor([scale_init], dtype=torch.float32, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([gamma, scale], lr=lr)
+    h = incidence(problem.rows, problem.cols, problem.m, problem.n, dev)
+    lg = torch.from_numpy(problem.logical.astype(np.float32)).to(dev)
+    history = []
+    for step in range(steps):
+        f, s = sample(step)
+        d_syn = torch.from_numpy(s).to(dev)
+        d_f = torch.from_numpy(f).to(dev)
+        loss = 0.0
+        for t in depths:
+            llr = RelayUnroll.apply(decoder, d_syn, gamma, scale, t, ckpt_every)
+            loss = loss + soft_decoding_loss(llr, d_syn, d_f, h, lg)
+        loss = loss / len(depths)
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        if step % log_every == 0 or step == steps - 1:
+            history.append((step, float(loss.item())))
+            if log is not None:
+                log(f"step {step} loss {history[-1][1]:.5f} scale {float(scale.item()):.4f}")
+    return gamma.detach().cpu().numpy(), float(scale.item()), history

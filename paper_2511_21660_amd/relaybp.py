@@ -83,6 +83,8 @@ def load_library():
     L.rb_get_gamma_table.argtypes = [P, P]
     L.rb_get_info.argtypes = [P, ctypes.POINTER(RBInfo)]
     L.rb_set_variant.argtypes = [P, i32]
+    L.rb_set_leg_gamma.argtypes = [P, i32, P]
+    L.rb_set_prior_scale.argtypes = [P, ctypes.c_float]
     L.rb_sync_status.argtypes = [P]
     L.rb_autotune.argtypes = [P, i64, P, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     L.rb_reserve.argtypes = [P, i64]
@@ -104,7 +106,8 @@ def load_library():
     for name in ("rb_params_default", "rb_create", "rb_decode", "rb_trace", "rb_get_llr",
                  "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status",
                  "rb_autotune", "rb_reserve", "rb_create_multi", "rb_decode_multi",
-                 "rb_autotune_multi", "rb_forward_train", "rb_backward"):
+                 "rb_autotune_multi", "rb_forward_train", "rb_backward", "rb_set_leg_gamma",
+                 "rb_set_prior_scale"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -242,6 +245,18 @@ class Decoder:
 
     def set_variant(self, v: int):
         _check(load_library().rb_set_variant(self._h, int(v)))
+
+    def set_leg_gamma(self, leg: int, gamma):
+        """Replaces leg `leg`'s memory strengths (float [N]) for later decodes
+        (e.g. a learned first leg).  Synchronises the device."""
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float32))
+        if g.shape != (self.n,):
+            raise ValueError(f"gamma must be float [{self.n}]")
+        _check(load_library().rb_set_leg_gamma(self._h, int(leg), g.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_prior_scale(self, scale: float):
+        """Sets s in Lambda(0) = s * w for later decodes.  Synchronises the device."""
+        _check(load_library().rb_set_prior_scale(self._h, float(scale)))
 
     def tape_bytes(self, b: int, t_iters: int, ckpt_every: int) -> int:
         return int(load_library().rb_train_tape_size(self._h, int(b), int(t_iters), int(ckpt_every)))

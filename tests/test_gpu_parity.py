@@ -212,6 +212,29 @@ def test_long_rows_split_over_two_lanes(rb):
     assert_parity(gpu, ref, syn, prob, "long rows")
 
 
+@pytest.mark.parametrize("name,anchor", [("bb144", 0), ("bb144", 1), ("dem", 0)])
+def test_learned_first_leg_parity(rb, name, anchor):
+    """rb_set_leg_gamma / rb_set_prior_scale (a learned first leg inside Relay)
+    against the oracle's gamma1 / scale, on the group kernel ([[144,12,12]]) and
+    the block kernel (DEM-shaped matrix); the table readback shows the row."""
+    prob = codes.dem_problem() if name == "dem" else codes.bb_problem(name, 0.05)
+    _, syn = sampling.sample_batch(prob, 71, 0, 120 if name == "dem" else 400)
+    g1 = np.random.default_rng(8).uniform(-0.2, 0.6, prob.n).astype(np.float32)
+    prm = dict(RELAY_DEFAULT, anchor=anchor, num_legs=6, num_solutions=2)
+    dec = rb.Decoder.from_problem(prob, **prm)
+    dec.set_leg_gamma(1, g1)
+    dec.set_prior_scale(0.8)
+    np.testing.assert_array_equal(dec.gamma_table()[0], g1)
+    out = dec.decode(torch.from_numpy(syn).cuda(), want_llr=True)
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    gpu["info"] = dec.info()
+    dec.close()
+    ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, prm, syn, want_llr=True,
+                        gamma1=g1, scale=0.8)
+    assert_parity(gpu, ref, syn, prob, f"learned first leg {name} anchor {anchor}")
+
+
 def test_unsatisfiable_syndrome_runs_full_budget(rb):
     code = codes.bb_code("bb72")
     h = np.vstack([code.hx, np.zeros((1, 72), np.uint8)])

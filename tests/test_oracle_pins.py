@@ -365,3 +365,62 @@ def test_leg_chaining_fixed_point(anchor):
         g2.append(lo32 + (hi32 - lo32) * (x >> 8) * 2.0 ** -24)
     leg2 = fixed_point(np.array(g2), leg1 if anchor == 0 else w)
     np.testing.assert_allclose(out["llr"][0], leg2, rtol=1e-9)
+
+
+# --------------------------------------------------------- learned first leg
+
+
+def test_uniform_gamma1_equals_gamma_first():
+    """A per-column leg-1 gamma vector filled with gamma_first is the paper's
+    decoder exactly."""
+    p = codes.bb_problem("bb72", 0.06)
+    _, syn = sampling.sample_batch(p, 41, 0, 200)
+    prm = dict(RELAY_DEFAULT, num_legs=8, num_solutions=2)
+    a = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, prm, syn, want_llr=True)
+    g1 = np.full(p.n, np.float32(prm["gamma_first"]), np.float32)
+    b = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, prm, syn, want_llr=True, gamma1=g1)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("anchor", [0, 1])
+def test_prior_scale_is_a_homogeneous_rescaling(anchor):
+    """Min-sum with memory is positively homogeneous in the initial LLRs (min,
+    signs, sums, products with gamma and the clip at 2^64 far away all commute
+    with scaling), and scaling by a power of two is exact in floating point:
+    with scale = 2 every decision, leg, iteration count and solution weight
+    equals scale = 1, and the final marginals are exactly doubled.  A learned
+    per-column gamma in leg 1 changes nothing in this."""
+    p = codes.bb_problem("bb90", 0.06)
+    _, syn = sampling.sample_batch(p, 43, 0, 200)
+    prm = dict(RELAY_DEFAULT, num_legs=6, num_solutions=2, anchor=anchor)
+    g1 = np.random.default_rng(4).uniform(-0.2, 0.6, p.n).astype(np.float32)
+    a = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, prm, syn, want_llr=True, gamma1=g1)
+    b = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, prm, syn, want_llr=True, gamma1=g1,
+                      scale=2.0)
+    for k in ("corr", "conv", "legs", "iters", "weight"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(b["llr"], np.float32(2.0) * a["llr"])
+
+
+def test_learned_gamma1_changes_the_first_leg_only():
+    """gamma1 enters leg 1 only: with one leg, the decode equals a leg-1 trace
+    with per-column gamma (a different code path of the oracle) run to the
+    first convergence."""
+    p = codes.bb_problem("bb72", 0.05)
+    _, syn = sampling.sample_batch(p, 47, 0, 60)
+    g1 = np.random.default_rng(5).uniform(0.0, 0.5, p.n).astype(np.float32)
+    T = 40
+    prm = dict(RELAY_DEFAULT, num_legs=1, iters_first=T)
+    out = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, prm, syn, want_llr=True, gamma1=g1,
+                        scale=0.75)
+    tr = oracle.trace(p.m, p.n, p.rows, p.cols, p.prior, g1, T, syn, scale=0.75)
+    h = p.dense().astype(np.int64)
+    for b in range(len(syn)):
+        f = (tr[b, 1:] < 0).astype(np.int64)             # decisions after t = 1..T
+        ok = np.nonzero(((f @ h.T) % 2 == (syn[b] != 0)).all(1))[0]
+        t_stop = ok[0] + 1 if ok.size else T
+        assert out["iters"][b] == t_stop
+        assert out["conv"][b] == (1 if ok.size else 0)
+        np.testing.assert_array_equal(out["llr"][b], tr[b, t_stop])
+        np.testing.assert_array_equal(out["corr"][b], (tr[b, t_stop] < 0).astype(np.uint8))
