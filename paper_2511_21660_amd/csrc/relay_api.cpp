@@ -1295,7 +1295,8 @@ rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const 
     const int32_t *ws = (const int32_t *)d_workspace;
     m.seg_start = ws + (size_t)nc * rb::kWeightBinsHost;
     m.seg_count = m.seg_start + nc;
-    m.list = ws + (size_t)nc * (rb::kWeightBinsHost + 2) + (size_t)B;
+    m.order = m.seg_count + nc;
+    m.list = ws + (size_t)nc * (rb::kWeightBinsHost + 3) + (size_t)B;
     m.queues = c->d_queues;
     const int64_t full = (int64_t)c->blocks_per_cu[0] * c->num_cu;
     const int grid = (int)std::max<int64_t>(1, full);

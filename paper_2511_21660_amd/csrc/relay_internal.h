@@ -153,6 +153,7 @@ struct MixedArgs {
     const int32_t *list;       // shot lists, all codes
     const int32_t *seg_start;  // [ncodes] (device, written by the list kernels)
     const int32_t *seg_count;  // [ncodes]
+    const int32_t *order;      // [ncodes] code visiting order (device, written by the list kernels)
     unsigned long long *queues;  // [ncodes]
 };
 
@@ -173,13 +174,13 @@ hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s);
 // positions sorted by (code, decreasing syndrome weight); the list of code c
 // starts at list + seg_start[c] and holds seg_count[c] shots.  Also zeroes the
 // per-code queue counters.  Layout: hist[ncodes*256], seg_start[ncodes],
-// seg_count[ncodes], key[B], list[B] (int32).
+// seg_count[ncodes], order[ncodes], key[B], list[B] (int32).
 hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
                              const int32_t *code_m, int ncodes, void *workspace,
                              unsigned long long *queues, hipStream_t s);
 size_t shot_list_bytes(int64_t B, int ncodes);
 constexpr int kWeightBinsHost = 256;              // weight bins of the shot-list sort
-constexpr int kListHeader = kWeightBinsHost + 2;  // int32 words before key[] for one code
+constexpr int kListHeader = kWeightBinsHost + 3;  // int32 words before key[] for one code
 
 // Unrolled one-leg DMem-BP with learnable gamma_j and LLR scale, and its adjoint.
 struct TrainArgs {

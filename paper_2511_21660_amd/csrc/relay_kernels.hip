@@ -104,6 +104,15 @@ __global__ void reset_queue_kernel(unsigned long long *q) { *q = 0ull; }
 // where used instead of being hoisted out of the persistent loop and spilled.
 __device__ __forceinline__ void opaque(uint32_t &x) { asm volatile("" : "+v"(x)); }
 
+// Orders the LDS accesses of one wave before and after this point for the
+// compiler.  The group kernels run one wave per block, whose LDS instructions
+// execute in issue order, so no hardware barrier and no wait for outstanding
+// global loads is needed (unlike __syncthreads).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // LDS word at a byte address (the kernels use no static LDS, so the dynamic
 // LDS window starts at address 0).
 template <typename T>
@@ -237,7 +246,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     };
 
     fetch();
-    __syncthreads();
+    wave_sync();
 
     while (__any(active)) {
 #pragma unroll
@@ -367,7 +376,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 fetch();
             }
         }
-        __syncthreads();
+        wave_sync();
 
         // ---------------- fault pass: memory term, marginals, Lambda(t+1)
         if (active && !event) {
@@ -392,7 +401,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
             ++t;
             ++total;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -413,7 +422,7 @@ template <bool PRIOR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 void relay_mixed_kernel(MixedArgs m) {
     for (int q = 0; q < m.ncodes; ++q) {
-        const int c = (int)((blockIdx.x + (unsigned)q) % (unsigned)m.ncodes);
+        const int c = m.order[q];
         const CodeStatic cs = m.codes[c];
         GroupArgs a = m.run;
         a.M = cs.M;
@@ -489,19 +498,46 @@ __global__ __launch_bounds__(kListThreads) void list_key_kernel(
 }
 
 // single thread: exclusive scan of the histogram into positions; per-code
-// segment start and length
-__global__ void list_scan_kernel(int ncodes, int32_t *hist, int32_t *seg_start, int32_t *seg_count) {
+// segment start and length; the order in which every block visits the codes:
+// decreasing mean syndrome weight, so the heaviest code's long-running shots
+// start first and the launch ends on the lightest code's shortest shots.
+__global__ void list_scan_kernel(int ncodes, int32_t *hist, int32_t *seg_start, int32_t *seg_count,
+                                 int32_t *order) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     int32_t run = 0;
     for (int c = 0; c < ncodes; ++c) {
         seg_start[c] = run;
+        double wsum = 0.0;
         for (int k = 0; k < kWeightBins; ++k) {
             const int32_t n = hist[c * kWeightBins + k];
             hist[c * kWeightBins + k] = run;
             run += n;
+            wsum += (double)n * (double)(kWeightBins - 1 - k);
         }
         seg_count[c] = run - seg_start[c];
+        // 256 x mean weight, held in order[c] until the sort below replaces it
+        order[c] = seg_count[c] > 0 ? (int32_t)(256.0 * wsum / seg_count[c]) : -1;
     }
+    // stable selection by decreasing mean weight (ncodes is small)
+    int32_t key[64], idx[64];
+    const int n = ncodes < 64 ? ncodes : 64;
+    for (int c = 0; c < n; ++c) {
+        key[c] = order[c];
+        idx[c] = c;
+    }
+    for (int a = 0; a < n; ++a) {
+        int best = a;
+        for (int b = a + 1; b < n; ++b)
+            if (key[b] > key[best]) best = b;
+        const int32_t tk = key[best], ti = idx[best];
+        for (int b = best; b > a; --b) {
+            key[b] = key[b - 1];
+            idx[b] = idx[b - 1];
+        }
+        key[a] = tk;
+        idx[a] = ti;
+    }
+    for (int c = 0; c < ncodes; ++c) order[c] = c < n ? idx[c] : c;
 }
 
 // Each block reserves one contiguous range per nonzero (block, bin) and
@@ -639,21 +675,22 @@ hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, 
     int32_t *hist = (int32_t *)workspace;                       // ncodes * bins
     int32_t *seg_start = hist + (size_t)ncodes * kWeightBins;   // ncodes
     int32_t *seg_count = seg_start + ncodes;                    // ncodes
-    int32_t *key = seg_count + ncodes;                          // B
+    int32_t *order = seg_count + ncodes;                        // ncodes
+    int32_t *key = order + ncodes;                              // B
     int32_t *list = key + B;                                    // B
     const int nh = ncodes * kWeightBins;
     hipLaunchKernelGGL(list_zero_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, hist, nh, queues, ncodes);
     const int blocks = (int)((B + kListThreads - 1) / kListThreads);
     hipLaunchKernelGGL(list_key_kernel, dim3(blocks), dim3(kListThreads), 4u * (size_t)nh, s, B, syn, syn_stride,
                        code_id, code_m, ncodes, key, hist);
-    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, ncodes, hist, seg_start, seg_count);
+    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, ncodes, hist, seg_start, seg_count, order);
     hipLaunchKernelGGL(list_scatter_kernel, dim3(blocks), dim3(kListThreads), 8u * (size_t)nh, s, B, nh, key, hist,
                        list);
     return hipGetLastError();
 }
 
 size_t shot_list_bytes(int64_t B, int ncodes) {
-    return sizeof(int32_t) * ((size_t)ncodes * (kWeightBins + 2) + 2 * (size_t)B);
+    return sizeof(int32_t) * ((size_t)ncodes * (kWeightBins + 3) + 2 * (size_t)B);
 }
 
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s) {
