@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -211,7 +212,7 @@ BlockLayout block_layout(const rb::BlockShape &s, int64_t msg_words) {
     l.npad = s.TPB * s.VPT;
     l.lampad_off = 4u * (uint32_t)l.npad;
     l.mupad_off = l.lampad_off + 4u;
-    l.red_off = (l.mupad_off + 4u + 7u) & ~7u;
+    l.red_off = (l.mupad_off + 4u + 15u) & ~15u;  // block-OR flags (red_off + 8 * TPB/64) 16-byte aligned
     // scratch: TPB/64 doubles (block sums), TPB/64 words (block OR), shot index
     l.mu0_off = (l.red_off + 12u * (uint32_t)(s.TPB / 64) + 8u + 15u) & ~15u;
     l.slack_off = l.mu0_off + 4u * (uint32_t)msg_words;
@@ -360,16 +361,276 @@ rb_status upload(T **dst, const std::vector<T> &src, const char *what) {
     return RB_OK;
 }
 
-rb_status build_block_plan(rb_ctx *c, int bv) {
-    const rb::BlockShape s = rb::block_variant_shape(bv);
+// Deterministic generator for the plan's local search (splitmix64).
+struct PlanRng {
+    uint64_t x;
+    uint32_t below(uint32_t n) {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (uint32_t)(z % n);
+    }
+};
+
+// Fault slots.  Band v holds the faults of degree rank [v*TPB, (v+1)*TPB)
+// (fault_order), so slots below N are exactly the real ones.  Within a band
+// the faults are placed with the LDS banks in mind (32 banks, word address
+// mod 32; a wave's access costs the largest number of distinct words on one
+// bank):
+//  * wave of the slot: the fault pass's k-th gather of a wave reads the
+//    message of each lane's k-th check, whose bank is fixed by the lane that
+//    owns that check; faults are grouped 64 to a wave so these banks are as
+//    even as possible (greedy, then pairwise swaps between waves);
+//  * lane of the slot: a fault's Lambda word (= its slot) lies in bank
+//    slot mod 32; lanes are chosen so that every check wave's edges spread
+//    evenly over the banks, which lets the check-side edge order (order_rows)
+//    read at most two words per bank in each step.
+std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, const std::vector<int32_t> &lane_of_edge,
+                                  const std::vector<int32_t> &wdeg, const BlockLayout &lay) {
+    const int TPB = s.TPB, nw = TPB / 64;
+    const std::vector<int32_t> fo = fault_order(c);
+    std::vector<int32_t> slot_col((size_t)TPB * s.VPT, -1);
+    const int mu0w = (int)(lay.mu0_off / 4u), padb = (int)((lay.mupad_off / 4u) % 32u);
+    std::vector<int32_t> load((size_t)nw * 32, 0);  // check wave x bank: Lambda gathers
+    PlanRng rng{0x5EED5EEDull};
+    for (int v = 0; v < s.VPT && (int64_t)v * TPB < c->N; ++v) {
+        const int64_t base = (int64_t)v * TPB;
+        const int nf = (int)std::min<int64_t>(TPB, c->N - base);
+        const int D = rb::prof_dv(s.prof, v);
+        // bank of each fault's k-th message (-1: the fault has fewer edges)
+        std::vector<int8_t> sig((size_t)nf * D, -1);
+        for (int f = 0; f < nf; ++f) {
+            const int32_t j = fo[(size_t)(base + f)];
+            for (int64_t k = 0; k < c->colptr[j + 1] - c->colptr[j] && k < D; ++k) {
+                const int32_t i = c->rowidx[c->colptr[j] + k];
+                const int32_t t = lane_of_edge[(size_t)(c->rowptr[i] + c->cpos[c->colptr[j] + k])];
+                sig[(size_t)f * D + k] = (int8_t)((mu0w + t) % 32);
+            }
+        }
+        std::vector<int> capg((size_t)nw), member((size_t)nw * 64, -1), fill((size_t)nw, 0);
+        for (int g = 0; g < nw; ++g) capg[g] = std::max(0, std::min(64, nf - 64 * g));
+        // cnt[(g*D + k)*33 + b]: lanes of wave g whose k-th gather hits bank b; b = 32: pads
+        std::vector<int> cnt((size_t)nw * D * 33, 0);
+        auto cost_gk = [&](int g, int k) {
+            const int *q = &cnt[((size_t)g * D + k) * 33];
+            int m = q[32] > 0 ? 1 : 0;
+            for (int b = 0; b < 32; ++b) m = std::max(m, q[b] + ((b == padb && q[32] > 0) ? 1 : 0));
+            return m;
+        };
+        auto add = [&](int g, int f, int d) {
+            for (int k = 0; k < D; ++k) {
+                const int b = sig[(size_t)f * D + k];
+                cnt[((size_t)g * D + k) * 33 + (b < 0 ? 32 : b)] += d;
+            }
+        };
+        // cost of a wave: its gathers' bank cycles, then (to steer the
+        // search) the lanes beyond two on any bank
+        auto cost_g = [&](int g) {
+            int tot = 0;
+            for (int k = 0; k < D; ++k) {
+                const int *q = &cnt[((size_t)g * D + k) * 33];
+                int ex = 0;
+                for (int b = 0; b < 32; ++b) ex += std::max(0, q[b] + ((b == padb && q[32] > 0) ? 1 : 0) - 2);
+                tot += 256 * cost_gk(g, k) + ex;
+            }
+            return tot;
+        };
+        // greedy: each fault to the wave where it adds least
+        for (int f = 0; f < nf; ++f) {
+            int best = -1;
+            long long bkey = 0;
+            for (int g = 0; g < nw; ++g) {
+                if (fill[g] >= capg[g]) continue;
+                const int before = cost_g(g);
+                add(g, f, 1);
+                const int after = cost_g(g);
+                add(g, f, -1);
+                const long long key = (long long)(after - before) * 4096 + fill[g];
+                if (best < 0 || key < bkey) {
+                    best = g;
+                    bkey = key;
+                }
+            }
+            member[(size_t)best * 64 + fill[best]++] = f;
+            add(best, f, 1);
+        }
+        // pairwise swaps between waves that do not raise the cost
+        const long long iters = 48ll * nf;
+        for (long long it = 0; it < iters && nf > 64; ++it) {
+            const int g1 = (int)rng.below((uint32_t)nw), g2 = (int)rng.below((uint32_t)nw);
+            if (g1 == g2 || fill[g1] == 0 || fill[g2] == 0) continue;
+            const int a = (int)rng.below((uint32_t)fill[g1]), b = (int)rng.below((uint32_t)fill[g2]);
+            const int f1 = member[(size_t)g1 * 64 + a], f2 = member[(size_t)g2 * 64 + b];
+            const int before = cost_g(g1) + cost_g(g2);
+            add(g1, f1, -1);
+            add(g2, f1, 1);
+            add(g2, f2, -1);
+            add(g1, f2, 1);
+            if (cost_g(g1) + cost_g(g2) <= before) {
+                member[(size_t)g1 * 64 + a] = f2;
+                member[(size_t)g2 * 64 + b] = f1;
+            } else {
+                add(g1, f2, -1);
+                add(g2, f2, 1);
+                add(g2, f1, -1);
+                add(g1, f1, 1);
+            }
+        }
+        // lanes within each wave: balance the check waves' bank loads
+        for (int g = 0; g < nw; ++g) {
+            std::vector<int> fs(member.begin() + (ptrdiff_t)g * 64, member.begin() + (ptrdiff_t)g * 64 + fill[g]);
+            auto degf = [&](int f) { const int32_t j = fo[(size_t)(base + f)]; return c->colptr[j + 1] - c->colptr[j]; };
+            std::stable_sort(fs.begin(), fs.end(), [&](int x, int y) { return degf(x) > degf(y); });
+            std::vector<char> used((size_t)capg[g], 0);
+            for (int f : fs) {
+                const int32_t j = fo[(size_t)(base + f)];
+                int best = -1;
+                long long bkey = 0;
+                for (int l = 0; l < capg[g]; ++l) {
+                    if (used[l]) continue;
+                    const int b = l % 32;
+                    long long over = LLONG_MIN, sum = 0;
+                    for (int64_t q = c->colptr[j]; q < c->colptr[j + 1]; ++q) {
+                        const int32_t i = c->rowidx[q];
+                        const int w = lane_of_edge[(size_t)(c->rowptr[i] + c->cpos[q])] / 64;
+                        const long long ld = load[(size_t)w * 32 + b];
+                        over = std::max(over, ld + 1 - 2ll * wdeg[w]);
+                        sum += ld;
+                    }
+                    const long long key = over * (1ll << 32) + sum;
+                    if (best < 0 || key < bkey) {
+                        best = l;
+                        bkey = key;
+                    }
+                }
+                used[best] = 1;
+                slot_col[(size_t)(base + 64 * g + best)] = j;
+                for (int64_t q = c->colptr[j]; q < c->colptr[j + 1]; ++q) {
+                    const int32_t i = c->rowidx[q];
+                    const int w = lane_of_edge[(size_t)(c->rowptr[i] + c->cpos[q])] / 64;
+                    ++load[(size_t)w * 32 + best % 32];
+                }
+            }
+        }
+    }
+    return slot_col;
+}
+
+// Edge order within the rows of each wave (free: the check update does not
+// depend on it).  Step k of a wave gathers Lambda of edge k of its 64 rows.
+// The order is a proper edge colouring, with wdeg colours (= steps), of the
+// bipartite multigraph lanes x (bank, copy), each bank split into two copies:
+// every step then reads at most two words per bank, the conflict-free rate.
+// Such a colouring exists when no bank carries more than 2 * wdeg of the
+// wave's edges (Koenig's edge-colouring theorem); it is built edge by edge,
+// swapping the two colours along an alternating path when the colours free
+// at the two ends differ.  An edge whose bank is full takes any free step.
+// epos[e] = step of CSR edge e; col16 = Lambda byte address per (thread, step).
+void order_rows(const rb_ctx *c, const rb::BlockShape &s, const std::vector<LaneSeg> &lanes,
+                const std::vector<int32_t> &wdeg, const std::vector<int32_t> &slot_of,
+                std::vector<int32_t> &epos, std::vector<uint16_t> &col16) {
+    const int nw = s.TPB / 64;
+    for (int w = 0; w < nw; ++w) {
+        const int D = wdeg[w];
+        if (D == 0) continue;
+        struct Ed {
+            int u, v;
+            int64_t e;
+        };
+        std::vector<Ed> ed;
+        int per_bank[32] = {0};
+        for (int l = 0; l < 64; ++l) {
+            const LaneSeg &g = lanes[(size_t)(64 * w + l)];
+            if (g.row < 0) continue;
+            for (int32_t q = g.b; q < g.e; ++q) {
+                const int64_t e = c->rowptr[g.row] + q;
+                const int b = slot_of[c->colidx[e]] & 31;
+                ed.push_back({l, 64 + 2 * b + (per_bank[b]++ & 1), e});
+            }
+        }
+        std::vector<int> at((size_t)128 * D, -1), col(ed.size(), -1);
+        auto free_at = [&](int x) {
+            for (int k = 0; k < D; ++k)
+                if (at[(size_t)x * D + k] < 0) return k;
+            return -1;
+        };
+        std::vector<int> path;
+        for (size_t q = 0; q < ed.size(); ++q) {
+            int u = ed[q].u, v = ed[q].v;
+            const int a = free_at(u);
+            int b = free_at(v);
+            if (b < 0) {
+                v ^= 1;  // the bank's other copy
+                b = free_at(v);
+                if (b < 0) continue;
+                ed[q].v = v;
+            }
+            int k = a;
+            if (at[(size_t)v * D + a] >= 0) {
+                if (at[(size_t)u * D + b] < 0) {
+                    k = b;
+                } else {
+                    // swap colours a and b along the alternating path from v
+                    path.clear();
+                    int x = v, cc = a;
+                    while (at[(size_t)x * D + cc] >= 0) {
+                        const int ej = at[(size_t)x * D + cc];
+                        path.push_back(ej);
+                        x = ed[ej].u == x ? ed[ej].v : ed[ej].u;
+                        cc = cc == a ? b : a;
+                    }
+                    for (int ej : path) {
+                        at[(size_t)ed[ej].u * D + col[ej]] = -1;
+                        at[(size_t)ed[ej].v * D + col[ej]] = -1;
+                    }
+                    for (int ej : path) {
+                        col[ej] = col[ej] == a ? b : a;
+                        at[(size_t)ed[ej].u * D + col[ej]] = ej;
+                        at[(size_t)ed[ej].v * D + col[ej]] = ej;
+                    }
+                }
+            }
+            col[q] = k;
+            at[(size_t)u * D + k] = (int)q;
+            at[(size_t)v * D + k] = (int)q;
+        }
+        for (size_t q = 0; q < ed.size(); ++q) {
+            if (col[q] < 0) {
+                col[q] = free_at(ed[q].u);
+                at[(size_t)ed[q].u * D + col[q]] = (int)q;
+            }
+            const int64_t e = ed[q].e;
+            epos[(size_t)e] = col[q];
+            col16[(size_t)(64 * w + ed[q].u) * s.DCMAX + col[q]] = (uint16_t)(4u * (uint32_t)slot_of[c->colidx[e]]);
+        }
+    }
+}
+
+// Host tables of the block kernel for one shape (no device work).
+struct BlockTables {
     std::vector<LaneSeg> lanes;
     std::vector<int32_t> wdeg, wbase;
+    BlockLayout lay{};
+    std::vector<int32_t> chk_row, chk_split, slot_col;
+    std::vector<uint16_t> col16, mu16;     // per thread: Lambda byte address per step; message words
+    std::vector<uint32_t> col_pk, mu_pk;  // the same, packed as the kernel reads them
+};
+
+BlockTables block_tables(const rb_ctx *c, const rb::BlockShape &s) {
+    BlockTables T;
+    std::vector<LaneSeg> &lanes = T.lanes;
+    std::vector<int32_t> &wdeg = T.wdeg, &wbase = T.wbase;
     int64_t words = 0;
     block_order(c, s, lanes, wdeg, wbase, words);
-    const BlockLayout lay = block_layout(s, words);
+    T.lay = block_layout(s, words);
+    const BlockLayout &lay = T.lay;
     // chk_row: the check whose syndrome bit thread t adds (first segment only);
     // chk_split: thread t shares its check with thread t ^ 1
-    std::vector<int32_t> chk_row((size_t)s.TPB, -1), chk_split((size_t)s.TPB, 0);
+    std::vector<int32_t> &chk_row = T.chk_row, &chk_split = T.chk_split;
+    chk_row.assign((size_t)s.TPB, -1);
+    chk_split.assign((size_t)s.TPB, 0);
     std::vector<int32_t> lane_of_edge((size_t)c->E, -1);
     for (int32_t t = 0; t < s.TPB; ++t) {
         const LaneSeg &g = lanes[(size_t)t];
@@ -378,54 +639,18 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
         chk_split[t] = g.split ? 1 : 0;
         for (int32_t q = g.b; q < g.e; ++q) lane_of_edge[(size_t)(c->rowptr[g.row] + q)] = t;
     }
-    // fault slots by decreasing column degree
-    const std::vector<int32_t> fo = fault_order(c);
-    std::vector<int32_t> slot_col((size_t)s.TPB * s.VPT, -1), slot_of((size_t)c->N);
-    for (int32_t q = 0; q < c->N; ++q) {
-        slot_col[q] = fo[q];
-        slot_of[fo[q]] = q;
-    }
+    T.slot_col = place_faults(c, s, lane_of_edge, wdeg, lay);
+    const std::vector<int32_t> &slot_col = T.slot_col;
+    std::vector<int32_t> slot_of((size_t)c->N, -1);
+    for (size_t q = 0; q < slot_col.size(); ++q)
+        if (slot_col[q] >= 0) slot_of[(size_t)slot_col[q]] = (int32_t)q;
     const int nmu = rb::prof_pre(s.prof, s.VPT);
     const int ncp = s.DCMAX / 2, nmp = (nmu + 1) / 2;
-    std::vector<uint16_t> col16((size_t)s.TPB * s.DCMAX, (uint16_t)lay.lampad_off);
-    std::vector<uint16_t> mu16((size_t)s.TPB * nmp * 2, (uint16_t)(lay.mupad_off / 4u));
-    // Edge order within each row (free: the check update does not depend on
-    // it).  Step k of a wave gathers Lambda of edge k of 64 rows at once; the
-    // edges are ordered greedily so that the 32 lanes of each half-wave hit
-    // distinct LDS banks (word address mod 32) as far as possible.
+    std::vector<uint16_t> &col16 = T.col16, &mu16 = T.mu16;
+    col16.assign((size_t)s.TPB * s.DCMAX, (uint16_t)lay.lampad_off);
+    mu16.assign((size_t)s.TPB * nmp * 2, (uint16_t)(lay.mupad_off / 4u));
     std::vector<int32_t> epos((size_t)c->E, 0);  // CSR edge -> message row k
-    {
-        const int nw = s.TPB / 64;
-        for (int w = 0; w < nw; ++w) {
-            std::vector<std::vector<int64_t>> left(64);
-            for (int l = 0; l < 64; ++l) {
-                const LaneSeg &g = lanes[(size_t)(64 * w + l)];
-                if (g.row < 0) continue;
-                for (int32_t q = g.b; q < g.e; ++q) left[l].push_back(c->rowptr[g.row] + q);
-            }
-            for (int k = 0; k < wdeg[w]; ++k)
-                for (int h = 0; h < 2; ++h) {
-                    int cnt[32] = {0};
-                    // lanes with the fewest edges left choose first
-                    int lanes[32];
-                    for (int q = 0; q < 32; ++q) lanes[q] = 32 * h + q;
-                    std::stable_sort(lanes, lanes + 32, [&](int x, int y) { return left[x].size() < left[y].size(); });
-                    for (int q = 0; q < 32; ++q) {
-                        const int l = lanes[q];
-                        if (left[l].empty()) continue;
-                        size_t best = 0;
-                        for (size_t u = 1; u < left[l].size(); ++u)
-                            if (cnt[slot_of[c->colidx[left[l][u]]] & 31] < cnt[slot_of[c->colidx[left[l][best]]] & 31])
-                                best = u;
-                        const int64_t e = left[l][best];
-                        left[l].erase(left[l].begin() + (std::ptrdiff_t)best);
-                        ++cnt[slot_of[c->colidx[e]] & 31];
-                        epos[(size_t)e] = k;
-                        col16[(size_t)(64 * w + l) * s.DCMAX + k] = (uint16_t)(4u * (uint32_t)slot_of[c->colidx[e]]);
-                    }
-                }
-        }
-    }
+    order_rows(c, s, lanes, wdeg, slot_of, epos, col16);
     for (int32_t t = 0; t < s.TPB; ++t)
         for (int v = 0; v < s.VPT; ++v) {
             const int32_t j = slot_col[(size_t)t + (size_t)s.TPB * v];
@@ -440,7 +665,9 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
         }
     // check table as [chunk][thread][4 words] (one 16-byte load per thread and
     // chunk of 8 edges, coalesced over a wave); fault table as [pair][thread]
-    std::vector<uint32_t> col_pk((size_t)ncp * s.TPB), mu_pk((size_t)nmp * s.TPB);
+    std::vector<uint32_t> &col_pk = T.col_pk, &mu_pk = T.mu_pk;
+    col_pk.assign((size_t)ncp * s.TPB, 0u);
+    mu_pk.assign((size_t)nmp * s.TPB, 0u);
     for (int32_t t = 0; t < s.TPB; ++t) {
         for (int e = 0; e < ncp; ++e) {
             const int ch = e / 4, d = e % 4;
@@ -452,11 +679,19 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
             mu_pk[(size_t)e * s.TPB + t] = (uint32_t)mu16[(size_t)t * nmp * 2 + 2 * e] |
                                           ((uint32_t)mu16[(size_t)t * nmp * 2 + 2 * e + 1] << 16);
     }
+    return T;
+}
+
+rb_status build_block_plan(rb_ctx *c, int bv) {
+    const rb::BlockShape s = rb::block_variant_shape(bv);
+    const BlockTables T = block_tables(c, s);
+    const BlockLayout &lay = T.lay;
+    const std::vector<int32_t> &slot_col = T.slot_col;
     rb_status st;
-    if ((st = upload(&c->d_lam_off, col_pk, "upload check table")) != RB_OK) return st;
-    if ((st = upload(&c->d_mu_off, mu_pk, "upload fault table")) != RB_OK) return st;
-    if ((st = upload(&c->d_chk_row, chk_row, "upload row map")) != RB_OK) return st;
-    if ((st = upload(&c->d_chk_split, chk_split, "upload split map")) != RB_OK) return st;
+    if ((st = upload(&c->d_lam_off, T.col_pk, "upload check table")) != RB_OK) return st;
+    if ((st = upload(&c->d_mu_off, T.mu_pk, "upload fault table")) != RB_OK) return st;
+    if ((st = upload(&c->d_chk_row, T.chk_row, "upload row map")) != RB_OK) return st;
+    if ((st = upload(&c->d_chk_split, T.chk_split, "upload split map")) != RB_OK) return st;
     if ((st = upload(&c->d_slot_col, slot_col, "upload slot map")) != RB_OK) return st;
     {
         const int npad = s.TPB * s.VPT, R = c->params.num_legs;
@@ -470,8 +705,8 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
                "gamma by slot");
         RB_HIP(hipDeviceSynchronize(), "gamma by slot");
     }
-    if ((st = upload(&c->d_wave_deg, wdeg, "upload wave degrees")) != RB_OK) return st;
-    if ((st = upload(&c->d_wave_base, wbase, "upload wave bases")) != RB_OK) return st;
+    if ((st = upload(&c->d_wave_deg, T.wdeg, "upload wave degrees")) != RB_OK) return st;
+    if ((st = upload(&c->d_wave_base, T.wbase, "upload wave bases")) != RB_OK) return st;
     {
         size_t st_lds = 0;
         RB_HIP(rb::block_static_lds(bv, &st_lds), "kernel attributes");

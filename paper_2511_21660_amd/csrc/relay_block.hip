@@ -70,21 +70,23 @@ __device__ __forceinline__ double block_sum(double x, uint32_t red) {
 }
 
 // OR of a predicate over the block (every thread gets the result); `flags` is
-// the byte address of TPB/64 words of LDS scratch.  One barrier: the caller
-// guarantees another barrier before the next call, so no wave can overwrite
-// a flag that another wave has still to read.  (The library's kernels
-// address LDS absolutely from 0 and must not use static LDS, so the runtime's
-// __syncthreads_or, which keeps its scratch in static LDS, is not used.)
+// the 16-byte aligned byte address of TPB/64 bytes of LDS scratch (zeroed at
+// kernel start), one byte per wave, read back as TPB/256 words.  One barrier:
+// the caller guarantees another barrier before the next call, so no wave can
+// overwrite a flag that another wave has still to read.  (The library's
+// kernels address LDS absolutely from 0 and must not use static LDS, so the
+// runtime's __syncthreads_or, which keeps its scratch in static LDS, is not
+// used.)
 template <int TPB>
 __device__ __forceinline__ bool block_or(bool pred, uint32_t flags) {
     const bool any = __any(pred);
     const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) lds_b<uint32_t>(flags + 4u * wave) = any ? 1u : 0u;
+    if ((threadIdx.x & 63) == 0) lds_b<uint8_t>(flags + (uint32_t)wave) = any ? 1 : 0;
     __syncthreads();
     uint32_t acc = 0;
 #pragma unroll
-    for (int w = 0; w < TPB / 64; ++w) acc |= lds_b<uint32_t>(flags + 4u * w);
-    return acc != 0;
+    for (int q = 0; q < TPB / 256; ++q) acc |= lds_b<uint32_t>(flags + 4u * (uint32_t)q);
+    return acc != 0u;
 }
 
 template <int TPB, int DCMAX, int VPT, uint64_t PROF, int WAVES, bool PRIOR, bool TRACE>
@@ -95,7 +97,7 @@ void relay_block_kernel(BlockArgs a) {
     constexpr int DV = prof_max(PROF, VPT);
     static_assert(TPB % 128 == 0 && CH == 8 && DCMAX % CH == 0 && DCMAX <= 64 && DV >= 1, "shape");
     const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
-    const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 words (block OR)
+    const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 bytes (block OR), 16-byte aligned
     const uint32_t shot_sh = flags + 4u * (TPB / 64);     // claimed shot index
     const int t = threadIdx.x;
     const int wave = t >> 6;
@@ -122,6 +124,7 @@ void relay_block_kernel(BlockArgs a) {
         lds_b<float>(a.lampad_off) = __int_as_float(0x7f800000);
         lds_b<float>(a.mupad_off) = __int_as_float(0x80000000);
     }
+    if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
     for (int q = t; q < (CH - 1) * 64; q += TPB) lds_b<float>(a.slack_off + 4u * q) = 0.0f;
 
     // Lambda of the thread's faults lives only in LDS (word j); it is read back
@@ -284,6 +287,11 @@ void relay_block_kernel(BlockArgs a) {
         if (conv_ev || leg_ev) {
             bool done = true;
             if (!TRACE) {
+                // (loads first, so their latencies overlap: the per-slot tables
+                // are padded to TPB * VPT entries)
+                float wv[VPT];
+#pragma unroll
+                for (int v = 0; v < VPT; ++v) wv[v] = a.w_slot[tl + TPB * v];
                 uint32_t fm = 0;
                 double part = 0.0;
 #pragma unroll
@@ -291,7 +299,7 @@ void relay_block_kernel(BlockArgs a) {
                     const uint32_t sl = tl + TPB * v;
                     if (sl < (uint32_t)a.N && lds_b<float>(4u * sl) < 0.0f) {
                         fm |= 1u << v;
-                        part += (double)a.w_slot[sl];
+                        part += (double)wv[v];
                     }
                 }
                 const double W = block_sum<TPB>(part, red);
@@ -307,10 +315,13 @@ void relay_block_kernel(BlockArgs a) {
                 }
                 if (done) {
                     const uint32_t out = count > 0 ? best_mask : fm;
+                    int jv[VPT];
+#pragma unroll
+                    for (int v = 0; v < VPT; ++v) jv[v] = a.slot_col[tl + TPB * v];
 #pragma unroll
                     for (int v = 0; v < VPT; ++v) {
                         const uint32_t sl = tl + TPB * v;
-                        const int j = a.slot_col[sl];
+                        const int j = jv[v];
                         if (j >= 0) {
                             a.corr[(size_t)shot * a.N + j] = (uint8_t)((out >> v) & 1u);
                             if (a.final_llr)
@@ -328,16 +339,21 @@ void relay_block_kernel(BlockArgs a) {
             if (!done) {
                 ++r;
                 tt = 0;
+                // every slot, spare ones included (their gamma and w are 0 and
+                // their Lambda stays 0), so the loads are issued together
                 const float *gr = a.gamma_slot + (size_t)(r - 1) * (TPB * VPT);
+                float gv[VPT], w0[VPT];
+#pragma unroll
+                for (int v = 0; v < VPT; ++v) {
+                    gv[v] = gr[tl + TPB * v];
+                    w0[v] = PRIOR ? a.w_slot[tl + TPB * v] : 0.0f;
+                }
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
                     const uint32_t sl = tl + TPB * v;
-                    if (sl < (uint32_t)a.N) {
-                        const float g = gr[sl];
-                        const float l0 = PRIOR ? a.scale * a.w_slot[sl] : clipb(lds_b<float>(4u * sl), L);
-                        gm[v] = g;
-                        xl[v] = (1.0f - g) * l0;
-                    }
+                    const float l0 = PRIOR ? a.scale * w0[v] : clipb(lds_b<float>(4u * sl), L);
+                    gm[v] = gv[v];
+                    xl[v] = (1.0f - gv[v]) * l0;
                 }
                 zero_row();
             } else {
@@ -348,30 +364,28 @@ void relay_block_kernel(BlockArgs a) {
         }
 
         // ---------------- fault pass
-        // Software-pipelined by one fault: the gathers of slot v+1 are issued
-        // before slot v's sum is stored (the stores go to the Lambda words,
-        // which no gather reads).  Band v gathers prof_dv(PROF, v) messages;
-        // a fault of smaller degree reads the -0 cell for the rest.
+        // Software-pipelined FD faults deep: the gathers of slot v+FD are
+        // issued before slot v's sum is stored (the stores go to the Lambda
+        // words of earlier slots, which no later load reads).  Band v gathers
+        // prof_dv(PROF, v) messages; a fault of smaller degree reads the -0
+        // cell for the rest.
+        constexpr int FD = 2;
         auto mu_word = [&](int e) -> uint32_t {
             return ((e & 1) ? (mu_pk[e >> 1] >> 16) : (mu_pk[e >> 1] & 0xffffu)) << 2;
         };
-        float nv[DV], lam_n;
+        float gv[FD + 1][DV], gl[FD + 1];
+        auto load_slot = [&](int v, float(&m)[DV], float &l) {
 #pragma unroll
-        for (int k = 0; k < prof_dv(PROF, 0); ++k) nv[k] = lds_b<float>(mu_word(k));
-        lam_n = lds_b<float>(4u * tl);
+            for (int k = 0; k < prof_dv(PROF, v); ++k) m[k] = lds_b<float>(mu_word(prof_pre(PROF, v) + k));
+            l = lds_b<float>(4u * (tl + TPB * v));
+        };
+#pragma unroll
+        for (int v = 0; v < FD && v < VPT; ++v) load_slot(v, gv[v], gl[v]);
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
-            float mv[DV];
-#pragma unroll
-            for (int k = 0; k < prof_dv(PROF, v); ++k) mv[k] = nv[k];
-            const float lam = lam_n;
-            if (v + 1 < VPT) {
-#pragma unroll
-                for (int k = 0; k < prof_dv(PROF, v + 1); ++k)
-                    nv[k] = lds_b<float>(mu_word(prof_pre(PROF, v + 1) + k));
-                lam_n = lds_b<float>(4u * (tl + TPB * (v + 1)));
-            }
-            const float y = gm[v] * clipb(lam, L);
+            if (v + FD < VPT) load_slot(v + FD, gv[(v + FD) % (FD + 1)], gl[(v + FD) % (FD + 1)]);
+            const float(&mv)[DV] = gv[v % (FD + 1)];
+            const float y = gm[v] * clipb(gl[v % (FD + 1)], L);
             float acc = clipb(xl[v] + y, L);
 #pragma unroll
             for (int k = 0; k < prof_dv(PROF, v); ++k) acc += mv[k];
