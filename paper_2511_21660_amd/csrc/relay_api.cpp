@@ -275,21 +275,60 @@ void block_order(const rb_ctx *c, const rb::BlockShape &s, std::vector<LaneSeg> 
     const int ng = ceil_div((int)seq.size(), 64);
     std::vector<int32_t> gdeg((size_t)ng, 0);
     for (size_t q = 0; q < seq.size(); ++q) gdeg[q / 64] = std::max(gdeg[q / 64], seq[q].e - seq[q].b);
-    // greedy placement of the groups (largest first) on the least loaded SIMD
+    // Steps the check pass runs for a group of row length d: chunks of
+    // kBlockChunk edges, the last one half as wide when at most half remains.
+    auto steps = [](int d) {
+        int n = 0;
+        for (int c = 0; c < d; c += rb::kBlockChunk) n += (c + rb::kBlockChunk / 2 >= d) ? rb::kBlockChunk / 2 : rb::kBlockChunk;
+        return n;
+    };
+    // Groups onto SIMDs: largest first onto the least loaded SIMD, then
+    // pairwise swaps between SIMDs while they lower the largest load (then
+    // the sum of squared loads).  Within a SIMD the longest group takes the
+    // lowest wave index (the wave that the hardware favours when issuing).
     std::vector<int> gorder((size_t)ng);
     for (int g = 0; g < ng; ++g) gorder[g] = g;
     std::stable_sort(gorder.begin(), gorder.end(), [&](int x, int y) { return gdeg[x] > gdeg[y]; });
-    std::vector<int> group_of_wave((size_t)nw, -1);
+    std::vector<std::vector<int>> on((size_t)4);
     int64_t load[4] = {0, 0, 0, 0};
-    int used[4] = {0, 0, 0, 0};
     for (int g : gorder) {
         int best = -1;
         for (int q = 0; q < 4; ++q)
-            if (used[q] < nw / 4 && (best < 0 || load[q] < load[best])) best = q;
+            if ((int)on[q].size() < nw / 4 && (best < 0 || load[q] < load[best])) best = q;
         if (best < 0) break;  // more groups than waves: caller rejects (words stays small)
-        group_of_wave[(size_t)(best + 4 * used[best])] = g;
-        load[best] += ceil_div(gdeg[g], rb::kBlockChunk);
-        ++used[best];
+        on[best].push_back(g);
+        load[best] += steps(gdeg[g]);
+    }
+    auto score = [&](const int64_t *l) {
+        int64_t mx = 0, sq = 0;
+        for (int q = 0; q < 4; ++q) {
+            mx = std::max(mx, l[q]);
+            sq += l[q] * l[q];
+        }
+        return mx * (int64_t)1000000 + sq;
+    };
+    for (bool improved = true; improved;) {
+        improved = false;
+        for (int q1 = 0; q1 < 4; ++q1)
+            for (int q2 = q1 + 1; q2 < 4; ++q2)
+                for (size_t a1 = 0; a1 < on[q1].size(); ++a1)
+                    for (size_t a2 = 0; a2 < on[q2].size(); ++a2) {
+                        const int64_t d = steps(gdeg[on[q1][a1]]) - steps(gdeg[on[q2][a2]]);
+                        if (d == 0) continue;
+                        int64_t l2[4] = {load[0], load[1], load[2], load[3]};
+                        l2[q1] -= d;
+                        l2[q2] += d;
+                        if (score(l2) < score(load)) {
+                            std::swap(on[q1][a1], on[q2][a2]);
+                            for (int q = 0; q < 4; ++q) load[q] = l2[q];
+                            improved = true;
+                        }
+                    }
+    }
+    std::vector<int> group_of_wave((size_t)nw, -1);
+    for (int q = 0; q < 4; ++q) {
+        std::stable_sort(on[q].begin(), on[q].end(), [&](int x, int y) { return gdeg[x] > gdeg[y]; });
+        for (size_t u = 0; u < on[q].size(); ++u) group_of_wave[(size_t)q + 4 * u] = on[q][u];
     }
     lanes.assign((size_t)s.TPB, LaneSeg{});
     wdeg.assign((size_t)nw, 0);
@@ -373,6 +412,91 @@ struct PlanRng {
         return (uint32_t)(z % n);
     }
 };
+
+// Check lanes within each wave (free: a wave's rows may sit on any of its
+// lanes, a split check on an aligned lane pair).  The fault pass's k-th
+// gather of band v reads, for every fault of the band, the message of its k-th
+// check, whose LDS bank is the owning lane mod 32; lanes are swapped within
+// waves (pairs with pairs, single lanes with single lanes) so that, for every
+// (band, k), the banks of these messages are as evenly spread as possible,
+// which is what place_faults needs to reach two words per bank.
+void spread_check_lanes(const rb_ctx *c, const rb::BlockShape &s, std::vector<LaneSeg> &lanes) {
+    const int TPB = s.TPB, nw = TPB / 64, D = rb::prof_max(s.prof, s.VPT);
+    const std::vector<int32_t> fo = fault_order(c);
+    std::vector<int32_t> band((size_t)c->N);
+    for (int64_t q = 0; q < c->N; ++q) band[(size_t)fo[(size_t)q]] = (int32_t)(q / TPB);
+    // per CSR edge: histogram row (band * D + k) of the fault-side gather
+    std::vector<int32_t> hrow((size_t)c->E, -1);
+    for (int32_t j = 0; j < c->N; ++j)
+        for (int64_t q = c->colptr[j]; q < c->colptr[j + 1] && q - c->colptr[j] < D; ++q)
+            hrow[(size_t)(c->rowptr[c->rowidx[q]] + c->cpos[q])] = band[j] * D + (int32_t)(q - c->colptr[j]);
+    std::vector<int64_t> hist((size_t)s.VPT * D * 32, 0);
+    auto apply = [&](const LaneSeg &g, int lane, int d) {
+        if (g.row < 0) return;
+        for (int32_t q = g.b; q < g.e; ++q) {
+            const int32_t h = hrow[(size_t)(c->rowptr[g.row] + q)];
+            if (h >= 0) hist[(size_t)h * 32 + (lane & 31)] += d;
+        }
+    };
+    // change of sum(hist^2) if segment g moves from lane a to lane b
+    auto delta = [&](const LaneSeg &g, int a, int b) {
+        int64_t dd = 0;
+        if (g.row < 0 || (a & 31) == (b & 31)) return dd;
+        for (int32_t q = g.b; q < g.e; ++q) {
+            const int32_t h = hrow[(size_t)(c->rowptr[g.row] + q)];
+            if (h < 0) continue;
+            int64_t &x = hist[(size_t)h * 32 + (a & 31)], &y = hist[(size_t)h * 32 + (b & 31)];
+            dd += (x - 1) * (x - 1) - x * x + (y + 1) * (y + 1) - y * y;
+            --x;
+            ++y;
+        }
+        for (int32_t q = g.b; q < g.e; ++q) {  // undo
+            const int32_t h = hrow[(size_t)(c->rowptr[g.row] + q)];
+            if (h < 0) continue;
+            ++hist[(size_t)h * 32 + (a & 31)];
+            --hist[(size_t)h * 32 + (b & 31)];
+        }
+        return dd;
+    };
+    for (int t = 0; t < TPB; ++t) apply(lanes[(size_t)t], t, 1);
+    PlanRng rng{0xC0FFEEull};
+    const int64_t iters = 64ll * TPB;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int w = (int)rng.below((uint32_t)nw);
+        int a = (int)rng.below(64), b = (int)rng.below(64);
+        const LaneSeg &ga = lanes[(size_t)(64 * w + a)], &gb = lanes[(size_t)(64 * w + b)];
+        if (ga.split != gb.split || a == b) continue;
+        if (ga.split) {  // move whole pairs
+            a &= ~1;
+            b &= ~1;
+            if (a == b) continue;
+        }
+        const int width = ga.split ? 2 : 1;
+        int64_t dd = 0;
+        for (int u = 0; u < width; ++u) {
+            // apply each half's move before scoring the next (halves share no edge)
+            const LaneSeg &x = lanes[(size_t)(64 * w + a + u)], &y = lanes[(size_t)(64 * w + b + u)];
+            const int64_t d1 = delta(x, 64 * w + a + u, 64 * w + b + u);
+            apply(x, 64 * w + a + u, -1);
+            apply(x, 64 * w + b + u, 1);
+            const int64_t d2 = delta(y, 64 * w + b + u, 64 * w + a + u);
+            apply(y, 64 * w + b + u, -1);
+            apply(y, 64 * w + a + u, 1);
+            dd += d1 + d2;
+        }
+        if (dd <= 0) {
+            for (int u = 0; u < width; ++u) std::swap(lanes[(size_t)(64 * w + a + u)], lanes[(size_t)(64 * w + b + u)]);
+        } else {
+            for (int u = 0; u < width; ++u) {
+                const LaneSeg &x = lanes[(size_t)(64 * w + a + u)], &y = lanes[(size_t)(64 * w + b + u)];
+                apply(y, 64 * w + a + u, -1);
+                apply(y, 64 * w + b + u, 1);
+                apply(x, 64 * w + b + u, -1);
+                apply(x, 64 * w + a + u, 1);
+            }
+        }
+    }
+}
 
 // Fault slots.  Band v holds the faults of degree rank [v*TPB, (v+1)*TPB)
 // (fault_order), so slots below N are exactly the real ones.  Within a band
@@ -624,6 +748,7 @@ BlockTables block_tables(const rb_ctx *c, const rb::BlockShape &s) {
     std::vector<int32_t> &wdeg = T.wdeg, &wbase = T.wbase;
     int64_t words = 0;
     block_order(c, s, lanes, wdeg, wbase, words);
+    spread_check_lanes(c, s, lanes);
     T.lay = block_layout(s, words);
     const BlockLayout &lay = T.lay;
     // chk_row: the check whose syndrome bit thread t adds (first segment only);
