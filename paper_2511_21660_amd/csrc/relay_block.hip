@@ -427,7 +427,9 @@ struct BlockVariant {
 // first that fits.
 const BlockVariant kBlockVariants[] = {
     // M <= 1024, N <= 9216, degrees sorted like a circuit-level DEM (weights
-    // 2..6, mostly 2 and 3), e.g. 936 x 8785: caps 6,6,5,4,3,3,3,2,2
+    // 2..6, mostly 2 and 3): band caps 6,5,4,3,3,3,2,2,2 (exactly those of the
+    // 936 x 8785 matrix), then a looser profile 6,6,5,4,3,3,3,2,2
+    RB_BVARIANT(1024, 64, 9, 0x222333456ull, 4),
     RB_BVARIANT(1024, 64, 9, 0x223334566ull, 4),
     RB_BVARIANT(1024, 64, 9, 0x666666666ull, 4),  // M <= 1024, N <= 9216, degree <= 6
     RB_BVARIANT(1024, 32, 4, 0x8888ull, 4),       // M <= 1024, N <= 4096, degree <= 8
