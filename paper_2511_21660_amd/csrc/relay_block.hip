@@ -116,8 +116,10 @@ void relay_block_kernel(BlockArgs a) {
     const int myrow = a.chk_row[t];           // check whose syndrome bit this thread adds, or -1
     const bool split = a.chk_split[t] != 0;   // shares its check with thread t ^ 1
     const bool first_half = (t & 1) == 0;
-    // row length of this wave (uniform: read back as a scalar)
-    const int wdeg = __builtin_amdgcn_readfirstlane(a.wave_deg[wave]);
+    // row length of this wave (uniform: read back as a scalar; made opaque
+    // at the top of every iteration so that the chunk conditions derived from
+    // it are recomputed by scalar compares rather than kept live in SGPRs)
+    int wdeg = __builtin_amdgcn_readfirstlane(a.wave_deg[wave]);
     const uint32_t mrow = a.mu0_off + 4u * ((uint32_t)a.wave_base[wave] + (uint32_t)(t & 63));
 
     if (t == 0) {
@@ -184,6 +186,7 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
         for (int e = 0; e < (NMU + 1) / 2; ++e) opaque_b(mu_pk[e]);
         opaque_b(tl);
+        asm volatile("" : "+s"(wdeg));
 
         // ---------------- check pass
         // pass 1: nu = clip(Lambda - mu_old) per edge; min1, min2 and the
@@ -297,10 +300,9 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
                     const uint32_t sl = tl + TPB * v;
-                    if (sl < (uint32_t)a.N && lds_b<float>(4u * sl) < 0.0f) {
-                        fm |= 1u << v;
-                        part += (double)wv[v];
-                    }
+                    const bool f = sl < (uint32_t)a.N && lds_b<float>(4u * sl) < 0.0f;
+                    fm |= f ? 1u << v : 0u;
+                    part += (double)(f ? wv[v] : 0.0f);  // + 0 leaves the sum's bits unchanged
                 }
                 const double W = block_sum<TPB>(part, red);
                 if (conv_ev) {
