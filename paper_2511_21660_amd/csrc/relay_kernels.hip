@@ -151,7 +151,10 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     const int slot = lane / G;
     uint32_t gl = (uint32_t)g;  // lane in slot, made opaque inside the loop
     const uint32_t base = 4u * (uint32_t)slot;     // word 0 of this slot
-    const uint32_t mu_row0 = base + a.mu0_off + WORD * RS * (uint32_t)g;  // row of check g
+    // row of check g; made opaque inside the loop like the tables, so that its
+    // constant row offsets fold into the LDS instructions instead of being
+    // hoisted into registers of their own
+    uint32_t mu_row0 = base + a.mu0_off + WORD * RS * (uint32_t)g;
     const uint32_t lam_w0 = base + WORD * (uint32_t)g;                    // Lambda of fault g
     const unsigned long long gmask =
         (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (uint32_t)(slot * G));
@@ -254,6 +257,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
         for (int e = 0; e < NMP; ++e) opaque(mu_pk[e]);
         opaque(gl);
+        opaque(mu_row0);
         // ---------------- check pass: mu(t+1) from Lambda(t), mu(t); parity of F(t)
         bool mism = false;
         if (active) {
