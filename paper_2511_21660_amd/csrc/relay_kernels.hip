@@ -207,15 +207,47 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
             for (int k = 0; k < DC; ++k) lds_at<float>(lds, mu_row0 + c * ROW_STRIDE + WORD * k) = 0.0f;
     };
 
-    // claim the next syndrome for this slot and initialise leg 1
+    // sum of w_j over the lane's faults with Lambda_j < 0 (FP64, over the
+    // slot's G lanes) and the decision bits; the loads are unconditional
+    // (indices clamped) so they issue together, and adding +0 for the other
+    // faults leaves the sum's bits unchanged
+    auto weight_of = [&](uint32_t &fm) -> double {
+        float wv[VPT];
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) wv[v] = a.w[min((int)gl + G * v, a.N - 1)];
+        double part = 0.0;
+        fm = 0;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const bool f = (int)gl + G * v < a.N && Lr[v] < 0.0f;
+            fm |= f ? 1u << v : 0u;
+            part += (double)(f ? wv[v] : 0.0f);
+        }
+        return group_sum<G>(part);
+    };
+
+    // Take the next syndrome for this slot and initialise leg 1.  Queue
+    // indices are claimed one ahead: lane 0 of the slot holds the index
+    // claimed at the previous fetch (its atomic has long completed) and claims
+    // the following one, so no fetch waits on the queue atomic.
+    unsigned long long claim = 0;
+    if (g == 0) claim = atomicAdd(a.queue, 1ull);
     auto fetch = [&]() {
-        unsigned long long nxt = 0;
-        if (g == 0) nxt = atomicAdd(a.queue, 1ull);
-        nxt = __shfl(nxt, 0, G);
+        // w and gamma of leg 1 do not depend on the shot: issue their loads
+        // first (indices clamped, so every load is in bounds)
+        float wv[VPT], gv[VPT];
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int j = min((int)gl + G * v, a.N - 1);
+            wv[v] = a.w[j];
+            gv[v] = TRACE ? a.trace_gamma[j] : a.gamma[j];
+        }
+        const unsigned long long nxt = __shfl(claim, 0, G);
         if (nxt >= (unsigned long long)a.count) {
             active = false;
             return;
         }
+        if (g == 0) claim = atomicAdd(a.queue, 1ull);
         active = true;
         shot = a.list ? (long long)a.list[nxt] : (long long)nxt;
         r = 1;
@@ -226,18 +258,21 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         best_mask = 0;
         sig = 0;
         const uint8_t *s = a.syn + (size_t)shot * a.syn_stride;
+        uint8_t sb[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) sb[c] = s[min((int)gl + G * c, a.M - 1)];
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int i = (int)gl + G * c;
-            if (i < a.M && s[i]) sig |= 1u << c;
+            if (i < a.M && sb[c]) sig |= 1u << c;
         }
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const int j = (int)gl + G * v;
             float wj = 0.0f, gj = 0.0f;
             if (j < a.N) {
-                wj = a.scale * a.w[j];
-                gj = TRACE ? a.trace_gamma[j] : a.gamma[j];
+                wj = a.scale * wv[v];
+                gj = gv[v];
                 lds_at<float>(lds, base + WORD * j) = wj;
                 if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
             }
@@ -311,23 +346,14 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         const bool event = conv_ev || leg_ev;
         if (event) {
             bool done = true;
+            uint32_t fm_conv = 0;
             if (!TRACE) {
                 if (conv_ev) {
                     ++count;
-                    double part = 0.0;
-                    uint32_t fm = 0;
-#pragma unroll
-                    for (int v = 0; v < VPT; ++v) {
-                        const int j = (int)gl + G * v;
-                        if (j < a.N && Lr[v] < 0.0f) {
-                            part += (double)a.w[j];
-                            fm |= 1u << v;
-                        }
-                    }
-                    const double W = group_sum<G>(part);
+                    const double W = weight_of(fm_conv);
                     if (W < best_w) {
                         best_w = W;
-                        best_mask = fm;
+                        best_mask = fm_conv;
                     }
                     done = count >= a.num_solutions || r >= a.num_legs || cut;
                 } else {
@@ -338,29 +364,30 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 // chain to leg r+1: restart check messages, new Gamma, new anchor
                 ++r;
                 t = 0;
+                // (indices clamped so every load is in bounds and all issue
+                // together; lanes past N keep their values)
                 const float *gr = a.gamma + (size_t)(r - 1) * a.N;
+                float gv[VPT], wv[VPT];
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
-                    const int j = (int)gl + G * v;
-                    if (j < a.N) {
-                        gm[v] = gr[j];
-                        l0[v] = PRIOR ? a.scale * a.w[j] : clipf(Lr[v], L);
+                    const int j = min((int)gl + G * v, a.N - 1);
+                    gv[v] = gr[j];
+                    wv[v] = PRIOR ? a.w[j] : 0.0f;
+                }
+#pragma unroll
+                for (int v = 0; v < VPT; ++v) {
+                    if ((int)gl + G * v < a.N) {
+                        gm[v] = gv[v];
+                        l0[v] = PRIOR ? a.scale * wv[v] : clipf(Lr[v], L);
                     }
                 }
                 zero_rows();
             } else {
                 if (!TRACE) {
+                    // the last decision and its weight are the output only when
+                    // no leg converged
                     uint32_t fm = 0;
-                    double part = 0.0;
-#pragma unroll
-                    for (int v = 0; v < VPT; ++v) {
-                        const int j = (int)gl + G * v;
-                        if (j < a.N && Lr[v] < 0.0f) {
-                            fm |= 1u << v;
-                            part += (double)a.w[j];
-                        }
-                    }
-                    const double Wlast = group_sum<G>(part);
+                    const double Wlast = count > 0 ? best_w : weight_of(fm);
                     const uint32_t out = count > 0 ? best_mask : fm;
 #pragma unroll
                     for (int v = 0; v < VPT; ++v) {
