@@ -82,6 +82,9 @@ struct rb_ctx {
     std::vector<rb_ctx *> subs;
     rb::CodeStatic *d_codes = nullptr;
     unsigned long long *d_queues = nullptr;
+    // families: codes with the same graph and tile (one shot list each)
+    int32_t nfam = 0;
+    int32_t *d_code_fam = nullptr, *d_fam_rep = nullptr, *d_fam_size = nullptr;
     int32_t m_max = 0, n_max = 0;
     // CSR / CSC on the device (training kernels)
     int32_t *d_rowptr = nullptr, *d_colidx = nullptr, *d_colptr = nullptr, *d_cedge = nullptr;
@@ -1025,7 +1028,7 @@ rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32
     if ((e = hipMalloc(&c->d_w, sizeof(float) * (size_t)N)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(w)"));
     if ((e = hipMalloc(&c->d_gamma, sizeof(float) * (size_t)N * (size_t)R)) != hipSuccess)
         return bail(hip_fail(e, "hipMalloc(gamma)"));
-    if ((e = hipMalloc(&c->d_queue, sizeof(unsigned long long))) != hipSuccess)
+    if ((e = hipMalloc(&c->d_queue, sizeof(unsigned long long) * rb::kQueueWords)) != hipSuccess)
         return bail(hip_fail(e, "hipMalloc(queue)"));
     if ((e = hipMemcpy(c->d_w, c->w.data(), sizeof(float) * (size_t)N, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(hip_fail(e, "copy w"));
@@ -1075,13 +1078,16 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_colptr);
         (void)hipFree(c->d_cedge);
     }
-    if (c->d_ws || c->d_code_m || c->d_codes || c->d_queues) {
+    if (c->d_ws || c->d_code_m || c->d_codes || c->d_queues || c->d_code_fam || c->d_fam_rep || c->d_fam_size) {
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();
         (void)hipFree(c->d_ws);
         (void)hipFree(c->d_code_m);
         (void)hipFree(c->d_codes);
         (void)hipFree(c->d_queues);
+        (void)hipFree(c->d_code_fam);
+        (void)hipFree(c->d_fam_rep);
+        (void)hipFree(c->d_fam_size);
     }
     for (rb_ctx *s : c->subs) rb_destroy(s);
     delete c;
@@ -1203,7 +1209,7 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
         // longest-first order: shot list sorted by decreasing syndrome weight
         hipStream_t s = (hipStream_t)stream;
         RB_HIP(hipSetDevice(c->device), "hipSetDevice");
-        RB_HIP(rb::launch_shot_lists(B, d_syn, c->M, nullptr, c->d_code_m, 1, c->d_ws, c->d_queue, s),
+        RB_HIP(rb::launch_shot_lists(B, d_syn, c->M, nullptr, c->d_code_m, 1, nullptr, 1, c->d_ws, c->d_queue, s),
                "shot list kernels");
         a.list = (const int32_t *)c->d_ws + (size_t)(rb::kListHeader + B);
         RB_HIP(rb::launch_group(c->variant, c->params.anchor == RB_ANCHOR_PRIOR, false, a,
@@ -1550,6 +1556,29 @@ rb_status upload_codes(rb_ctx *m) {
     }
     rb_status st = upload(&m->d_codes, cs, "upload code table");
     if (st != RB_OK) return st;
+    // families: same tile and the same graph (identical CSR), hence identical
+    // gather tables and LDS layout; members differ only in w and gamma
+    std::vector<int32_t> fam(m->subs.size(), -1), rep, size;
+    for (size_t k = 0; k < m->subs.size(); ++k) {
+        const rb_ctx *a = m->subs[k];
+        for (size_t f = 0; f < rep.size() && fam[k] < 0; ++f) {
+            const rb_ctx *b = m->subs[(size_t)rep[f]];
+            if (cs[k].tile == cs[(size_t)rep[f]].tile && a->M == b->M && a->N == b->N && a->rowptr == b->rowptr &&
+                a->colidx == b->colidx) {
+                fam[k] = (int32_t)f;
+                ++size[f];
+            }
+        }
+        if (fam[k] < 0) {
+            fam[k] = (int32_t)rep.size();
+            rep.push_back((int32_t)k);
+            size.push_back(1);
+        }
+    }
+    m->nfam = (int32_t)rep.size();
+    if ((st = upload(&m->d_code_fam, fam, "upload code families")) != RB_OK) return st;
+    if ((st = upload(&m->d_fam_rep, rep, "upload family members")) != RB_OK) return st;
+    if ((st = upload(&m->d_fam_size, size, "upload family sizes")) != RB_OK) return st;
     m->lds_bytes = lds;
     int blocks = 0;
     RB_HIP(rb::mixed_occupancy(m->params.anchor == RB_ANCHOR_PRIOR, (size_t)lds, &blocks), "occupancy query");
@@ -1614,7 +1643,7 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
         rb_destroy(m);
         return st;
     }
-    hipError_t e = hipMalloc(&m->d_queues, sizeof(unsigned long long) * (size_t)n_codes);
+    hipError_t e = hipMalloc(&m->d_queues, sizeof(unsigned long long) * rb::kQueueWords * (size_t)n_codes);
     if (e != hipSuccess) {
         rb_destroy(m);
         return hip_fail(e, "hipMalloc(queues)");
@@ -1638,7 +1667,8 @@ rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const 
     if (workspace_bytes < rb::shot_list_bytes(B, nc)) return fail(RB_E_WORKSPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
-    RB_HIP(rb::launch_shot_lists(B, d_syn, c->m_max, d_code_id, c->d_code_m, nc, d_workspace, c->d_queues, s),
+    RB_HIP(rb::launch_shot_lists(B, d_syn, c->m_max, d_code_id, c->d_code_m, nc, c->d_code_fam, c->nfam,
+                                 d_workspace, c->d_queues, s),
            "shot list kernels");
     rb::MixedArgs m{};
     m.run = base_args(c->subs[0], B, d_syn);
@@ -1652,6 +1682,10 @@ rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const 
     m.run.final_llr = d_final_llr;
     m.codes = c->d_codes;
     m.ncodes = nc;
+    m.nfam = c->nfam;
+    m.fam_rep = c->d_fam_rep;
+    m.fam_size = c->d_fam_size;
+    m.code_id = d_code_id;
     const int32_t *ws = (const int32_t *)d_workspace;
     m.seg_start = ws + (size_t)nc * rb::kWeightBinsHost;
     m.seg_count = m.seg_start + nc;

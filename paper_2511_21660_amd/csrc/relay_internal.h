@@ -17,6 +17,17 @@ struct TileShape {
 };
 
 // Arguments of the group kernel (passed by value).
+struct CodeStatic;
+
+// Work queues of the group kernels: kQueueSplit counters, kQueueStride
+// unsigned long longs (256 bytes) apart; slot s claims positions
+// s % kQueueSplit + kQueueSplit * n from counter s % kQueueSplit, which spreads
+// the claims of thousands of slots over several L2 atomic units.  The block
+// kernel uses counter 0 alone.  A queue occupies kQueueWords words.
+constexpr int kQueueSplit = 4;
+constexpr int kQueueStride = 32;
+constexpr int kQueueWords = kQueueSplit * kQueueStride;
+
 struct GroupArgs {
     int32_t M, N;
     int32_t syn_stride, corr_stride;  // bytes per syndrome row, entries per correction row
@@ -32,12 +43,16 @@ struct GroupArgs {
     float *final_llr;     // [B][N] or null
     const float *w;       // [N] channel LLRs
     const float *gamma;   // [R][N] memory strengths, row r-1 = leg r
+    // codes sharing one graph (mixed launch): when code_id is set, the shot's
+    // own code, codes[code_id[shot]], supplies w and gamma
+    const int32_t *code_id;
+    const CodeStatic *codes;
     // per-lane gather tables, two 16-bit slot-relative LDS byte offsets per
     // word: lane g's entries e = c*DC + k (Lambda of check edge) and
     // e = v*DV + k (mu of fault edge) at word g*ceil(n/2) + e/2, half e%2
     const uint32_t *lam_off;  // [G][ceil(CPT*DC/2)]
     const uint32_t *mu_off;   // [G][ceil(VPT*DV/2)]
-    unsigned long long *queue;  // next unclaimed shot
+    unsigned long long *queue;  // work queue (kQueueWords counters, see below)
     int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
     float L;
     // LDS offsets in interleaved form (slot word w -> byte 4 * w * NS; the
@@ -150,11 +165,18 @@ struct MixedArgs {
     GroupArgs run;  // outputs, strides (M_max, N_max), relay parameters
     const CodeStatic *codes;
     int32_t ncodes;
+    // families: codes with the same graph and tile share one shot list and
+    // queue; fam_rep[f] is a member whose tables the family uses, fam_size[f]
+    // its number of members
+    int32_t nfam;
+    const int32_t *fam_rep;
+    const int32_t *fam_size;
+    const int32_t *code_id;    // [B] code of each shot
     const int32_t *list;       // shot lists, all codes
-    const int32_t *seg_start;  // [ncodes] (device, written by the list kernels)
-    const int32_t *seg_count;  // [ncodes]
-    const int32_t *order;      // [ncodes] code visiting order (device, written by the list kernels)
-    unsigned long long *queues;  // [ncodes]
+    const int32_t *seg_start;  // [nfam] (device, written by the list kernels)
+    const int32_t *seg_count;  // [nfam]
+    const int32_t *order;      // [nfam] family visiting order (device, written by the list kernels)
+    unsigned long long *queues;  // [nfam]
 };
 
 int num_variants();
@@ -171,13 +193,15 @@ hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_f
                               float hi, hipStream_t s);
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s);
 // Builds per-code shot lists in `workspace` (shot_list_bytes(B, ncodes) bytes):
-// positions sorted by (code, decreasing syndrome weight); the list of code c
-// starts at list + seg_start[c] and holds seg_count[c] shots.  Also zeroes the
-// per-code queue counters.  Layout: hist[ncodes*256], seg_start[ncodes],
-// seg_count[ncodes], order[ncodes], key[B], list[B] (int32).
+// positions sorted by (family, decreasing syndrome weight), the family of
+// code c being code_fam[c] (identity when code_fam is null); the list of
+// family f starts at list + seg_start[f] and holds seg_count[f] shots.  Also
+// zeroes the per-family queue counters.  Layout (sized for ncodes >= nfam):
+// hist[ncodes*256], seg_start[ncodes], seg_count[ncodes], order[ncodes],
+// key[B], list[B] (int32).
 hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
-                             const int32_t *code_m, int ncodes, void *workspace,
-                             unsigned long long *queues, hipStream_t s);
+                             const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam,
+                             void *workspace, unsigned long long *queues, hipStream_t s);
 size_t shot_list_bytes(int64_t B, int ncodes);
 constexpr int kWeightBinsHost = 256;              // weight bins of the shot-list sort
 constexpr int kListHeader = kWeightBinsHost + 3;  // int32 words before key[] for one code

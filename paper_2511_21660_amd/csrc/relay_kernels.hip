@@ -96,7 +96,9 @@ __global__ void gamma_table_kernel(float *tab, int R, int N, uint64_t seed, floa
     tab[idx] = g;
 }
 
-__global__ void reset_queue_kernel(unsigned long long *q) { *q = 0ull; }
+__global__ void reset_queue_kernel(unsigned long long *q) {
+    if (threadIdx.x < kQueueSplit) q[threadIdx.x * kQueueStride] = 0ull;
+}
 
 // Makes `x` opaque to the optimiser for one loop trip (no instruction is
 // emitted).  Used on loop-invariant registers so that values derived from
@@ -134,7 +136,7 @@ __device__ __forceinline__ double group_sum(double x) {
 // Decodes the syndromes of one code: slots claim queue positions k < a.count
 // (shot = a.list[k], or k without a list) until the queue is exhausted, and
 // the function returns once every slot of the wave is idle.
-template <int G, int CPT, int DC, int VPT, int DV, bool PRIOR, bool TRACE>
+template <int G, int CPT, int DC, int VPT, int DV, bool PRIOR, bool TRACE, bool MULTI = false>
 __device__ __forceinline__ void group_loop(const GroupArgs a) {
     static_assert(64 % G == 0, "G must divide the wave");
     static_assert(CPT <= 32 && VPT <= 32, "per-lane bit masks are 32 bits");
@@ -207,14 +209,23 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
             for (int k = 0; k < DC; ++k) lds_at<float>(lds, mu_row0 + c * ROW_STRIDE + WORD * k) = 0.0f;
     };
 
+    // w and gamma of the code of the slot's shot: the launch's own, or (MULTI,
+    // codes sharing one graph) those of codes[cid], cid = code_id[shot] set by
+    // fetch; the pointers are looked up where used (event paths only), so
+    // the loop carries one index rather than two pointers
+    int cid = 0;
+    auto code_w = [&]() -> const float * { return (MULTI && a.code_id) ? a.codes[cid].w : a.w; };
+    auto code_gamma = [&]() -> const float * { return (MULTI && a.code_id) ? a.codes[cid].gamma : a.gamma; };
+
     // sum of w_j over the lane's faults with Lambda_j < 0 (FP64, over the
     // slot's G lanes) and the decision bits; the loads are unconditional
     // (indices clamped) so they issue together, and adding +0 for the other
     // faults leaves the sum's bits unchanged
     auto weight_of = [&](uint32_t &fm) -> double {
         float wv[VPT];
+        const float *cw = code_w();
 #pragma unroll
-        for (int v = 0; v < VPT; ++v) wv[v] = a.w[min((int)gl + G * v, a.N - 1)];
+        for (int v = 0; v < VPT; ++v) wv[v] = cw[min((int)gl + G * v, a.N - 1)];
         double part = 0.0;
         fm = 0;
 #pragma unroll
@@ -226,30 +237,34 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         return group_sum<G>(part);
     };
 
-    // Take the next syndrome for this slot and initialise leg 1.  Queue
-    // indices are claimed one ahead: lane 0 of the slot holds the index
-    // claimed at the previous fetch (its atomic has long completed) and claims
-    // the following one, so no fetch waits on the queue atomic.
+    // Take the next syndrome for this slot and initialise leg 1.  The slot
+    // draws positions sq + kQueueSplit * n from sub-counter sq, claimed one
+    // ahead: lane 0 of the slot holds the position claimed at the previous
+    // fetch (its atomic has long completed) and claims the following one, so
+    // no fetch waits on the queue atomic.
+    const unsigned sq = (blockIdx.x * (unsigned)NS + (unsigned)slot) % (unsigned)kQueueSplit;
+    unsigned long long *const qk = a.queue + (size_t)sq * kQueueStride;
     unsigned long long claim = 0;
-    if (g == 0) claim = atomicAdd(a.queue, 1ull);
+    if (g == 0) claim = atomicAdd(qk, 1ull);
     auto fetch = [&]() {
-        // w and gamma of leg 1 do not depend on the shot: issue their loads
-        // first (indices clamped, so every load is in bounds)
-        float wv[VPT], gv[VPT];
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int j = min((int)gl + G * v, a.N - 1);
-            wv[v] = a.w[j];
-            gv[v] = TRACE ? a.trace_gamma[j] : a.gamma[j];
-        }
-        const unsigned long long nxt = __shfl(claim, 0, G);
+        const unsigned long long nxt = (unsigned long long)sq + kQueueSplit * __shfl(claim, 0, G);
         if (nxt >= (unsigned long long)a.count) {
             active = false;
             return;
         }
-        if (g == 0) claim = atomicAdd(a.queue, 1ull);
+        if (g == 0) claim = atomicAdd(qk, 1ull);
         active = true;
         shot = a.list ? (long long)a.list[nxt] : (long long)nxt;
+        if (MULTI && a.code_id) cid = a.code_id[shot];
+        const float *cw = code_w(), *cgam = code_gamma();
+        // loads unconditional (indices clamped, so in bounds): they issue together
+        float wv[VPT], gv[VPT];
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int j = min((int)gl + G * v, a.N - 1);
+            wv[v] = cw[j];
+            gv[v] = TRACE ? a.trace_gamma[j] : cgam[j];
+        }
         r = 1;
         t = 0;
         total = 0;
@@ -366,13 +381,14 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 t = 0;
                 // (indices clamped so every load is in bounds and all issue
                 // together; lanes past N keep their values)
-                const float *gr = a.gamma + (size_t)(r - 1) * a.N;
+                const float *gr = code_gamma() + (size_t)(r - 1) * a.N;
+                const float *cw = code_w();
                 float gv[VPT], wv[VPT];
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
                     const int j = min((int)gl + G * v, a.N - 1);
                     gv[v] = gr[j];
-                    wv[v] = PRIOR ? a.w[j] : 0.0f;
+                    wv[v] = PRIOR ? cw[j] : 0.0f;
                 }
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
@@ -443,18 +459,20 @@ void relay_group_kernel(GroupArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// Mixed-code launch: each wave decodes one code at a time with that code's
-// compiled tile, drains the code's queue, then moves on to the next code
-// (starting at blockIdx mod ncodes, so the codes are worked on concurrently).
+// Mixed-code launch: each wave decodes one family at a time (the codes that
+// share a graph and a tile, e.g. one code at several noise rates) with the
+// family's compiled tile, drains the family's queue (one longest-first list
+// over all its codes; every slot takes w and gamma from its shot's own code),
+// then moves on to the next family in the order the list kernels set.
 // Only tiles within a 128-VGPR budget take part, so mixing never lowers
 // occupancy below what the largest code needs on its own.
 // ------------------------------------------------------------------------
 template <bool PRIOR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 void relay_mixed_kernel(MixedArgs m) {
-    for (int q = 0; q < m.ncodes; ++q) {
-        const int c = m.order[q];
-        const CodeStatic cs = m.codes[c];
+    for (int q = 0; q < m.nfam; ++q) {
+        const int f = m.order[q];
+        const CodeStatic cs = m.codes[m.fam_rep[f]];
         GroupArgs a = m.run;
         a.M = cs.M;
         a.N = cs.N;
@@ -465,14 +483,16 @@ void relay_mixed_kernel(MixedArgs m) {
         a.lampad_off = cs.lampad_off;
         a.mupad_off = cs.mupad_off;
         a.mu0_off = cs.mu0_off;
-        a.list = m.list + m.seg_start[c];
-        a.count = m.seg_count[c];
-        a.queue = m.queues + c;
+        a.list = m.list + m.seg_start[f];
+        a.count = m.seg_count[f];
+        a.queue = m.queues + (size_t)f * kQueueWords;
+        a.code_id = m.fam_size[f] > 1 ? m.code_id : nullptr;
+        a.codes = m.codes;
         switch (cs.tile) {
-            case 0: group_loop<8, 5, 6, 9, 3, PRIOR, false>(a); break;
-            case 1: group_loop<16, 3, 6, 6, 3, PRIOR, false>(a); break;
-            case 2: group_loop<16, 5, 6, 9, 3, PRIOR, false>(a); break;
-            case 3: group_loop<32, 5, 6, 9, 3, PRIOR, false>(a); break;
+            case 0: group_loop<8, 5, 6, 9, 3, PRIOR, false, true>(a); break;
+            case 1: group_loop<16, 3, 6, 6, 3, PRIOR, false, true>(a); break;
+            case 2: group_loop<16, 5, 6, 9, 3, PRIOR, false, true>(a); break;
+            case 3: group_loop<32, 5, 6, 9, 3, PRIOR, false, true>(a); break;
             default: break;
         }
     }
@@ -488,34 +508,36 @@ constexpr int kWeightBins = 256;
 __global__ void list_zero_kernel(int32_t *p, int n, unsigned long long *queues, int nq) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
-    if (i < nq) queues[i] = 0ull;
+    if (i < nq * kQueueSplit) queues[(size_t)(i / kQueueSplit) * kQueueWords + (i % kQueueSplit) * kQueueStride] = 0ull;
 }
 
 constexpr int kListThreads = 256;
 
-// Key of shot b: code-major, then decreasing syndrome weight (bin), or -1.
+// Key of shot b: family-major, then decreasing syndrome weight (bin), or -1.
 __device__ __forceinline__ int shot_key(int64_t b, const uint8_t *syn, int32_t syn_stride,
-                                        const int32_t *code_id, const int32_t *code_m, int ncodes) {
+                                        const int32_t *code_id, const int32_t *code_m, int ncodes,
+                                        const int32_t *code_fam) {
     const int c = code_id ? code_id[b] : 0;
     if (c < 0 || c >= ncodes) return -1;  // invalid code id: shot skipped, outputs untouched
     const int m = code_m[c];
     const uint8_t *s = syn + (size_t)b * syn_stride;
     int wgt = 0;
     for (int i = 0; i < m; ++i) wgt += s[i] != 0;
-    return c * kWeightBins + (kWeightBins - 1 - min(wgt, kWeightBins - 1));
+    const int f = code_fam ? code_fam[c] : c;
+    return f * kWeightBins + (kWeightBins - 1 - min(wgt, kWeightBins - 1));
 }
 
 // Block-local histogram in LDS (dynamic LDS: nbins words), then one global
 // atomic per nonzero (block, bin).
 __global__ __launch_bounds__(kListThreads) void list_key_kernel(
         int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
-        const int32_t *code_m, int ncodes, int32_t *key, int32_t *hist) {
-    const int nb = ncodes * kWeightBins;
+        const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam, int32_t *key, int32_t *hist) {
+    const int nb = nfam * kWeightBins;
     for (int k = threadIdx.x; k < nb; k += kListThreads) *(__attribute__((address_space(3))) int32_t *)(size_t)(4u * k) = 0;
     __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * kListThreads + threadIdx.x;
     if (b < B) {
-        const int k = shot_key(b, syn, syn_stride, code_id, code_m, ncodes);
+        const int k = shot_key(b, syn, syn_stride, code_id, code_m, ncodes, code_fam);
         key[b] = k;
         if (k >= 0)
             __hip_atomic_fetch_add((__attribute__((address_space(3))) int32_t *)(size_t)(4u * k), 1,
@@ -701,20 +723,20 @@ hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_f
 }
 
 hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
-                             const int32_t *code_m, int ncodes, void *workspace,
-                             unsigned long long *queues, hipStream_t s) {
+                             const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam,
+                             void *workspace, unsigned long long *queues, hipStream_t s) {
     int32_t *hist = (int32_t *)workspace;                       // ncodes * bins
     int32_t *seg_start = hist + (size_t)ncodes * kWeightBins;   // ncodes
     int32_t *seg_count = seg_start + ncodes;                    // ncodes
     int32_t *order = seg_count + ncodes;                        // ncodes
     int32_t *key = order + ncodes;                              // B
     int32_t *list = key + B;                                    // B
-    const int nh = ncodes * kWeightBins;
-    hipLaunchKernelGGL(list_zero_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, hist, nh, queues, ncodes);
+    const int nh = nfam * kWeightBins;
+    hipLaunchKernelGGL(list_zero_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, hist, nh, queues, nfam);
     const int blocks = (int)((B + kListThreads - 1) / kListThreads);
     hipLaunchKernelGGL(list_key_kernel, dim3(blocks), dim3(kListThreads), 4u * (size_t)nh, s, B, syn, syn_stride,
-                       code_id, code_m, ncodes, key, hist);
-    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, ncodes, hist, seg_start, seg_count, order);
+                       code_id, code_m, ncodes, code_fam, nfam, key, hist);
+    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, nfam, hist, seg_start, seg_count, order);
     hipLaunchKernelGGL(list_scatter_kernel, dim3(blocks), dim3(kListThreads), 8u * (size_t)nh, s, B, nh, key, hist,
                        list);
     return hipGetLastError();
@@ -725,7 +747,7 @@ size_t shot_list_bytes(int64_t B, int ncodes) {
 }
 
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s) {
-    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, q);
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(kQueueSplit), 0, s, q);
     return hipGetLastError();
 }
 
