@@ -24,7 +24,7 @@ struct CodeStatic;
 // s % kQueueSplit + kQueueSplit * n from counter s % kQueueSplit, which spreads
 // the claims of thousands of slots over several L2 atomic units.  The block
 // kernel uses counter 0 alone.  A queue occupies kQueueWords words.
-constexpr int kQueueSplit = 4;
+constexpr int kQueueSplit = 8;
 constexpr int kQueueStride = 32;
 constexpr int kQueueWords = kQueueSplit * kQueueStride;
 
