@@ -794,7 +794,7 @@ BlockTables block_tables(const rb_ctx *c, const rb::BlockShape &s) {
     // check table as [chunk][thread][4 words] (one 16-byte load per thread and
     // chunk of 8 edges, coalesced over a wave); fault table as [pair][thread]
     std::vector<uint32_t> &col_pk = T.col_pk, &mu_pk = T.mu_pk;
-    col_pk.assign((size_t)ncp * s.TPB, 0u);
+    col_pk.assign((size_t)(ncp + 4) * s.TPB, (uint32_t)lay.lampad_off * 0x10001u);  // + one padding chunk
     mu_pk.assign((size_t)nmp * s.TPB, 0u);
     for (int32_t t = 0; t < s.TPB; ++t) {
         for (int e = 0; e < ncp; ++e) {

@@ -45,6 +45,16 @@ __device__ __forceinline__ float clipb(float x, float L) { return __builtin_amdg
 
 __device__ __forceinline__ void opaque_b(uint32_t &x) { asm volatile("" : "+v"(x)); }
 
+// (x & 0xffff) << 2 as one VALU instruction (an SDWA shift of the low half
+// word), where the compiler would emit a shift and a mask
+__device__ __forceinline__ uint32_t lo_half_x4(uint32_t x) {
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(r)
+        : "v"(2u), "v"(x));
+    return r;
+}
+
 // value of lane l ^ 1 (DPP quad permutation 1,0,3,2; the whole wave is active)
 __device__ __forceinline__ int swap_pair(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
 
@@ -107,7 +117,7 @@ void relay_block_kernel(BlockArgs a) {
     // check side: Lambda byte addresses (16-bit, Lambda region < 64 KiB) of
     // the row's edges, kBlockChunk per uint4.  Chunk 0 stays in registers; the
     // others stream from the (L2-resident) table one chunk ahead of use.
-    const uint4 *ctab = reinterpret_cast<const uint4 *>(a.chk_col);  // [DCMAX/CH][TPB]
+    const uint4 *ctab = reinterpret_cast<const uint4 *>(a.chk_col);  // [DCMAX/CH + 1][TPB]
     uint4 col0 = ctab[t];
     // fault side: message word indices (16-bit)
     uint32_t mu_pk[(NMU + 1) / 2];
@@ -224,12 +234,14 @@ void relay_block_kernel(BlockArgs a) {
                 m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
             }
         };
+        // The next table entry is loaded unconditionally (the table holds one
+        // padding entry past the last chunk), so the unrolled chunks rename
+        // the two entries instead of copying them at branch merges.
         uint4 cur = col0;
 #pragma unroll
         for (int c = 0; c < DCMAX; c += CH) {
             if (c >= wdeg) break;  // wave-uniform row length
-            uint4 nxt = cur;
-            if (c + CH < DCMAX && c + CH < wdeg) nxt = ctab[(size_t)(c / CH + 1) * TPB + tl];
+            const uint4 nxt = ctab[(size_t)(c / CH + 1) * TPB + tl];
             if (c + CH / 2 >= wdeg)
                 chunk(std::integral_constant<int, CH / 2>{}, c, cur);
             else
@@ -373,7 +385,8 @@ void relay_block_kernel(BlockArgs a) {
         // cell for the rest.
         constexpr int FD = 2;
         auto mu_word = [&](int e) -> uint32_t {
-            return ((e & 1) ? (mu_pk[e >> 1] >> 16) : (mu_pk[e >> 1] & 0xffffu)) << 2;
+            if (e & 1) return (mu_pk[e >> 1] >> 16) << 2;  // the compiler emits one SDWA shift
+            return lo_half_x4(mu_pk[e >> 1]);
         };
         float gv[FD + 1][DV], gl[FD + 1];
         auto load_slot = [&](int v, float(&m)[DV], float &l) {

@@ -113,7 +113,7 @@ struct BlockArgs {
     float *final_llr;
     const float *w;
     const float *gamma;
-    const uint32_t *chk_col;   // [DCMAX/8][TPB][4] 16-bit Lambda byte addresses, 8 per chunk
+    const uint32_t *chk_col;   // [DCMAX/8 + 1][TPB][4] 16-bit Lambda byte addresses, 8 per chunk (last: padding)
     const uint32_t *col_mu;    // [ceil(prof_pre(VPT)/2)][TPB] two 16-bit message word indices
     const int32_t *slot_col;   // [TPB*VPT] fault held by slot s, or -1 (slots >= N)
     const float *w_slot;       // [TPB*VPT] channel LLR by slot (0 for spare slots)
