@@ -55,6 +55,17 @@ __device__ __forceinline__ uint32_t lo_half_x4(uint32_t x) {
     return r;
 }
 
+// 2 * x + bit as one add with carry-in (the compare that produced `bit`
+// already is the lane mask the carry-in reads)
+__device__ __forceinline__ uint32_t shift_in(uint32_t x, bool bit) {
+    uint32_t r;
+    unsigned long long carry_out;
+    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3"
+        : "=v"(r), "=s"(carry_out)
+        : "v"(x), "s"(__builtin_amdgcn_ballot_w64(bit)));
+    return r;
+}
+
 // value of lane l ^ 1 (DPP quad permutation 1,0,3,2; the whole wave is active)
 __device__ __forceinline__ int swap_pair(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
 
@@ -224,10 +235,13 @@ void relay_block_kernel(BlockArgs a) {
                 const float nu = clipb(lv[q] - mo[q], L);
                 const bool sn = nu < 0.0f;
                 neg ^= sn;
+                // shift the sign in at the bottom (one add with carry-in): after
+                // P processed steps, edge k sits at bit min(P,32)-1-k of sg_lo
+                // (k < 32) or P-1-k of sg_hi
                 if (k < 32)
-                    sg_lo |= sn ? (1u << k) : 0u;
+                    sg_lo = shift_in(sg_lo, sn);
                 else
-                    sg_hi |= sn ? (1u << (k - 32)) : 0u;
+                    sg_hi = shift_in(sg_hi, sn);
                 const float av = fabsf(nu);
                 amin = av < m1 ? k : amin;
                 m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
@@ -270,12 +284,14 @@ void relay_block_kernel(BlockArgs a) {
             const uint32_t flip = neg ? 0xffffffffu : 0u;
             const uint32_t s_lo = sg_lo ^ flip, s_hi = sg_hi ^ flip;
             const uint32_t b1 = __float_as_uint(m1);
+            const int P = (wdeg + 3) & ~3;  // steps pass 1 processed
+            const int P32 = P < 32 ? P : 32;
             auto pass2 = [&](auto full_tag, int c) {
                 constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
                 for (int q = 0; q < CH; ++q) {
                     const int k = c + q;
-                    const uint32_t sb = k < 32 ? (s_lo << (31 - k)) : (s_hi << (63 - k));
+                    const uint32_t sb = k < 32 ? (s_lo << (32 - P32 + k)) : (s_hi << (32 - P + k));
                     if (FULL || k < wdeg) lds_b<uint32_t>(mrow + 256u * k) = (sb & 0x80000000u) | b1;
                 }
             };
@@ -288,7 +304,7 @@ void relay_block_kernel(BlockArgs a) {
                     pass2(std::false_type{}, c);
             }
             if (wdeg > 0 && owns_min) {
-                const uint32_t sa = amin < 32 ? (s_lo >> amin) : (s_hi >> (amin - 32));
+                const uint32_t sa = amin < 32 ? (s_lo >> (P32 - 1 - amin)) : (s_hi >> (P - 1 - amin));
                 lds_b<uint32_t>(mrow + 256u * (uint32_t)amin) = (sa << 31) | __float_as_uint(m2);
             }
         }
