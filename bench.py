@@ -51,11 +51,12 @@ RELAY = dict(num_legs=301, iters_first=80, iters_leg=60, num_solutions=5, gamma_
 RELAY_R20 = dict(RELAY, num_legs=20, num_solutions=1)
 
 # Algorithmic work per edge-update (one edge in one iteration), from the
-# update rules: check side nu = clip(Lambda - mu) (2), sign parity (1),
-# min1/min2 tracking (3), per-edge magnitude select (2) and sign (1); fault
-# side sum (1); syndrome parity (1) => 11 per edge, plus per fault 7
-# (1 - gamma, two products, sum, two clips, decision) and per check 3.
-OPS_PER_EDGE = 11.0
+# update rules: check side nu = clip(Lambda - mu) (2), sign parity (1), the
+# two smallest magnitudes and the position of the smallest (compare, min1,
+# min2, position: 4), per-edge magnitude select (2) and sign (1); fault side
+# sum (1); syndrome parity (1) => 12 per edge, plus per fault 7 (1 - gamma,
+# two products, sum, two clips, decision) and per check 3.
+OPS_PER_EDGE = 12.0
 OPS_PER_FAULT = 7.0
 OPS_PER_CHECK = 3.0
 
