@@ -8,7 +8,11 @@ T_r = 60, R = 301 legs in total, S = 5 solutions kept (lowest weight output).
 One step decodes all 4 x 10^5 syndromes, already resident in HBM.
 
 Other workloads:
-  --workload dem          DEM-shaped 936 x 8785 matrix, 10^6 shots, R = 20, S = 1
+  --workload dem          DEM-shaped 936 x 8785 matrix, 10^6 shots, R = 20, S = 1;
+                          with the latency tail: completion and LER within FPGA-cycle
+                          budgets, epsilon(T_ref) and the latency-tail condition
+  --workload bp-llr       plain min-sum BP (one leg, gamma = 0, 25 rounds) on the
+                          DEM-shaped matrix, 10^5 shots, returning the marginals
   --workload mixed-codes  [[72,12,6]], [[90,8,10]], [[144,12,12]], [[288,12,18]]
                           interleaved 4:3:2:1, 4 x 10^5 shots at p = 0.04, R = 20,
                           S = 1: one autotuned mixed launch (eager and replayed from
@@ -60,7 +64,7 @@ OPS_PER_EDGE = 12.0
 OPS_PER_FAULT = 7.0
 OPS_PER_CHECK = 3.0
 
-DEFAULT_STEPS = {"bb144": 20, "dem": 5, "mixed-codes": 10, "learned": 3}
+DEFAULT_STEPS = {"bb144": 20, "dem": 5, "mixed-codes": 10, "learned": 3, "bp-llr": 10}
 
 
 def ops_per_iteration(m, n, e):
@@ -343,11 +347,75 @@ def run_dem(args, torch, rb, codes, sampling):
         "edges": E, "shots": shots, "T_first": 80, "T_leg": 60, "legs": 20, "solutions": 1,
         "gamma_first": 0.125, "gamma_range": [-0.24, 0.66], "anchor": "chain",
         "parallelism": "single_gpu"})
+    # latency tail (Sec. 7.2): completion within FPGA-cycle budgets (2 cycles
+    # per iteration), LER at each budget, epsilon(T_ref = 500 cycles), and the
+    # latency-tail condition for T_gen = 1000 cycles and C = 10 code blocks
+    from paper_2511_21660_amd import latency
+
+    tail = latency.summary(iters, fail.cpu().numpy(), [100, 200, 300, 500, 1000, 1500, 2440],
+                           t_ref_cycles=500, t_gen_cycles=1000, blocks=10)
     line.update({"edge_updates_per_s": iters_launch * E * args.steps / elapsed,
                  "launch_ms": [kernel_ms], "roofline": roof, "lds_roofline": lds,
                  "ler": {"ler": k / shots, "wilson95": wilson(k, shots),
                          "conv": float(conv.mean()), "mean_iters": float(iters.mean()),
                          "max_iters": int(iters.max()), "faults_per_shot": f_shots.size / shots},
+                 "latency_tail": tail, "kernel_config": dec.info(), "cpu_baseline": cpu})
+    return line
+
+
+# --------------------------------------------------------------------------
+# plain-BP LLR export on the DEM-shaped matrix (25 rounds, gamma = 0)
+# --------------------------------------------------------------------------
+
+
+def run_bp_llr(args, torch, rb, codes, sampling):
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    prob = codes.dem_problem()
+    M, N, E = prob.m, prob.n, prob.nnz
+    shots = args.shots or 100000
+    syn_np, _ = sampling.sample_syndromes_sparse(prob, 0xB9C5, shots)
+    prm = rb.bp_params(25)
+    dec = rb.Decoder.from_problem(prob, device=0, **prm)
+    d_syn = torch.from_numpy(syn_np).to(dev)
+    out = dec.decode(d_syn, want_llr=True)
+
+    def step(ev):
+        if ev is not None:
+            ev[0][0].record(stream)
+        dec.decode(d_syn, out=out)
+        if ev is not None:
+            ev[0][1].record(stream)
+
+    elapsed, per_launch = timed(torch, step, 1, args.steps, args.warmup)
+    kernel_ms = float(np.mean(per_launch))
+    iters = out["iters"].cpu().numpy()
+    conv = out["conv"].cpu().numpy()
+    iters_launch = int(iters.astype(np.int64).sum())
+    roof, lds = roofline("relay_block_kernel", kernel_ms, iters_launch * ops_per_iteration(M, N, E),
+                         iters_launch * E, lds_bytes_per_edge_update(M, N, E), None)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = oracle_threads()
+        n_cpu = min(args.cpu_sample or 20000, shots)
+        t1 = time.perf_counter()
+        ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, prm, syn_np[:n_cpu],
+                            threads=threads, want_llr=True)
+        tc = time.perf_counter() - t1
+        agree = bool(np.array_equal(ref["llr"], out["llr"][:n_cpu].cpu().numpy())
+                     and np.array_equal(ref["iters"], iters[:n_cpu]))
+        cpu = {"value": n_cpu / tc, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n_cpu} of {shots} syndromes, same inputs, {tc:.1f} s",
+               "paired_with_gpu_bit_exact": agree}
+    line = head(args, shots * args.steps / elapsed, elapsed, {
+        "workload": "plain_bp_llr_dem_936x8785", "matrix": "DEM-shaped synthetic 936x8785",
+        "edges": E, "shots": shots, "rounds": 25, "gamma": 0.0, "legs": 1, "output": "llr f32 [B, N]",
+        "parallelism": "single_gpu"})
+    line.update({"edge_updates_per_s": iters_launch * E * args.steps / elapsed,
+                 "launch_ms": [kernel_ms], "roofline": roof, "lds_roofline": lds,
+                 "converged": float(conv.mean()), "mean_iters": float(iters.mean()),
                  "kernel_config": dec.info(), "cpu_baseline": cpu})
     return line
 
@@ -561,7 +629,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["bb144", "dem", "mixed-codes", "learned"], default="bb144")
+    ap.add_argument("--workload", choices=["bb144", "dem", "mixed-codes", "learned", "bp-llr"], default="bb144")
     ap.add_argument("--train-steps", type=int, default=0, help="learned: Adam steps (default 2000)")
     ap.add_argument("--shots", type=int, default=0,
                     help="syndromes per p (bb144) or in total (default per workload)")
@@ -594,7 +662,7 @@ def main():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
     run = {"bb144": run_bb144, "dem": run_dem, "mixed-codes": run_mixed_codes,
-           "learned": run_learned}[args.workload]
+           "learned": run_learned, "bp-llr": run_bp_llr}[args.workload]
     line = run(args, torch, rb, codes, sampling)
     if args.calibrate_copy > 0:
         n_el = args.calibrate_copy * (1 << 20) // 4

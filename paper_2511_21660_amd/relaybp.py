@@ -134,6 +134,20 @@ def default_params(**overrides) -> RBParams:
     return p
 
 
+def bp_params(rounds=25, **overrides) -> dict:
+    """Decoder parameters for plain min-sum BP as a special case of Relay: one
+    leg of `rounds` iterations with gamma = 0, so the memory term
+    (1 - gamma) lambda(0) + gamma Lambda(t-1) is the prior itself (paper Sec.
+    2.3 with gamma = 0).  The paper hands the next decoding stage the LLRs of
+    25 such rounds when the memory-BP pre-decoder fails (Sec. 7.1); decode
+    with want_llr=True returns them (after `rounds` iterations, or at
+    convergence if plain BP converges earlier)."""
+    p = dict(num_legs=1, iters_first=rounds, iters_leg=rounds, num_solutions=1, gamma_first=0.0,
+             gamma_lo=0.0, gamma_hi=0.0, llr_clip=2.0 ** 64, seed=0, anchor=ANCHOR_CHAIN, max_total_iters=0)
+    p.update(overrides)
+    return p
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 

@@ -22,3 +22,13 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def relay_default():
     return dict(RELAY_DEFAULT)
+
+
+def logical_failures_np(prob, faults, corr, conv):
+    """Per-shot logical failure: not converged, or the residual F + F_hat
+    anticommutes with a row of the logical matrix."""
+    import numpy as np
+
+    resid = (faults ^ corr).astype(np.int64)
+    bad = ((prob.logical.astype(np.int64) @ resid.T) % 2).any(0)
+    return (~conv.astype(bool)) | bad
