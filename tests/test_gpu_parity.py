@@ -447,3 +447,37 @@ def test_longest_first_schedule_keeps_results(rb):
     sub = {k: lpt[k][:500] for k in KEYS}
     sub["info"] = dec.info()
     assert_parity(sub, ref, syn[:500], prob, "longest-first")
+
+
+def test_mixed_family_of_noise_rates(rb):
+    """One graph at several noise rates plus a second graph in one launch: the
+    codes sharing the graph form one family (one shot list; every slot takes w
+    and Gamma from its own shot's code), and every shot still equals the
+    oracle's decode of its own code (S = 2, so convergence events, leg
+    changes and new shots all read the per-shot code)."""
+    specs = [("bb72", 0.03), ("bb72", 0.05), ("bb90", 0.04), ("bb72", 0.07)]
+    probs = [codes.bb_problem(nm, p) for nm, p in specs]
+    b = 2000
+    pattern = np.array([0, 1, 3, 2, 1, 0, 3, 3, 2, 1], np.int32)
+    code_id = np.resize(pattern, b).astype(np.int32)
+    m_max = max(pr.m for pr in probs)
+    syn = np.zeros((b, m_max), np.uint8)
+    per = []
+    for k, pr in enumerate(probs):
+        idx = np.nonzero(code_id == k)[0]
+        _, s = sampling.sample_batch(pr, (11 << 32) | k, 0, idx.size)
+        syn[idx, :pr.m] = s
+        per.append((idx, s))
+    prm = dict(RELAY_DEFAULT, num_solutions=2)
+    dec = rb.MultiDecoder(probs, **prm)
+    out = dec.decode(torch.from_numpy(code_id).cuda(), torch.from_numpy(syn).cuda(), want_llr=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items() if k != "workspace"}
+    for k, pr in enumerate(probs):
+        idx, s = per[k]
+        ref = oracle.decode(pr.m, pr.n, pr.rows, pr.cols, pr.prior, prm, s, want_llr=True)
+        sub = {"corr": g["corr"][idx, :pr.n], "conv": g["conv"][idx], "legs": g["legs"][idx],
+               "iters": g["iters"][idx], "weight": g["weight"][idx], "llr": g["llr"][idx, :pr.n],
+               "info": {"variant": "mixed family"}}
+        assert_parity(sub, ref, s, pr, f"family member {specs[k]}")
+    dec.close()
