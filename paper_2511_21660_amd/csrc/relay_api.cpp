@@ -140,6 +140,130 @@ double variant_cost(const rb::TileShape &s) {
     return work * occ;
 }
 
+// Deterministic generator for the plan's local search (splitmix64).
+struct PlanRng {
+    uint64_t x;
+    uint32_t below(uint32_t n) {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (uint32_t)(z % n);
+    }
+};
+
+// Edge order within each check for a group-kernel tile (free: the check
+// update does not depend on it).  A wave's gathers cost the largest number of
+// distinct words on one LDS bank.  The NS slots of a wave are interleaved word
+// by word, so each slot owns 32/NS banks (its "classes") and its G lanes are
+// conflict-free at two words per class.  Step k of check row c gathers Lambda
+// of the k-th fault of the G checks g + G*c (class: fault index mod 32/NS);
+// gather k of fault slot v reads the message of the k-th check of the G
+// faults g + G*v (class: message word mod 32/NS, which depends on the edge's
+// step in its check).  Random swaps of two edges of one check, accepted by a
+// simulated-annealing rule, lower the sum of both kinds of costs.  Returns the
+// step of every CSR edge.
+std::vector<int32_t> group_edge_order(const rb_ctx *c, const rb::TileShape &s, const Layout &lay) {
+    const int NS = 64 / s.G, ncls = 32 / NS;
+    std::vector<int32_t> pos((size_t)c->E), at((size_t)c->E);  // edge -> step; (row, step) -> edge
+    for (int32_t i = 0; i < c->M; ++i)
+        for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) {
+            pos[(size_t)e] = (int32_t)(e - c->rowptr[i]);
+            at[(size_t)e] = (int32_t)e;
+        }
+    if (c->E == 0) return pos;
+    const int lampad_cls = (int)((lay.lampad_off / lay.word) % (uint32_t)ncls);
+    const int mupad_cls = (int)((lay.mupad_off / lay.word) % (uint32_t)ncls);
+    const uint32_t mu0w = lay.mu0_off / lay.word;
+    // edge e of check i: its k-th place in its fault's ascending check list
+    std::vector<int32_t> fk((size_t)c->E);
+    for (int32_t j = 0; j < c->N; ++j)
+        for (int64_t q = c->colptr[j]; q < c->colptr[j + 1]; ++q)
+            fk[(size_t)(c->rowptr[c->rowidx[q]] + c->cpos[q])] = (int32_t)(q - c->colptr[j]);
+    std::vector<int32_t> fcol((size_t)c->E);  // fault of each CSR edge
+    for (int32_t i = 0; i < c->M; ++i)
+        for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) fcol[(size_t)e] = c->colidx[e];
+    auto deg_r = [&](int i) { return (int)(c->rowptr[i + 1] - c->rowptr[i]); };
+    auto deg_c = [&](int j) { return (int)(c->colptr[j + 1] - c->colptr[j]); };
+    int h[64];
+    auto ccost = [&](int cc, int k) {
+        for (int q = 0; q < ncls; ++q) h[q] = 0;
+        bool pad = false;
+        for (int g = 0; g < s.G; ++g) {
+            const int i = g + s.G * cc;
+            if (i >= c->M || k >= deg_r(i)) {
+                pad = true;
+                continue;
+            }
+            ++h[fcol[(size_t)at[(size_t)(c->rowptr[i] + k)]] % ncls];
+        }
+        if (pad) ++h[lampad_cls];
+        int m = 0;
+        for (int q = 0; q < ncls; ++q) m = std::max(m, h[q]);
+        return m;
+    };
+    auto fcost = [&](int vv, int k) {
+        for (int q = 0; q < ncls; ++q) h[q] = 0;
+        bool pad = false;
+        for (int g = 0; g < s.G; ++g) {
+            const int j = g + s.G * vv;
+            if (j >= c->N || k >= deg_c(j)) {
+                pad = true;
+                continue;
+            }
+            const int64_t q = c->colptr[j] + k;
+            const int i = c->rowidx[q];
+            const int p = pos[(size_t)(c->rowptr[i] + c->cpos[q])];
+            ++h[(int)((mu0w + (uint32_t)i * (uint32_t)lay.rs + (uint32_t)p) % (uint32_t)ncls)];
+        }
+        if (pad) ++h[mupad_cls];
+        int m = 0;
+        for (int q = 0; q < ncls; ++q) m = std::max(m, h[q]);
+        return m;
+    };
+    std::vector<int> C((size_t)s.CPT * s.DC), F((size_t)s.VPT * s.DV);
+    for (int cc = 0; cc < s.CPT; ++cc)
+        for (int k = 0; k < s.DC; ++k) C[(size_t)cc * s.DC + k] = ccost(cc, k);
+    for (int vv = 0; vv < s.VPT; ++vv)
+        for (int k = 0; k < s.DV; ++k) F[(size_t)vv * s.DV + k] = fcost(vv, k);
+    PlanRng rng{0xBA4C5EEDull};
+    const int64_t iters = std::min<int64_t>(2000000, 600 * c->E);
+    for (int64_t it = 0; it < iters; ++it) {
+        const int i = (int)rng.below((uint32_t)c->M);
+        const int d = deg_r(i);
+        if (d < 2) continue;
+        const int a = (int)rng.below((uint32_t)d), b = (int)rng.below((uint32_t)d);
+        if (a == b) continue;
+        const int cc = i / s.G;
+        const int ea = at[(size_t)(c->rowptr[i] + a)], eb = at[(size_t)(c->rowptr[i] + b)];
+        const int ja = fcol[(size_t)ea], jb = fcol[(size_t)eb];
+        const size_t c1 = (size_t)cc * s.DC + a, c2 = (size_t)cc * s.DC + b;
+        const size_t f1 = (size_t)(ja / s.G) * s.DV + fk[(size_t)ea], f2 = (size_t)(jb / s.G) * s.DV + fk[(size_t)eb];
+        const int before = C[c1] + C[c2] + F[f1] + (f2 != f1 ? F[f2] : 0);
+        std::swap(at[(size_t)(c->rowptr[i] + a)], at[(size_t)(c->rowptr[i] + b)]);
+        pos[(size_t)ea] = b;
+        pos[(size_t)eb] = a;
+        const int nc1 = ccost(cc, a), nc2 = ccost(cc, b);
+        const int nf1 = fcost(ja / s.G, fk[(size_t)ea]), nf2 = f2 != f1 ? fcost(jb / s.G, fk[(size_t)eb]) : 0;
+        const int after = nc1 + nc2 + nf1 + nf2;
+        const double temp = 0.5 * (1.0 - (double)it / (double)iters);
+        bool take = after <= before;
+        if (!take && temp > 0.0) take = (double)rng.below(1u << 20) < std::exp((before - after) / temp) * (double)(1u << 20);
+        if (take) {
+            C[c1] = nc1;
+            C[c2] = nc2;
+            F[f1] = nf1;
+            if (f2 != f1) F[f2] = nf2;
+        } else {
+            std::swap(at[(size_t)(c->rowptr[i] + a)], at[(size_t)(c->rowptr[i] + b)]);
+            pos[(size_t)ea] = a;
+            pos[(size_t)eb] = b;
+        }
+    }
+    return pos;
+}
+
 rb_status build_plan(rb_ctx *c, int v) {
     const rb::TileShape s = rb::variant_shape(v);
     const Layout lay = slot_layout(s, c->N);
@@ -147,13 +271,14 @@ rb_status build_plan(rb_ctx *c, int v) {
     const int nlp = (nl + 1) / 2, nmp = (nm + 1) / 2;
     std::vector<uint16_t> lam16((size_t)s.G * nlp * 2, (uint16_t)lay.lampad_off);
     std::vector<uint16_t> mu16((size_t)s.G * nmp * 2, (uint16_t)lay.mupad_off);
+    const std::vector<int32_t> pos = group_edge_order(c, s, lay);  // CSR edge -> step in its check
     for (int g = 0; g < s.G; ++g) {
         for (int cc = 0; cc < s.CPT; ++cc) {
             const int i = g + s.G * cc;
             if (i >= c->M) continue;
-            const int64_t b = c->rowptr[i], e = c->rowptr[i + 1];
-            for (int64_t k = 0; k < e - b; ++k)
-                lam16[(size_t)g * nlp * 2 + cc * s.DC + k] = (uint16_t)(lay.word * (uint32_t)c->colidx[b + k]);
+            for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e)
+                lam16[(size_t)g * nlp * 2 + cc * s.DC + pos[(size_t)e]] =
+                    (uint16_t)(lay.word * (uint32_t)c->colidx[e]);
         }
         for (int vv = 0; vv < s.VPT; ++vv) {
             const int j = g + s.G * vv;
@@ -161,7 +286,8 @@ rb_status build_plan(rb_ctx *c, int v) {
             const int64_t b = c->colptr[j], e = c->colptr[j + 1];
             for (int64_t k = 0; k < e - b; ++k) {
                 const int i = c->rowidx[b + k];
-                const uint32_t word = (uint32_t)i * (uint32_t)lay.rs + (uint32_t)c->cpos[b + k];
+                const int p = pos[(size_t)(c->rowptr[i] + c->cpos[b + k])];
+                const uint32_t word = (uint32_t)i * (uint32_t)lay.rs + (uint32_t)p;
                 mu16[(size_t)g * nmp * 2 + vv * s.DV + k] = (uint16_t)(lay.mu0_off + lay.word * word);
             }
         }
@@ -403,18 +529,6 @@ rb_status upload(T **dst, const std::vector<T> &src, const char *what) {
     return RB_OK;
 }
 
-// Deterministic generator for the plan's local search (splitmix64).
-struct PlanRng {
-    uint64_t x;
-    uint32_t below(uint32_t n) {
-        x += 0x9E3779B97F4A7C15ull;
-        uint64_t z = x;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        z ^= z >> 31;
-        return (uint32_t)(z % n);
-    }
-};
 
 // Check lanes within each wave (free: a wave's rows may sit on any of its
 // lanes, a split check on an aligned lane pair).  The fault pass's k-th
