@@ -256,8 +256,11 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
  *   d_conv, d_legs, d_iters, d_weight, d_final_llr ([B][N_max]) as in rb_decode
  *   d_workspace  device buffer of at least rb_workspace_size(ctx, B) bytes, owned
  *                by the caller, not used concurrently by another call
- * Per code the shots are ordered by decreasing syndrome weight; each wave of
- * the launch decodes one code at a time with that code's tile.  Enqueues on
+ * Codes with the same graph and tile (for instance one code at several noise
+ * rates) form a family whose shots share one list, ordered by decreasing
+ * syndrome weight; each shot is decoded with its own code's priors and
+ * memory strengths.  Each wave of the launch decodes one family at a time
+ * with the family's tile.  Enqueues on
  * `stream` only (no allocation, no synchronisation, no memset): the call can
  * be captured in a hipGraph and replayed.  Results equal per-code rb_decode.
  */
