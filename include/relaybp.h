@@ -56,7 +56,8 @@ typedef enum {
     RB_E_OOM = 6,             /* device or host allocation failed */
     RB_E_WORKSPACE = 7,       /* caller-provided buffer too small */
     RB_E_UNSUPPORTED = 8,     /* graph exceeds every kernel configuration built in */
-    RB_E_NONFINITE = 9        /* non-finite value where a finite one is required */
+    RB_E_NONFINITE = 9,       /* non-finite value where a finite one is required */
+    RB_E_INTERNAL = 10        /* the library's own tables failed a consistency check */
 } rb_status;
 
 /* Anchor of the memory term in legs r >= 2 (leg 1 always uses w_j). */
@@ -198,6 +199,37 @@ rb_status rb_get_info(const rb_ctx *ctx, rb_info *info);
  * later decodes; RB_E_UNSUPPORTED if the graph does not fit it.  Rebuilds the
  * gather tables (allocates and synchronises). */
 rb_status rb_set_variant(rb_ctx *ctx, int32_t variant);
+
+/* Report of rb_plan_check.  LDS cost model: 32 banks of 4-byte words; a
+ * wave-wide gather costs the largest number of distinct words on one bank, so
+ * a gather of 64 distinct words costs at least 2 (conflict-free). */
+typedef struct {
+    int32_t variant;            /* configuration checked (index as in rb_info) */
+    int32_t block_kernel;       /* 1: large-graph block kernel, 0: group-kernel tile */
+    int32_t lds_bytes;          /* LDS image of one block (block kernel) or one wave (tile) */
+    int64_t check_gathers;      /* table-driven Lambda gathers of one iteration (wave-wide) */
+    int64_t check_bank_cycles;  /* their summed modelled cost */
+    int64_t fault_gathers;      /* table-driven message gathers of one iteration (wave-wide) */
+    int64_t fault_bank_cycles;  /* their summed modelled cost */
+} rb_plan_report;
+
+/*
+ * Host-only diagnostics (no device use, no context): builds the per-lane LDS
+ * gather tables that rb_create would upload for H (M, N, nnz, rows, cols as in
+ * rb_create) and configuration `variant` (-1: the one rb_create chooses), then
+ * reads them back the way the kernels do and checks them against H: every
+ * edge (i, j) is gathered exactly once on the check side, at the marginal of
+ * fault j, by a lane working on check i; fault j gathers the messages of its
+ * checks in ascending i (the summation order of the marginal, paper Sec. 2.3
+ * DMem-BP), each at the word where check i writes the message of edge (i, j);
+ * every other entry addresses the pad cell; addresses fit their 16-bit fields
+ * and the LDS image.  On success *out holds the modelled bank cost of the
+ * gathers.  RB_E_SHAPE / RB_E_INVALID_ARG / RB_E_DUPLICATE_ENTRY as in
+ * rb_create; RB_E_UNSUPPORTED if the graph does not fit the configuration;
+ * RB_E_INTERNAL if a table breaks a rule (rb_last_error_message names it).
+ */
+rb_status rb_plan_check(int32_t M, int32_t N, int64_t nnz, const int32_t *rows, const int32_t *cols,
+                        int32_t variant, rb_plan_report *out);
 
 /*
  * Measures every built-in kernel configuration the graph fits on B syndromes

@@ -264,9 +264,20 @@ std::vector<int32_t> group_edge_order(const rb_ctx *c, const rb::TileShape &s, c
     return pos;
 }
 
-rb_status build_plan(rb_ctx *c, int v) {
-    const rb::TileShape s = rb::variant_shape(v);
-    const Layout lay = slot_layout(s, c->N);
+// Host tables of a group-kernel tile: per lane, two 16-bit slot-relative LDS
+// byte offsets per word (entry 2q in the low half, 2q+1 in the high half).
+// lam: [G][ceil(CPT*DC/2)], the Lambda gathers of each check step (pad: the
+// +inf cell); mu: [G][ceil(VPT*DV/2)], the message gathers of each fault in
+// ascending check order (pad: the -0 cell).
+struct GroupTables {
+    Layout lay{};
+    std::vector<uint32_t> lam, mu;
+};
+
+GroupTables group_tables(const rb_ctx *c, const rb::TileShape &s) {
+    GroupTables T;
+    T.lay = slot_layout(s, c->N);
+    const Layout &lay = T.lay;
     const int nl = s.CPT * s.DC, nm = s.VPT * s.DV;
     const int nlp = (nl + 1) / 2, nmp = (nm + 1) / 2;
     std::vector<uint16_t> lam16((size_t)s.G * nlp * 2, (uint16_t)lay.lampad_off);
@@ -292,10 +303,18 @@ rb_status build_plan(rb_ctx *c, int v) {
             }
         }
     }
-    // pack pairs (entry 2q in the low half, 2q+1 in the high half)
-    std::vector<uint32_t> lam((size_t)s.G * nlp), mu((size_t)s.G * nmp);
-    for (size_t q = 0; q < lam.size(); ++q) lam[q] = (uint32_t)lam16[2 * q] | ((uint32_t)lam16[2 * q + 1] << 16);
-    for (size_t q = 0; q < mu.size(); ++q) mu[q] = (uint32_t)mu16[2 * q] | ((uint32_t)mu16[2 * q + 1] << 16);
+    T.lam.resize((size_t)s.G * nlp);
+    T.mu.resize((size_t)s.G * nmp);
+    for (size_t q = 0; q < T.lam.size(); ++q) T.lam[q] = (uint32_t)lam16[2 * q] | ((uint32_t)lam16[2 * q + 1] << 16);
+    for (size_t q = 0; q < T.mu.size(); ++q) T.mu[q] = (uint32_t)mu16[2 * q] | ((uint32_t)mu16[2 * q + 1] << 16);
+    return T;
+}
+
+rb_status build_plan(rb_ctx *c, int v) {
+    const rb::TileShape s = rb::variant_shape(v);
+    const GroupTables T = group_tables(c, s);
+    const Layout &lay = T.lay;
+    const std::vector<uint32_t> &lam = T.lam, &mu = T.mu;
     (void)hipFree(c->d_lam_off);
     (void)hipFree(c->d_mu_off);
     c->d_lam_off = nullptr;
@@ -924,6 +943,214 @@ BlockTables block_tables(const rb_ctx *c, const rb::BlockShape &s) {
     return T;
 }
 
+// ---- independent reading of the gather tables (rb_plan_check) ----
+//
+// The tables are decoded exactly as the kernels read them and compared with
+// the graph itself, not with the planner's intermediate maps.  LDS cost model:
+// 32 banks of 4-byte words (bank = word address mod 32); a wave-wide gather
+// costs the largest number of distinct words on one bank (64 distinct words
+// cost at least 2; a word read by several lanes counts once).
+
+int gather_cost(std::vector<uint32_t> &words) {
+    std::sort(words.begin(), words.end());
+    words.erase(std::unique(words.begin(), words.end()), words.end());
+    int per_bank[32] = {0}, m = 0;
+    for (uint32_t w : words) m = std::max(m, ++per_bank[w % 32u]);
+    return m;
+}
+
+// CSR edge of (i, j), or -1
+int64_t find_edge(const rb_ctx *c, int32_t i, int32_t j) {
+    const auto b = c->colidx.begin() + c->rowptr[i], e = c->colidx.begin() + c->rowptr[i + 1];
+    const auto it = std::lower_bound(b, e, j);
+    return (it != e && *it == j) ? (int64_t)(it - c->colidx.begin()) : -1;
+}
+
+std::string check_group_tables(const rb_ctx *c, const rb::TileShape &s, const GroupTables &T, rb_plan_report *r) {
+    const Layout &lay = T.lay;
+    const int NS = 64 / s.G, nl = s.CPT * s.DC, nm = s.VPT * s.DV;
+    const int nlp = (nl + 1) / 2, nmp = (nm + 1) / 2;
+    if (T.lam.size() != (size_t)s.G * nlp || T.mu.size() != (size_t)s.G * nmp) return "table sizes";
+    if (lay.lds_bytes > 65536) return "LDS image exceeds the 16-bit offsets";
+    auto entry = [](const std::vector<uint32_t> &t, size_t row, int idx) {
+        const uint32_t w = t[row + (size_t)(idx / 2)];
+        return (idx & 1) ? (w >> 16) : (w & 0xffffu);
+    };
+    // offsets are ORed with the slot base 4*slot < word: multiples of word
+    for (uint32_t w : T.lam)
+        if ((w & 0xffffu) % lay.word || (w >> 16) % lay.word) return "Lambda offset not slot-aligned";
+    for (uint32_t w : T.mu)
+        if ((w & 0xffffu) % lay.word || (w >> 16) % lay.word) return "message offset not slot-aligned";
+    std::vector<int32_t> step((size_t)c->E, -1);
+    for (int g = 0; g < s.G; ++g)
+        for (int cc = 0; cc < s.CPT; ++cc) {
+            const int i = g + s.G * cc;
+            for (int k = 0; k < s.DC; ++k) {
+                const uint32_t a = entry(T.lam, (size_t)g * nlp, cc * s.DC + k);
+                if (a == lay.lampad_off) continue;
+                const std::string at = "check " + std::to_string(i) + " step " + std::to_string(k);
+                if (i >= c->M) return at + ": gather on a spare check row";
+                const uint32_t j = a / lay.word;
+                if (j >= (uint32_t)c->N) return at + ": Lambda offset outside the marginals";
+                const int64_t e = find_edge(c, i, (int32_t)j);
+                if (e < 0) return at + ": fault " + std::to_string(j) + " is not in the check";
+                if (step[(size_t)e] >= 0) return at + ": edge gathered twice";
+                step[(size_t)e] = k;
+            }
+        }
+    for (int64_t e = 0; e < c->E; ++e)
+        if (step[(size_t)e] < 0) return "CSR edge " + std::to_string(e) + " never gathered by its check";
+    for (int g = 0; g < s.G; ++g)
+        for (int vv = 0; vv < s.VPT; ++vv) {
+            const int j = g + s.G * vv;
+            const int64_t d = j < c->N ? c->colptr[j + 1] - c->colptr[j] : 0;
+            for (int k = 0; k < s.DV; ++k) {
+                const uint32_t a = entry(T.mu, (size_t)g * nmp, vv * s.DV + k);
+                uint32_t want = lay.mupad_off;
+                if (k < d) {  // k-th check of the fault in ascending order
+                    const int32_t i = c->rowidx[(size_t)(c->colptr[j] + k)];
+                    const int64_t e = find_edge(c, i, j);
+                    want = lay.mu0_off + lay.word * ((uint32_t)i * (uint32_t)lay.rs + (uint32_t)step[(size_t)e]);
+                }
+                if (a != want)
+                    return "fault " + std::to_string(j) + " gather " + std::to_string(k) + ": offset " +
+                           std::to_string(a) + ", the message word is " + std::to_string(want);
+            }
+        }
+    // bank model over a whole wave (NS interleaved slots of G lanes)
+    std::vector<uint32_t> words;
+    auto wave = [&](const std::vector<uint32_t> &t, int nrow, int idx) {
+        words.clear();
+        for (int sl = 0; sl < NS; ++sl)
+            for (int g = 0; g < s.G; ++g) words.push_back((entry(t, (size_t)g * nrow, idx) | (4u * sl)) / 4u);
+        return gather_cost(words);
+    };
+    for (int q = 0; q < nl; ++q) {
+        r->check_gathers += 1;
+        r->check_bank_cycles += wave(T.lam, nlp, q);
+    }
+    for (int q = 0; q < nm; ++q) {
+        r->fault_gathers += 1;
+        r->fault_bank_cycles += wave(T.mu, nmp, q);
+    }
+    r->lds_bytes = lay.lds_bytes;
+    return "";
+}
+
+std::string check_block_tables(const rb_ctx *c, const rb::BlockShape &s, const BlockTables &T, rb_plan_report *r) {
+    const BlockLayout &lay = T.lay;
+    const int TPB = s.TPB, nw = TPB / 64;
+    const int nmu = rb::prof_pre(s.prof, s.VPT), nmp = (nmu + 1) / 2, ncp = s.DCMAX / 2;
+    if (T.col_pk.size() != (size_t)(ncp + 4) * TPB || T.mu_pk.size() != (size_t)nmp * TPB) return "table sizes";
+    if (T.chk_row.size() != (size_t)TPB || T.chk_split.size() != (size_t)TPB ||
+        T.slot_col.size() != (size_t)TPB * s.VPT || T.wdeg.size() != (size_t)nw || T.wbase.size() != (size_t)nw)
+        return "map sizes";
+    if (lay.lds_bytes > 160 * 1024) return "LDS image exceeds a CU";
+    // slots: a permutation of the faults on slots 0..N-1, band caps respected
+    std::vector<int32_t> slot_of((size_t)c->N, -1);
+    for (int64_t q = 0; q < (int64_t)TPB * s.VPT; ++q) {
+        const int32_t j = T.slot_col[(size_t)q];
+        if ((q < c->N) != (j >= 0)) return "slot " + std::to_string(q) + ": real slots must be exactly 0..N-1";
+        if (j < 0) continue;
+        if (j >= c->N || slot_of[(size_t)j] >= 0) return "slot " + std::to_string(q) + ": fault repeated or out of range";
+        slot_of[(size_t)j] = (int32_t)q;
+        if (c->colptr[j + 1] - c->colptr[j] > rb::prof_dv(s.prof, (int)(q / TPB)))
+            return "fault " + std::to_string(j) + " exceeds its band's gather count";
+    }
+    if (lay.lampad_off < 4u * (uint32_t)c->N || lay.lampad_off + 4u > 65536u) return "Lambda pad cell";
+    // message rows: wave w owns words [wbase[w], wbase[w] + 64 wdeg[w]) after mu0
+    int64_t words_end = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (T.wdeg[w] < 0 || T.wdeg[w] > s.DCMAX) return "wave " + std::to_string(w) + ": row count";
+        if (T.wbase[w] != words_end) return "wave " + std::to_string(w) + ": message rows not contiguous";
+        words_end += 64ll * T.wdeg[w];
+    }
+    const int64_t mu0w = lay.mu0_off / 4u;
+    if (mu0w + words_end > 65535) return "message words exceed the 16-bit indices";
+    if (4 * (mu0w + words_end + (rb::kBlockChunk - 1) * 64) > (int64_t)lay.lds_bytes)
+        return "message rows and slack exceed the LDS image";
+    // checks: chk_row names each check once; a split check sits on lanes 2p, 2p+1
+    std::vector<int32_t> row_of((size_t)TPB, -1), seen((size_t)c->M, 0);
+    for (int t = 0; t < TPB; ++t) {
+        const int32_t i = T.chk_row[t];
+        if (i < -1 || i >= c->M) return "thread " + std::to_string(t) + ": check index";
+        if (i >= 0 && seen[(size_t)i]++) return "check " + std::to_string(i) + " on two threads";
+    }
+    for (int32_t i = 0; i < c->M; ++i)
+        if (!seen[(size_t)i]) return "check " + std::to_string(i) + " has no thread";
+    for (int t = 0; t < TPB; ++t) {
+        if (T.chk_split[t]) {
+            if (!T.chk_split[t ^ 1]) return "thread " + std::to_string(t) + ": split partner";
+            if ((T.chk_row[t] >= 0) == (T.chk_row[t ^ 1] >= 0)) return "thread " + std::to_string(t) + ": split owner";
+            row_of[t] = T.chk_row[t] >= 0 ? T.chk_row[t] : T.chk_row[t ^ 1];
+        } else {
+            row_of[t] = T.chk_row[t];
+        }
+    }
+    auto col_entry = [&](int t, int k) {  // [chunk of 8][thread][4 words of two halves]
+        const uint32_t w = T.col_pk[((size_t)(k / 8) * TPB + t) * 4 + (size_t)((k / 2) % 4)];
+        return (k & 1) ? (w >> 16) : (w & 0xffffu);
+    };
+    for (int k = 0; k < (ncp + 4) * 2; ++k)  // the padding chunk included
+        for (int t = 0; t < TPB; ++t)
+            if (k >= T.wdeg[t / 64] && col_entry(t, k) != lay.lampad_off)
+                return "thread " + std::to_string(t) + " step " + std::to_string(k) + ": gather past the wave's rows";
+    std::vector<int64_t> word_of((size_t)c->E, -1);  // message word each edge's check writes
+    for (int t = 0; t < TPB; ++t)
+        for (int k = 0; k < T.wdeg[t / 64]; ++k) {
+            const uint32_t a = col_entry(t, k);
+            if (a == lay.lampad_off) continue;
+            const std::string at = "thread " + std::to_string(t) + " step " + std::to_string(k);
+            if (row_of[t] < 0) return at + ": gather on an idle thread";
+            if (a % 4u || a / 4u >= (uint32_t)c->N) return at + ": Lambda address outside the marginals";
+            const int32_t j = T.slot_col[a / 4u];
+            const int64_t e = find_edge(c, row_of[t], j);
+            if (e < 0) return at + ": fault " + std::to_string(j) + " is not in check " + std::to_string(row_of[t]);
+            if (word_of[(size_t)e] >= 0) return at + ": edge gathered twice";
+            word_of[(size_t)e] = mu0w + T.wbase[t / 64] + 64ll * k + (t % 64);
+        }
+    for (int64_t e = 0; e < c->E; ++e)
+        if (word_of[(size_t)e] < 0) return "CSR edge " + std::to_string(e) + " never gathered by its check";
+    auto mu_entry = [&](int t, int idx) {
+        const uint32_t w = T.mu_pk[(size_t)(idx / 2) * TPB + t];
+        return (idx & 1) ? (w >> 16) : (w & 0xffffu);
+    };
+    for (int t = 0; t < TPB; ++t)
+        for (int v = 0; v < s.VPT; ++v) {
+            const int32_t j = T.slot_col[(size_t)t + (size_t)TPB * v];
+            const int64_t d = j >= 0 ? c->colptr[j + 1] - c->colptr[j] : 0;
+            for (int k = 0; k < rb::prof_dv(s.prof, v); ++k) {
+                const uint32_t a = mu_entry(t, rb::prof_pre(s.prof, v) + k);
+                int64_t want = lay.mupad_off / 4u;
+                if (k < d) {  // k-th check of the fault in ascending order
+                    const int32_t i = c->rowidx[(size_t)(c->colptr[j] + k)];
+                    want = word_of[(size_t)find_edge(c, i, j)];
+                }
+                if ((int64_t)a != want)
+                    return "fault " + std::to_string(j) + " gather " + std::to_string(k) + ": word " + std::to_string(a) +
+                           ", the message word is " + std::to_string(want);
+            }
+        }
+    std::vector<uint32_t> words;
+    for (int w = 0; w < nw; ++w)
+        for (int k = 0; k < T.wdeg[w]; ++k) {
+            words.clear();
+            for (int l = 0; l < 64; ++l) words.push_back(col_entry(64 * w + l, k) / 4u);
+            r->check_gathers += 1;
+            r->check_bank_cycles += gather_cost(words);
+        }
+    for (int w = 0; w < nw; ++w)
+        for (int v = 0; v < s.VPT; ++v)
+            for (int k = 0; k < rb::prof_dv(s.prof, v); ++k) {
+                words.clear();
+                for (int l = 0; l < 64; ++l) words.push_back(mu_entry(64 * w + l, rb::prof_pre(s.prof, v) + k));
+                r->fault_gathers += 1;
+                r->fault_bank_cycles += gather_cost(words);
+            }
+    r->lds_bytes = lay.lds_bytes;
+    return "";
+}
+
 rb_status build_block_plan(rb_ctx *c, int bv) {
     const rb::BlockShape s = rb::block_variant_shape(bv);
     const BlockTables T = block_tables(c, s);
@@ -998,6 +1225,92 @@ rb_status check_params(const rb_params *p) {
     return RB_OK;
 }
 
+// Validates H (COO) and the priors and builds the host part of a context: the
+// CSR / CSC edge layouts, the degrees and the FP32 channel LLRs (no device
+// work).  prior_p may be NULL (plan diagnostics only: w = 0).
+rb_status host_graph(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32_t *rows, const int32_t *cols,
+                     const double *prior_p) {
+    *out = nullptr;
+    if (M < 1 || N < 1) return fail(RB_E_SHAPE, "M and N must be >= 1");
+    if (nnz < 0) return fail(RB_E_INVALID_ARG, "nnz must be >= 0");
+    if (nnz > 0 && (!rows || !cols)) return fail(RB_E_INVALID_ARG, "rows/cols is NULL");
+    if (nnz > (int64_t)M * (int64_t)N) return fail(RB_E_SHAPE, "nnz exceeds M*N");
+    for (int64_t k = 0; k < nnz; ++k)
+        if (rows[k] < 0 || rows[k] >= M || cols[k] < 0 || cols[k] >= N)
+            return fail(RB_E_SHAPE, "entry " + std::to_string(k) + " out of range");
+    for (int32_t j = 0; prior_p && j < N; ++j) {
+        const double p = prior_p[j];
+        if (!std::isfinite(p)) return fail(RB_E_PRIOR_RANGE, "prior " + std::to_string(j) + " not finite");
+        if (!(p > 0.0 && p < 1.0)) return fail(RB_E_PRIOR_RANGE, "prior " + std::to_string(j) + " outside (0, 1)");
+    }
+    // sort (row, col) pairs; duplicates would silently cancel over F_2
+    std::vector<std::pair<int32_t, int32_t>> rc((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) rc[k] = {rows[k], cols[k]};
+    std::sort(rc.begin(), rc.end());
+    for (int64_t k = 1; k < nnz; ++k)
+        if (rc[k] == rc[k - 1])
+            return fail(RB_E_DUPLICATE_ENTRY, "duplicate entry (" + std::to_string(rc[k].first) + ", " +
+                                                  std::to_string(rc[k].second) + ")");
+    rb_ctx *c = new (std::nothrow) rb_ctx();
+    if (!c) return fail(RB_E_OOM, "host allocation failed");
+    c->M = M;
+    c->N = N;
+    c->E = nnz;
+    c->rowptr.assign((size_t)M + 1, 0);
+    c->colidx.resize((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) {
+        c->rowptr[rc[k].first + 1]++;
+        c->colidx[k] = rc[k].second;
+    }
+    for (int32_t i = 0; i < M; ++i) c->rowptr[i + 1] += c->rowptr[i];
+    c->colptr.assign((size_t)N + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) c->colptr[rc[k].second + 1]++;
+    for (int32_t j = 0; j < N; ++j) c->colptr[j + 1] += c->colptr[j];
+    c->rowidx.resize((size_t)nnz);
+    c->cpos.resize((size_t)nnz);
+    {
+        std::vector<int64_t> fill(c->colptr.begin(), c->colptr.end() - 1);
+        for (int32_t i = 0; i < M; ++i)  // rows ascending => column lists ascending in i
+            for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) {
+                const int32_t j = c->colidx[e];
+                c->rowidx[fill[j]] = i;
+                c->cpos[fill[j]] = (int32_t)(e - c->rowptr[i]);
+                ++fill[j];
+            }
+    }
+    for (int32_t i = 0; i < M; ++i) c->max_row = std::max<int32_t>(c->max_row, (int32_t)(c->rowptr[i + 1] - c->rowptr[i]));
+    for (int32_t j = 0; j < N; ++j) c->max_col = std::max<int32_t>(c->max_col, (int32_t)(c->colptr[j + 1] - c->colptr[j]));
+    c->w.assign((size_t)N, 0.0f);
+    for (int32_t j = 0; prior_p && j < N; ++j) c->w[j] = (float)std::log((1.0 - prior_p[j]) / prior_p[j]);
+    *out = c;
+    return RB_OK;
+}
+
+// The cheapest built-in group-kernel tile the graph fits; for larger graphs
+// the first block-kernel shape that fits; -1 if none.
+int choose_variant(const rb_ctx *c) {
+    int best = -1;
+    double best_cost = 0.0;
+    for (int v = 0; v < rb::num_variants(); ++v) {
+        const rb::TileShape s = rb::variant_shape(v);
+        if (!variant_fits(c, s)) continue;
+        const double cost = variant_cost(s);
+        if (best < 0 || cost < best_cost) {
+            best = v;
+            best_cost = cost;
+        }
+    }
+    for (int bv = 0; bv < rb::num_block_variants() && best < 0; ++bv)
+        if (block_fits(c, rb::block_variant_shape(bv))) best = rb::num_variants() + bv;
+    return best;
+}
+
+std::string unsupported_message(const rb_ctx *c) {
+    return "graph exceeds every built-in kernel configuration (M=" + std::to_string(c->M) + ", N=" +
+           std::to_string(c->N) + ", max row degree " + std::to_string(c->max_row) + ", max column degree " +
+           std::to_string(c->max_col) + ")";
+}
+
 }  // namespace
 
 extern "C" {
@@ -1014,6 +1327,7 @@ const char *rb_status_string(rb_status s) {
         case RB_E_WORKSPACE: return "workspace too small";
         case RB_E_UNSUPPORTED: return "unsupported graph or configuration";
         case RB_E_NONFINITE: return "non-finite value";
+        case RB_E_INTERNAL: return "internal consistency check failed";
     }
     return "unknown status";
 }
@@ -1043,87 +1357,17 @@ rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32
     g_last_error.clear();
     if (!out) return fail(RB_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (M < 1 || N < 1) return fail(RB_E_SHAPE, "M and N must be >= 1");
-    if (nnz < 0) return fail(RB_E_INVALID_ARG, "nnz must be >= 0");
-    if (nnz > 0 && (!rows || !cols)) return fail(RB_E_INVALID_ARG, "rows/cols is NULL");
     if (!prior_p) return fail(RB_E_INVALID_ARG, "prior_p is NULL");
     if (device < 0) return fail(RB_E_INVALID_ARG, "device must be >= 0");
-    if (nnz > (int64_t)M * (int64_t)N) return fail(RB_E_SHAPE, "nnz exceeds M*N");
     rb_status st = check_params(params);
     if (st != RB_OK) return st;
-    for (int64_t k = 0; k < nnz; ++k)
-        if (rows[k] < 0 || rows[k] >= M || cols[k] < 0 || cols[k] >= N)
-            return fail(RB_E_SHAPE, "entry " + std::to_string(k) + " out of range");
-    for (int32_t j = 0; j < N; ++j) {
-        const double p = prior_p[j];
-        if (!std::isfinite(p)) return fail(RB_E_PRIOR_RANGE, "prior " + std::to_string(j) + " not finite");
-        if (!(p > 0.0 && p < 1.0)) return fail(RB_E_PRIOR_RANGE, "prior " + std::to_string(j) + " outside (0, 1)");
-    }
-    // sort (row, col) pairs; duplicates would silently cancel over F_2
-    std::vector<std::pair<int32_t, int32_t>> rc((size_t)nnz);
-    for (int64_t k = 0; k < nnz; ++k) rc[k] = {rows[k], cols[k]};
-    std::sort(rc.begin(), rc.end());
-    for (int64_t k = 1; k < nnz; ++k)
-        if (rc[k] == rc[k - 1])
-            return fail(RB_E_DUPLICATE_ENTRY, "duplicate entry (" + std::to_string(rc[k].first) + ", " +
-                                                  std::to_string(rc[k].second) + ")");
-
-    rb_ctx *c = new (std::nothrow) rb_ctx();
-    if (!c) return fail(RB_E_OOM, "host allocation failed");
+    rb_ctx *c = nullptr;
+    if ((st = host_graph(&c, M, N, nnz, rows, cols, prior_p)) != RB_OK) return st;
     c->device = device;
-    c->M = M;
-    c->N = N;
-    c->E = nnz;
     c->params = *params;
-    c->rowptr.assign((size_t)M + 1, 0);
-    c->colidx.resize((size_t)nnz);
-    for (int64_t k = 0; k < nnz; ++k) {
-        c->rowptr[rc[k].first + 1]++;
-        c->colidx[k] = rc[k].second;
-    }
-    for (int32_t i = 0; i < M; ++i) c->rowptr[i + 1] += c->rowptr[i];
-    c->colptr.assign((size_t)N + 1, 0);
-    for (int64_t k = 0; k < nnz; ++k) c->colptr[rc[k].second + 1]++;
-    for (int32_t j = 0; j < N; ++j) c->colptr[j + 1] += c->colptr[j];
-    c->rowidx.resize((size_t)nnz);
-    c->cpos.resize((size_t)nnz);
-    {
-        std::vector<int64_t> fill(c->colptr.begin(), c->colptr.end() - 1);
-        for (int32_t i = 0; i < M; ++i)  // rows ascending => column lists ascending in i
-            for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) {
-                const int32_t j = c->colidx[e];
-                c->rowidx[fill[j]] = i;
-                c->cpos[fill[j]] = (int32_t)(e - c->rowptr[i]);
-                ++fill[j];
-            }
-    }
-    for (int32_t i = 0; i < M; ++i) c->max_row = std::max<int32_t>(c->max_row, (int32_t)(c->rowptr[i + 1] - c->rowptr[i]));
-    for (int32_t j = 0; j < N; ++j) c->max_col = std::max<int32_t>(c->max_col, (int32_t)(c->colptr[j + 1] - c->colptr[j]));
-    c->w.resize((size_t)N);
-    for (int32_t j = 0; j < N; ++j) c->w[j] = (float)std::log((1.0 - prior_p[j]) / prior_p[j]);
-
-    // pick the cheapest built-in configuration the graph fits
-    int best = -1;
-    double best_cost = 0.0;
-    for (int v = 0; v < rb::num_variants(); ++v) {
-        const rb::TileShape s = rb::variant_shape(v);
-        if (!variant_fits(c, s)) continue;
-        const double cost = variant_cost(s);
-        if (best < 0 || cost < best_cost) {
-            best = v;
-            best_cost = cost;
-        }
-    }
+    const int best = choose_variant(c);
     if (best < 0) {
-        // large graphs: the first block-kernel shape that fits
-        for (int bv = 0; bv < rb::num_block_variants() && best < 0; ++bv)
-            if (block_fits(c, rb::block_variant_shape(bv))) best = rb::num_variants() + bv;
-    }
-    if (best < 0) {
-        const std::string msg = "graph exceeds every built-in kernel configuration (M=" +
-                                std::to_string(M) + ", N=" + std::to_string(N) +
-                                ", max row degree " + std::to_string(c->max_row) +
-                                ", max column degree " + std::to_string(c->max_col) + ")";
+        const std::string msg = unsupported_message(c);
         delete c;
         return fail(RB_E_UNSUPPORTED, msg);
     }
@@ -1444,6 +1688,36 @@ rb_status rb_set_variant(rb_ctx *c, int32_t v) {
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(hipDeviceSynchronize(), "sync before re-plan");
     return plan(c, v);
+}
+
+rb_status rb_plan_check(int32_t M, int32_t N, int64_t nnz, const int32_t *rows, const int32_t *cols,
+                        int32_t variant, rb_plan_report *out) {
+    g_last_error.clear();
+    if (!out) return fail(RB_E_INVALID_ARG, "out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    if (variant < -1 || variant >= total_variants()) return fail(RB_E_INVALID_ARG, "variant out of range");
+    rb_ctx *c = nullptr;
+    rb_status st = host_graph(&c, M, N, nnz, rows, cols, nullptr);
+    if (st != RB_OK) return st;
+    const int v = variant < 0 ? choose_variant(c) : variant;
+    if (v < 0 || !any_fits(c, v)) {
+        const std::string msg = v < 0 ? unsupported_message(c) : "graph does not fit the variant";
+        delete c;
+        return fail(RB_E_UNSUPPORTED, msg);
+    }
+    out->variant = v;
+    std::string err;
+    if (v < rb::num_variants()) {
+        const rb::TileShape s = rb::variant_shape(v);
+        err = check_group_tables(c, s, group_tables(c, s), out);
+    } else {
+        const rb::BlockShape s = rb::block_variant_shape(v - rb::num_variants());
+        out->block_kernel = 1;
+        err = check_block_tables(c, s, block_tables(c, s), out);
+    }
+    delete c;
+    if (!err.empty()) return fail(RB_E_INTERNAL, "gather tables of variant " + std::to_string(v) + ": " + err);
+    return RB_OK;
 }
 
 // mean time of one decode of B syndromes with the context's current plan

@@ -20,7 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "relaybp.h")
 STATUS = {
     0: "RB_OK", 1: "RB_E_INVALID_ARG", 2: "RB_E_SHAPE", 3: "RB_E_DUPLICATE_ENTRY",
     4: "RB_E_PRIOR_RANGE", 5: "RB_E_DEVICE", 6: "RB_E_OOM", 7: "RB_E_WORKSPACE",
-    8: "RB_E_UNSUPPORTED", 9: "RB_E_NONFINITE",
+    8: "RB_E_UNSUPPORTED", 9: "RB_E_NONFINITE", 10: "RB_E_INTERNAL",
 }
 ANCHOR_CHAIN, ANCHOR_PRIOR = 0, 1
 
@@ -54,6 +54,12 @@ class RBInfo(ctypes.Structure):
             "row_slots", "cols_per_lane", "col_slots", "shots_per_block", "threads_per_block",
             "waves_per_simd_target", "lds_bytes_per_block", "blocks_per_cu", "grid_blocks",
             "num_variants")]
+
+
+class RBPlanReport(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("block_kernel", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("check_gathers", ctypes.c_int64), ("check_bank_cycles", ctypes.c_int64),
+                ("fault_gathers", ctypes.c_int64), ("fault_bank_cycles", ctypes.c_int64)]
 
 
 class RBCodeDesc(ctypes.Structure):
@@ -99,6 +105,7 @@ def load_library():
     L.rb_train_tape_size.restype = ctypes.c_size_t
     L.rb_forward_train.argtypes = [P, i64, P, P, P, i32, i32, P, P, ctypes.c_size_t, P]
     L.rb_backward.argtypes = [P, i64, P, P, P, i32, i32, P, ctypes.c_size_t, P, P, P, P]
+    L.rb_plan_check.argtypes = [i32, i32, i64, P, P, i32, ctypes.POINTER(RBPlanReport)]
     L.rb_status_string.argtypes = [ctypes.c_int]
     L.rb_status_string.restype = ctypes.c_char_p
     L.rb_last_error_message.argtypes = []
@@ -107,7 +114,7 @@ def load_library():
                  "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status",
                  "rb_autotune", "rb_reserve", "rb_create_multi", "rb_decode_multi",
                  "rb_autotune_multi", "rb_forward_train", "rb_backward", "rb_set_leg_gamma",
-                 "rb_set_prior_scale"):
+                 "rb_set_prior_scale", "rb_plan_check"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -146,6 +153,21 @@ def bp_params(rounds=25, **overrides) -> dict:
              gamma_lo=0.0, gamma_hi=0.0, llr_clip=2.0 ** 64, seed=0, anchor=ANCHOR_CHAIN, max_total_iters=0)
     p.update(overrides)
     return p
+
+
+def plan_check(m: int, n: int, rows, cols, variant: int = -1) -> dict:
+    """Host-only check of the LDS gather tables for H (rows, cols: COO) on
+    configuration `variant` (-1: the automatic choice); raises RelayError
+    (RB_E_INTERNAL) if a table is inconsistent with H.  Returns the report:
+    configuration, LDS bytes, and the number and modelled bank cost of the
+    table-driven gathers of one iteration (2 per gather is conflict-free)."""
+    L = load_library()
+    rows = np.ascontiguousarray(rows, np.int32)
+    cols = np.ascontiguousarray(cols, np.int32)
+    rep = RBPlanReport()
+    _check(L.rb_plan_check(m, n, rows.size, rows.ctypes.data_as(ctypes.c_void_p),
+                           cols.ctypes.data_as(ctypes.c_void_p), variant, ctypes.byref(rep)))
+    return {f: getattr(rep, f) for f, _ in RBPlanReport._fields_}
 
 
 def _ptr(t):

@@ -23,7 +23,7 @@ def test_exports_every_header_symbol(lib):
 
 
 def test_status_strings(lib):
-    for code in range(10):
+    for code in range(11):
         s = lib.rb_status_string(code)
         assert s and s != b"unknown status"
     assert lib.rb_status_string(99) == b"unknown status"

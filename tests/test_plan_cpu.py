@@ -1,0 +1,127 @@
+"""Host-only checks of the LDS gather tables (rb_plan_check): for every kernel
+configuration a graph fits, the tables that rb_create would upload are read
+back the way the kernels read them and compared with H itself -- every edge
+gathered once on each side, each fault's messages in ascending check order
+(the summation order of the marginal, paper Sec. 2.3 DMem-BP), pads on the pad
+cells, addresses inside their 16-bit fields and the LDS image.  No GPU."""
+import numpy as np
+import pytest
+
+from paper_2511_21660_amd import relaybp as rb
+from workloads import codes
+
+
+def _num_configs():
+    p = codes.bb_problem("bb72", 0.05)
+    lib = rb.load_library()
+    # variant out of range is rejected before any work; probe the table size
+    n = 0
+    while True:
+        try:
+            rb.plan_check(p.m, p.n, p.rows, p.cols, n)
+        except rb.RelayError as e:
+            if e.status == 1:
+                return n
+        n += 1
+        assert n < 64, lib
+
+
+def _all_fitting(m, n, rows, cols):
+    """Report per configuration the graph fits (RB_E_UNSUPPORTED skipped)."""
+    out = {}
+    for v in range(_num_configs()):
+        try:
+            out[v] = rb.plan_check(m, n, rows, cols, v)
+        except rb.RelayError as e:
+            assert e.status == 8, str(e)
+    return out
+
+
+def _random_graph(m, n, row_deg, col_cap, seed, empty_rows=0, empty_cols=0):
+    """Random H with the given mean row degree, column degree capped, and some
+    rows / columns left empty."""
+    rng = np.random.default_rng(seed)
+    live_r = np.arange(empty_rows, m)
+    live_c = np.arange(empty_cols, n)
+    cnt = np.zeros(n, np.int64)
+    rows, cols = [], []
+    for i in live_r:
+        d = int(rng.integers(1, 2 * row_deg))
+        choice = [j for j in rng.permutation(live_c) if cnt[j] < col_cap][:d]
+        for j in choice:
+            cnt[j] += 1
+            rows.append(i)
+            cols.append(j)
+    return np.array(rows, np.int32), np.array(cols, np.int32)
+
+
+@pytest.mark.parametrize("name", ["bb72", "bb90", "bb144", "bb288"])
+def test_bb_codes_every_configuration(name):
+    p = codes.bb_problem(name, 0.05)
+    reps = _all_fitting(p.m, p.n, p.rows, p.cols)
+    assert reps, "no configuration fits"
+    for v, r in reps.items():
+        assert r["variant"] == v
+        # every gather reads at least one word; 64 distinct words cost >= 2
+        assert r["check_gathers"] <= r["check_bank_cycles"] <= 64 * r["check_gathers"]
+        assert r["fault_gathers"] <= r["fault_bank_cycles"] <= 64 * r["fault_gathers"]
+    auto = rb.plan_check(p.m, p.n, p.rows, p.cols)
+    assert auto["variant"] in reps and auto["block_kernel"] == 0
+
+
+def test_dem_block_kernel_tables_and_bank_cost():
+    d = codes.dem_problem()
+    r = rb.plan_check(d.m, d.n, d.rows, d.cols)
+    assert r["block_kernel"] == 1 and r["lds_bytes"] <= 160 * 1024
+    # bank-aware placement: close to the conflict-free 2 cycles per gather
+    # (values of the current planner: 2.36 check side, 2.81 fault side)
+    assert r["check_bank_cycles"] / r["check_gathers"] < 2.5
+    assert r["fault_bank_cycles"] / r["fault_gathers"] < 3.0
+    reps = _all_fitting(d.m, d.n, d.rows, d.cols)
+    assert all(x["block_kernel"] == 1 for x in reps.values()) and len(reps) >= 2
+
+
+def test_ragged_graphs_with_empty_rows_and_columns():
+    # small: group tiles; larger with long rows: block kernel (split rows)
+    cases = [(20, 50, 4, 3, 1, 2, 3), (64, 200, 8, 6, 2, 0, 5), (300, 1500, 12, 8, 3, 7, 11),
+             (700, 4000, 30, 6, 4, 5, 0)]
+    for m, n, rd, cap, seed, er, ec in cases:
+        rows, cols = _random_graph(m, n, rd, cap, seed, er, ec)
+        reps = _all_fitting(m, n, rows, cols)
+        assert reps, (m, n)
+        for v, r in reps.items():
+            assert r["check_gathers"] > 0
+
+
+def test_long_rows_split_over_lane_pairs():
+    # rows of degree 40..60 (> 32) are split over two lanes in the block kernel
+    rng = np.random.default_rng(5)
+    m, n = 120, 3000
+    rows, cols = [], []
+    for i in range(m):
+        for j in rng.choice(n, int(rng.integers(40, 61)), replace=False):
+            rows.append(i)
+            cols.append(j)
+    rows, cols = np.array(rows, np.int32), np.array(cols, np.int32)
+    reps = _all_fitting(m, n, rows, cols)
+    assert any(r["block_kernel"] for r in reps.values())
+
+
+def test_rejections():
+    p = codes.bb_problem("bb72", 0.05)
+    with pytest.raises(rb.RelayError) as e:
+        rb.plan_check(p.m, p.n, p.rows, p.cols, -2)
+    assert e.value.status == 1
+    d = codes.dem_problem()
+    with pytest.raises(rb.RelayError) as e:
+        rb.plan_check(d.m, d.n, d.rows, d.cols, 0)  # the DEM does not fit a group tile
+    assert e.value.status == 8
+    rows = p.rows.copy()
+    rows[0] = p.m
+    with pytest.raises(rb.RelayError) as e:
+        rb.plan_check(p.m, p.n, rows, p.cols)
+    assert e.value.status == 2
+    with pytest.raises(rb.RelayError) as e:
+        rb.plan_check(p.m, p.n, np.r_[p.rows, p.rows[:1]], np.r_[p.cols, p.cols[:1]])
+    assert e.value.status == 3
+    assert rb.load_library().rb_plan_check(1, 1, 0, None, None, -1, None) == 1
