@@ -88,7 +88,7 @@ struct rb_ctx {
     int32_t m_max = 0, n_max = 0;
     // CSR / CSC on the device (training kernels)
     int32_t *d_rowptr = nullptr, *d_colidx = nullptr, *d_colptr = nullptr, *d_cedge = nullptr;
-    uint32_t lampad_off = 0, mupad_off = 0, mu0_off = 0;
+    uint32_t lampad_off = 0, mupad_off = 0, mu0_off = 0, half_off = 0;
     int lds_bytes = 0;
     int blocks_per_cu[2] = {0, 0};  // [trace]
     int num_cu = 0;
@@ -99,26 +99,34 @@ namespace {
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 struct Layout {
-    uint32_t lampad_off, mupad_off, mu0_off;  // interleaved byte offsets (word w -> 4 * w * NS)
-    uint32_t word;                            // bytes between consecutive words of a slot
+    uint32_t lampad_off, mupad_off, mu0_off;  // byte offsets within a slot's region (word w -> 4 * SPH * w)
+    uint32_t word;                            // bytes between consecutive words of a slot (4 * SPH)
+    uint32_t half_off;                        // bytes between the two half-wave regions
+    int sph;                                  // slots per half-wave region
     int rs;                                   // words per check-message row
     int lds_bytes;
 };
 
 // Slot layout in words: Lambda[0..G*VPT) (faults j >= N are spare words the
 // padded lanes write), +inf pad, -0 pad, then G*CPT check-message rows of
-// RS = DC|1 words.  The NS = 64/G slots of a wave are interleaved word by word.
+// RS = DC|1 words.  The SPH = 32/G slots of a half-wave (1 for G >= 32) are
+// interleaved word by word in one region; the wave's NS = 64/G slots fill
+// NS/SPH regions.
 Layout slot_layout(const rb::TileShape &s, int N) {
     Layout l{};
     const uint32_t ns = (uint32_t)(64 / s.G);
+    const uint32_t sph = s.G >= 32 ? 1u : 32u / (uint32_t)s.G;
     const uint32_t nl = (uint32_t)std::max(N, s.G * s.VPT);
-    l.word = 4u * ns;
+    l.sph = (int)sph;
+    l.word = 4u * sph;
     l.rs = s.DC | 1;
     l.lampad_off = l.word * nl;
     l.mupad_off = l.word * (nl + 1);
     l.mu0_off = l.word * (nl + 2);
     const uint64_t words = (uint64_t)(nl + 2) + (uint64_t)s.G * s.CPT * l.rs;
-    const uint64_t bytes = words * l.word;
+    const uint64_t region = words * l.word;
+    l.half_off = region > (1u << 30) ? (1u << 30) : (uint32_t)region;
+    const uint64_t bytes = region * (ns / sph);
     l.lds_bytes = bytes > (1u << 30) ? (1 << 30) : (int)bytes;
     return l;
 }
@@ -154,18 +162,21 @@ struct PlanRng {
 };
 
 // Edge order within each check for a group-kernel tile (free: the check
-// update does not depend on it).  A wave's gathers cost the largest number of
-// distinct words on one LDS bank.  The NS slots of a wave are interleaved word
-// by word, so each slot owns 32/NS banks (its "classes") and its G lanes are
-// conflict-free at two words per class.  Step k of check row c gathers Lambda
-// of the k-th fault of the G checks g + G*c (class: fault index mod 32/NS);
-// gather k of fault slot v reads the message of the k-th check of the G
-// faults g + G*v (class: message word mod 32/NS, which depends on the edge's
-// step in its check).  Random swaps of two edges of one check, accepted by a
-// simulated-annealing rule, lower the sum of both kinds of costs.  Returns the
-// step of every CSR edge.
+// update does not depend on it).  A wave's access is served in two halves of
+// 32 lanes, each costing the largest number of distinct words on one LDS
+// bank.  The slots of a half are interleaved word by word, so each slot owns
+// ncls = min(G, 32) banks (its "classes", word index mod ncls) and a gather
+// costs, per half, the largest number of the slot's lanes on one class (all
+// slots of a wave run the same tables; for G = 64 the slot spans both
+// halves).  Step k of check row c gathers Lambda of the k-th fault of the G
+// checks g + G*c (class: fault index mod ncls); gather k of fault slot v
+// reads the message of the k-th check of the G faults g + G*v (class:
+// message word mod ncls, which depends on the edge's step in its check).
+// Random swaps of two edges of one check, accepted by a simulated-annealing
+// rule, lower the sum of both kinds of costs.  Returns the step of every CSR
+// edge.
 std::vector<int32_t> group_edge_order(const rb_ctx *c, const rb::TileShape &s, const Layout &lay) {
-    const int NS = 64 / s.G, ncls = 32 / NS;
+    const int ncls = std::min(s.G, 32);
     std::vector<int32_t> pos((size_t)c->E), at((size_t)c->E);  // edge -> step; (row, step) -> edge
     for (int32_t i = 0; i < c->M; ++i)
         for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) {
@@ -186,41 +197,51 @@ std::vector<int32_t> group_edge_order(const rb_ctx *c, const rb::TileShape &s, c
         for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) fcol[(size_t)e] = c->colidx[e];
     auto deg_r = [&](int i) { return (int)(c->rowptr[i + 1] - c->rowptr[i]); };
     auto deg_c = [&](int j) { return (int)(c->colptr[j + 1] - c->colptr[j]); };
-    int h[64];
-    auto ccost = [&](int cc, int k) {
-        for (int q = 0; q < ncls; ++q) h[q] = 0;
-        bool pad = false;
-        for (int g = 0; g < s.G; ++g) {
-            const int i = g + s.G * cc;
-            if (i >= c->M || k >= deg_r(i)) {
-                pad = true;
-                continue;
-            }
-            ++h[fcol[(size_t)at[(size_t)(c->rowptr[i] + k)]] % ncls];
+    const int nh = s.G == 64 ? 2 : 1;  // halves a slot spans
+    int h[2][32];
+    bool padh[2];
+    auto clear = [&]() {
+        for (int x = 0; x < nh; ++x) {
+            padh[x] = false;
+            for (int q = 0; q < ncls; ++q) h[x][q] = 0;
         }
-        if (pad) ++h[lampad_cls];
+    };
+    auto total = [&](int pad_cls) {
         int m = 0;
-        for (int q = 0; q < ncls; ++q) m = std::max(m, h[q]);
+        for (int x = 0; x < nh; ++x) {
+            if (padh[x]) ++h[x][pad_cls];
+            int mx = 0;
+            for (int q = 0; q < ncls; ++q) mx = std::max(mx, h[x][q]);
+            m += mx;
+        }
         return m;
     };
-    auto fcost = [&](int vv, int k) {
-        for (int q = 0; q < ncls; ++q) h[q] = 0;
-        bool pad = false;
+    auto ccost = [&](int cc, int k) {
+        clear();
         for (int g = 0; g < s.G; ++g) {
-            const int j = g + s.G * vv;
+            const int x = g >> 5, i = g + s.G * cc;
+            if (i >= c->M || k >= deg_r(i)) {
+                padh[x] = true;
+                continue;
+            }
+            ++h[x][fcol[(size_t)at[(size_t)(c->rowptr[i] + k)]] % ncls];
+        }
+        return total(lampad_cls);
+    };
+    auto fcost = [&](int vv, int k) {
+        clear();
+        for (int g = 0; g < s.G; ++g) {
+            const int x = g >> 5, j = g + s.G * vv;
             if (j >= c->N || k >= deg_c(j)) {
-                pad = true;
+                padh[x] = true;
                 continue;
             }
             const int64_t q = c->colptr[j] + k;
             const int i = c->rowidx[q];
             const int p = pos[(size_t)(c->rowptr[i] + c->cpos[q])];
-            ++h[(int)((mu0w + (uint32_t)i * (uint32_t)lay.rs + (uint32_t)p) % (uint32_t)ncls)];
+            ++h[x][(int)((mu0w + (uint32_t)i * (uint32_t)lay.rs + (uint32_t)p) % (uint32_t)ncls)];
         }
-        if (pad) ++h[mupad_cls];
-        int m = 0;
-        for (int q = 0; q < ncls; ++q) m = std::max(m, h[q]);
-        return m;
+        return total(mupad_cls);
     };
     std::vector<int> C((size_t)s.CPT * s.DC), F((size_t)s.VPT * s.DV);
     for (int cc = 0; cc < s.CPT; ++cc)
@@ -333,6 +354,7 @@ rb_status build_plan(rb_ctx *c, int v) {
     c->lampad_off = lay.lampad_off;
     c->mupad_off = lay.mupad_off;
     c->mu0_off = lay.mu0_off;
+    c->half_off = lay.half_off;
     c->lds_bytes = lay.lds_bytes;
     const bool prior = c->params.anchor == RB_ANCHOR_PRIOR;
     for (int tr = 0; tr < 2; ++tr) {
@@ -636,24 +658,30 @@ void spread_check_lanes(const rb_ctx *c, const rb::BlockShape &s, std::vector<La
 
 // Fault slots.  Band v holds the faults of degree rank [v*TPB, (v+1)*TPB)
 // (fault_order), so slots below N are exactly the real ones.  Within a band
-// the faults are placed with the LDS banks in mind (32 banks, word address
-// mod 32; a wave's access costs the largest number of distinct words on one
-// bank):
-//  * wave of the slot: the fault pass's k-th gather of a wave reads the
-//    message of each lane's k-th check, whose bank is fixed by the lane that
-//    owns that check; faults are grouped 64 to a wave so these banks are as
-//    even as possible (greedy, then pairwise swaps between waves);
-//  * lane of the slot: a fault's Lambda word (= its slot) lies in bank
-//    slot mod 32; lanes are chosen so that every check wave's edges spread
-//    evenly over the banks, which lets the check-side edge order (order_rows)
-//    read at most two words per bank in each step.
+// the faults are placed with the LDS banks in mind: 32 banks (word address
+// mod 32), and a wave's access is served in two halves of 32 lanes, each
+// costing the largest number of distinct words on one bank:
+//  * half-wave of the slot: the fault pass's k-th gather reads the message of
+//    each lane's k-th check, whose bank is fixed by the lane that owns that
+//    check; faults are grouped 32 to a half-wave so these banks are as
+//    distinct as possible (greedy, then a local search over swaps);
+//  * lane of the slot within its half: a fault's Lambda word (= its slot)
+//    lies in bank slot mod 32; lanes are chosen so that, for every check wave
+//    and half, no bank carries more of its edges than the wave has steps,
+//    which lets the check-side edge order (order_rows) read one word per bank
+//    and half in each step.
 std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, const std::vector<int32_t> &lane_of_edge,
                                   const std::vector<int32_t> &wdeg, const BlockLayout &lay) {
-    const int TPB = s.TPB, nw = TPB / 64;
+    const int TPB = s.TPB, nw = TPB / 64, ng = 2 * nw;
     const std::vector<int32_t> fo = fault_order(c);
     std::vector<int32_t> slot_col((size_t)TPB * s.VPT, -1);
     const int mu0w = (int)(lay.mu0_off / 4u), padb = (int)((lay.mupad_off / 4u) % 32u);
-    std::vector<int32_t> load((size_t)nw * 32, 0);  // check wave x bank: Lambda gathers
+    // check wave x half x bank: Lambda gathers
+    std::vector<int32_t> load((size_t)nw * 64, 0);
+    auto load_at = [&](int64_t e, int b) -> int32_t & {
+        const int32_t t = lane_of_edge[(size_t)e];
+        return load[(size_t)(t / 64) * 64 + (size_t)((t % 64) / 32) * 32 + (size_t)b];
+    };
     PlanRng rng{0x5EED5EEDull};
     for (int v = 0; v < s.VPT && (int64_t)v * TPB < c->N; ++v) {
         const int64_t base = (int64_t)v * TPB;
@@ -669,10 +697,10 @@ std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, cons
                 sig[(size_t)f * D + k] = (int8_t)((mu0w + t) % 32);
             }
         }
-        std::vector<int> capg((size_t)nw), member((size_t)nw * 64, -1), fill((size_t)nw, 0);
-        for (int g = 0; g < nw; ++g) capg[g] = std::max(0, std::min(64, nf - 64 * g));
-        // cnt[(g*D + k)*33 + b]: lanes of wave g whose k-th gather hits bank b; b = 32: pads
-        std::vector<int> cnt((size_t)nw * D * 33, 0);
+        std::vector<int> capg((size_t)ng), member((size_t)ng * 32, -1), fill((size_t)ng, 0);
+        for (int g = 0; g < ng; ++g) capg[g] = std::max(0, std::min(32, nf - 32 * g));
+        // cnt[(g*D + k)*33 + b]: lanes of half-wave g whose k-th gather hits bank b; b = 32: pads
+        std::vector<int> cnt((size_t)ng * D * 33, 0);
         auto cost_gk = [&](int g, int k) {
             const int *q = &cnt[((size_t)g * D + k) * 33];
             int m = q[32] > 0 ? 1 : 0;
@@ -685,23 +713,23 @@ std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, cons
                 cnt[((size_t)g * D + k) * 33 + (b < 0 ? 32 : b)] += d;
             }
         };
-        // cost of a wave: its gathers' bank cycles, then (to steer the
-        // search) the lanes beyond two on any bank
+        // cost of a group: its gathers' bank cycles, then (to steer the
+        // search) the lanes beyond one on any bank
         auto cost_g = [&](int g) {
             int tot = 0;
             for (int k = 0; k < D; ++k) {
                 const int *q = &cnt[((size_t)g * D + k) * 33];
                 int ex = 0;
-                for (int b = 0; b < 32; ++b) ex += std::max(0, q[b] + ((b == padb && q[32] > 0) ? 1 : 0) - 2);
+                for (int b = 0; b < 32; ++b) ex += std::max(0, q[b] + ((b == padb && q[32] > 0) ? 1 : 0) - 1);
                 tot += 256 * cost_gk(g, k) + ex;
             }
             return tot;
         };
-        // greedy: each fault to the wave where it adds least
+        // greedy: each fault to the group where it adds least
         for (int f = 0; f < nf; ++f) {
             int best = -1;
             long long bkey = 0;
-            for (int g = 0; g < nw; ++g) {
+            for (int g = 0; g < ng; ++g) {
                 if (fill[g] >= capg[g]) continue;
                 const int before = cost_g(g);
                 add(g, f, 1);
@@ -713,34 +741,105 @@ std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, cons
                     bkey = key;
                 }
             }
-            member[(size_t)best * 64 + fill[best]++] = f;
+            member[(size_t)best * 32 + fill[best]++] = f;
             add(best, f, 1);
         }
-        // pairwise swaps between waves that do not raise the cost
-        const long long iters = 48ll * nf;
-        for (long long it = 0; it < iters && nf > 64; ++it) {
-            const int g1 = (int)rng.below((uint32_t)nw), g2 = (int)rng.below((uint32_t)nw);
-            if (g1 == g2 || fill[g1] == 0 || fill[g2] == 0) continue;
-            const int a = (int)rng.below((uint32_t)fill[g1]), b = (int)rng.below((uint32_t)fill[g2]);
-            const int f1 = member[(size_t)g1 * 64 + a], f2 = member[(size_t)g2 * 64 + b];
-            const int before = cost_g(g1) + cost_g(g2);
-            add(g1, f1, -1);
-            add(g2, f1, 1);
-            add(g2, f2, -1);
-            add(g1, f2, 1);
-            if (cost_g(g1) + cost_g(g2) <= before) {
-                member[(size_t)g1 * 64 + a] = f2;
-                member[(size_t)g2 * 64 + b] = f1;
-            } else {
-                add(g1, f2, -1);
-                add(g2, f2, 1);
-                add(g2, f1, -1);
-                add(g1, f1, 1);
+        // local search over swaps of two faults of different groups.  Cost of
+        // a group's k-th gather: the largest number of its faults on one bank
+        // (pads: one word); objective 64 x the summed costs plus the number of
+        // same-bank pairs, so that unavoidable doubles gather in few gathers.
+        // Faults that share a bank with another fault of their group are
+        // moved, each to the best of a few random partners.
+        std::vector<int> gof((size_t)nf), pos_in((size_t)nf);
+        for (int g = 0; g < ng; ++g)
+            for (int q = 0; q < fill[g]; ++q) {
+                gof[(size_t)member[(size_t)g * 32 + q]] = g;
+                pos_in[(size_t)member[(size_t)g * 32 + q]] = q;
             }
+        auto bin = [&](int f, int k) { const int b = sig[(size_t)f * D + k]; return b < 0 ? 32 : b; };
+        auto n_at = [&](int g, int k, int b) { return cnt[((size_t)g * D + k) * 33 + b]; };
+        // per gather (g, k): how many banks hold n faults, and the largest n
+        std::vector<int> nc((size_t)ng * D * 34, 0), mx((size_t)ng * D, 0);
+        for (int g = 0; g < ng; ++g)
+            for (int k = 0; k < D; ++k) {
+                const size_t cell = (size_t)g * D + k;
+                for (int b2 = 0; b2 < 32; ++b2) {
+                    const int n = n_at(g, k, b2);
+                    ++nc[cell * 34 + (size_t)n];
+                    mx[cell] = std::max(mx[cell], n);
+                }
+            }
+        auto cell_cost = [&](size_t cell) { return std::max(mx[cell], cnt[cell * 33 + 32] > 0 ? 1 : 0); };
+        auto move = [&](int g, int k, int b2, int d) {  // one fault into (d = 1) or out of (d = -1) bank b2
+            const size_t cell = (size_t)g * D + k;
+            int &n = cnt[cell * 33 + (size_t)b2];
+            if (b2 < 32) {
+                --nc[cell * 34 + (size_t)n];
+                ++nc[cell * 34 + (size_t)(n + d)];
+                if (d > 0 && n + 1 > mx[cell]) mx[cell] = n + 1;
+                if (d < 0 && n == mx[cell] && nc[cell * 34 + (size_t)n] == 0) mx[cell] = n - 1;
+            }
+            n += d;
+        };
+        auto clash = [&](int f) {  // other faults of f's group in f's banks
+            int x = 0;
+            for (int k = 0; k < D; ++k) {
+                const int b2 = bin(f, k);
+                if (b2 < 32) x += n_at(gof[(size_t)f], k, b2) - 1;
+            }
+            return x;
+        };
+        auto do_swap = [&](int f1, int f2) {
+            const int g1 = gof[(size_t)f1], g2 = gof[(size_t)f2];
+            for (int k = 0; k < D; ++k) {
+                const int b1 = bin(f1, k), b2 = bin(f2, k);
+                if (b1 == b2) continue;
+                move(g1, k, b1, -1);
+                move(g2, k, b2, -1);
+                move(g1, k, b2, 1);
+                move(g2, k, b1, 1);
+            }
+            std::swap(member[(size_t)g1 * 32 + pos_in[(size_t)f1]], member[(size_t)g2 * 32 + pos_in[(size_t)f2]]);
+            std::swap(pos_in[(size_t)f1], pos_in[(size_t)f2]);
+            gof[(size_t)f1] = g2;
+            gof[(size_t)f2] = g1;
+        };
+        auto objective_delta = [&](int f1, int f2) {
+            const int g1 = gof[(size_t)f1], g2 = gof[(size_t)f2];
+            int before = 0, pd = 0;
+            for (int k = 0; k < D; ++k) {
+                const int b1 = bin(f1, k), b2 = bin(f2, k);
+                if (b1 == b2) continue;
+                before += cell_cost((size_t)g1 * D + k) + cell_cost((size_t)g2 * D + k);
+                if (b1 < 32) pd += n_at(g2, k, b1) - (n_at(g1, k, b1) - 1);
+                if (b2 < 32) pd += n_at(g1, k, b2) - (n_at(g2, k, b2) - 1);
+            }
+            do_swap(f1, f2);
+            int after = 0;
+            for (int k = 0; k < D; ++k)
+                if (bin(f1, k) != bin(f2, k)) after += cell_cost((size_t)g1 * D + k) + cell_cost((size_t)g2 * D + k);
+            do_swap(f1, f2);  // undo
+            return 64 * (after - before) + pd;
+        };
+        const long long iters = 400ll * nf;
+        for (long long it = 0; it < iters && nf > 32; ++it) {
+            const int f1 = (int)rng.below((uint32_t)nf);
+            if (clash(f1) == 0) continue;
+            int best = -1, bd = 1;
+            for (int tr = 0; tr < 8; ++tr) {
+                const int f2 = (int)rng.below((uint32_t)nf);
+                if (gof[(size_t)f2] == gof[(size_t)f1]) continue;
+                const int d = objective_delta(f1, f2);
+                if (d < bd || (d == bd && rng.below(2))) {
+                    best = f2;
+                    bd = d;
+                }
+            }
+            if (best >= 0 && bd <= 0) do_swap(f1, best);
         }
-        // lanes within each wave: balance the check waves' bank loads
-        for (int g = 0; g < nw; ++g) {
-            std::vector<int> fs(member.begin() + (ptrdiff_t)g * 64, member.begin() + (ptrdiff_t)g * 64 + fill[g]);
+        // lanes within each half-wave: bank = lane, balancing the check side
+        for (int g = 0; g < ng; ++g) {
+            std::vector<int> fs(member.begin() + (ptrdiff_t)g * 32, member.begin() + (ptrdiff_t)g * 32 + fill[g]);
             auto degf = [&](int f) { const int32_t j = fo[(size_t)(base + f)]; return c->colptr[j + 1] - c->colptr[j]; };
             std::stable_sort(fs.begin(), fs.end(), [&](int x, int y) { return degf(x) > degf(y); });
             std::vector<char> used((size_t)capg[g], 0);
@@ -750,13 +849,11 @@ std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, cons
                 long long bkey = 0;
                 for (int l = 0; l < capg[g]; ++l) {
                     if (used[l]) continue;
-                    const int b = l % 32;
                     long long over = LLONG_MIN, sum = 0;
                     for (int64_t q = c->colptr[j]; q < c->colptr[j + 1]; ++q) {
-                        const int32_t i = c->rowidx[q];
-                        const int w = lane_of_edge[(size_t)(c->rowptr[i] + c->cpos[q])] / 64;
-                        const long long ld = load[(size_t)w * 32 + b];
-                        over = std::max(over, ld + 1 - 2ll * wdeg[w]);
+                        const int64_t e = c->rowptr[c->rowidx[q]] + c->cpos[q];
+                        const long long ld = load_at(e, l);
+                        over = std::max(over, ld + 1 - (long long)wdeg[lane_of_edge[(size_t)e] / 64]);
                         sum += ld;
                     }
                     const long long key = over * (1ll << 32) + sum;
@@ -766,12 +863,9 @@ std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, cons
                     }
                 }
                 used[best] = 1;
-                slot_col[(size_t)(base + 64 * g + best)] = j;
-                for (int64_t q = c->colptr[j]; q < c->colptr[j + 1]; ++q) {
-                    const int32_t i = c->rowidx[q];
-                    const int w = lane_of_edge[(size_t)(c->rowptr[i] + c->cpos[q])] / 64;
-                    ++load[(size_t)w * 32 + best % 32];
-                }
+                slot_col[(size_t)(base + 32 * g + best)] = j;
+                for (int64_t q = c->colptr[j]; q < c->colptr[j + 1]; ++q)
+                    ++load_at(c->rowptr[c->rowidx[q]] + c->cpos[q], best);
             }
         }
     }
@@ -781,12 +875,13 @@ std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, cons
 // Edge order within the rows of each wave (free: the check update does not
 // depend on it).  Step k of a wave gathers Lambda of edge k of its 64 rows.
 // The order is a proper edge colouring, with wdeg colours (= steps), of the
-// bipartite multigraph lanes x (bank, copy), each bank split into two copies:
-// every step then reads at most two words per bank, the conflict-free rate.
-// Such a colouring exists when no bank carries more than 2 * wdeg of the
-// wave's edges (Koenig's edge-colouring theorem); it is built edge by edge,
-// swapping the two colours along an alternating path when the colours free
-// at the two ends differ.  An edge whose bank is full takes any free step.
+// bipartite multigraph lanes x (bank, half), where half is the lane's half of
+// the wave: every step then reads at most one word per bank in each half, the
+// conflict-free rate.  Such a colouring exists when no (bank, half) carries
+// more than wdeg of the wave's edges (Koenig's edge-colouring theorem); it is
+// built edge by edge, swapping the two colours along an alternating path when
+// the colours free at the two ends differ.  An edge whose (bank, half) is full
+// takes the free step of its lane with the fewest such extra edges.
 // epos[e] = step of CSR edge e; col16 = Lambda byte address per (thread, step).
 void order_rows(const rb_ctx *c, const rb::BlockShape &s, const std::vector<LaneSeg> &lanes,
                 const std::vector<int32_t> &wdeg, const std::vector<int32_t> &slot_of,
@@ -800,14 +895,13 @@ void order_rows(const rb_ctx *c, const rb::BlockShape &s, const std::vector<Lane
             int64_t e;
         };
         std::vector<Ed> ed;
-        int per_bank[32] = {0};
         for (int l = 0; l < 64; ++l) {
             const LaneSeg &g = lanes[(size_t)(64 * w + l)];
             if (g.row < 0) continue;
             for (int32_t q = g.b; q < g.e; ++q) {
                 const int64_t e = c->rowptr[g.row] + q;
                 const int b = slot_of[c->colidx[e]] & 31;
-                ed.push_back({l, 64 + 2 * b + (per_bank[b]++ & 1), e});
+                ed.push_back({l, 64 + 2 * b + (l >> 5), e});
             }
         }
         std::vector<int> at((size_t)128 * D, -1), col(ed.size(), -1);
@@ -820,13 +914,8 @@ void order_rows(const rb_ctx *c, const rb::BlockShape &s, const std::vector<Lane
         for (size_t q = 0; q < ed.size(); ++q) {
             int u = ed[q].u, v = ed[q].v;
             const int a = free_at(u);
-            int b = free_at(v);
-            if (b < 0) {
-                v ^= 1;  // the bank's other copy
-                b = free_at(v);
-                if (b < 0) continue;
-                ed[q].v = v;
-            }
+            const int b = free_at(v);
+            if (b < 0) continue;  // (bank, half) full: placed below
             int k = a;
             if (at[(size_t)v * D + a] >= 0) {
                 if (at[(size_t)u * D + b] < 0) {
@@ -856,11 +945,19 @@ void order_rows(const rb_ctx *c, const rb::BlockShape &s, const std::vector<Lane
             at[(size_t)u * D + k] = (int)q;
             at[(size_t)v * D + k] = (int)q;
         }
+        std::vector<int> extra((size_t)128 * D, 0);  // (bank, half) x step: edges beyond one
         for (size_t q = 0; q < ed.size(); ++q) {
-            if (col[q] < 0) {
-                col[q] = free_at(ed[q].u);
-                at[(size_t)ed[q].u * D + col[q]] = (int)q;
-            }
+            if (col[q] >= 0) continue;
+            int k = -1;
+            for (int x = 0; x < D; ++x)
+                if (at[(size_t)ed[q].u * D + x] < 0 &&
+                    (k < 0 || extra[(size_t)ed[q].v * D + x] < extra[(size_t)ed[q].v * D + k]))
+                    k = x;
+            col[q] = k;
+            at[(size_t)ed[q].u * D + k] = (int)q;
+            ++extra[(size_t)ed[q].v * D + k];
+        }
+        for (size_t q = 0; q < ed.size(); ++q) {
             const int64_t e = ed[q].e;
             epos[(size_t)e] = col[q];
             col16[(size_t)(64 * w + ed[q].u) * s.DCMAX + col[q]] = (uint16_t)(4u * (uint32_t)slot_of[c->colidx[e]]);
@@ -946,17 +1043,24 @@ BlockTables block_tables(const rb_ctx *c, const rb::BlockShape &s) {
 // ---- independent reading of the gather tables (rb_plan_check) ----
 //
 // The tables are decoded exactly as the kernels read them and compared with
-// the graph itself, not with the planner's intermediate maps.  LDS cost model:
-// 32 banks of 4-byte words (bank = word address mod 32); a wave-wide gather
-// costs the largest number of distinct words on one bank (64 distinct words
-// cost at least 2; a word read by several lanes counts once).
+// the graph itself, not with the planner's intermediate maps.  LDS cost model
+// (measured on gfx950): 32 banks of 4-byte words (bank = word address mod 32);
+// a wave-wide read is served in two halves (lanes 0-31, then 32-63), each
+// costing the largest number of distinct words on one bank (a word read by
+// several lanes counts once), so a gather costs at least 2 cycles.
 
-int gather_cost(std::vector<uint32_t> &words) {
+int half_cost(std::vector<uint32_t> &words) {
     std::sort(words.begin(), words.end());
     words.erase(std::unique(words.begin(), words.end()), words.end());
     int per_bank[32] = {0}, m = 0;
     for (uint32_t w : words) m = std::max(m, ++per_bank[w % 32u]);
     return m;
+}
+
+// cost of one wave-wide gather: words[l] is lane l's word address
+int gather_cost(const std::vector<uint32_t> &words) {
+    std::vector<uint32_t> lo(words.begin(), words.begin() + 32), hi(words.begin() + 32, words.end());
+    return half_cost(lo) + half_cost(hi);
 }
 
 // CSR edge of (i, j), or -1
@@ -969,14 +1073,15 @@ int64_t find_edge(const rb_ctx *c, int32_t i, int32_t j) {
 std::string check_group_tables(const rb_ctx *c, const rb::TileShape &s, const GroupTables &T, rb_plan_report *r) {
     const Layout &lay = T.lay;
     const int NS = 64 / s.G, nl = s.CPT * s.DC, nm = s.VPT * s.DV;
+    if (lay.sph * s.G != 32 && !(s.G >= 32 && lay.sph == 1)) return "slots per half-wave";
     const int nlp = (nl + 1) / 2, nmp = (nm + 1) / 2;
     if (T.lam.size() != (size_t)s.G * nlp || T.mu.size() != (size_t)s.G * nmp) return "table sizes";
-    if (lay.lds_bytes > 65536) return "LDS image exceeds the 16-bit offsets";
+    if (lay.half_off > 65536 || lay.lds_bytes > 65536) return "LDS image exceeds the 16-bit offsets";
     auto entry = [](const std::vector<uint32_t> &t, size_t row, int idx) {
         const uint32_t w = t[row + (size_t)(idx / 2)];
         return (idx & 1) ? (w >> 16) : (w & 0xffffu);
     };
-    // offsets are ORed with the slot base 4*slot < word: multiples of word
+    // offsets address words of slot 0 of a region: multiples of word
     for (uint32_t w : T.lam)
         if ((w & 0xffffu) % lay.word || (w >> 16) % lay.word) return "Lambda offset not slot-aligned";
     for (uint32_t w : T.mu)
@@ -1021,8 +1126,10 @@ std::string check_group_tables(const rb_ctx *c, const rb::TileShape &s, const Gr
     std::vector<uint32_t> words;
     auto wave = [&](const std::vector<uint32_t> &t, int nrow, int idx) {
         words.clear();
-        for (int sl = 0; sl < NS; ++sl)
-            for (int g = 0; g < s.G; ++g) words.push_back((entry(t, (size_t)g * nrow, idx) | (4u * sl)) / 4u);
+        for (int sl = 0; sl < NS; ++sl) {  // lane = slot * G + g
+            const uint32_t base = 4u * (uint32_t)(sl % lay.sph) + lay.half_off * (uint32_t)(sl / lay.sph);
+            for (int g = 0; g < s.G; ++g) words.push_back((entry(t, (size_t)g * nrow, idx) + base) / 4u);
+        }
         return gather_cost(words);
     };
     for (int q = 0; q < nl; ++q) {
@@ -1475,6 +1582,7 @@ static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     a.lampad_off = c->lampad_off;
     a.mupad_off = c->mupad_off;
     a.mu0_off = c->mu0_off;
+    a.half_off = c->half_off;
     a.scale = c->prior_scale;
     return a;
 }
@@ -1939,6 +2047,7 @@ rb_status upload_codes(rb_ctx *m) {
         cs[k].lampad_off = s->lampad_off;
         cs[k].mupad_off = s->mupad_off;
         cs[k].mu0_off = s->mu0_off;
+        cs[k].half_off = s->half_off;
         lds = std::max(lds, s->lds_bytes);
         if (cs[k].tile < 0) return fail(RB_E_UNSUPPORTED, "code planned outside the mixed tile set");
     }

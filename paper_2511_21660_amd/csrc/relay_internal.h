@@ -55,11 +55,13 @@ struct GroupArgs {
     unsigned long long *queue;  // work queue (kQueueWords counters, see below)
     int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
     float L;
-    // LDS offsets in interleaved form (slot word w -> byte 4 * w * NS; the
-    // kernel adds 4 * slot)
+    // LDS byte offsets within a slot's region (slot word w -> byte 4 * SPH * w
+    // with SPH = max(1, 32 / G) slots per half-wave; the kernel adds the slot
+    // base 4 * (slot % SPH) + half_off * (slot / SPH))
     uint32_t lampad_off;   // +inf cell: Lambda of padded check edges
     uint32_t mupad_off;    // -0 cell: mu of padded fault edges
     uint32_t mu0_off;      // start of the check-message rows
+    uint32_t half_off;     // bytes between the regions of the two half-waves
     // trace mode (rb_trace): per-column gamma, LLR scale, iteration count, output
     const float *trace_gamma;
     float scale;
@@ -158,7 +160,7 @@ struct CodeStatic {
     const float *gamma;
     const uint32_t *lam_off;
     const uint32_t *mu_off;
-    uint32_t lampad_off, mupad_off, mu0_off;
+    uint32_t lampad_off, mupad_off, mu0_off, half_off;
 };
 
 struct MixedArgs {

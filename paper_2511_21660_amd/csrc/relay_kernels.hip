@@ -19,11 +19,15 @@
 // syndrome bits).  The graph is precompiled into per-lane LDS byte offsets
 // held in registers, so a gather is a single ds_read with no index load.
 //
-// LDS layout.  The NS slots of a wave are interleaved word by word: word w of
-// slot s sits at LDS word w*NS + s.  All slots run the same graph, so the
-// lanes of different slots that execute the same gather hit NS consecutive
-// banks; check-message rows have an odd stride (DC | 1 words) so that the
-// row accesses of the G lanes of a slot spread over the banks as well.
+// LDS layout.  The LDS serves a wave's access in two halves of 32 lanes, each
+// costing the largest number of distinct words on one of the 32 banks.  The
+// SPH = 32/G slots of a half-wave (1 for G >= 32) are interleaved word by word
+// in a region of their own: word w of slot s sits at word w*SPH + s % SPH of
+// region s / SPH.  The slots of a half then occupy disjoint banks and each
+// slot's G lanes can reach G banks (32 for G = 64), so the lanes' own
+// accesses (Lambda of fault g + G*v, check-message rows of odd stride DC | 1
+// words) are conflict-free and a gather is conflict-free when its words are
+// distinct modulo G; the host orders every check's edges towards that.
 //
 // Check update (min1 / min2 / sign parity): for one check the two smallest
 // |nu| are tracked with min/max only; edge k then receives m2 if |nu_k| == m1
@@ -142,8 +146,9 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     static_assert(CPT <= 32 && VPT <= 32, "per-lane bit masks are 32 bits");
     char *lds = nullptr;  // LDS is addressed by absolute byte offsets
     constexpr int NS = 64 / G;                     // slots per wave
+    constexpr int SPH = G >= 32 ? 1 : 32 / G;      // slots per half-wave region
     constexpr int RS = DC | 1;                     // words per check-message row (odd)
-    constexpr uint32_t WORD = 4u * NS;             // bytes between consecutive words of a slot
+    constexpr uint32_t WORD = 4u * SPH;            // bytes between consecutive words of a slot
     constexpr uint32_t ROW_STRIDE = WORD * G * RS; // bytes between the rows of checks c, c+1
 
     uint32_t lane_rt = threadIdx.x;
@@ -152,7 +157,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     const int g = lane % G;
     const int slot = lane / G;
     uint32_t gl = (uint32_t)g;  // lane in slot, made opaque inside the loop
-    const uint32_t base = 4u * (uint32_t)slot;     // word 0 of this slot
+    const uint32_t base = 4u * (uint32_t)(slot % SPH) + a.half_off * (uint32_t)(slot / SPH);  // word 0 of this slot
     // row of check g; made opaque inside the loop like the tables, so that its
     // constant row offsets fold into the LDS instructions instead of being
     // hoisted into registers of their own
@@ -163,8 +168,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     const float L = a.L;
 
     // ---- per-lane gather tables: two 16-bit slot-relative LDS byte offsets
-    // per register.  Offsets are multiples of 4*NS and the slot base 4*slot is
-    // below 4*NS, so address = offset | base.
+    // per register; address = offset + slot base.
     constexpr int NLP = (CPT * DC + 1) / 2;
     constexpr int NMP = (VPT * DV + 1) / 2;
     uint32_t lam_pk[NLP];
@@ -179,11 +183,11 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     }
     auto lam_addr = [&](int c, int k) -> uint32_t {
         const int e = c * DC + k;
-        return ((e & 1) ? (lam_pk[e >> 1] >> 16) : (lam_pk[e >> 1] & 0xffffu)) | base;
+        return ((e & 1) ? (lam_pk[e >> 1] >> 16) : (lam_pk[e >> 1] & 0xffffu)) + base;
     };
     auto mu_addr = [&](int v, int k) -> uint32_t {
         const int e = v * DV + k;
-        return ((e & 1) ? (mu_pk[e >> 1] >> 16) : (mu_pk[e >> 1] & 0xffffu)) | base;
+        return ((e & 1) ? (mu_pk[e >> 1] >> 16) : (mu_pk[e >> 1] & 0xffffu)) + base;
     };
 
     if (g == 0) {
@@ -483,6 +487,7 @@ void relay_mixed_kernel(MixedArgs m) {
         a.lampad_off = cs.lampad_off;
         a.mupad_off = cs.mupad_off;
         a.mu0_off = cs.mu0_off;
+        a.half_off = cs.half_off;
         a.list = m.list + m.seg_start[f];
         a.count = m.seg_count[f];
         a.queue = m.queues + (size_t)f * kQueueWords;

@@ -67,16 +67,21 @@ def test_bb_codes_every_configuration(name):
         assert r["fault_gathers"] <= r["fault_bank_cycles"] <= 64 * r["fault_gathers"]
     auto = rb.plan_check(p.m, p.n, p.rows, p.cols)
     assert auto["variant"] in reps and auto["block_kernel"] == 0
+    # slots of a half-wave on disjoint banks and annealed edge order: well
+    # below the 4+ cycles per gather of slots that share their banks
+    assert auto["check_bank_cycles"] / auto["check_gathers"] < 4.0
+    assert auto["fault_bank_cycles"] / auto["fault_gathers"] < 4.1
 
 
 def test_dem_block_kernel_tables_and_bank_cost():
     d = codes.dem_problem()
     r = rb.plan_check(d.m, d.n, d.rows, d.cols)
     assert r["block_kernel"] == 1 and r["lds_bytes"] <= 160 * 1024
-    # bank-aware placement: close to the conflict-free 2 cycles per gather
-    # (values of the current planner: 2.36 check side, 2.81 fault side)
-    assert r["check_bank_cycles"] / r["check_gathers"] < 2.5
-    assert r["fault_bank_cycles"] / r["fault_gathers"] < 3.0
+    # bank-aware placement (half-wave model; 2 cycles per gather is
+    # conflict-free, the unplanned tables cost 4 to 6): current planner
+    # 2.47 check side, 3.23 fault side
+    assert r["check_bank_cycles"] / r["check_gathers"] < 2.6
+    assert r["fault_bank_cycles"] / r["fault_gathers"] < 3.4
     reps = _all_fitting(d.m, d.n, d.rows, d.cols)
     assert all(x["block_kernel"] == 1 for x in reps.values()) and len(reps) >= 2
 
