@@ -103,13 +103,13 @@ struct Layout {
     uint32_t word;                            // bytes between consecutive words of a slot (4 * SPH)
     uint32_t half_off;                        // bytes between the two half-wave regions
     int sph;                                  // slots per half-wave region
-    int rs;                                   // words per check-message row
+    int ks;                                   // words between the messages of steps k, k+1 (G * CPT)
     int lds_bytes;
 };
 
 // Slot layout in words: Lambda[0..G*VPT) (faults j >= N are spare words the
-// padded lanes write), +inf pad, -0 pad, then G*CPT check-message rows of
-// RS = DC|1 words.  The SPH = 32/G slots of a half-wave (1 for G >= 32) are
+// padded lanes write), +inf pad, -0 pad, then the check messages step-major:
+// message k of check position q (= check index) at word k * G*CPT + q.  The SPH = 32/G slots of a half-wave (1 for G >= 32) are
 // interleaved word by word in one region; the wave's NS = 64/G slots fill
 // NS/SPH regions.
 Layout slot_layout(const rb::TileShape &s, int N) {
@@ -119,11 +119,11 @@ Layout slot_layout(const rb::TileShape &s, int N) {
     const uint32_t nl = (uint32_t)std::max(N, s.G * s.VPT);
     l.sph = (int)sph;
     l.word = 4u * sph;
-    l.rs = s.DC | 1;
+    l.ks = s.G * s.CPT;
     l.lampad_off = l.word * nl;
     l.mupad_off = l.word * (nl + 1);
     l.mu0_off = l.word * (nl + 2);
-    const uint64_t words = (uint64_t)(nl + 2) + (uint64_t)s.G * s.CPT * l.rs;
+    const uint64_t words = (uint64_t)(nl + 2) + (uint64_t)s.G * s.CPT * s.DC;
     const uint64_t region = words * l.word;
     l.half_off = region > (1u << 30) ? (1u << 30) : (uint32_t)region;
     const uint64_t bytes = region * (ns / sph);
@@ -168,120 +168,75 @@ struct PlanRng {
 // ncls = min(G, 32) banks (its "classes", word index mod ncls) and a gather
 // costs, per half, the largest number of the slot's lanes on one class (all
 // slots of a wave run the same tables; for G = 64 the slot spans both
-// halves).  Step k of check row c gathers Lambda of the k-th fault of the G
-// checks g + G*c (class: fault index mod ncls); gather k of fault slot v
-// reads the message of the k-th check of the G faults g + G*v (class:
-// message word mod ncls, which depends on the edge's step in its check).
-// Random swaps of two edges of one check, accepted by a simulated-annealing
-// rule, lower the sum of both kinds of costs.  Returns the step of every CSR
-// edge.
+// halves).  Step k of check row c gathers Lambda of the fault at step k of
+// each of the G checks g + G*c (class: fault index mod ncls; steps without an
+// edge gather the pad cell).  The fault side does not depend on the order:
+// messages are stored step-major with a step stride that is a multiple of
+// ncls, so a message's class is its check's position mod ncls.  Random swaps
+// of two steps of one check (edges or pads), accepted by a simulated-annealing
+// rule, lower the summed cost.  Returns the step of every CSR edge.
 std::vector<int32_t> group_edge_order(const rb_ctx *c, const rb::TileShape &s, const Layout &lay) {
-    const int ncls = std::min(s.G, 32);
-    std::vector<int32_t> pos((size_t)c->E), at((size_t)c->E);  // edge -> step; (row, step) -> edge
+    const int ncls = std::min(s.G, 32), DC = s.DC;
+    std::vector<int32_t> pos((size_t)c->E), at((size_t)c->M * DC, -1);  // edge -> step; (check, step) -> edge
     for (int32_t i = 0; i < c->M; ++i)
         for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) {
             pos[(size_t)e] = (int32_t)(e - c->rowptr[i]);
-            at[(size_t)e] = (int32_t)e;
+            at[(size_t)i * DC + pos[(size_t)e]] = (int32_t)e;
         }
     if (c->E == 0) return pos;
     const int lampad_cls = (int)((lay.lampad_off / lay.word) % (uint32_t)ncls);
-    const int mupad_cls = (int)((lay.mupad_off / lay.word) % (uint32_t)ncls);
-    const uint32_t mu0w = lay.mu0_off / lay.word;
-    // edge e of check i: its k-th place in its fault's ascending check list
-    std::vector<int32_t> fk((size_t)c->E);
-    for (int32_t j = 0; j < c->N; ++j)
-        for (int64_t q = c->colptr[j]; q < c->colptr[j + 1]; ++q)
-            fk[(size_t)(c->rowptr[c->rowidx[q]] + c->cpos[q])] = (int32_t)(q - c->colptr[j]);
-    std::vector<int32_t> fcol((size_t)c->E);  // fault of each CSR edge
-    for (int32_t i = 0; i < c->M; ++i)
-        for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e) fcol[(size_t)e] = c->colidx[e];
-    auto deg_r = [&](int i) { return (int)(c->rowptr[i + 1] - c->rowptr[i]); };
-    auto deg_c = [&](int j) { return (int)(c->colptr[j + 1] - c->colptr[j]); };
     const int nh = s.G == 64 ? 2 : 1;  // halves a slot spans
     int h[2][32];
-    bool padh[2];
-    auto clear = [&]() {
-        for (int x = 0; x < nh; ++x) {
-            padh[x] = false;
+    auto ccost = [&](int cc, int k) {
+        bool padh[2] = {false, false};
+        for (int x = 0; x < nh; ++x)
             for (int q = 0; q < ncls; ++q) h[x][q] = 0;
+        for (int g = 0; g < s.G; ++g) {
+            const int x = g >> 5, i = g + s.G * cc;
+            const int e = i < c->M ? at[(size_t)i * DC + k] : -1;
+            if (e < 0)
+                padh[x] = true;
+            else
+                ++h[x][c->colidx[(size_t)e] % ncls];
         }
-    };
-    auto total = [&](int pad_cls) {
         int m = 0;
         for (int x = 0; x < nh; ++x) {
-            if (padh[x]) ++h[x][pad_cls];
+            if (padh[x]) ++h[x][lampad_cls];
             int mx = 0;
             for (int q = 0; q < ncls; ++q) mx = std::max(mx, h[x][q]);
             m += mx;
         }
         return m;
     };
-    auto ccost = [&](int cc, int k) {
-        clear();
-        for (int g = 0; g < s.G; ++g) {
-            const int x = g >> 5, i = g + s.G * cc;
-            if (i >= c->M || k >= deg_r(i)) {
-                padh[x] = true;
-                continue;
-            }
-            ++h[x][fcol[(size_t)at[(size_t)(c->rowptr[i] + k)]] % ncls];
-        }
-        return total(lampad_cls);
-    };
-    auto fcost = [&](int vv, int k) {
-        clear();
-        for (int g = 0; g < s.G; ++g) {
-            const int x = g >> 5, j = g + s.G * vv;
-            if (j >= c->N || k >= deg_c(j)) {
-                padh[x] = true;
-                continue;
-            }
-            const int64_t q = c->colptr[j] + k;
-            const int i = c->rowidx[q];
-            const int p = pos[(size_t)(c->rowptr[i] + c->cpos[q])];
-            ++h[x][(int)((mu0w + (uint32_t)i * (uint32_t)lay.rs + (uint32_t)p) % (uint32_t)ncls)];
-        }
-        return total(mupad_cls);
-    };
-    std::vector<int> C((size_t)s.CPT * s.DC), F((size_t)s.VPT * s.DV);
+    std::vector<int> C((size_t)s.CPT * DC);
     for (int cc = 0; cc < s.CPT; ++cc)
-        for (int k = 0; k < s.DC; ++k) C[(size_t)cc * s.DC + k] = ccost(cc, k);
-    for (int vv = 0; vv < s.VPT; ++vv)
-        for (int k = 0; k < s.DV; ++k) F[(size_t)vv * s.DV + k] = fcost(vv, k);
+        for (int k = 0; k < DC; ++k) C[(size_t)cc * DC + k] = ccost(cc, k);
     PlanRng rng{0xBA4C5EEDull};
-    const int64_t iters = std::min<int64_t>(2000000, 600 * c->E);
+    const int64_t iters = std::min<int64_t>(4000000, 3000 * c->E);
     for (int64_t it = 0; it < iters; ++it) {
         const int i = (int)rng.below((uint32_t)c->M);
-        const int d = deg_r(i);
-        if (d < 2) continue;
-        const int a = (int)rng.below((uint32_t)d), b = (int)rng.below((uint32_t)d);
-        if (a == b) continue;
+        const int a = (int)rng.below((uint32_t)DC), b = (int)rng.below((uint32_t)DC);
+        int32_t &ea = at[(size_t)i * DC + a], &eb = at[(size_t)i * DC + b];
+        if (a == b || (ea < 0 && eb < 0)) continue;
         const int cc = i / s.G;
-        const int ea = at[(size_t)(c->rowptr[i] + a)], eb = at[(size_t)(c->rowptr[i] + b)];
-        const int ja = fcol[(size_t)ea], jb = fcol[(size_t)eb];
-        const size_t c1 = (size_t)cc * s.DC + a, c2 = (size_t)cc * s.DC + b;
-        const size_t f1 = (size_t)(ja / s.G) * s.DV + fk[(size_t)ea], f2 = (size_t)(jb / s.G) * s.DV + fk[(size_t)eb];
-        const int before = C[c1] + C[c2] + F[f1] + (f2 != f1 ? F[f2] : 0);
-        std::swap(at[(size_t)(c->rowptr[i] + a)], at[(size_t)(c->rowptr[i] + b)]);
-        pos[(size_t)ea] = b;
-        pos[(size_t)eb] = a;
+        const size_t c1 = (size_t)cc * DC + a, c2 = (size_t)cc * DC + b;
+        const int before = C[c1] + C[c2];
+        std::swap(ea, eb);
         const int nc1 = ccost(cc, a), nc2 = ccost(cc, b);
-        const int nf1 = fcost(ja / s.G, fk[(size_t)ea]), nf2 = f2 != f1 ? fcost(jb / s.G, fk[(size_t)eb]) : 0;
-        const int after = nc1 + nc2 + nf1 + nf2;
-        const double temp = 0.5 * (1.0 - (double)it / (double)iters);
+        const int after = nc1 + nc2;
+        const double temp = 1.0 * (1.0 - (double)it / (double)iters);
         bool take = after <= before;
         if (!take && temp > 0.0) take = (double)rng.below(1u << 20) < std::exp((before - after) / temp) * (double)(1u << 20);
         if (take) {
             C[c1] = nc1;
             C[c2] = nc2;
-            F[f1] = nf1;
-            if (f2 != f1) F[f2] = nf2;
         } else {
-            std::swap(at[(size_t)(c->rowptr[i] + a)], at[(size_t)(c->rowptr[i] + b)]);
-            pos[(size_t)ea] = a;
-            pos[(size_t)eb] = b;
+            std::swap(ea, eb);
         }
     }
+    for (int32_t i = 0; i < c->M; ++i)
+        for (int k = 0; k < DC; ++k)
+            if (at[(size_t)i * DC + k] >= 0) pos[(size_t)at[(size_t)i * DC + k]] = k;
     return pos;
 }
 
@@ -319,7 +274,7 @@ GroupTables group_tables(const rb_ctx *c, const rb::TileShape &s) {
             for (int64_t k = 0; k < e - b; ++k) {
                 const int i = c->rowidx[b + k];
                 const int p = pos[(size_t)(c->rowptr[i] + c->cpos[b + k])];
-                const uint32_t word = (uint32_t)i * (uint32_t)lay.rs + (uint32_t)p;
+                const uint32_t word = (uint32_t)p * (uint32_t)lay.ks + (uint32_t)i;
                 mu16[(size_t)g * nmp * 2 + vv * s.DV + k] = (uint16_t)(lay.mu0_off + lay.word * word);
             }
         }
@@ -1115,7 +1070,7 @@ std::string check_group_tables(const rb_ctx *c, const rb::TileShape &s, const Gr
                 if (k < d) {  // k-th check of the fault in ascending order
                     const int32_t i = c->rowidx[(size_t)(c->colptr[j] + k)];
                     const int64_t e = find_edge(c, i, j);
-                    want = lay.mu0_off + lay.word * ((uint32_t)i * (uint32_t)lay.rs + (uint32_t)step[(size_t)e]);
+                    want = lay.mu0_off + lay.word * ((uint32_t)step[(size_t)e] * (uint32_t)lay.ks + (uint32_t)i);
                 }
                 if (a != want)
                     return "fault " + std::to_string(j) + " gather " + std::to_string(k) + ": offset " +

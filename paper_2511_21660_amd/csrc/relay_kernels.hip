@@ -24,10 +24,12 @@
 // SPH = 32/G slots of a half-wave (1 for G >= 32) are interleaved word by word
 // in a region of their own: word w of slot s sits at word w*SPH + s % SPH of
 // region s / SPH.  The slots of a half then occupy disjoint banks and each
-// slot's G lanes can reach G banks (32 for G = 64), so the lanes' own
-// accesses (Lambda of fault g + G*v, check-message rows of odd stride DC | 1
-// words) are conflict-free and a gather is conflict-free when its words are
-// distinct modulo G; the host orders every check's edges towards that.
+// slot's G lanes can reach G banks (32 for G = 64).  Check messages are
+// stored step-major (message k of check position q at word mu0 + k*G*CPT + q),
+// so the lanes' own accesses (Lambda of fault g + G*v, the messages of checks
+// g + G*c) touch consecutive words and are conflict-free, and a gather is
+// conflict-free when its words are distinct modulo G; the host orders every
+// check's edges towards that.
 //
 // Check update (min1 / min2 / sign parity): for one check the two smallest
 // |nu| are tracked with min/max only; edge k then receives m2 if |nu_k| == m1
@@ -147,9 +149,9 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     char *lds = nullptr;  // LDS is addressed by absolute byte offsets
     constexpr int NS = 64 / G;                     // slots per wave
     constexpr int SPH = G >= 32 ? 1 : 32 / G;      // slots per half-wave region
-    constexpr int RS = DC | 1;                     // words per check-message row (odd)
     constexpr uint32_t WORD = 4u * SPH;            // bytes between consecutive words of a slot
-    constexpr uint32_t ROW_STRIDE = WORD * G * RS; // bytes between the rows of checks c, c+1
+    constexpr uint32_t ROW_STRIDE = WORD * G;      // bytes between the messages of checks c, c+1
+    constexpr uint32_t KSTRIDE = WORD * G * CPT;   // bytes between the messages of steps k, k+1
 
     uint32_t lane_rt = threadIdx.x;
     opaque(lane_rt);  // keeps lane-derived constants inside this tile's code path
@@ -161,7 +163,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     // row of check g; made opaque inside the loop like the tables, so that its
     // constant row offsets fold into the LDS instructions instead of being
     // hoisted into registers of their own
-    uint32_t mu_row0 = base + a.mu0_off + WORD * RS * (uint32_t)g;
+    uint32_t mu_row0 = base + a.mu0_off + WORD * (uint32_t)g;
     const uint32_t lam_w0 = base + WORD * (uint32_t)g;                    // Lambda of fault g
     const unsigned long long gmask =
         (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (uint32_t)(slot * G));
@@ -210,7 +212,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
 #pragma unroll
-            for (int k = 0; k < DC; ++k) lds_at<float>(lds, mu_row0 + c * ROW_STRIDE + WORD * k) = 0.0f;
+            for (int k = 0; k < DC; ++k) lds_at<float>(lds, mu_row0 + c * ROW_STRIDE + KSTRIDE * k) = 0.0f;
     };
 
     // w and gamma of the code of the slot's shot: the launch's own, or (MULTI,
@@ -320,7 +322,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 const uint32_t row = mu_row0 + c * ROW_STRIDE;
                 float mo[DC], lv[DC];
 #pragma unroll
-                for (int k = 0; k < DC; ++k) mo[k] = lds_at<float>(lds, row + WORD * k);
+                for (int k = 0; k < DC; ++k) mo[k] = lds_at<float>(lds, row + KSTRIDE * k);
 #pragma unroll
                 for (int k = 0; k < DC; ++k) lv[k] = lds_at<float>(lds, lam_addr(c, k));
                 const bool sc = (sig >> c) & 1u;
@@ -347,7 +349,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     const float mag = (av[k] == m1) ? m2 : m1;
-                    lds_at<float>(lds, row + WORD * k) = (neg ^ sk[k]) ? -mag : mag;
+                    lds_at<float>(lds, row + KSTRIDE * k) = (neg ^ sk[k]) ? -mag : mag;
                 }
                 // keep the scheduler from hoisting the next check's gathers above
                 // this one: bounded live ranges keep the kernel inside its

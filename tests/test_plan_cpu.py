@@ -67,10 +67,11 @@ def test_bb_codes_every_configuration(name):
         assert r["fault_gathers"] <= r["fault_bank_cycles"] <= 64 * r["fault_gathers"]
     auto = rb.plan_check(p.m, p.n, p.rows, p.cols)
     assert auto["variant"] in reps and auto["block_kernel"] == 0
-    # slots of a half-wave on disjoint banks and annealed edge order: well
-    # below the 4+ cycles per gather of slots that share their banks
+    # slots of a half-wave on disjoint banks and annealed edge order: below
+    # the 4.6 to 5.6 cycles per check gather of slots that share their banks
+    # (the fault side is fixed by the check positions: 3.4 to 4.3)
     assert auto["check_bank_cycles"] / auto["check_gathers"] < 4.0
-    assert auto["fault_bank_cycles"] / auto["fault_gathers"] < 4.1
+    assert auto["fault_bank_cycles"] / auto["fault_gathers"] < 4.5
 
 
 def test_dem_block_kernel_tables_and_bank_cost():
