@@ -341,9 +341,10 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                     // two smallest magnitudes: with m1 <= m2, min(m2, max(m1, av)) is the
                     // median of (m1, av, m2)
                     m2 = __builtin_amdgcn_fmed3f(m1, av[k], m2);
-                    // min(m1, av) as med3(m1, av, -inf): one VOP3 op taking |nu| as a
-                    // source modifier
-                    m1 = __builtin_amdgcn_fmed3f(m1, av[k], -__builtin_inff());
+                    // min(m1, av) as med3(m1, av, -1) (both are >= +0): one VOP3 op
+                    // taking |nu| as a source modifier (a -inf bound would be
+                    // rewritten into a VOP2 min that needs |nu| in a register)
+                    m1 = __builtin_amdgcn_fmed3f(m1, av[k], -1.0f);
                 }
                 mism |= fpar;
 #pragma unroll
