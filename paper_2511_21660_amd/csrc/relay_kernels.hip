@@ -199,7 +199,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 
     // ---- per-slot state (identical in the G lanes of a slot)
     float Lr[VPT];  // Lambda_j of the lane's faults (unclipped)
-    float l0[VPT];  // lambda_j(0)
+    float xl[VPT];  // (1 - gamma_j) lambda_j(0), fixed within a leg
     float gm[VPT];  // gamma_j of the current leg
     uint32_t sig = 0;        // sigma bits of the lane's checks
     uint32_t best_mask = 0;  // best solution bits of the lane's faults
@@ -298,7 +298,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
             }
             Lr[v] = wj;
-            l0[v] = wj;
+            xl[v] = (1.0f - gj) * wj;
             gm[v] = gj;
         }
         zero_rows();
@@ -401,7 +401,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 for (int v = 0; v < VPT; ++v) {
                     if ((int)gl + G * v < a.N) {
                         gm[v] = gv[v];
-                        l0[v] = PRIOR ? a.scale * wv[v] : clipf(Lr[v], L);
+                        xl[v] = (1.0f - gv[v]) * (PRIOR ? a.scale * wv[v] : clipf(Lr[v], L));
                     }
                 }
                 zero_rows();
@@ -436,10 +436,8 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         if (active && !event) {
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
-                const float om = 1.0f - gm[v];
-                const float x = om * l0[v];
                 const float y = gm[v] * clipf(Lr[v], L);
-                float acc = clipf(x + y, L);
+                float acc = clipf(xl[v] + y, L);
 #pragma unroll
                 for (int k = 0; k < DV; ++k) acc += lds_at<float>(lds, mu_addr(v, k));
                 Lr[v] = acc;
