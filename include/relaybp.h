@@ -205,7 +205,7 @@ rb_status rb_set_variant(rb_ctx *ctx, int32_t variant);
  * a gather of 64 distinct words costs at least 2 (conflict-free). */
 typedef struct {
     int32_t variant;            /* configuration checked (index as in rb_info) */
-    int32_t block_kernel;       /* 1: large-graph block kernel, 0: group-kernel tile */
+    int32_t block_kernel;       /* 0: group-kernel tile, 1: block kernel, 2: large-graph kernel (no tables costed) */
     int32_t lds_bytes;          /* LDS image of one block (block kernel) or one wave (tile) */
     int64_t check_gathers;      /* table-driven Lambda gathers of one iteration (wave-wide) */
     int64_t check_bank_cycles;  /* their summed modelled cost */

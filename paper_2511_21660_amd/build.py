@@ -12,7 +12,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librelaybp.so")
-SOURCES = ["relay_kernels.hip", "relay_block.hip", "relay_train.hip", "relay_api.cpp"]
+SOURCES = ["relay_kernels.hip", "relay_block.hip", "relay_large.hip", "relay_train.hip", "relay_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -86,6 +86,14 @@ struct rb_ctx {
     int32_t nfam = 0;
     int32_t *d_code_fam = nullptr, *d_fam_rep = nullptr, *d_fam_size = nullptr;
     int32_t m_max = 0, n_max = 0;
+    // large-graph kernel (compressed messages): CSR / CSC copies and tables
+    bool large = false;
+    rb::LargeShape lshape{};
+    int32_t lrounds = 0, nsw = 0;
+    uint32_t chk_off = 0, sgn_off = 0;
+    int32_t *d_lrowptr = nullptr, *d_lcolptr = nullptr, *d_chk_of = nullptr;
+    uint16_t *d_col16 = nullptr;
+    uint32_t *d_fedge = nullptr;
     // CSR / CSC on the device (training kernels)
     int32_t *d_rowptr = nullptr, *d_colidx = nullptr, *d_colptr = nullptr, *d_cedge = nullptr;
     uint32_t lampad_off = 0, mupad_off = 0, mu0_off = 0, half_off = 0;
@@ -322,7 +330,7 @@ rb_status build_plan(rb_ctx *c, int v) {
     return RB_OK;
 }
 
-int total_variants() { return rb::num_variants() + rb::num_block_variants(); }
+int total_variants() { return rb::num_variants() + rb::num_block_variants() + rb::num_large_variants(); }
 
 struct BlockLayout {
     uint32_t lampad_off, mupad_off, red_off, mu0_off, slack_off;
@@ -511,9 +519,36 @@ bool block_fits(const rb_ctx *c, const rb::BlockShape &s) {
     return l.lds_bytes <= 160 * 1024;
 }
 
+// Large-graph kernel LDS: Lambda[N], one 16-byte state per check, the E sign
+// bits, reduction scratch.
+struct LargeLayout {
+    uint32_t chk_off, sgn_off, red_off;
+    int32_t nsw;
+    int64_t lds_bytes;
+};
+
+LargeLayout large_layout(const rb_ctx *c, const rb::LargeShape &s) {
+    LargeLayout l{};
+    l.nsw = (int32_t)((c->E + 31) / 32);
+    l.chk_off = ((4u * (uint32_t)c->N) + 15u) & ~15u;
+    l.sgn_off = l.chk_off + 16u * (uint32_t)c->M;
+    l.red_off = (l.sgn_off + 4u * (uint32_t)l.nsw + 15u) & ~15u;
+    l.lds_bytes = (int64_t)l.red_off + 12 * (s.TPB / 64) + 8;
+    return l;
+}
+
+bool large_fits(const rb_ctx *c, const rb::LargeShape &s) {
+    if (c->M > rb::kLargeRounds * s.TPB || c->N > s.TPB * s.VR) return false;
+    if (c->N > 65535 || c->M > (1 << (32 - rb::kLargeEdgeBits)) || c->E >= (int64_t)1 << rb::kLargeEdgeBits)
+        return false;
+    return large_layout(c, s).lds_bytes <= 160 * 1024;
+}
+
 bool any_fits(const rb_ctx *c, int v) {
     if (v < rb::num_variants()) return variant_fits(c, rb::variant_shape(v));
-    return block_fits(c, rb::block_variant_shape(v - rb::num_variants()));
+    v -= rb::num_variants();
+    if (v < rb::num_block_variants()) return block_fits(c, rb::block_variant_shape(v));
+    return large_fits(c, rb::large_variant_shape(v - rb::num_block_variants()));
 }
 
 template <typename T>
@@ -1264,12 +1299,130 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
     return RB_OK;
 }
 
+// Host tables of the large-graph kernel (no device work).  Checks sorted by
+// decreasing degree are dealt round by round (round r takes the next TPB of
+// them, thread t the t-th), so the 64 checks a wave handles in one round have
+// nearly the same length; fault-side entries pack each CSC entry's check and
+// CSR edge.
+struct LargeTables {
+    LargeLayout lay{};
+    int32_t rounds = 0;
+    std::vector<int32_t> chk_of, rowptr, colptr;
+    std::vector<uint16_t> col16;
+    std::vector<uint32_t> fedge;
+};
+
+LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
+    LargeTables T;
+    T.lay = large_layout(c, s);
+    T.rounds = (c->M + s.TPB - 1) / s.TPB;
+    std::vector<int32_t> order((size_t)c->M);
+    for (int32_t i = 0; i < c->M; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return c->rowptr[x + 1] - c->rowptr[x] > c->rowptr[y + 1] - c->rowptr[y];
+    });
+    T.chk_of.assign((size_t)rb::kLargeRounds * s.TPB, -1);
+    for (int32_t q = 0; q < c->M; ++q) T.chk_of[(size_t)q] = order[(size_t)q];
+    T.rowptr.assign(c->rowptr.begin(), c->rowptr.end());
+    T.colptr.assign(c->colptr.begin(), c->colptr.end());
+    T.col16.resize((size_t)c->E);
+    for (int64_t e = 0; e < c->E; ++e) T.col16[(size_t)e] = (uint16_t)c->colidx[(size_t)e];
+    T.fedge.resize((size_t)c->E);
+    for (int64_t q = 0; q < c->E; ++q) {
+        const int32_t i = c->rowidx[(size_t)q];
+        const int64_t e = c->rowptr[i] + c->cpos[(size_t)q];
+        T.fedge[(size_t)q] = ((uint32_t)i << rb::kLargeEdgeBits) | (uint32_t)e;
+    }
+    return T;
+}
+
+// Independent reading of the large-graph tables: every check on exactly one
+// (round, thread); rounds in use hold the checks (kernel reads rounds <
+// ceil(M/TPB)); each CSR edge's fault and each CSC entry's (check, edge) agree
+// with H; the LDS image fits.
+std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const LargeTables &T, rb_plan_report *r) {
+    if (T.lay.lds_bytes > 160 * 1024) return "LDS image exceeds a CU";
+    if (T.rounds < 1 || T.rounds > rb::kLargeRounds || (int64_t)T.rounds * s.TPB < c->M) return "check rounds";
+    std::vector<int> seen((size_t)c->M, 0);
+    for (size_t q = 0; q < T.chk_of.size(); ++q) {
+        const int32_t i = T.chk_of[q];
+        if (i < -1 || i >= c->M) return "placement entry " + std::to_string(q) + " out of range";
+        if (i < 0) continue;
+        if ((int64_t)(q / (size_t)s.TPB) >= T.rounds) return "check placed in an unused round";
+        if (seen[(size_t)i]++) return "check " + std::to_string(i) + " placed twice";
+    }
+    for (int32_t i = 0; i < c->M; ++i)
+        if (!seen[(size_t)i]) return "check " + std::to_string(i) + " not placed";
+    for (int32_t i = 0; i < c->M; ++i)
+        for (int64_t e = T.rowptr[(size_t)i]; e < T.rowptr[(size_t)i + 1]; ++e) {
+            const int32_t j = T.col16[(size_t)e];
+            if (j >= c->N) return "edge " + std::to_string(e) + ": fault out of range";
+            bool hit = false;  // (i, j) must be a column entry of fault j
+            for (int64_t q = T.colptr[(size_t)j]; q < T.colptr[(size_t)j + 1] && !hit; ++q)
+                hit = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits) == i &&
+                      (int64_t)(T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u)) == e;
+            if (!hit) return "edge " + std::to_string(e) + " missing from its fault's entries";
+        }
+    for (int32_t j = 0; j < c->N; ++j) {
+        int32_t prev = -1;
+        for (int64_t q = T.colptr[(size_t)j]; q < T.colptr[(size_t)j + 1]; ++q) {
+            const int32_t i = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits);
+            const int64_t e = T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u);
+            if (i <= prev) return "fault " + std::to_string(j) + ": checks not ascending";
+            if (e < T.rowptr[(size_t)i] || e >= T.rowptr[(size_t)i + 1] || T.col16[(size_t)e] != j)
+                return "fault " + std::to_string(j) + ": entry " + std::to_string(q) + " is not its edge";
+            prev = i;
+        }
+    }
+    r->lds_bytes = (int32_t)T.lay.lds_bytes;
+    return "";
+}
+
+rb_status build_large_plan(rb_ctx *c, int lv) {
+    const rb::LargeShape s = rb::large_variant_shape(lv);
+    const LargeTables T = large_tables(c, s);
+    rb_status st;
+    if ((st = upload(&c->d_chk_of, T.chk_of, "upload check placement")) != RB_OK) return st;
+    if ((st = upload(&c->d_lrowptr, T.rowptr, "upload rowptr")) != RB_OK) return st;
+    if ((st = upload(&c->d_lcolptr, T.colptr, "upload colptr")) != RB_OK) return st;
+    if ((st = upload(&c->d_col16, T.col16, "upload edge faults")) != RB_OK) return st;
+    if ((st = upload(&c->d_fedge, T.fedge, "upload fault entries")) != RB_OK) return st;
+    {
+        size_t st_lds = 0;
+        RB_HIP(rb::large_static_lds(lv, &st_lds), "kernel attributes");
+        if (st_lds != 0) return fail(RB_E_DEVICE, "internal: large-graph kernel uses static LDS");
+    }
+    RB_HIP(rb::large_prepare(lv, (size_t)T.lay.lds_bytes), "allow dynamic LDS");
+    c->variant = rb::num_variants() + rb::num_block_variants() + lv;
+    c->block = false;
+    c->large = true;
+    c->lshape = s;
+    c->lrounds = T.rounds;
+    c->nsw = T.lay.nsw;
+    c->chk_off = T.lay.chk_off;
+    c->sgn_off = T.lay.sgn_off;
+    c->red_off = T.lay.red_off;
+    c->lds_bytes = (int)T.lay.lds_bytes;
+    const bool prior = c->params.anchor == RB_ANCHOR_PRIOR;
+    for (int tr = 0; tr < 2; ++tr) {
+        int blocks = 0;
+        RB_HIP(rb::large_variant_occupancy(lv, prior, tr != 0, (size_t)T.lay.lds_bytes, &blocks),
+               "occupancy query");
+        if (blocks < 1) return fail(RB_E_UNSUPPORTED, "large-graph configuration does not fit on a CU");
+        c->blocks_per_cu[tr] = blocks;
+    }
+    return RB_OK;
+}
+
 rb_status plan(rb_ctx *c, int v) {
+    c->large = false;
     if (v < rb::num_variants()) {
         c->block = false;
         return build_plan(c, v);
     }
-    return build_block_plan(c, v - rb::num_variants());
+    v -= rb::num_variants();
+    if (v < rb::num_block_variants()) return build_block_plan(c, v);
+    return build_large_plan(c, v - rb::num_block_variants());
 }
 
 rb_status check_params(const rb_params *p) {
@@ -1364,6 +1517,8 @@ int choose_variant(const rb_ctx *c) {
     }
     for (int bv = 0; bv < rb::num_block_variants() && best < 0; ++bv)
         if (block_fits(c, rb::block_variant_shape(bv))) best = rb::num_variants() + bv;
+    for (int lv = 0; lv < rb::num_large_variants() && best < 0; ++lv)
+        if (large_fits(c, rb::large_variant_shape(lv))) best = rb::num_variants() + rb::num_block_variants() + lv;
     return best;
 }
 
@@ -1489,6 +1644,11 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_chk_split);
         (void)hipFree(c->d_w_slot);
         (void)hipFree(c->d_gamma_slot);
+        (void)hipFree(c->d_chk_of);
+        (void)hipFree(c->d_lrowptr);
+        (void)hipFree(c->d_lcolptr);
+        (void)hipFree(c->d_col16);
+        (void)hipFree(c->d_fedge);
     }
     if (c->d_rowptr || c->d_colidx || c->d_colptr || c->d_cedge) {
         (void)hipSetDevice(c->device);
@@ -1584,7 +1744,45 @@ static rb::BlockArgs block_args(const rb::GroupArgs &g, const rb_ctx *c) {
     return b;
 }
 
-static int shots_per_block(const rb_ctx *c) { return c->block ? 1 : 64 / c->shape.G; }
+static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
+    rb::LargeArgs b{};
+    b.M = g.M;
+    b.N = g.N;
+    b.B = g.B;
+    b.syn = g.syn;
+    b.corr = g.corr;
+    b.conv = g.conv;
+    b.legs = g.legs;
+    b.iters = g.iters;
+    b.weight = g.weight;
+    b.final_llr = g.final_llr;
+    b.w = g.w;
+    b.gamma = g.gamma;
+    b.rowptr = c->d_lrowptr;
+    b.colidx = c->d_col16;
+    b.colptr = c->d_lcolptr;
+    b.fedge = c->d_fedge;
+    b.chk_of = c->d_chk_of;
+    b.rounds = c->lrounds;
+    b.nsw = c->nsw;
+    b.queue = g.queue;
+    b.num_legs = g.num_legs;
+    b.iters_first = g.iters_first;
+    b.iters_leg = g.iters_leg;
+    b.num_solutions = g.num_solutions;
+    b.max_total_iters = g.max_total_iters;
+    b.L = g.L;
+    b.chk_off = c->chk_off;
+    b.sgn_off = c->sgn_off;
+    b.red_off = c->red_off;
+    b.trace_gamma = g.trace_gamma;
+    b.scale = g.scale;
+    b.trace_T = g.trace_T;
+    b.trace = g.trace;
+    return b;
+}
+
+static int shots_per_block(const rb_ctx *c) { return (c->block || c->large) ? 1 : 64 / c->shape.G; }
 
 static int grid_for(const rb_ctx *c, int64_t B, int trace) {
     const int spb = shots_per_block(c);
@@ -1598,7 +1796,11 @@ static rb_status launch(rb_ctx *c, const rb::GroupArgs &a, bool trace, hipStream
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(rb::launch_reset_queue(c->d_queue, s), "queue reset");
     const int grid = grid_for(c, a.B, trace ? 1 : 0);
-    if (c->block) {
+    if (c->large) {
+        RB_HIP(rb::launch_large(c->variant - rb::num_variants() - rb::num_block_variants(), prior, trace,
+                                large_args(a, c), grid, (size_t)c->lds_bytes, s),
+               "relay large-graph kernel launch");
+    } else if (c->block) {
         RB_HIP(rb::launch_block(c->variant - rb::num_variants(), prior, trace, block_args(a, c), grid,
                                 (size_t)c->lds_bytes, s),
                "relay block kernel launch");
@@ -1626,7 +1828,7 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
     a.iters = d_iters;
     a.weight = d_weight;
     a.final_llr = d_final_llr;
-    if (!c->block && c->d_ws && B <= c->ws_capacity) {
+    if (!c->block && !c->large && c->d_ws && B <= c->ws_capacity) {
         // longest-first order: shot list sorted by decreasing syndrome weight
         hipStream_t s = (hipStream_t)stream;
         RB_HIP(hipSetDevice(c->device), "hipSetDevice");
@@ -1717,7 +1919,16 @@ rb_status rb_get_info(const rb_ctx *c, rb_info *info) {
     info->max_row_degree = c->max_row;
     info->max_col_degree = c->max_col;
     info->variant = c->variant;
-    if (c->block) {
+    if (c->large) {
+        info->lanes_per_shot = c->lshape.TPB;
+        info->checks_per_lane = c->lrounds;
+        info->row_slots = c->max_row;
+        info->cols_per_lane = c->lshape.VR;
+        info->col_slots = c->max_col;
+        info->shots_per_block = 1;
+        info->threads_per_block = c->lshape.TPB;
+        info->waves_per_simd_target = c->lshape.TPB / 256;
+    } else if (c->block) {
         info->lanes_per_shot = c->bshape.TPB;
         info->checks_per_lane = 1;
         info->row_slots = c->bshape.DCMAX;
@@ -1773,10 +1984,14 @@ rb_status rb_plan_check(int32_t M, int32_t N, int64_t nnz, const int32_t *rows, 
     if (v < rb::num_variants()) {
         const rb::TileShape s = rb::variant_shape(v);
         err = check_group_tables(c, s, group_tables(c, s), out);
-    } else {
+    } else if (v < rb::num_variants() + rb::num_block_variants()) {
         const rb::BlockShape s = rb::block_variant_shape(v - rb::num_variants());
         out->block_kernel = 1;
         err = check_block_tables(c, s, block_tables(c, s), out);
+    } else {
+        const rb::LargeShape s = rb::large_variant_shape(v - rb::num_variants() - rb::num_block_variants());
+        out->block_kernel = 2;
+        err = check_large_tables(c, s, large_tables(c, s), out);
     }
     delete c;
     if (!err.empty()) return fail(RB_E_INTERNAL, "gather tables of variant " + std::to_string(v) + ": " + err);

@@ -152,6 +152,51 @@ hipError_t launch_gather_slots(const float *src, int64_t src_stride, const int32
 hipError_t launch_block(int v, bool prior_anchor, bool trace, const BlockArgs &a, int grid,
                         size_t lds, hipStream_t s);
 
+// Shape of a large-graph configuration: TPB threads decode one syndrome;
+// thread t owns faults t + TPB*v (v < VR) and up to kLargeRounds checks.
+struct LargeShape {
+    int TPB, VR;
+};
+constexpr int kLargeRounds = 4;       // checks per thread at most (M <= 4 * TPB)
+constexpr int kLargeEdgeBits = 20;    // fault-side entries: check << 20 | CSR edge
+
+struct LargeArgs {
+    int32_t M, N;
+    int64_t B;
+    const uint8_t *syn;
+    uint8_t *corr;
+    uint8_t *conv;
+    int32_t *legs;
+    int32_t *iters;
+    double *weight;
+    float *final_llr;
+    const float *w;            // [N]
+    const float *gamma;        // [R][N]
+    const int32_t *rowptr;     // [M+1] CSR
+    const uint16_t *colidx;    // [E] fault of each CSR edge
+    const int32_t *colptr;     // [N+1] CSC
+    const uint32_t *fedge;     // [E] CSC order (ascending check): check << kLargeEdgeBits | CSR edge
+    const int32_t *chk_of;     // [kLargeRounds][TPB] check of thread t in round c, or -1
+    int32_t rounds;            // check rounds in use (<= kLargeRounds)
+    int32_t nsw;               // words of edge sign bits (ceil(E / 32))
+    unsigned long long *queue;
+    int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
+    float L;
+    uint32_t chk_off, sgn_off, red_off;  // LDS byte offsets: check states, sign bits, scratch
+    const float *trace_gamma;
+    float scale;
+    int32_t trace_T;
+    float *trace;
+};
+
+int num_large_variants();
+LargeShape large_variant_shape(int v);
+hipError_t large_static_lds(int v, size_t *bytes);
+hipError_t large_variant_occupancy(int v, bool prior_anchor, bool trace, size_t lds, int *blocks);
+hipError_t large_prepare(int v, size_t lds);
+hipError_t launch_large(int v, bool prior_anchor, bool trace, const LargeArgs &a, int grid, size_t lds,
+                        hipStream_t s);
+
 // Per-code data of the mixed launch (device array).
 struct CodeStatic {
     int32_t M, N;

@@ -1,0 +1,358 @@
+// relay_large.hip -- Relay-BP for Tanner graphs whose check-to-fault messages
+// do not fit in LDS (gfx950), such as detector-error-model matrices with a few
+// thousand checks and tens of thousands of faults.
+//
+// Same decoder as the group and block kernels (paper Sec. 2.3: DMem-BP legs,
+// Relay chaining, S solutions).  One workgroup of TPB threads decodes one
+// syndrome at a time and pulls the next one from a global queue.
+//
+// Compressed messages.  The min-sum update gives every edge of check i the
+// magnitude m1 (the smallest |nu| over the check) except the edge holding that
+// minimum (its first position), which gets m2 (the second smallest), and the
+// sign sign(nu_e) XOR neg_i, where neg_i is the parity of sigma_i and of the
+// signs of all nu of the check.  A check's messages are therefore fixed by
+// the state (m1, m2, position of the minimum, neg) plus one sign bit per edge.
+// LDS holds Lambda[N], one 16-byte state per check and the E sign bits of
+// nu; a fault rebuilds each message it sums from the state of its check,
+// bit for bit the message the other kernels store.  A 2736 x 26208 matrix
+// with 82.6K edges takes 155 KiB.
+//
+// Roles.  Thread t owns the faults j = t + TPB*v (v < VR) and the checks
+// chk_of[c][t] (c < rounds), placed on the host so that every thread's checks
+// hold about the same number of edges.  The graph tables (fault of each CSR
+// edge, check and edge of each CSC entry) stay in global memory, shared by
+// all workgroups and L2-resident.  A 32-bit word of sign bits can hold edges
+// of two checks owned by different threads, so a check writes its bits of a
+// shared word with two LDS atomics (clear, then set its own bits).
+//
+// Iteration (as in the block kernel): the check pass of iteration t+1 reads
+// Lambda(t) for every edge, so the parity of F(t) per check is folded into it
+// and reduced with one barrier; leg and shot events are block-uniform.
+
+#include <algorithm>
+
+#include "relay_device.h"
+#include "relay_internal.h"
+
+namespace rb {
+namespace {
+
+__device__ __forceinline__ float clipl(float x, float L) { return __builtin_amdgcn_fmed3f(x, -L, L); }
+
+__device__ __forceinline__ void lds_and(uint32_t byte_addr, uint32_t v) {
+    __hip_atomic_fetch_and((__attribute__((address_space(3))) uint32_t *)(size_t)byte_addr, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
+    __hip_atomic_fetch_or((__attribute__((address_space(3))) uint32_t *)(size_t)byte_addr, v, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int TPB, int VR, bool PRIOR, bool TRACE>
+__global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
+    static_assert(VR <= 32 && TPB % 256 == 0, "shape");
+    const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
+    const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 bytes (block OR), 16-byte aligned
+    const uint32_t shot_sh = flags + 4u * (TPB / 64);     // claimed shot index
+    const uint32_t chk = a.chk_off, sgn = a.sgn_off;
+    const int t = threadIdx.x;
+    const float L = a.L;
+    const int N = a.N;
+    // thread index made opaque at the top of every iteration, so that the
+    // per-fault addresses are recomputed where used instead of being hoisted
+    // out of the persistent loop (2 * VR 64-bit pointers would spill)
+    uint32_t tl = (uint32_t)t;
+
+    // this thread's checks and their CSR ranges
+    int ci[kLargeRounds], cb[kLargeRounds], ce[kLargeRounds];
+#pragma unroll
+    for (int c = 0; c < kLargeRounds; ++c) {
+        const int i = c < a.rounds ? a.chk_of[c * TPB + t] : -1;
+        ci[c] = i;
+        cb[c] = i >= 0 ? a.rowptr[i] : 0;
+        ce[c] = i >= 0 ? a.rowptr[i + 1] : 0;
+    }
+    if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
+
+    // xl = (1 - gamma) * lambda(0) is constant within a leg and kept as such
+    float xl[VR], gm[VR];
+    uint32_t sig = 0;  // bit c: syndrome bit of check ci[c]
+    uint32_t best_mask = 0;
+    double best_w = 0.0;
+    long long shot = -1;
+    int r = 0, tt = 0, total = 0, count = 0;
+
+    // messages restart at zero: states (0, 0, 0, 0) and all sign bits clear
+    // rebuild +0 on every edge
+    auto zero_messages = [&]() {
+#pragma unroll
+        for (int c = 0; c < kLargeRounds; ++c)
+            if (ci[c] >= 0) {
+                const uint32_t sa = chk + 16u * (uint32_t)ci[c];
+                lds_b<uint32_t>(sa) = 0u;
+                lds_b<uint32_t>(sa + 4u) = 0u;
+                lds_b<uint32_t>(sa + 8u) = 0u;
+                lds_b<uint32_t>(sa + 12u) = 0u;
+            }
+        for (int q = t; q < a.nsw; q += TPB) lds_b<uint32_t>(sgn + 4u * (uint32_t)q) = 0u;
+    };
+
+    auto fetch = [&]() -> bool {
+        if (t == 0) lds_b<unsigned long long>(shot_sh) = atomicAdd(a.queue, 1ull);
+        __syncthreads();
+        const unsigned long long nxt = lds_b<unsigned long long>(shot_sh);
+        __syncthreads();
+        if (nxt >= (unsigned long long)a.B) return false;
+        shot = (long long)nxt;
+        r = 1;
+        tt = 0;
+        total = 0;
+        count = 0;
+        best_w = __longlong_as_double(0x7ff0000000000000ll);
+        best_mask = 0;
+        sig = 0;
+#pragma unroll
+        for (int c = 0; c < kLargeRounds; ++c)
+            if (ci[c] >= 0 && a.syn[(size_t)shot * a.M + ci[c]] != 0) sig |= 1u << c;
+#pragma unroll
+        for (int v = 0; v < VR; ++v) {
+            const int j = (int)tl + TPB * v;
+            float wj = 0.0f, gj = 0.0f;
+            if (j < N) {
+                wj = a.scale * a.w[j];
+                gj = TRACE ? a.trace_gamma[j] : a.gamma[j];
+                lds_b<float>(4u * (uint32_t)j) = wj;
+                if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * N + j] = wj;
+            }
+            xl[v] = (1.0f - gj) * wj;
+            gm[v] = gj;
+        }
+        zero_messages();
+        return true;
+    };
+
+    bool active = fetch();
+    __syncthreads();
+
+    while (active) {
+        asm volatile("" : "+v"(tl));
+        // ---------------- check pass: new states from Lambda(t) and the old
+        // messages; parity of F(t) per check
+        bool unsat_local = false;
+#pragma unroll
+        for (int c = 0; c < kLargeRounds; ++c) {
+            const int i = ci[c];
+            if (i < 0) continue;
+            const uint32_t sa = chk + 16u * (uint32_t)i;
+            const float m1o = lds_b<float>(sa);
+            const float m2o = lds_b<float>(sa + 4u);
+            const int amo = lds_b<int>(sa + 8u);
+            const uint32_t flipo = lds_b<uint32_t>(sa + 12u) ? 0xffffffffu : 0u;
+            const bool sc = (sig >> c) & 1u;
+            bool fpar = sc, neg = sc;
+            float m1 = L, m2 = L;
+            int amin = cb[c];
+            int e = cb[c];
+            const int e1 = ce[c];
+            while (e < e1) {
+                const int wi = e >> 5;
+                const int we = min(e1, (wi + 1) << 5);  // end of the row's part of word wi
+                const uint32_t wa = sgn + 4u * (uint32_t)wi;
+                const uint32_t osg = lds_b<uint32_t>(wa) ^ flipo;  // old message signs
+                uint32_t nb = 0u, mask = 0u;
+                for (; e < we; ++e) {
+                    const float lv = lds_b<float>(4u * (uint32_t)a.colidx[e]);
+                    const uint32_t bit = 1u << (e & 31);
+                    const float mag = e == amo ? m2o : m1o;
+                    const float mo = __uint_as_float((osg & bit ? 0x80000000u : 0u) | __float_as_uint(mag));
+                    fpar ^= lv < 0.0f;
+                    const float nu = clipl(lv - mo, L);
+                    const bool sn = nu < 0.0f;
+                    neg ^= sn;
+                    nb |= sn ? bit : 0u;
+                    mask |= bit;
+                    const float av = fabsf(nu);
+                    amin = av < m1 ? e : amin;
+                    m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
+                    m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
+                }
+                if (mask == 0xffffffffu) {
+                    lds_b<uint32_t>(wa) = nb;
+                } else {
+                    lds_and(wa, ~mask);
+                    lds_or(wa, nb);
+                }
+            }
+            lds_b<float>(sa) = m1;
+            lds_b<float>(sa + 4u) = m2;
+            lds_b<int>(sa + 8u) = amin;
+            lds_b<uint32_t>(sa + 12u) = neg ? 1u : 0u;
+            unsat_local |= fpar;
+        }
+        const bool unsat = block_or<TPB>(unsat_local, flags);
+
+        // ---------------- leg scheduler (block-uniform)
+        const bool cut = a.max_total_iters > 0 && total >= a.max_total_iters;
+        const bool conv_ev = !TRACE && tt >= 1 && !unsat;
+        const int T_r = TRACE ? a.trace_T : (r == 1 ? a.iters_first : a.iters_leg);
+        const bool leg_ev = !conv_ev && (tt >= T_r || (!TRACE && cut));
+        if (conv_ev || leg_ev) {
+            bool done = true;
+            if (!TRACE) {
+                uint32_t fm = 0;
+                double part = 0.0;
+#pragma unroll
+                for (int v = 0; v < VR; ++v) {
+                    const int j = (int)tl + TPB * v;
+                    if (j < N) {
+                        const bool f = lds_b<float>(4u * (uint32_t)j) < 0.0f;
+                        fm |= f ? 1u << v : 0u;
+                        part += (double)(f ? a.w[j] : 0.0f);  // + 0 leaves the sum's bits unchanged
+                    }
+                }
+                const double W = block_sum<TPB>(part, red);
+                if (conv_ev) {
+                    ++count;
+                    if (W < best_w) {
+                        best_w = W;
+                        best_mask = fm;
+                    }
+                    done = count >= a.num_solutions || r >= a.num_legs || cut;
+                } else {
+                    done = r >= a.num_legs || cut;
+                }
+                if (done) {
+                    const uint32_t out = count > 0 ? best_mask : fm;
+#pragma unroll
+                    for (int v = 0; v < VR; ++v) {
+                        const int j = (int)tl + TPB * v;
+                        if (j < N) {
+                            a.corr[(size_t)shot * N + j] = (uint8_t)((out >> v) & 1u);
+                            if (a.final_llr) a.final_llr[(size_t)shot * N + j] = lds_b<float>(4u * (uint32_t)j);
+                        }
+                    }
+                    if (t == 0) {
+                        a.conv[shot] = count > 0 ? 1 : 0;
+                        a.legs[shot] = r;
+                        a.iters[shot] = total;
+                        if (a.weight) a.weight[shot] = count > 0 ? best_w : W;
+                    }
+                }
+            }
+            if (!done) {
+                ++r;
+                tt = 0;
+                const float *gr = a.gamma + (size_t)(r - 1) * N;
+#pragma unroll
+                for (int v = 0; v < VR; ++v) {
+                    const int j = (int)tl + TPB * v;
+                    if (j < N) {
+                        const float gv = gr[j];
+                        const float l0 = PRIOR ? a.scale * a.w[j] : clipl(lds_b<float>(4u * (uint32_t)j), L);
+                        gm[v] = gv;
+                        xl[v] = (1.0f - gv) * l0;
+                    }
+                }
+                zero_messages();
+            } else {
+                active = fetch();
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // ---------------- fault pass: memory term, then the messages of the
+        // fault's checks in ascending check order, each rebuilt from its
+        // check's state and its edge's sign bit
+#pragma unroll
+        for (int v = 0; v < VR; ++v) {
+            const int j = (int)tl + TPB * v;
+            if (j >= N) continue;
+            const float y = gm[v] * clipl(lds_b<float>(4u * (uint32_t)j), L);
+            float acc = clipl(xl[v] + y, L);
+            const int q1 = a.colptr[j + 1];
+            for (int q = a.colptr[j]; q < q1; ++q) {
+                const uint32_t pk = a.fedge[q];
+                const uint32_t e = pk & ((1u << kLargeEdgeBits) - 1u);
+                const uint32_t sa = chk + 16u * (pk >> kLargeEdgeBits);
+                const float m1 = lds_b<float>(sa);
+                const float m2 = lds_b<float>(sa + 4u);
+                const uint32_t am = lds_b<uint32_t>(sa + 8u);
+                const uint32_t ng = lds_b<uint32_t>(sa + 12u);
+                const uint32_t sw = lds_b<uint32_t>(sgn + 4u * (e >> 5));
+                const float mag = e == am ? m2 : m1;
+                const uint32_t s = ((sw >> (e & 31u)) ^ ng) & 1u;
+                acc += __uint_as_float((s << 31) | __float_as_uint(mag));
+            }
+            lds_b<float>(4u * (uint32_t)j) = acc;
+            if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + j] = acc;
+        }
+        ++tt;
+        ++total;
+        __syncthreads();
+    }
+}
+
+struct LargeVariant {
+    LargeShape shape;
+    const void *fn[2][2];
+};
+
+#define RB_LVARIANT(TPB, VR)                                                                   \
+    {{TPB, VR},                                                                                \
+     {{(const void *)relay_large_kernel<TPB, VR, false, false>,                                \
+       (const void *)relay_large_kernel<TPB, VR, false, true>},                                \
+      {(const void *)relay_large_kernel<TPB, VR, true, false>,                                 \
+       (const void *)relay_large_kernel<TPB, VR, true, true>}}}
+
+// (threads, fault rounds per thread): N <= TPB * VR, M <= kLargeRounds * TPB;
+// the planner takes the first that fits
+const LargeVariant kLargeVariants[] = {
+    RB_LVARIANT(1024, 16),  // N <= 16384
+    RB_LVARIANT(1024, 32),  // N <= 32768
+};
+
+}  // namespace
+
+int num_large_variants() { return (int)(sizeof(kLargeVariants) / sizeof(kLargeVariants[0])); }
+
+LargeShape large_variant_shape(int v) { return kLargeVariants[v].shape; }
+
+hipError_t large_variant_occupancy(int v, bool prior_anchor, bool trace, size_t lds, int *blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, kLargeVariants[v].fn[prior_anchor ? 1 : 0][trace ? 1 : 0], kLargeVariants[v].shape.TPB, lds);
+}
+
+hipError_t large_static_lds(int v, size_t *bytes) {
+    size_t mx = 0;
+    for (int p = 0; p < 2; ++p)
+        for (int tr = 0; tr < 2; ++tr) {
+            hipFuncAttributes attr;
+            const hipError_t e = hipFuncGetAttributes(&attr, kLargeVariants[v].fn[p][tr]);
+            if (e != hipSuccess) return e;
+            mx = std::max(mx, (size_t)attr.sharedSizeBytes);
+        }
+    *bytes = mx;
+    return hipSuccess;
+}
+
+hipError_t large_prepare(int v, size_t lds) {
+    for (int p = 0; p < 2; ++p)
+        for (int tr = 0; tr < 2; ++tr) {
+            hipError_t e = hipFuncSetAttribute(kLargeVariants[v].fn[p][tr],
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+hipError_t launch_large(int v, bool prior_anchor, bool trace, const LargeArgs &a, int grid, size_t lds,
+                        hipStream_t s) {
+    const void *fn = kLargeVariants[v].fn[prior_anchor ? 1 : 0][trace ? 1 : 0];
+    LargeArgs copy = a;
+    void *args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kLargeVariants[v].shape.TPB), args, lds, s);
+}
+
+}  // namespace rb

@@ -96,9 +96,9 @@ def test_unsupported_graph_is_reported():
 
     if torch.cuda.is_available():
         pytest.skip("checked on CPU hosts only")
-    # a row of degree 200 exceeds every built-in configuration (the block
-    # kernel splits a long row over two lanes of at most 64 edges each)
-    n = 200
+    # 40,000 faults exceed every built-in configuration (the large-graph
+    # kernel keeps Lambda of at most 32,768 faults in LDS)
+    n = 40000
     st, msg = _create(1, n, np.zeros(n, np.int32), np.arange(n, dtype=np.int32), np.full(n, 0.1))
     assert st == 8 and "exceeds" in msg
 
