@@ -11,6 +11,8 @@ Other workloads:
   --workload dem          DEM-shaped 936 x 8785 matrix, 10^6 shots, R = 20, S = 1;
                           with the latency tail: completion and LER within FPGA-cycle
                           budgets, epsilon(T_ref) and the latency-tail condition
+  --workload dem-2gross   two-gross-scale DEM-shaped 2736 x 26208 matrix (82.6K edges)
+                          on the large-graph kernel, 2 x 10^5 shots, R = 20, S = 1
   --workload bp-llr       plain min-sum BP (one leg, gamma = 0, 25 rounds) on the
                           DEM-shaped matrix, 10^5 shots, returning the marginals
   --workload mixed-codes  [[72,12,6]], [[90,8,10]], [[144,12,12]], [[288,12,18]]
@@ -64,7 +66,7 @@ OPS_PER_EDGE = 12.0
 OPS_PER_FAULT = 7.0
 OPS_PER_CHECK = 3.0
 
-DEFAULT_STEPS = {"bb144": 20, "dem": 5, "mixed-codes": 10, "learned": 3, "bp-llr": 10}
+DEFAULT_STEPS = {"bb144": 20, "dem": 5, "dem-2gross": 3, "mixed-codes": 10, "learned": 3, "bp-llr": 10}
 
 
 def ops_per_iteration(m, n, e):
@@ -76,6 +78,14 @@ def lds_bytes_per_edge_update(m, n, e):
     back (8 B), plus Lambda / lambda per fault (8 B) and the check state
     (12 B) per check, spread over the edges."""
     return 8.0 + (8.0 * n + 12.0 * m) / e
+
+
+def lds_bytes_per_edge_update_large(m, n, e):
+    """The same for the large-graph kernel's compressed messages: Lambda to
+    the check (4 B) and the check's state (16 B) plus the edge's sign word
+    (4 B) to the fault; per check its state read and written (32 B) and its
+    sign words (2 x 4 B per 32 edges); per fault Lambda read and written."""
+    return 24.0 + 8.0 / 32.0 + (32.0 * m + 8.0 * n) / e
 
 
 def wilson(k, n, z=1.96):
@@ -279,15 +289,18 @@ def run_bb144(args, torch, rb, codes, sampling):
 # --------------------------------------------------------------------------
 
 
-def run_dem(args, torch, rb, codes, sampling):
+def run_dem(args, torch, rb, codes, sampling, two_gross=False):
+    """DEM-shaped matrix: 936 x 8785 on the block kernel, or (two_gross) the
+    two-gross-scale 2736 x 26208 on the large-graph kernel."""
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
-    prob = codes.dem_problem()
+    prob = codes.dem_problem(2736, 26208) if two_gross else codes.dem_problem()
     M, N, E = prob.m, prob.n, prob.nnz
-    shots = args.shots or 1000000
+    tag = f"{M}x{N}"
+    shots = args.shots or (200000 if two_gross else 1000000)
     t_in = time.perf_counter()
     syn_np, (f_shots, f_cols) = sampling.sample_syndromes_sparse(prob, 0xDE3, shots)
-    print(f"# dem inputs: {shots} shots, {f_shots.size} faults, "
+    print(f"# dem {tag} inputs: {shots} shots, {f_shots.size} faults, "
           f"{time.perf_counter() - t_in:.1f} s", file=sys.stderr, flush=True)
     dec = rb.Decoder.from_problem(prob, device=0, **RELAY_R20)
     if args.variant is not None:
@@ -307,9 +320,10 @@ def run_dem(args, torch, rb, codes, sampling):
     iters = out["iters"].cpu().numpy()
     conv = out["conv"].cpu().numpy()
     iters_launch = int(iters.astype(np.int64).sum())
-    roof, lds = roofline("relay_block_kernel", kernel_ms, iters_launch * ops_per_iteration(M, N, E),
-                         iters_launch * E, lds_bytes_per_edge_update(M, N, E),
-                         stored_traffic("relay_block_kernel_dem936x8785_hbm_traffic.txt"))
+    kernel = "relay_large_kernel" if two_gross else "relay_block_kernel"
+    lds_b = lds_bytes_per_edge_update_large(M, N, E) if two_gross else lds_bytes_per_edge_update(M, N, E)
+    roof, lds = roofline(kernel, kernel_ms, iters_launch * ops_per_iteration(M, N, E), iters_launch * E, lds_b,
+                         stored_traffic(f"{kernel}_dem{tag}_hbm_traffic.txt"))
     # logical failures on the GPU, so that the 8.8 GB correction array stays in
     # HBM: A (F xor F_hat) = A F xor A F_hat over GF(2).
     a = torch.from_numpy(prob.logical.astype(np.float32)).to(dev)
@@ -331,7 +345,7 @@ def run_dem(args, torch, rb, codes, sampling):
         import oracle
 
         threads = oracle_threads()
-        n_cpu = min(args.cpu_sample or 20000, shots)
+        n_cpu = min(args.cpu_sample or (200 if two_gross else 20000), shots)
         t1 = time.perf_counter()
         ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n_cpu],
                             threads=threads)
@@ -343,7 +357,7 @@ def run_dem(args, torch, rb, codes, sampling):
                "sample": f"first {n_cpu} of {shots} syndromes, same inputs, {tc:.1f} s",
                "paired_with_gpu_bit_exact": agree}
     line = head(args, shots * args.steps / elapsed, elapsed, {
-        "workload": "relay_bp_dem_936x8785", "matrix": "DEM-shaped synthetic 936x8785",
+        "workload": f"relay_bp_dem_{tag}", "matrix": f"DEM-shaped synthetic {tag}",
         "edges": E, "shots": shots, "T_first": 80, "T_leg": 60, "legs": 20, "solutions": 1,
         "gamma_first": 0.125, "gamma_range": [-0.24, 0.66], "anchor": "chain",
         "parallelism": "single_gpu"})
@@ -629,7 +643,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["bb144", "dem", "mixed-codes", "learned", "bp-llr"], default="bb144")
+    ap.add_argument("--workload", choices=["bb144", "dem", "dem-2gross", "mixed-codes", "learned", "bp-llr"],
+                    default="bb144")
     ap.add_argument("--train-steps", type=int, default=0, help="learned: Adam steps (default 2000)")
     ap.add_argument("--shots", type=int, default=0,
                     help="syndromes per p (bb144) or in total (default per workload)")
@@ -650,7 +665,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print(json.dumps({"error": "this build decodes on one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the decoder runs on one GPU (shots are independent; no multi-GPU path): run with --gpus 1"}))
         sys.exit(2)
 
     import torch
@@ -661,7 +676,8 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
-    run = {"bb144": run_bb144, "dem": run_dem, "mixed-codes": run_mixed_codes,
+    run = {"bb144": run_bb144, "dem": run_dem, "dem-2gross": lambda *x: run_dem(*x, two_gross=True),
+           "mixed-codes": run_mixed_codes,
            "learned": run_learned, "bp-llr": run_bp_llr}[args.workload]
     line = run(args, torch, rb, codes, sampling)
     if args.calibrate_copy > 0:

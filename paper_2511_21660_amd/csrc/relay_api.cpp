@@ -92,8 +92,9 @@ struct rb_ctx {
     int32_t lrounds = 0, nsw = 0;
     uint32_t chk_off = 0, sgn_off = 0;
     int32_t *d_lrowptr = nullptr, *d_lcolptr = nullptr, *d_chk_of = nullptr;
-    uint16_t *d_col16 = nullptr;
-    uint32_t *d_fedge = nullptr;
+    uint16_t *d_col16 = nullptr;            // row chunks of fault indices
+    int32_t *d_rbase = nullptr;
+    uint32_t *d_fedge = nullptr, *d_frec = nullptr;
     // CSR / CSC on the device (training kernels)
     int32_t *d_rowptr = nullptr, *d_colidx = nullptr, *d_colptr = nullptr, *d_cedge = nullptr;
     uint32_t lampad_off = 0, mupad_off = 0, mu0_off = 0, half_off = 0;
@@ -1307,12 +1308,13 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
 struct LargeTables {
     LargeLayout lay{};
     int32_t rounds = 0;
-    std::vector<int32_t> chk_of, rowptr, colptr;
-    std::vector<uint16_t> col16;
-    std::vector<uint32_t> fedge;
+    std::vector<int32_t> chk_of, rowptr, colptr, rbase;
+    std::vector<uint16_t> ctab;  // rows padded to multiples of kLargeGather entries, + one zero chunk
+    std::vector<uint32_t> frec, fedge;
 };
 
 LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
+    constexpr int G = rb::kLargeGather;
     LargeTables T;
     T.lay = large_layout(c, s);
     T.rounds = (c->M + s.TPB - 1) / s.TPB;
@@ -1325,14 +1327,26 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     for (int32_t q = 0; q < c->M; ++q) T.chk_of[(size_t)q] = order[(size_t)q];
     T.rowptr.assign(c->rowptr.begin(), c->rowptr.end());
     T.colptr.assign(c->colptr.begin(), c->colptr.end());
-    T.col16.resize((size_t)c->E);
-    for (int64_t e = 0; e < c->E; ++e) T.col16[(size_t)e] = (uint16_t)c->colidx[(size_t)e];
-    T.fedge.resize((size_t)c->E);
+    T.rbase.resize((size_t)c->M);
+    int64_t chunks = 0;
+    for (int32_t i = 0; i < c->M; ++i) {
+        T.rbase[(size_t)i] = (int32_t)chunks;
+        chunks += (c->rowptr[i + 1] - c->rowptr[i] + G - 1) / G;
+    }
+    T.ctab.assign((size_t)(chunks + 1) * G, 0);
+    for (int32_t i = 0; i < c->M; ++i)
+        for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e)
+            T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)(e - c->rowptr[i])] = (uint16_t)c->colidx[(size_t)e];
+    T.fedge.resize((size_t)std::max<int64_t>(1, c->E), 0u);
     for (int64_t q = 0; q < c->E; ++q) {
         const int32_t i = c->rowidx[(size_t)q];
         const int64_t e = c->rowptr[i] + c->cpos[(size_t)q];
         T.fedge[(size_t)q] = ((uint32_t)i << rb::kLargeEdgeBits) | (uint32_t)e;
     }
+    T.frec.assign((size_t)c->N * G, 0u);
+    for (int32_t j = 0; j < c->N; ++j)
+        for (int64_t q = c->colptr[j]; q < c->colptr[j + 1] && q - c->colptr[j] < G; ++q)
+            T.frec[(size_t)j * G + (size_t)(q - c->colptr[j])] = T.fedge[(size_t)q];
     return T;
 }
 
@@ -1343,6 +1357,28 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
 std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const LargeTables &T, rb_plan_report *r) {
     if (T.lay.lds_bytes > 160 * 1024) return "LDS image exceeds a CU";
     if (T.rounds < 1 || T.rounds > rb::kLargeRounds || (int64_t)T.rounds * s.TPB < c->M) return "check rounds";
+    // the kernel loads whole chunks of kLargeGather entries: a row's chunk
+    // past its last edge and a record past a column's last entry hold zeros
+    // (valid addresses), and every chunk lies inside the table
+    constexpr int G = rb::kLargeGather;
+    if (T.frec.size() != (size_t)c->N * G) return "fault records";
+    auto col_of_edge = [&](int32_t i, int64_t e) -> int64_t {  // fault of CSR edge e of row i, from ctab
+        const size_t at = (size_t)T.rbase[(size_t)i] * G + (size_t)(e - T.rowptr[(size_t)i]);
+        return at < T.ctab.size() ? (int64_t)T.ctab[at] : -1;
+    };
+    for (int32_t i = 0; i < c->M; ++i) {
+        const int64_t d = T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i];
+        if ((size_t)(T.rbase[(size_t)i] + (d + G - 1) / G) * G > T.ctab.size()) return "row chunks past the table";
+        for (int64_t k = d; k < (d + G - 1) / G * G; ++k)
+            if (T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)k] != 0) return "row padding values";
+    }
+    for (int32_t j = 0; j < c->N; ++j) {
+        const int64_t d = T.colptr[(size_t)j + 1] - T.colptr[(size_t)j];
+        for (int k = 0; k < G; ++k) {
+            const uint32_t want = k < d ? T.fedge[(size_t)(T.colptr[(size_t)j] + k)] : 0u;
+            if (T.frec[(size_t)j * G + k] != want) return "fault " + std::to_string(j) + ": record entry " + std::to_string(k);
+        }
+    }
     std::vector<int> seen((size_t)c->M, 0);
     for (size_t q = 0; q < T.chk_of.size(); ++q) {
         const int32_t i = T.chk_of[q];
@@ -1355,8 +1391,8 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
         if (!seen[(size_t)i]) return "check " + std::to_string(i) + " not placed";
     for (int32_t i = 0; i < c->M; ++i)
         for (int64_t e = T.rowptr[(size_t)i]; e < T.rowptr[(size_t)i + 1]; ++e) {
-            const int32_t j = T.col16[(size_t)e];
-            if (j >= c->N) return "edge " + std::to_string(e) + ": fault out of range";
+            const int64_t j = col_of_edge(i, e);
+            if (j < 0 || j >= c->N) return "edge " + std::to_string(e) + ": fault out of range";
             bool hit = false;  // (i, j) must be a column entry of fault j
             for (int64_t q = T.colptr[(size_t)j]; q < T.colptr[(size_t)j + 1] && !hit; ++q)
                 hit = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits) == i &&
@@ -1369,7 +1405,7 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
             const int32_t i = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits);
             const int64_t e = T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u);
             if (i <= prev) return "fault " + std::to_string(j) + ": checks not ascending";
-            if (e < T.rowptr[(size_t)i] || e >= T.rowptr[(size_t)i + 1] || T.col16[(size_t)e] != j)
+            if (e < T.rowptr[(size_t)i] || e >= T.rowptr[(size_t)i + 1] || col_of_edge(i, e) != j)
                 return "fault " + std::to_string(j) + ": entry " + std::to_string(q) + " is not its edge";
             prev = i;
         }
@@ -1385,7 +1421,9 @@ rb_status build_large_plan(rb_ctx *c, int lv) {
     if ((st = upload(&c->d_chk_of, T.chk_of, "upload check placement")) != RB_OK) return st;
     if ((st = upload(&c->d_lrowptr, T.rowptr, "upload rowptr")) != RB_OK) return st;
     if ((st = upload(&c->d_lcolptr, T.colptr, "upload colptr")) != RB_OK) return st;
-    if ((st = upload(&c->d_col16, T.col16, "upload edge faults")) != RB_OK) return st;
+    if ((st = upload(&c->d_col16, T.ctab, "upload row chunks")) != RB_OK) return st;
+    if ((st = upload(&c->d_rbase, T.rbase, "upload row bases")) != RB_OK) return st;
+    if ((st = upload(&c->d_frec, T.frec, "upload fault records")) != RB_OK) return st;
     if ((st = upload(&c->d_fedge, T.fedge, "upload fault entries")) != RB_OK) return st;
     {
         size_t st_lds = 0;
@@ -1648,7 +1686,9 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_lrowptr);
         (void)hipFree(c->d_lcolptr);
         (void)hipFree(c->d_col16);
+        (void)hipFree(c->d_rbase);
         (void)hipFree(c->d_fedge);
+        (void)hipFree(c->d_frec);
     }
     if (c->d_rowptr || c->d_colidx || c->d_colptr || c->d_cedge) {
         (void)hipSetDevice(c->device);
@@ -1759,8 +1799,10 @@ static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.w = g.w;
     b.gamma = g.gamma;
     b.rowptr = c->d_lrowptr;
-    b.colidx = c->d_col16;
+    b.ctab = c->d_col16;
+    b.rbase = c->d_rbase;
     b.colptr = c->d_lcolptr;
+    b.frec = c->d_frec;
     b.fedge = c->d_fedge;
     b.chk_of = c->d_chk_of;
     b.rounds = c->lrounds;

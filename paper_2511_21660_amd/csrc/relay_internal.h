@@ -159,6 +159,9 @@ struct LargeShape {
 };
 constexpr int kLargeRounds = 4;       // checks per thread at most (M <= 4 * TPB)
 constexpr int kLargeEdgeBits = 20;    // fault-side entries: check << 20 | CSR edge
+constexpr int kLargeGather = 8;       // row chunk and fault record length (table entries per load step)
+constexpr int kLargeBatch = 4;        // faults whose loads the fault pass issues together
+constexpr int kLargeSure = 4;         // fault entries read whatever the degree (padding included)
 
 struct LargeArgs {
     int32_t M, N;
@@ -173,8 +176,11 @@ struct LargeArgs {
     const float *w;            // [N]
     const float *gamma;        // [R][N]
     const int32_t *rowptr;     // [M+1] CSR
-    const uint16_t *colidx;    // [E] fault of each CSR edge
+    const uint16_t *ctab;      // row i's fault indices from entry 8 * rbase[i], padded with 0 to a
+                               // multiple of kLargeGather (16-byte aligned chunks)
+    const int32_t *rbase;      // [M] first chunk of row i in ctab
     const int32_t *colptr;     // [N+1] CSC
+    const uint32_t *frec;      // [N][kLargeGather] first entries of each column (padding: 0)
     const uint32_t *fedge;     // [E] CSC order (ascending check): check << kLargeEdgeBits | CSR edge
     const int32_t *chk_of;     // [kLargeRounds][TPB] check of thread t in round c, or -1
     int32_t rounds;            // check rounds in use (<= kLargeRounds)

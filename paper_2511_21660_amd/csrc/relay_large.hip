@@ -18,10 +18,12 @@
 // with 82.6K edges takes 155 KiB.
 //
 // Roles.  Thread t owns the faults j = t + TPB*v (v < VR) and the checks
-// chk_of[c][t] (c < rounds), placed on the host so that every thread's checks
-// hold about the same number of edges.  The graph tables (fault of each CSR
-// edge, check and edge of each CSC entry) stay in global memory, shared by
-// all workgroups and L2-resident.  A 32-bit word of sign bits can hold edges
+// chk_of[c][t] (c < rounds): checks sorted by degree and dealt round by round,
+// so the 64 rows a wave handles in one round have nearly the same length.
+// The graph tables stay in global memory, shared by all workgroups and
+// L2-resident: each row's fault indices padded to a multiple of 8 (one
+// aligned 16-byte load per 8 edges) and one 32-byte record per fault with its
+// first 8 (check, edge) entries (the records of a wave's lanes contiguous).  A 32-bit word of sign bits can hold edges
 // of two checks owned by different threads, so a check writes its bits of a
 // shared word with two LDS atomics (clear, then set its own bits).
 //
@@ -39,6 +41,10 @@ namespace {
 
 __device__ __forceinline__ float clipl(float x, float L) { return __builtin_amdgcn_fmed3f(x, -L, L); }
 
+// four words in one LDS access (a plain vector type: the LDS helpers take no
+// class types)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void lds_and(uint32_t byte_addr, uint32_t v) {
     __hip_atomic_fetch_and((__attribute__((address_space(3))) uint32_t *)(size_t)byte_addr, v, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -51,7 +57,7 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
 
 template <int TPB, int VR, bool PRIOR, bool TRACE>
 __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
-    static_assert(VR <= 32 && TPB % 256 == 0, "shape");
+    static_assert(VR <= 32 && VR % kLargeBatch == 0 && TPB % 256 == 0, "shape");
     const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
     const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 bytes (block OR), 16-byte aligned
     const uint32_t shot_sh = flags + 4u * (TPB / 64);     // claimed shot index
@@ -65,18 +71,20 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     uint32_t tl = (uint32_t)t;
 
     // this thread's checks and their CSR ranges
-    int ci[kLargeRounds], cb[kLargeRounds], ce[kLargeRounds];
+    int ci[kLargeRounds], cb[kLargeRounds], ce[kLargeRounds], crb[kLargeRounds];
 #pragma unroll
     for (int c = 0; c < kLargeRounds; ++c) {
         const int i = c < a.rounds ? a.chk_of[c * TPB + t] : -1;
         ci[c] = i;
         cb[c] = i >= 0 ? a.rowptr[i] : 0;
         ce[c] = i >= 0 ? a.rowptr[i + 1] : 0;
+        crb[c] = i >= 0 ? a.rbase[i] : 0;
     }
     if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
 
     // xl = (1 - gamma) * lambda(0) is constant within a leg and kept as such
-    float xl[VR], gm[VR];
+    float xl[VR];
+    const float *gcur = a.gamma;  // memory strengths of the current leg (per fault, read each iteration)
     uint32_t sig = 0;  // bit c: syndrome bit of check ci[c]
     uint32_t best_mask = 0;
     double best_w = 0.0;
@@ -126,8 +134,8 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * N + j] = wj;
             }
             xl[v] = (1.0f - gj) * wj;
-            gm[v] = gj;
         }
+        gcur = TRACE ? a.trace_gamma : a.gamma;
         zero_messages();
         return true;
     };
@@ -145,45 +153,71 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             const int i = ci[c];
             if (i < 0) continue;
             const uint32_t sa = chk + 16u * (uint32_t)i;
-            const float m1o = lds_b<float>(sa);
-            const float m2o = lds_b<float>(sa + 4u);
-            const int amo = lds_b<int>(sa + 8u);
-            const uint32_t flipo = lds_b<uint32_t>(sa + 12u) ? 0xffffffffu : 0u;
+            const u32x4 sto = lds_b<u32x4>(sa);
+            const float m1o = __uint_as_float(sto.x);
+            const float m2o = __uint_as_float(sto.y);
+            const int amo = (int)sto.z;
+            const uint32_t flipo = sto.w ? 0xffffffffu : 0u;
             const bool sc = (sig >> c) & 1u;
             bool fpar = sc, neg = sc;
             float m1 = L, m2 = L;
             int amin = cb[c];
-            int e = cb[c];
-            const int e1 = ce[c];
-            while (e < e1) {
-                const int wi = e >> 5;
-                const int we = min(e1, (wi + 1) << 5);  // end of the row's part of word wi
-                const uint32_t wa = sgn + 4u * (uint32_t)wi;
-                const uint32_t osg = lds_b<uint32_t>(wa) ^ flipo;  // old message signs
-                uint32_t nb = 0u, mask = 0u;
-                for (; e < we; ++e) {
-                    const float lv = lds_b<float>(4u * (uint32_t)a.colidx[e]);
-                    const uint32_t bit = 1u << (e & 31);
-                    const float mag = e == amo ? m2o : m1o;
+            const int e0 = cb[c], deg = ce[c] - cb[c];
+            // sign bits of the word being filled: old message signs, new nu
+            // signs and the row's bits in it; a word shared with another
+            // check is written with two atomics
+            int cw = e0 >> 5;
+            uint32_t osg = lds_b<uint32_t>(sgn + 4u * (uint32_t)cw) ^ flipo, nb = 0u, mask = 0u;
+            auto flush = [&]() {
+                const uint32_t wa = sgn + 4u * (uint32_t)cw;
+                if (mask == 0xffffffffu) {
+                    lds_b<uint32_t>(wa) = nb;
+                } else if (mask != 0u) {
+                    lds_and(wa, ~mask);
+                    lds_or(wa, nb);
+                }
+            };
+            // eight edges per step from one aligned 16-byte load of the row's
+            // padded fault indices; the Lambda gathers are issued together
+            // the next chunk is loaded one step ahead (the table ends with a
+            // zero chunk, so the load past a row's last chunk stays inside it)
+            const uint4 *rt = reinterpret_cast<const uint4 *>(a.ctab) + crb[c];
+            uint4 cur = rt[0];
+            for (int k = 0; k < deg; k += kLargeGather) {
+                const uint4 pk = cur;
+                cur = rt[k / kLargeGather + 1];
+                const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
+                float lv[kLargeGather];
+#pragma unroll
+                for (int q = 0; q < kLargeGather; ++q)
+                    lv[q] = lds_b<float>(4u * ((q & 1) ? (pw[q >> 1] >> 16) : (pw[q >> 1] & 0xffffu)));
+#pragma unroll
+                for (int q = 0; q < kLargeGather; ++q) {
+                    if (k + q >= deg) break;
+                    const int eq = e0 + k + q;
+                    if ((eq >> 5) != cw) {  // the row enters the next word of sign bits
+                        flush();
+                        cw = eq >> 5;
+                        osg = lds_b<uint32_t>(sgn + 4u * (uint32_t)cw) ^ flipo;
+                        nb = 0u;
+                        mask = 0u;
+                    }
+                    const uint32_t bit = 1u << (eq & 31);
+                    const float mag = eq == amo ? m2o : m1o;
                     const float mo = __uint_as_float((osg & bit ? 0x80000000u : 0u) | __float_as_uint(mag));
-                    fpar ^= lv < 0.0f;
-                    const float nu = clipl(lv - mo, L);
+                    fpar ^= lv[q] < 0.0f;
+                    const float nu = clipl(lv[q] - mo, L);
                     const bool sn = nu < 0.0f;
                     neg ^= sn;
                     nb |= sn ? bit : 0u;
                     mask |= bit;
                     const float av = fabsf(nu);
-                    amin = av < m1 ? e : amin;
+                    amin = av < m1 ? eq : amin;
                     m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
                     m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
                 }
-                if (mask == 0xffffffffu) {
-                    lds_b<uint32_t>(wa) = nb;
-                } else {
-                    lds_and(wa, ~mask);
-                    lds_or(wa, nb);
-                }
             }
+            flush();
             lds_b<float>(sa) = m1;
             lds_b<float>(sa + 4u) = m2;
             lds_b<int>(sa + 8u) = amin;
@@ -244,13 +278,13 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 ++r;
                 tt = 0;
                 const float *gr = a.gamma + (size_t)(r - 1) * N;
+                gcur = gr;
 #pragma unroll
                 for (int v = 0; v < VR; ++v) {
                     const int j = (int)tl + TPB * v;
                     if (j < N) {
                         const float gv = gr[j];
                         const float l0 = PRIOR ? a.scale * a.w[j] : clipl(lds_b<float>(4u * (uint32_t)j), L);
-                        gm[v] = gv;
                         xl[v] = (1.0f - gv) * l0;
                     }
                 }
@@ -264,29 +298,63 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
 
         // ---------------- fault pass: memory term, then the messages of the
         // fault's checks in ascending check order, each rebuilt from its
-        // check's state and its edge's sign bit
+        // check's state and its edge's sign bit.  Faults go in batches of
+        // kLargeBatch whose loads (column range, the 32-byte record of its
+        // first kLargeGather entries, gamma, Lambda) are all issued first;
+        // indices are clamped so every load is in bounds.
+        // message of one (check, edge) entry, from the check's 16-byte state
+        // (one LDS load) and the edge's sign word
+        auto msg_of = [&](uint32_t pk) -> float {
+            const uint32_t e = pk & ((1u << kLargeEdgeBits) - 1u);
+            const u32x4 st = lds_b<u32x4>(chk + 16u * (pk >> kLargeEdgeBits));
+            const uint32_t sw = lds_b<uint32_t>(sgn + 4u * (e >> 5));
+            const uint32_t mag = e == st.z ? st.y : st.x;
+            const uint32_t sb = ((sw >> (e & 31u)) ^ st.w) & 1u;
+            return __uint_as_float((sb << 31) | mag);
+        };
 #pragma unroll
-        for (int v = 0; v < VR; ++v) {
-            const int j = (int)tl + TPB * v;
-            if (j >= N) continue;
-            const float y = gm[v] * clipl(lds_b<float>(4u * (uint32_t)j), L);
-            float acc = clipl(xl[v] + y, L);
-            const int q1 = a.colptr[j + 1];
-            for (int q = a.colptr[j]; q < q1; ++q) {
-                const uint32_t pk = a.fedge[q];
-                const uint32_t e = pk & ((1u << kLargeEdgeBits) - 1u);
-                const uint32_t sa = chk + 16u * (pk >> kLargeEdgeBits);
-                const float m1 = lds_b<float>(sa);
-                const float m2 = lds_b<float>(sa + 4u);
-                const uint32_t am = lds_b<uint32_t>(sa + 8u);
-                const uint32_t ng = lds_b<uint32_t>(sa + 12u);
-                const uint32_t sw = lds_b<uint32_t>(sgn + 4u * (e >> 5));
-                const float mag = e == am ? m2 : m1;
-                const uint32_t s = ((sw >> (e & 31u)) ^ ng) & 1u;
-                acc += __uint_as_float((s << 31) | __float_as_uint(mag));
+        for (int vb = 0; vb < VR; vb += kLargeBatch) {
+            int qa[kLargeBatch], qb[kLargeBatch];
+            uint4 ra[kLargeBatch], rc[kLargeBatch];
+            float gv[kLargeBatch], lam[kLargeBatch];
+#pragma unroll
+            for (int f = 0; f < kLargeBatch; ++f) {
+                const int j = min((int)tl + TPB * (vb + f), N - 1);
+                qa[f] = a.colptr[j];
+                qb[f] = a.colptr[j + 1];
+                const uint4 *fr = reinterpret_cast<const uint4 *>(a.frec) + 2 * (size_t)j;
+                ra[f] = fr[0];
+                rc[f] = fr[1];
+                gv[f] = gcur[j];
+                lam[f] = lds_b<float>(4u * (uint32_t)j);
             }
-            lds_b<float>(4u * (uint32_t)j) = acc;
-            if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + j] = acc;
+#pragma unroll
+            for (int f = 0; f < kLargeBatch; ++f) {
+                const int j = (int)tl + TPB * (vb + f);
+                if (j >= N) continue;
+                const float y = gv[f] * clipl(lam[f], L);
+                float acc = clipl(xl[vb + f] + y, L);
+                const uint32_t pk[kLargeGather] = {ra[f].x, ra[f].y, ra[f].z, ra[f].w,
+                                                   rc[f].x, rc[f].y, rc[f].z, rc[f].w};
+                // the first kLargeSure entries are read whatever the degree
+                // (padding entries address check 0 and sign word 0), so their
+                // loads issue together; the sum skips the padding (a select,
+                // not an added 0, which would turn -0 into +0)
+                const int deg = qb[f] - qa[f];
+                float mv[kLargeSure];
+#pragma unroll
+                for (int k = 0; k < kLargeSure; ++k) mv[k] = msg_of(pk[k]);
+#pragma unroll
+                for (int k = 0; k < kLargeSure; ++k) acc = k < deg ? acc + mv[k] : acc;
+#pragma unroll
+                for (int k = kLargeSure; k < kLargeGather; ++k) {
+                    if (k >= deg) break;
+                    acc += msg_of(pk[k]);
+                }
+                for (int q = qa[f] + kLargeGather; q < qb[f]; ++q) acc += msg_of(a.fedge[q]);
+                lds_b<float>(4u * (uint32_t)j) = acc;
+                if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + j] = acc;
+            }
         }
         ++tt;
         ++total;
