@@ -92,6 +92,7 @@ struct rb_ctx {
     int32_t lrounds = 0, nsw = 0;
     uint32_t chk_off = 0, sgn_off = 0;
     int32_t *d_lrowptr = nullptr, *d_lcolptr = nullptr, *d_chk_of = nullptr;
+    float *d_lambda0 = nullptr;  // [blocks_per_cu * num_cu][N] large-graph kernel workspace
     uint16_t *d_col16 = nullptr;            // row chunks of fault indices
     int32_t *d_rbase = nullptr;
     uint32_t *d_fedge = nullptr, *d_frec = nullptr;
@@ -1449,6 +1450,11 @@ rb_status build_large_plan(rb_ctx *c, int lv) {
         if (blocks < 1) return fail(RB_E_UNSUPPORTED, "large-graph configuration does not fit on a CU");
         c->blocks_per_cu[tr] = blocks;
     }
+    // lambda(0) slices for the largest grid a launch uses
+    (void)hipFree(c->d_lambda0);
+    c->d_lambda0 = nullptr;
+    const size_t grid_max = (size_t)std::max(c->blocks_per_cu[0], c->blocks_per_cu[1]) * (size_t)c->num_cu;
+    RB_HIP(hipMalloc(&c->d_lambda0, sizeof(float) * grid_max * (size_t)c->N), "hipMalloc(lambda0 workspace)");
     return RB_OK;
 }
 
@@ -1689,6 +1695,7 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_rbase);
         (void)hipFree(c->d_fedge);
         (void)hipFree(c->d_frec);
+        (void)hipFree(c->d_lambda0);
     }
     if (c->d_rowptr || c->d_colidx || c->d_colptr || c->d_cedge) {
         (void)hipSetDevice(c->device);
@@ -1798,6 +1805,7 @@ static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.final_llr = g.final_llr;
     b.w = g.w;
     b.gamma = g.gamma;
+    b.lambda0 = c->d_lambda0;
     b.rowptr = c->d_lrowptr;
     b.ctab = c->d_col16;
     b.rbase = c->d_rbase;

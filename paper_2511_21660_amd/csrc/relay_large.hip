@@ -83,8 +83,12 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
 
     // xl = (1 - gamma) * lambda(0) is constant within a leg and kept as such
-    float xl[VR];
-    const float *gcur = a.gamma;  // memory strengths of the current leg (per fault, read each iteration)
+    // per fault: lambda(0) of the current leg in this workgroup's slice of
+    // global memory and gamma of the current leg in the table, both read each
+    // iteration (coalesced: a wave's lanes own consecutive faults), which
+    // keeps the registers for the loads in flight
+    float *l0w = a.lambda0 + (size_t)blockIdx.x * N;
+    const float *gcur = a.gamma;
     uint32_t sig = 0;  // bit c: syndrome bit of check ci[c]
     uint32_t best_mask = 0;
     double best_w = 0.0;
@@ -126,14 +130,12 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
 #pragma unroll
         for (int v = 0; v < VR; ++v) {
             const int j = (int)tl + TPB * v;
-            float wj = 0.0f, gj = 0.0f;
             if (j < N) {
-                wj = a.scale * a.w[j];
-                gj = TRACE ? a.trace_gamma[j] : a.gamma[j];
+                const float wj = a.scale * a.w[j];
                 lds_b<float>(4u * (uint32_t)j) = wj;
+                l0w[j] = wj;
                 if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * N + j] = wj;
             }
-            xl[v] = (1.0f - gj) * wj;
         }
         gcur = TRACE ? a.trace_gamma : a.gamma;
         zero_messages();
@@ -282,11 +284,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
 #pragma unroll
                 for (int v = 0; v < VR; ++v) {
                     const int j = (int)tl + TPB * v;
-                    if (j < N) {
-                        const float gv = gr[j];
-                        const float l0 = PRIOR ? a.scale * a.w[j] : clipl(lds_b<float>(4u * (uint32_t)j), L);
-                        xl[v] = (1.0f - gv) * l0;
-                    }
+                    if (j < N) l0w[j] = PRIOR ? a.scale * a.w[j] : clipl(lds_b<float>(4u * (uint32_t)j), L);
                 }
                 zero_messages();
             } else {
@@ -316,7 +314,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         for (int vb = 0; vb < VR; vb += kLargeBatch) {
             int qa[kLargeBatch], qb[kLargeBatch];
             uint4 ra[kLargeBatch], rc[kLargeBatch];
-            float gv[kLargeBatch], lam[kLargeBatch];
+            float gv[kLargeBatch], l0[kLargeBatch], lam[kLargeBatch];
 #pragma unroll
             for (int f = 0; f < kLargeBatch; ++f) {
                 const int j = min((int)tl + TPB * (vb + f), N - 1);
@@ -326,6 +324,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 ra[f] = fr[0];
                 rc[f] = fr[1];
                 gv[f] = gcur[j];
+                l0[f] = l0w[j];
                 lam[f] = lds_b<float>(4u * (uint32_t)j);
             }
 #pragma unroll
@@ -333,7 +332,8 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 const int j = (int)tl + TPB * (vb + f);
                 if (j >= N) continue;
                 const float y = gv[f] * clipl(lam[f], L);
-                float acc = clipl(xl[vb + f] + y, L);
+                const float x = (1.0f - gv[f]) * l0[f];  // (1 - gamma) lambda(0)
+                float acc = clipl(x + y, L);
                 const uint32_t pk[kLargeGather] = {ra[f].x, ra[f].y, ra[f].z, ra[f].w,
                                                    rc[f].x, rc[f].y, rc[f].z, rc[f].w};
                 // the first kLargeSure entries are read whatever the degree
