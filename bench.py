@@ -13,6 +13,9 @@ Other workloads:
                           budgets, epsilon(T_ref) and the latency-tail condition
   --workload dem-2gross   two-gross-scale DEM-shaped 2736 x 26208 matrix (82.6K edges)
                           on the large-graph kernel, 2 x 10^5 shots, R = 20, S = 1
+  --workload dem-window   the DEM-shaped matrix decoded in overlapping windows of
+                          T_commit = T_overlap = 3 detector rounds (4 windows), 2 x 10^5
+                          shots, R = 20, S = 1; LER against the full-matrix decode
   --workload bp-llr       plain min-sum BP (one leg, gamma = 0, 25 rounds) on the
                           DEM-shaped matrix, 10^5 shots, returning the marginals
   --workload mixed-codes  [[72,12,6]], [[90,8,10]], [[144,12,12]], [[288,12,18]]
@@ -66,7 +69,8 @@ OPS_PER_EDGE = 12.0
 OPS_PER_FAULT = 7.0
 OPS_PER_CHECK = 3.0
 
-DEFAULT_STEPS = {"bb144": 20, "dem": 5, "dem-2gross": 3, "mixed-codes": 10, "learned": 3, "bp-llr": 10}
+DEFAULT_STEPS = {"bb144": 20, "dem": 5, "dem-2gross": 3, "dem-window": 3, "mixed-codes": 10, "learned": 3,
+                 "bp-llr": 10}
 
 
 def ops_per_iteration(m, n, e):
@@ -378,6 +382,93 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
 
 
 # --------------------------------------------------------------------------
+# windowed decoding of the DEM-shaped matrix (T_commit + T_overlap rounds)
+# --------------------------------------------------------------------------
+
+
+def run_dem_window(args, torch, rb, codes, sampling):
+    """Windows of Tc = To = 3 detector rounds (72 detectors per round, 13
+    rounds) over the DEM-shaped 936 x 8785 matrix: 4 window decodes per batch
+    (block kernel) plus the residual-syndrome kernel between them."""
+    from paper_2511_21660_amd import window
+
+    dev = torch.device("cuda", 0)
+    prob, first = codes.dem_rounds_problem()
+    band, tc, to = 72, 3, 3
+    shots = args.shots or 200000
+    f_np, syn_np = sampling.sample_batch(prob, 0xDE4 << 32, 0, shots)
+    wd = window.WindowedDecoder(prob, first, band, tc, to, device=0, **RELAY_R20)
+    d_syn = torch.from_numpy(syn_np).to(dev)
+    nw = len(wd.plan)
+    holder = {}
+
+    def step(ev):
+        # HIP events on the launch stream around each window's decode
+        holder["out"] = wd.decode(d_syn, events=ev)
+
+    elapsed, per_launch = timed(torch, step, nw, args.steps, args.warmup)
+    win_ms = launch_means(per_launch)
+    out = holder["out"]
+    iters = out["iters"].cpu().numpy().astype(np.int64)  # [W, B]
+    conv = out["conv"].cpu().numpy()
+    ops = 0.0
+    eu = 0.0
+    for k, (r0, r1, c0, c1, _) in enumerate(wd.plan):
+        keep = (prob.rows >= r0) & (prob.rows < r1) & (prob.cols >= c0) & (prob.cols < c1)
+        ew = int(keep.sum())
+        ops += float(iters[k].sum()) * ops_per_iteration(r1 - r0, c1 - c0, ew)
+        eu += float(iters[k].sum()) * ew
+    kernel_ms = float(sum(win_ms))
+    roof, lds = roofline("relay_block_kernel", kernel_ms, ops, eu, lds_bytes_per_edge_update(prob.m, prob.n, prob.nnz),
+                         None)
+    # logical failures on the GPU in chunks: A (F xor F_hat) over GF(2)
+    a_t = torch.from_numpy(prob.logical.astype(np.float32)).to(dev)
+    d_f = torch.from_numpy(f_np).to(dev)
+
+    def failures(d_corr, d_ok):
+        bad = torch.zeros(shots, dtype=torch.bool, device=dev)
+        for s0 in range(0, shots, 50000):
+            r = (d_f[s0:s0 + 50000] ^ d_corr[s0:s0 + 50000]).float()
+            bad[s0:s0 + 50000] = (torch.round(r @ a_t.T).to(torch.int32) % 2).any(1)
+        return (bad | ~d_ok.bool()).cpu().numpy()
+
+    fail = failures(out["corr"], out["conv"].bool().all(0))
+    k_fail = int(fail.sum())
+    full = rb.Decoder.from_problem(prob, device=0, **RELAY_R20)
+    fo = full.decode(d_syn)
+    fail_full = failures(fo["corr"], fo["conv"].bool())
+    full.close()
+    corr = out["corr"][: min(shots, args.cpu_sample or 300)].cpu().numpy()
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = oracle_threads()
+        n_cpu = min(args.cpu_sample or 300, shots)
+        t1 = time.perf_counter()
+        ref = oracle.decode_windowed(prob.m, prob.n, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n_cpu],
+                                     band, first, tc, to, threads=threads)
+        tcpu = time.perf_counter() - t1
+        agree = bool(np.array_equal(ref["corr"], corr[:n_cpu]) and np.array_equal(ref["iters"], iters[:, :n_cpu]))
+        cpu = {"value": n_cpu / tcpu, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n_cpu} of {shots} syndromes, same inputs and windows, {tcpu:.1f} s",
+               "paired_with_gpu_bit_exact": agree}
+    wd.close()
+    line = head(args, shots * args.steps / elapsed, elapsed, {
+        "workload": "relay_bp_dem_936x8785_windowed", "matrix": "DEM-shaped synthetic 936x8785, 13 rounds of 72",
+        "t_commit_rounds": tc, "t_overlap_rounds": to, "windows": nw, "shots": shots, "T_first": 80, "T_leg": 60,
+        "legs": 20, "solutions": 1, "parallelism": "single_gpu"})
+    line.update({"edge_updates_per_s": eu * args.steps / elapsed, "launch_ms": win_ms, "roofline": roof,
+                 "lds_roofline": lds,
+                 "ler": {"windowed": k_fail / shots, "wilson95": wilson(k_fail, shots),
+                         "full_matrix": float(fail_full.mean()),
+                         "all_windows_converged": float(conv.all(0).mean()),
+                         "mean_iters_per_window": [float(x) for x in iters.mean(1)]},
+                 "cpu_baseline": cpu})
+    return line
+
+
+# --------------------------------------------------------------------------
 # plain-BP LLR export on the DEM-shaped matrix (25 rounds, gamma = 0)
 # --------------------------------------------------------------------------
 
@@ -643,7 +734,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["bb144", "dem", "dem-2gross", "mixed-codes", "learned", "bp-llr"],
+    ap.add_argument("--workload", choices=["bb144", "dem", "dem-2gross", "dem-window", "mixed-codes", "learned",
+                                           "bp-llr"],
                     default="bb144")
     ap.add_argument("--train-steps", type=int, default=0, help="learned: Adam steps (default 2000)")
     ap.add_argument("--shots", type=int, default=0,
@@ -677,6 +769,7 @@ def main():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
     run = {"bb144": run_bb144, "dem": run_dem, "dem-2gross": lambda *x: run_dem(*x, two_gross=True),
+           "dem-window": run_dem_window,
            "mixed-codes": run_mixed_codes,
            "learned": run_learned, "bp-llr": run_bp_llr}[args.workload]
     line = run(args, torch, rb, codes, sampling)

@@ -171,6 +171,21 @@ rb_status rb_decode(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, uint8_t 
 rb_status rb_trace(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, const float *d_gamma,
                    float scale, int32_t T, float *d_trace, void *stream);
 
+/*
+ * Syndrome of a batch of corrections over F_2 (the decoding problem of paper
+ * Sec. 2.1: sigma = H F), optionally added to a given syndrome:
+ *   d_corr      uint8 [B][N], nonzero = 1 (device)
+ *   d_syn_in    uint8 [B][M] or NULL (device); NULL reads as all zero
+ *   d_syn_out   uint8 [B][M] out (device): d_syn_in XOR (H d_corr mod 2); may
+ *               alias d_syn_in
+ * Windowed decoding uses it to pass the residual syndrome of committed faults
+ * to the next window; it also checks corrections.  Enqueues on `stream`; no
+ * allocation.  RB_E_INVALID_ARG for null required pointers, B < 0 or a
+ * mixed-code context.
+ */
+rb_status rb_syndrome(const rb_ctx *ctx, int64_t B, const uint8_t *d_corr, const uint8_t *d_syn_in,
+                      uint8_t *d_syn_out, void *stream);
+
 /* Copies the FP32 channel LLRs w_j (host float[N]) -- test hook. */
 rb_status rb_get_llr(const rb_ctx *ctx, float *host_w);
 

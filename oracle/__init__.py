@@ -8,6 +8,7 @@ from .oracle import (  # noqa: F401
     OracleParams,
     build,
     decode,
+    decode_windowed,
     gamma_f32,
     lib,
     minsum_trace,

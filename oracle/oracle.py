@@ -192,3 +192,50 @@ def sumproduct_trace(m, n, rows, cols, llr, t_iters, syn):
     if rc != 0:
         raise ValueError(f"oracle sum-product failed with code {rc}")
     return out
+
+
+def decode_windowed(m, n, rows, cols, prior, params: dict, syn, band, first_round, t_commit, t_overlap,
+                    threads=None):
+    """Windowed Relay decoding over detector rounds (the overlapping windows of
+    T_commit + T_overlap rounds of the paper's closing caveat), written from
+    the definition with boolean masks:
+
+      rounds R = ceil(m / band); window k covers detector rounds
+      [s, e) = [k*Tc, min(k*Tc + Tc + To, R)) and decodes the faults whose
+      first detector round lies in [s, e), on the rows of those rounds, with
+      the residual syndrome sigma + H F (F = the faults committed so far);
+      it commits the faults whose first round lies in [s, s + Tc), or every
+      fault of the window if e = R (the last window).
+
+    Columns may be in any order.  Returns corr [B, N] and per-window conv and
+    iters [W, B]."""
+    rows = np.asarray(rows, np.int64)
+    cols = np.asarray(cols, np.int64)
+    first_round = np.asarray(first_round, np.int64)
+    syn = np.ascontiguousarray(syn, dtype=np.uint8)
+    h = np.zeros((m, n), dtype=np.uint8)
+    h[rows, cols] = 1
+    n_rounds = -(-m // band)
+    b = syn.shape[0]
+    corr = np.zeros((b, n), np.uint8)
+    convs, iters = [], []
+    s = 0
+    while True:
+        e = min(s + t_commit + t_overlap, n_rounds)
+        row_in = (np.arange(m) // band >= s) & (np.arange(m) // band < e)
+        col_in = (first_round >= s) & (first_round < e)
+        commit = col_in if e == n_rounds else (first_round >= s) & (first_round < s + t_commit)
+        residual = (syn.astype(np.int64) + corr.astype(np.int64) @ h.T.astype(np.int64)) % 2
+        ri, ci = np.nonzero(row_in)[0], np.nonzero(col_in)[0]
+        sub = h[np.ix_(ri, ci)]
+        sr, sc = np.nonzero(sub)
+        out = decode(ri.size, ci.size, sr, sc, np.asarray(prior)[ci], params,
+                     residual[:, ri].astype(np.uint8), threads=threads)
+        keep = commit[ci]
+        corr[:, ci[keep]] = out["corr"][:, keep]
+        convs.append(out["conv"])
+        iters.append(out["iters"])
+        if e == n_rounds:
+            break
+        s += t_commit
+    return {"corr": corr, "conv": np.stack(convs), "iters": np.stack(iters)}

@@ -1893,6 +1893,22 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
     return launch(c, a, false, (hipStream_t)stream);
 }
 
+rb_status rb_syndrome(const rb_ctx *c, int64_t B, const uint8_t *d_corr, const uint8_t *d_syn_in,
+                      uint8_t *d_syn_out, void *stream) {
+    g_last_error.clear();
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use a single code's context");
+    if (B < 0) return fail(RB_E_INVALID_ARG, "B must be >= 0");
+    if (B == 0) return RB_OK;
+    if (!d_corr || !d_syn_out) return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
+    if (B > INT64_MAX / ((int64_t)c->M + 1)) return fail(RB_E_SHAPE, "B * M overflows");
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    RB_HIP(rb::launch_syndrome(B, c->M, c->N, c->d_rowptr, c->d_colidx, d_corr, d_syn_in, d_syn_out,
+                               (hipStream_t)stream),
+           "syndrome kernel launch");
+    return RB_OK;
+}
+
 rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma, float scale,
                    int32_t T, float *d_trace, void *stream) {
     g_last_error.clear();

@@ -246,6 +246,9 @@ hipError_t launch_group(int v, bool prior_anchor, bool trace, const GroupArgs &a
 hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_first, float lo,
                               float hi, hipStream_t s);
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s);
+// syn_out[b][i] = (syn_in ? syn_in[b][i] : 0) XOR parity of corr[b][j] over row i (CSR rowptr / colidx)
+hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowptr, const int32_t *colidx,
+                           const uint8_t *corr, const uint8_t *syn_in, uint8_t *syn_out, hipStream_t s);
 // Builds per-code shot lists in `workspace` (shot_list_bytes(B, ncodes) bytes):
 // positions sorted by (family, decreasing syndrome weight), the family of
 // code c being code_fam[c] (identity when code_fam is null); the list of

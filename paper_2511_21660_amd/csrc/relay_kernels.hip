@@ -657,6 +657,25 @@ const Variant kVariants[] = {
     RB_VARIANT(64, 4, 16, 8, 8, 2),   // M <= 256, N <= 512
 };
 
+// ------------------------------------------------------------------------
+// Syndrome of a batch of corrections (decoding problem of Sec. 2.1: sigma =
+// H F over F_2), optionally XORed into a given syndrome: out[b][i] = in[b][i]
+// XOR parity of corr[b][j] over the row of check i.  One thread per (shot,
+// check); a wave's lanes take consecutive checks of one shot.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void syndrome_kernel(int64_t B, int32_t M, int32_t N, const int32_t *rowptr,
+                                                       const int32_t *colidx, const uint8_t *corr,
+                                                       const uint8_t *syn_in, uint8_t *syn_out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * (int64_t)M) return;
+    const int64_t b = idx / M;
+    const int i = (int)(idx % M);
+    const uint8_t *f = corr + (size_t)b * N;
+    uint32_t par = syn_in ? (syn_in[idx] != 0 ? 1u : 0u) : 0u;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) par ^= f[colidx[e]] != 0 ? 1u : 0u;
+    syn_out[idx] = (uint8_t)par;
+}
+
 }  // namespace
 
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
@@ -750,6 +769,15 @@ hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, 
 
 size_t shot_list_bytes(int64_t B, int ncodes) {
     return sizeof(int32_t) * ((size_t)ncodes * (kWeightBins + 3) + 2 * (size_t)B);
+}
+
+hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowptr, const int32_t *colidx,
+                           const uint8_t *corr, const uint8_t *syn_in, uint8_t *syn_out, hipStream_t s) {
+    const int64_t n = B * (int64_t)M;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(syndrome_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B, M, N, rowptr, colidx,
+                       corr, syn_in, syn_out);
+    return hipGetLastError();
 }
 
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s) {

@@ -106,6 +106,7 @@ def load_library():
     L.rb_forward_train.argtypes = [P, i64, P, P, P, i32, i32, P, P, ctypes.c_size_t, P]
     L.rb_backward.argtypes = [P, i64, P, P, P, i32, i32, P, ctypes.c_size_t, P, P, P, P]
     L.rb_plan_check.argtypes = [i32, i32, i64, P, P, i32, ctypes.POINTER(RBPlanReport)]
+    L.rb_syndrome.argtypes = [P, i64, P, P, P, P]
     L.rb_status_string.argtypes = [ctypes.c_int]
     L.rb_status_string.restype = ctypes.c_char_p
     L.rb_last_error_message.argtypes = []
@@ -114,7 +115,7 @@ def load_library():
                  "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status",
                  "rb_autotune", "rb_reserve", "rb_create_multi", "rb_decode_multi",
                  "rb_autotune_multi", "rb_forward_train", "rb_backward", "rb_set_leg_gamma",
-                 "rb_set_prior_scale", "rb_plan_check"):
+                 "rb_set_prior_scale", "rb_plan_check", "rb_syndrome"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -250,6 +251,23 @@ class Decoder:
                                         _ptr(out["conv"]), _ptr(out["legs"]), _ptr(out["iters"]),
                                         _ptr(out.get("weight")), _ptr(out.get("llr")),
                                         _stream(dev)))
+        return out
+
+    def syndrome(self, corr, syn_in=None, out=None):
+        """(syn_in XOR H corr) mod 2 for corr uint8 [B, N] on the device: uint8 [B, M]
+        (syn_in None reads as zero; out may be syn_in).  Enqueued on the current stream."""
+        import torch
+
+        if corr.dtype != torch.uint8 or corr.dim() != 2 or corr.shape[1] != self.n or not corr.is_cuda:
+            raise ValueError(f"corr must be a uint8 CUDA tensor [B, {self.n}]")
+        corr = corr.contiguous()
+        b = corr.shape[0]
+        if syn_in is not None and (syn_in.dtype != torch.uint8 or tuple(syn_in.shape) != (b, self.m)
+                                   or not syn_in.is_contiguous()):
+            raise ValueError(f"syn_in must be a contiguous uint8 CUDA tensor [{b}, {self.m}]")
+        if out is None:
+            out = torch.empty((b, self.m), dtype=torch.uint8, device=corr.device)
+        _check(load_library().rb_syndrome(self._h, b, _ptr(corr), _ptr(syn_in), _ptr(out), _stream(corr.device)))
         return out
 
     def trace(self, syndromes, gamma, t_iters, scale=1.0):

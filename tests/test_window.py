@@ -1,0 +1,135 @@
+"""Windowed decoding over detector rounds (the overlapping windows of
+T_commit + T_overlap rounds of the paper's closing caveat, Sec. 8).
+
+CPU: the oracle's windowed decoder against properties its definition fixes,
+and the GPU driver's window plan (host logic).  GPU: the driver against the
+oracle, bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import RELAY_DEFAULT
+from workloads import codes, sampling
+
+
+@pytest.fixture(scope="module")
+def rounds_dem():
+    return codes.dem_rounds_problem()
+
+
+def test_rounds_problem_sorted_and_equivalent(rounds_dem):
+    p, first = rounds_dem
+    assert np.all(np.diff(first) >= 0)
+    lo = np.full(p.n, p.m)
+    np.minimum.at(lo, p.cols, p.rows)
+    assert np.array_equal(lo // 72, first)
+    q = codes.dem_problem()
+    assert (p.m, p.n, p.nnz) == (q.m, q.n, q.nnz)
+    # the same columns, reordered: equal multisets of column supports
+    sup = lambda pr: sorted(tuple(np.sort(pr.rows[pr.cols == j])) for j in range(pr.n))
+    assert sup(p) == sup(q)
+
+
+def test_single_window_is_the_plain_decode(rounds_dem):
+    p, first = rounds_dem
+    _, syn = sampling.sample_batch(p, 21, 0, 24)
+    w = oracle.decode_windowed(p.m, p.n, p.rows, p.cols, p.prior, RELAY_DEFAULT, syn, 72, first, 13, 0)
+    f = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, RELAY_DEFAULT, syn)
+    assert w["conv"].shape == (1, 24)
+    assert np.array_equal(w["corr"], f["corr"])
+    assert np.array_equal(w["conv"][0], f["conv"]) and np.array_equal(w["iters"][0], f["iters"])
+
+
+def test_converged_windows_give_a_valid_correction(rounds_dem):
+    """If every window converges, the committed faults reproduce the syndrome:
+    a window's commit rounds are touched only by faults beginning no later,
+    all of which it commits, and later commits begin after them."""
+    p, first = rounds_dem
+    _, syn = sampling.sample_batch(p, 7 << 32, 0, 48)
+    for tc, to in ((3, 3), (2, 4), (4, 1)):
+        w = oracle.decode_windowed(p.m, p.n, p.rows, p.cols, p.prior, RELAY_DEFAULT, syn, 72, first, tc, to)
+        ok = ((w["corr"].astype(np.int64) @ p.dense().T.astype(np.int64)) % 2 == syn).all(1)
+        allc = w["conv"].all(0).astype(bool)
+        assert allc.mean() > 0.8 and ok[allc].all(), (tc, to)
+
+
+def test_block_diagonal_windows_decode_blocks_independently():
+    """Two copies of a matrix stacked in separate rounds, with no fault
+    across them: windows of one round each decode the copies separately."""
+    base = codes.bb_problem("bb72", 0.04)
+    m, n = base.m, base.n
+    rows = np.concatenate([base.rows, base.rows + m])
+    cols = np.concatenate([base.cols, base.cols + n])
+    prior = np.concatenate([base.prior, base.prior])
+    first = np.repeat([0, 1], n)
+    _, s1 = sampling.sample_batch(base, 3, 0, 40)
+    _, s2 = sampling.sample_batch(base, 4, 0, 40)
+    syn = np.concatenate([s1, s2], axis=1)
+    prm = dict(RELAY_DEFAULT, num_legs=8)
+    w = oracle.decode_windowed(2 * m, 2 * n, rows, cols, prior, prm, syn, m, first, 1, 0)
+    d1 = oracle.decode(m, n, base.rows, base.cols, base.prior, prm, s1)
+    d2 = oracle.decode(m, n, base.rows, base.cols, base.prior, prm, s2)
+    assert np.array_equal(w["corr"], np.concatenate([d1["corr"], d2["corr"]], axis=1))
+    assert np.array_equal(w["iters"], np.stack([d1["iters"], d2["iters"]]))
+
+
+def test_window_plan_commits_every_fault_once(rounds_dem):
+    from paper_2511_21660_amd import window
+
+    p, first = rounds_dem
+    for tc, to in ((3, 3), (1, 0), (5, 2), (13, 0), (20, 3)):
+        plan = window.window_plan(p.m, 72, first, tc, to)
+        committed = np.zeros(p.n, np.int64)
+        for r0, r1, c0, c1, cc in plan:
+            assert 0 <= r0 < r1 <= p.m and c0 <= cc <= c1
+            assert np.all(first[c0:c1] >= r0 // 72) and np.all(first[c0:c1] * 72 < r1)
+            committed[c0:cc] += 1
+        assert (committed == 1).all(), (tc, to)
+        assert plan[-1][1] == p.m
+    with pytest.raises(ValueError):
+        window.window_plan(p.m, 72, first[::-1], 3, 3)
+
+
+@pytest.mark.gpu
+def test_gpu_windowed_decoding_matches_oracle(rounds_dem):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2511_21660_amd import window
+
+    p, first = rounds_dem
+    _, syn = sampling.sample_batch(p, 9 << 32, 0, 160)
+    for tc, to in ((3, 3), (2, 4)):
+        wd = window.WindowedDecoder(p, first, 72, tc, to, **RELAY_DEFAULT)
+        out = wd.decode(torch.from_numpy(syn).cuda())
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        wd.close()
+        ref = oracle.decode_windowed(p.m, p.n, p.rows, p.cols, p.prior, RELAY_DEFAULT, syn, 72, first, tc, to)
+        print(f"[parity] windowed Tc={tc} To={to}: B={len(syn)} windows={got['conv'].shape[0]}", flush=True)
+        for k in ("corr", "conv", "iters"):
+            assert np.array_equal(got[k], ref[k]), (tc, to, k)
+
+
+@pytest.mark.gpu
+def test_gpu_syndrome_kernel(rounds_dem):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2511_21660_amd import relaybp
+
+    p, _ = rounds_dem
+    f, syn = sampling.sample_batch(p, 5, 0, 300)
+    dec = relaybp.Decoder.from_problem(p, **RELAY_DEFAULT)
+    h = p.dense().astype(np.int64)
+    d_f = torch.from_numpy(f.astype(np.uint8)).cuda()
+    s0 = dec.syndrome(d_f).cpu().numpy()
+    assert np.array_equal(s0, syn)
+    rng = np.random.default_rng(1)
+    base = (rng.random((300, p.m)) < 0.3).astype(np.uint8)
+    d_b = torch.from_numpy(base).cuda()
+    s1 = dec.syndrome(d_f, syn_in=d_b).cpu().numpy()
+    assert np.array_equal(s1, (base.astype(np.int64) + f.astype(np.int64) @ h.T) % 2)
+    dec.syndrome(d_f, syn_in=d_b, out=d_b)  # in place
+    assert np.array_equal(d_b.cpu().numpy(), s1)
+    dec.close()

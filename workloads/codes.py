@@ -271,3 +271,24 @@ def dem_problem(m: int = 936, n: int = 8785, band: int = 72, seed: int = 9368785
     prior = 10.0 ** rng.uniform(np.log10(p_lo), np.log10(p_hi), size=n)
     logical = (rng.random((logical_rows, n)) < 0.5).astype(np.uint8)
     return Problem(f"dem{m}x{n}", m, n, rows, cols, prior, logical)
+
+
+def dem_rounds_problem(m: int = 936, n: int = 8785, band: int = 72, seed: int = 9368785):
+    """The DEM-shaped matrix of dem_problem with detector rounds made explicit
+    for windowed decoding: rows of round r are [r*band, (r+1)*band), and the
+    columns are reordered (stably) by the round of their first detector, so
+    that the faults beginning in a range of rounds form a contiguous range of
+    columns.  Returns (problem, first_round) with first_round[j] the round of
+    column j's first detector (the number of rounds if the column is empty)."""
+    p = dem_problem(m, n, band, seed)
+    lo = np.full(n, m, dtype=np.int64)
+    np.minimum.at(lo, p.cols, p.rows)
+    first = lo // band
+    order = np.argsort(first, kind="stable")
+    new_of_old = np.empty(n, dtype=np.int64)
+    new_of_old[order] = np.arange(n)
+    cols = new_of_old[p.cols]
+    srt = np.lexsort((cols, p.rows))
+    prob = Problem(f"{p.name}_rounds", m, n, p.rows[srt].astype(np.int32), cols[srt].astype(np.int32),
+                   p.prior[order], p.logical[:, order])
+    return prob, first[order].astype(np.int32)
