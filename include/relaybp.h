@@ -130,7 +130,12 @@ rb_status rb_params_default(rb_params *out);
  * the check-major (CSR) and fault-major (CSC) edge layouts, the per-lane
  * gather tables of the chosen kernel configuration and the table of memory
  * strengths Gamma_1..Gamma_R on the device.  This call allocates and
- * synchronises the device.
+ * synchronises the device.  Configurations, tried in this order: group tiles
+ * (a few lanes per syndrome; small and medium codes), block shapes (one
+ * 1024-thread workgroup per syndrome, M <= 1024, N <= 9216, row degree <= 64
+ * after splitting rows over lane pairs), large-graph shapes (one workgroup
+ * per syndrome with compressed messages, M <= 4096, N <= 32768, E < 2^20,
+ * 4N + 16M + E/8 bytes of LDS within 160 KiB).  RB_E_UNSUPPORTED beyond.
  */
 rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32_t *rows,
                     const int32_t *cols, const double *prior_p, const rb_params *params,
