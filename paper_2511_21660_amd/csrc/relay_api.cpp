@@ -569,7 +569,8 @@ rb_status upload(T **dst, const std::vector<T> &src, const char *what) {
 // check, whose LDS bank is the owning lane mod 32; lanes are swapped within
 // waves (pairs with pairs, single lanes with single lanes) so that, for every
 // (band, k), the banks of these messages are as evenly spread as possible,
-// which is what place_faults needs to reach two words per bank.
+// which is what place_faults needs to give each half-wave of faults 32
+// distinct banks per gather.
 void spread_check_lanes(const rb_ctx *c, const rb::BlockShape &s, std::vector<LaneSeg> &lanes) {
     const int TPB = s.TPB, nw = TPB / 64, D = rb::prof_max(s.prof, s.VPT);
     const std::vector<int32_t> fo = fault_order(c);
@@ -1114,7 +1115,8 @@ std::string check_group_tables(const rb_ctx *c, const rb::TileShape &s, const Gr
                            std::to_string(a) + ", the message word is " + std::to_string(want);
             }
         }
-    // bank model over a whole wave (NS interleaved slots of G lanes)
+    // bank model over the wave's 64 lanes (slot-major: lane = slot * G + g),
+    // each half of 32 lanes costed on its own
     std::vector<uint32_t> words;
     auto wave = [&](const std::vector<uint32_t> &t, int nrow, int idx) {
         words.clear();
