@@ -417,6 +417,9 @@ struct BlockVariant {
 // slot bands (band 0 in the low nibble), waves/SIMD); the planner takes the
 // first that fits.
 const BlockVariant kBlockVariants[] = {
+    // M <= 512, N <= 4608 with the DEM's band caps: half-size workgroups, so
+    // that two shots share a CU (windows of a few detector rounds of a DEM)
+    RB_BVARIANT(512, 64, 9, 0x222333456ull, 4),
     // M <= 1024, N <= 9216, degrees sorted like a circuit-level DEM (weights
     // 2..6, mostly 2 and 3): band caps 6,5,4,3,3,3,2,2,2 (exactly those of the
     // 936 x 8785 matrix), then a looser profile 6,6,5,4,3,3,3,2,2
