@@ -31,6 +31,8 @@ def window_plan(m, band, first_round, t_commit, t_overlap):
     are committed.  first_round must be non-decreasing (columns sorted)."""
     if t_commit < 1 or t_overlap < 0:
         raise ValueError("t_commit must be >= 1 and t_overlap >= 0")
+    if band < 1 or m < 1:
+        raise ValueError("m and band must be >= 1")
     first_round = np.asarray(first_round)
     if np.any(np.diff(first_round) < 0):
         raise ValueError("columns must be sorted by the round of their first detector")
@@ -55,6 +57,8 @@ class WindowedDecoder:
 
     def __init__(self, problem, first_round, band, t_commit, t_overlap, device=0, **params):
         self.m, self.n = problem.m, problem.n
+        if np.asarray(first_round).shape != (problem.n,):
+            raise ValueError("first_round needs one entry per column")
         self.plan = window_plan(problem.m, band, first_round, t_commit, t_overlap)
         self.full = relaybp.Decoder.from_problem(problem, device=device, **params)
         self.decs = []
@@ -77,6 +81,8 @@ class WindowedDecoder:
         current stream."""
         import torch
 
+        if syndromes.dtype != torch.uint8 or syndromes.dim() != 2 or syndromes.shape[1] != self.m:
+            raise ValueError(f"syndromes must be uint8 [B, {self.m}]")
         b = syndromes.shape[0]
         dev = syndromes.device
         syndromes = syndromes.contiguous()

@@ -109,4 +109,5 @@ def test_null_arguments(lib):
     assert lib.rb_trace(None, 1, None, None, ctypes.c_float(1.0), 1, None, None) == 1
     assert lib.rb_get_info(None, None) == 1
     assert lib.rb_sync_status(None) == 1
+    assert lib.rb_syndrome(None, 1, None, None, None, None) == 1
     lib.rb_destroy(None)

@@ -88,6 +88,9 @@ def test_window_plan_commits_every_fault_once(rounds_dem):
         assert plan[-1][1] == p.m
     with pytest.raises(ValueError):
         window.window_plan(p.m, 72, first[::-1], 3, 3)
+    for bad in ((p.m, 72, first, 0, 3), (p.m, 0, first, 3, 3), (p.m, 72, first, 2, -1)):
+        with pytest.raises(ValueError):
+            window.window_plan(*bad)
 
 
 @pytest.mark.gpu
