@@ -175,7 +175,7 @@ struct LargeArgs {
     float *final_llr;
     const float *w;            // [N]
     const float *gamma;        // [R][N]
-    float *lambda0;            // [grid][N] workspace: lambda(0) of the current leg per workgroup
+    float *lambda0;            // [grid][N] workspace: lambda(0) of the current chained leg per workgroup
     const int32_t *rowptr;     // [M+1] CSR
     const uint16_t *ctab;      // row i's fault indices from entry 8 * rbase[i], padded with 0 to a
                                // multiple of kLargeGather (16-byte aligned chunks)

@@ -82,11 +82,12 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     }
     if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
 
-    // xl = (1 - gamma) * lambda(0) is constant within a leg and kept as such
-    // per fault: lambda(0) of the current leg in this workgroup's slice of
-    // global memory and gamma of the current leg in the table, both read each
-    // iteration (coalesced: a wave's lanes own consecutive faults), which
-    // keeps the registers for the loads in flight
+    // (1 - gamma) * lambda(0) is formed each iteration from two values per
+    // fault, read each iteration (coalesced: a wave's lanes own
+    // consecutive faults), which keeps the registers for the loads in flight:
+    // gamma of the current leg from the table; lambda(0) from w in leg 1 and
+    // under the prior anchor, else (chained legs) from this workgroup's slice
+    // of global memory, written at each leg change
     float *l0w = a.lambda0 + (size_t)blockIdx.x * N;
     const float *gcur = a.gamma;
     uint32_t sig = 0;  // bit c: syndrome bit of check ci[c]
@@ -133,7 +134,6 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             if (j < N) {
                 const float wj = a.scale * a.w[j];
                 lds_b<float>(4u * (uint32_t)j) = wj;
-                l0w[j] = wj;
                 if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * N + j] = wj;
             }
         }
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
 #pragma unroll
                 for (int v = 0; v < VR; ++v) {
                     const int j = (int)tl + TPB * v;
-                    if (j < N) l0w[j] = PRIOR ? a.scale * a.w[j] : clipl(lds_b<float>(4u * (uint32_t)j), L);
+                    if (!PRIOR && j < N) l0w[j] = clipl(lds_b<float>(4u * (uint32_t)j), L);
                 }
                 zero_messages();
             } else {
@@ -324,7 +324,9 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 ra[f] = fr[0];
                 rc[f] = fr[1];
                 gv[f] = gcur[j];
-                l0[f] = l0w[j];
+                // lambda(0) is s * w in leg 1 and under the prior anchor (read
+                // from the shared, L2-resident w), else the chained anchor
+                l0[f] = (PRIOR || r == 1) ? a.scale * a.w[j] : l0w[j];
                 lam[f] = lds_b<float>(4u * (uint32_t)j);
             }
 #pragma unroll
