@@ -144,3 +144,50 @@ def test_rejections():
         rb.plan_check(p.m, p.n, np.r_[p.rows, p.rows[:1]], np.r_[p.cols, p.cols[:1]])
     assert e.value.status == 3
     assert rb.load_library().rb_plan_check(1, 1, 0, None, None, -1, None) == 1
+
+
+def test_compressed_check_messages_rebuild_min_sum_exactly():
+    """The large-graph kernel stores a check's messages as (m1, m2, first
+    position of the minimum, sign parity) plus the sign bit of each nu.
+    Min-sum (paper Sec. 2.3) gives edge e of check i the sign sigma_i times
+    the product of the other nu's signs and the smallest other |nu|; rebuilt
+    from the state this is bit-identical, ties, zeros and saturated values
+    included."""
+    rng = np.random.default_rng(4)
+    L = np.float32(2.0 ** 64)
+    for trial in range(3000):
+        d = int(rng.integers(1, 12))
+        kind = trial % 4
+        if kind == 0:
+            nu = rng.normal(0, 3, d).astype(np.float32)
+        elif kind == 1:  # ties
+            nu = rng.choice(np.float32([-2, -1, -0.5, 0.5, 1, 2]), d)
+        elif kind == 2:  # signed zeros and saturation
+            nu = rng.choice(np.float32([0.0, -0.0, L, -L, 1.5]), d)
+        else:
+            nu = (rng.integers(-4, 5, d) * 0.25).astype(np.float32)
+        sigma = bool(rng.integers(0, 2))
+        # definition: over the other edges
+        ref = np.empty(d, np.float32)
+        for e in range(d):
+            others = np.delete(nu, e)
+            neg = sigma ^ bool(np.signbit(others).sum() % 2)
+            mag = np.float32(np.min(np.abs(others))) if d > 1 else L
+            ref[e] = -mag if neg else mag
+        # compressed state, accumulated as the kernel does
+        m1 = m2 = L
+        amin = 0
+        par = sigma
+        for e in range(d):
+            av = np.float32(abs(nu[e]))
+            par ^= bool(np.signbit(nu[e]))
+            if av < m1:
+                amin = e
+            m2 = np.float32(np.median([m1, av, m2]))
+            m1 = min(m1, av)
+        rebuilt = np.empty(d, np.float32)
+        for e in range(d):
+            mag = m2 if e == amin else m1
+            neg = par ^ bool(np.signbit(nu[e]))
+            rebuilt[e] = -mag if neg else mag
+        assert np.array_equal(rebuilt.view(np.uint32), ref.view(np.uint32)), (nu, sigma, rebuilt, ref)
