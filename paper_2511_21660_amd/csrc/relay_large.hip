@@ -313,6 +313,8 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         };
 #pragma unroll
         for (int vb = 0; vb < VR; vb += kLargeBatch) {
+            // this thread's faults of this and every later batch lie past N
+            if ((int)tl + TPB * vb >= N) break;
             int qa[kLargeBatch], qb[kLargeBatch];
             uint4 ra[kLargeBatch], rc[kLargeBatch];
             float gv[kLargeBatch], l0[kLargeBatch], lam[kLargeBatch];
