@@ -521,8 +521,18 @@ bool block_fits(const rb_ctx *c, const rb::BlockShape &s) {
     return l.lds_bytes <= 160 * 1024;
 }
 
-// Large-graph kernel LDS: Lambda[N], one 16-byte state per check, the E sign
-// bits, reduction scratch.
+// Slots of the large-graph kernel's padded row table: each row rounded up to
+// whole chunks of kLargeGather entries.  Slot rbase*kLargeGather + k holds the
+// fault of edge k of a row and indexes that edge's sign bit.
+int64_t large_slots(const rb_ctx *c) {
+    int64_t n = 0;
+    for (int32_t i = 0; i < c->M; ++i)
+        n += (c->rowptr[i + 1] - c->rowptr[i] + rb::kLargeGather - 1) / rb::kLargeGather * rb::kLargeGather;
+    return n;
+}
+
+// Large-graph kernel LDS: Lambda[N], one 16-byte state per check, one sign
+// bit per slot, reduction scratch.
 struct LargeLayout {
     uint32_t chk_off, sgn_off, red_off;
     int32_t nsw;
@@ -531,7 +541,7 @@ struct LargeLayout {
 
 LargeLayout large_layout(const rb_ctx *c, const rb::LargeShape &s) {
     LargeLayout l{};
-    l.nsw = (int32_t)((c->E + 31) / 32);
+    l.nsw = (int32_t)((large_slots(c) + 31) / 32);
     l.chk_off = ((4u * (uint32_t)c->N) + 15u) & ~15u;
     l.sgn_off = l.chk_off + 16u * (uint32_t)c->M;
     l.red_off = (l.sgn_off + 4u * (uint32_t)l.nsw + 15u) & ~15u;
@@ -541,7 +551,7 @@ LargeLayout large_layout(const rb_ctx *c, const rb::LargeShape &s) {
 
 bool large_fits(const rb_ctx *c, const rb::LargeShape &s) {
     if (c->M > rb::kLargeRounds * s.TPB || c->N > s.TPB * s.VR) return false;
-    if (c->N > 65535 || c->M > (1 << (32 - rb::kLargeEdgeBits)) || c->E >= (int64_t)1 << rb::kLargeEdgeBits)
+    if (c->N > 65535 || c->M > (1 << (32 - rb::kLargeEdgeBits)) || large_slots(c) >= (int64_t)1 << rb::kLargeEdgeBits)
         return false;
     return large_layout(c, s).lds_bytes <= 160 * 1024;
 }
@@ -1307,7 +1317,7 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
 // decreasing degree are dealt round by round (round r takes the next TPB of
 // them, thread t the t-th), so the 64 checks a wave handles in one round have
 // nearly the same length; fault-side entries pack each CSC entry's check and
-// CSR edge.
+// the slot of its edge in the padded row table (which indexes its sign bit).
 struct LargeTables {
     LargeLayout lay{};
     int32_t rounds = 0;
@@ -1343,7 +1353,7 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     T.fedge.resize((size_t)std::max<int64_t>(1, c->E), 0u);
     for (int64_t q = 0; q < c->E; ++q) {
         const int32_t i = c->rowidx[(size_t)q];
-        const int64_t e = c->rowptr[i] + c->cpos[(size_t)q];
+        const int64_t e = (int64_t)T.rbase[(size_t)i] * G + c->cpos[(size_t)q];  // sign-bit slot
         T.fedge[(size_t)q] = ((uint32_t)i << rb::kLargeEdgeBits) | (uint32_t)e;
     }
     T.frec.assign((size_t)c->N * G, 0u);
@@ -1355,8 +1365,9 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
 
 // Independent reading of the large-graph tables: every check on exactly one
 // (round, thread); rounds in use hold the checks (kernel reads rounds <
-// ceil(M/TPB)); each CSR edge's fault and each CSC entry's (check, edge) agree
-// with H; the LDS image fits.
+// ceil(M/TPB)); each CSR edge's fault and each CSC entry's (check, slot) agree
+// with H; slots start rows on whole chunks and their sign bits lie inside the
+// LDS sign words; the LDS image fits.
 std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const LargeTables &T, rb_plan_report *r) {
     if (T.lay.lds_bytes > 160 * 1024) return "LDS image exceeds a CU";
     if (T.rounds < 1 || T.rounds > rb::kLargeRounds || (int64_t)T.rounds * s.TPB < c->M) return "check rounds";
@@ -1365,9 +1376,11 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
     // (valid addresses), and every chunk lies inside the table
     constexpr int G = rb::kLargeGather;
     if (T.frec.size() != (size_t)c->N * G) return "fault records";
-    auto col_of_edge = [&](int32_t i, int64_t e) -> int64_t {  // fault of CSR edge e of row i, from ctab
-        const size_t at = (size_t)T.rbase[(size_t)i] * G + (size_t)(e - T.rowptr[(size_t)i]);
-        return at < T.ctab.size() ? (int64_t)T.ctab[at] : -1;
+    auto slot_of_edge = [&](int32_t i, int64_t e) -> int64_t {  // table slot of CSR edge e of row i
+        return (int64_t)T.rbase[(size_t)i] * G + (e - T.rowptr[(size_t)i]);
+    };
+    auto col_of_slot = [&](int64_t at) -> int64_t {
+        return at >= 0 && (size_t)at < T.ctab.size() ? (int64_t)T.ctab[(size_t)at] : -1;
     };
     for (int32_t i = 0; i < c->M; ++i) {
         const int64_t d = T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i];
@@ -1394,12 +1407,14 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
         if (!seen[(size_t)i]) return "check " + std::to_string(i) + " not placed";
     for (int32_t i = 0; i < c->M; ++i)
         for (int64_t e = T.rowptr[(size_t)i]; e < T.rowptr[(size_t)i + 1]; ++e) {
-            const int64_t j = col_of_edge(i, e);
+            const int64_t at = slot_of_edge(i, e);
+            const int64_t j = col_of_slot(at);
             if (j < 0 || j >= c->N) return "edge " + std::to_string(e) + ": fault out of range";
-            bool hit = false;  // (i, j) must be a column entry of fault j
+            if (at >= 32 * (int64_t)T.lay.nsw) return "edge " + std::to_string(e) + ": sign bit past the sign words";
+            bool hit = false;  // (i, slot) must be a column entry of fault j
             for (int64_t q = T.colptr[(size_t)j]; q < T.colptr[(size_t)j + 1] && !hit; ++q)
                 hit = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits) == i &&
-                      (int64_t)(T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u)) == e;
+                      (int64_t)(T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u)) == at;
             if (!hit) return "edge " + std::to_string(e) + " missing from its fault's entries";
         }
     for (int32_t j = 0; j < c->N; ++j) {
@@ -1408,7 +1423,8 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
             const int32_t i = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits);
             const int64_t e = T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u);
             if (i <= prev) return "fault " + std::to_string(j) + ": checks not ascending";
-            if (e < T.rowptr[(size_t)i] || e >= T.rowptr[(size_t)i + 1] || col_of_edge(i, e) != j)
+            const int64_t k = e - (int64_t)T.rbase[(size_t)i] * G;  // position in the row
+            if (k < 0 || k >= T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i] || col_of_slot(e) != j)
                 return "fault " + std::to_string(j) + ": entry " + std::to_string(q) + " is not its edge";
             prev = i;
         }

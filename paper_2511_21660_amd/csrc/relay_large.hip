@@ -12,10 +12,10 @@
 // sign sign(nu_e) XOR neg_i, where neg_i is the parity of sigma_i and of the
 // signs of all nu of the check.  A check's messages are therefore fixed by
 // the state (m1, m2, position of the minimum, neg) plus one sign bit per edge.
-// LDS holds Lambda[N], one 16-byte state per check and the E sign bits of
-// nu; a fault rebuilds each message it sums from the state of its check,
-// bit for bit the message the other kernels store.  A 2736 x 26208 matrix
-// with 82.6K edges takes 155 KiB.
+// LDS holds Lambda[N], one 16-byte state per check and the sign bits of nu,
+// one per slot of the padded row table; a fault rebuilds each message it sums
+// from the state of its check, bit for bit the message the other kernels
+// store.  A 2736 x 26208 matrix with 82.6K edges takes about 156 KiB.
 //
 // Roles.  Thread t owns the faults j = t + TPB*v (v < VR) and the checks
 // chk_of[c][t] (c < rounds): checks sorted by degree and dealt round by round,
@@ -59,6 +59,7 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
 template <int TPB, int VR, bool PRIOR, bool TRACE>
 __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     static_assert(VR <= 32 && VR % kLargeBatch == 0 && TPB % 256 == 0, "shape");
+    static_assert(32 % kLargeGather == 0, "a row chunk lies in one sign word");
     const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
     const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 bytes (block OR), 16-byte aligned
     const uint32_t shot_sh = flags + 4u * (TPB / 64);     // claimed shot index
@@ -71,14 +72,13 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     // out of the persistent loop (2 * VR 64-bit pointers would spill)
     uint32_t tl = (uint32_t)t;
 
-    // this thread's checks and their CSR ranges
-    int ci[kLargeRounds], cb[kLargeRounds], ce[kLargeRounds], crb[kLargeRounds];
+    // this thread's checks, their degrees and first row chunks
+    int ci[kLargeRounds], cd[kLargeRounds], crb[kLargeRounds];
 #pragma unroll
     for (int c = 0; c < kLargeRounds; ++c) {
         const int i = c < a.rounds ? a.chk_of[c * TPB + t] : -1;
         ci[c] = i;
-        cb[c] = i >= 0 ? a.rowptr[i] : 0;
-        ce[c] = i >= 0 ? a.rowptr[i + 1] : 0;
+        cd[c] = i >= 0 ? a.rowptr[i + 1] - a.rowptr[i] : 0;
         crb[c] = i >= 0 ? a.rbase[i] : 0;
     }
     if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
@@ -164,8 +164,11 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             const bool sc = (sig >> c) & 1u;
             bool fpar = sc, neg = sc;
             float m1 = L, m2 = L;
-            int amin = cb[c];
-            const int e0 = cb[c], deg = ce[c] - cb[c];
+            // edge k of the row has the sign-bit slot e0 + k, its position in
+            // the padded row table: rows start on multiples of kLargeGather,
+            // so a chunk of kLargeGather edges never straddles a sign word
+            const int e0 = crb[c] * kLargeGather, deg = cd[c];
+            int amin = e0;
             // sign bits of the word being filled: old message signs, new nu
             // signs and the row's bits in it; a word shared with another
             // check is written with two atomics
@@ -194,17 +197,17 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
 #pragma unroll
                 for (int q = 0; q < kLargeGather; ++q)
                     lv[q] = lds_b<float>(4u * ((q & 1) ? (pw[q >> 1] >> 16) : (pw[q >> 1] & 0xffffu)));
+                if (((e0 + k) >> 5) != cw) {  // the row enters the next word of sign bits
+                    flush();
+                    cw = (e0 + k) >> 5;
+                    osg = lds_b<uint32_t>(sgn + 4u * (uint32_t)cw) ^ flipo;
+                    nb = 0u;
+                    mask = 0u;
+                }
 #pragma unroll
                 for (int q = 0; q < kLargeGather; ++q) {
                     if (k + q >= deg) break;
                     const int eq = e0 + k + q;
-                    if ((eq >> 5) != cw) {  // the row enters the next word of sign bits
-                        flush();
-                        cw = eq >> 5;
-                        osg = lds_b<uint32_t>(sgn + 4u * (uint32_t)cw) ^ flipo;
-                        nb = 0u;
-                        mask = 0u;
-                    }
                     const uint32_t bit = 1u << (eq & 31);
                     const float mag = eq == amo ? m2o : m1o;
                     const float mo = __uint_as_float((osg & bit ? 0x80000000u : 0u) | __float_as_uint(mag));
