@@ -158,7 +158,7 @@ struct LargeShape {
     int TPB, VR;
 };
 constexpr int kLargeRounds = 4;       // checks per thread at most (M <= 4 * TPB)
-constexpr int kLargeEdgeBits = 20;    // fault-side entries: check << 20 | CSR edge
+constexpr int kLargeEdgeBits = 20;    // fault-side entries: check << 20 | sign-bit slot
 constexpr int kLargeGather = 8;       // row chunk and fault record length (table entries per load step)
 constexpr int kLargeBatch = 4;        // faults whose loads the fault pass issues together
 constexpr int kLargeSure = 4;         // fault entries read whatever the degree (padding included)
@@ -182,7 +182,7 @@ struct LargeArgs {
     const int32_t *rbase;      // [M] first chunk of row i in ctab
     const int32_t *colptr;     // [N+1] CSC
     const uint32_t *frec;      // [N][kLargeGather] first entries of each column (padding: 0)
-    const uint32_t *fedge;     // [E] CSC order (ascending check): check << kLargeEdgeBits | CSR edge
+    const uint32_t *fedge;     // [E] CSC order (ascending check): check << kLargeEdgeBits | slot
     const int32_t *chk_of;     // [kLargeRounds][TPB] check of thread t in round c, or -1
     int32_t rounds;            // check rounds in use (<= kLargeRounds)
     int32_t nsw;               // words of edge sign bits (ceil(E / 32))

@@ -23,7 +23,8 @@
 // The graph tables stay in global memory, shared by all workgroups and
 // L2-resident: each row's fault indices padded to a multiple of 8 (one
 // aligned 16-byte load per 8 edges) and one 32-byte record per fault with its
-// first 8 (check, edge) entries (the records of a wave's lanes contiguous).
+// first 8 (check, slot) entries (the records of a wave's lanes contiguous),
+// the slot being the edge's position in the padded row table.
 // A 32-bit word of sign bits can hold edges of two checks owned by different
 // threads, so a check writes its bits of a shared word with two LDS atomics
 // (clear, then set its own bits).
