@@ -531,8 +531,9 @@ int64_t large_slots(const rb_ctx *c) {
     return n;
 }
 
-// Large-graph kernel LDS: Lambda[N], one 16-byte state per check, one sign
-// bit per slot, reduction scratch.
+// Large-graph kernel LDS: Lambda[N + 1] (entry N = +inf is the target of row
+// padding), one 16-byte state per check, one sign bit per slot, reduction
+// scratch.
 struct LargeLayout {
     uint32_t chk_off, sgn_off, red_off;
     int32_t nsw;
@@ -542,7 +543,7 @@ struct LargeLayout {
 LargeLayout large_layout(const rb_ctx *c, const rb::LargeShape &s) {
     LargeLayout l{};
     l.nsw = (int32_t)((large_slots(c) + 31) / 32);
-    l.chk_off = ((4u * (uint32_t)c->N) + 15u) & ~15u;
+    l.chk_off = ((4u * (uint32_t)c->N + 4u) + 15u) & ~15u;
     l.sgn_off = l.chk_off + 16u * (uint32_t)c->M;
     l.red_off = (l.sgn_off + 4u * (uint32_t)l.nsw + 15u) & ~15u;
     l.lds_bytes = (int64_t)l.red_off + 12 * (s.TPB / 64) + 8;
@@ -1346,7 +1347,13 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
         T.rbase[(size_t)i] = (int32_t)chunks;
         chunks += (c->rowptr[i + 1] - c->rowptr[i] + G - 1) / G;
     }
+    // padding entries of a row's last chunk hold N (the +inf entry of Lambda);
+    // the closing chunk, only ever prefetched, holds zeros
     T.ctab.assign((size_t)(chunks + 1) * G, 0);
+    for (int32_t i = 0; i < c->M; ++i) {
+        const int64_t d = c->rowptr[i + 1] - c->rowptr[i];
+        for (int64_t k = d; k < (d + G - 1) / G * G; ++k) T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)k] = (uint16_t)c->N;
+    }
     for (int32_t i = 0; i < c->M; ++i)
         for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e)
             T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)(e - c->rowptr[i])] = (uint16_t)c->colidx[(size_t)e];
@@ -1372,8 +1379,10 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
     if (T.lay.lds_bytes > 160 * 1024) return "LDS image exceeds a CU";
     if (T.rounds < 1 || T.rounds > rb::kLargeRounds || (int64_t)T.rounds * s.TPB < c->M) return "check rounds";
     // the kernel loads whole chunks of kLargeGather entries: a row's chunk
-    // past its last edge and a record past a column's last entry hold zeros
-    // (valid addresses), and every chunk lies inside the table
+    // past its last edge holds N (the +inf entry of Lambda, which must not
+    // overlap the check states), a record past a column's last entry holds
+    // zeros (valid addresses), and every chunk lies inside the table
+    if (T.lay.chk_off < 4u * (uint32_t)c->N + 4u) return "Lambda[N] overlaps the check states";
     constexpr int G = rb::kLargeGather;
     if (T.frec.size() != (size_t)c->N * G) return "fault records";
     auto slot_of_edge = [&](int32_t i, int64_t e) -> int64_t {  // table slot of CSR edge e of row i
@@ -1386,7 +1395,7 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
         const int64_t d = T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i];
         if ((size_t)(T.rbase[(size_t)i] + (d + G - 1) / G) * G > T.ctab.size()) return "row chunks past the table";
         for (int64_t k = d; k < (d + G - 1) / G * G; ++k)
-            if (T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)k] != 0) return "row padding values";
+            if (T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)k] != (uint32_t)c->N) return "row padding values";
     }
     for (int32_t j = 0; j < c->N; ++j) {
         const int64_t d = T.colptr[(size_t)j + 1] - T.colptr[(size_t)j];

@@ -12,8 +12,9 @@
 // sign sign(nu_e) XOR neg_i, where neg_i is the parity of sigma_i and of the
 // signs of all nu of the check.  A check's messages are therefore fixed by
 // the state (m1, m2, position of the minimum, neg) plus one sign bit per edge.
-// LDS holds Lambda[N], one 16-byte state per check and the sign bits of nu,
-// one per slot of the padded row table; a fault rebuilds each message it sums
+// LDS holds Lambda[0..N-1] and one more entry, Lambda[N] = +inf, that row
+// padding reads; one 16-byte state per check; the sign bits of nu, one per
+// slot of the padded row table.  A fault rebuilds each message it sums
 // from the state of its check, bit for bit the message the other kernels
 // store.  A 2736 x 26208 matrix with 82.6K edges takes about 156 KiB.
 //
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         crb[c] = i >= 0 ? a.rbase[i] : 0;
     }
     if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
+    if (t == 0) lds_b<float>(4u * (uint32_t)N) = __builtin_inff();  // target of row padding entries
 
     // (1 - gamma) * lambda(0) is formed each iteration from two values per
     // fault, read each iteration (coalesced: a wave's lanes own
@@ -187,7 +189,13 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             // eight edges per step from one aligned 16-byte load of the row's
             // padded fault indices; the Lambda gathers are issued together
             // the next chunk is loaded one step ahead (the table ends with a
-            // zero chunk, so the load past a row's last chunk stays inside it)
+            // zero chunk, so the load past a row's last chunk stays inside it).
+            // Padding entries of a row's last chunk address Lambda[N] = +inf:
+            // their nu is clip(inf - mu) = L, which leaves m1 <= m2 <= L, the
+            // position of the minimum, both parities and the sign bits as
+            // they are, so all eight entries run without a per-edge test.
+            // A chunk is one byte of a sign word (its slot is a multiple of
+            // 8): old signs are read and new ones collected per byte.
             const uint4 *rt = reinterpret_cast<const uint4 *>(a.ctab) + crb[c];
             uint4 cur = rt[0];
             for (int k = 0; k < deg; k += kLargeGather) {
@@ -198,31 +206,34 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
 #pragma unroll
                 for (int q = 0; q < kLargeGather; ++q)
                     lv[q] = lds_b<float>(4u * ((q & 1) ? (pw[q >> 1] >> 16) : (pw[q >> 1] & 0xffffu)));
-                if (((e0 + k) >> 5) != cw) {  // the row enters the next word of sign bits
+                const int ec = e0 + k;  // slot of the chunk's first entry
+                if ((ec >> 5) != cw) {  // the row enters the next word of sign bits
                     flush();
-                    cw = (e0 + k) >> 5;
+                    cw = ec >> 5;
                     osg = lds_b<uint32_t>(sgn + 4u * (uint32_t)cw) ^ flipo;
                     nb = 0u;
                     mask = 0u;
                 }
+                const uint32_t sh = (uint32_t)ec & 31u;
+                const uint32_t ob = osg >> sh;  // old message signs, entry q in bit q
+                const int am = amo - ec;        // entry of the old minimum, if in 0..7
+                uint32_t nb8 = 0u;
 #pragma unroll
                 for (int q = 0; q < kLargeGather; ++q) {
-                    if (k + q >= deg) break;
-                    const int eq = e0 + k + q;
-                    const uint32_t bit = 1u << (eq & 31);
-                    const float mag = eq == amo ? m2o : m1o;
-                    const float mo = __uint_as_float((osg & bit ? 0x80000000u : 0u) | __float_as_uint(mag));
+                    const float mag = am == q ? m2o : m1o;
+                    const float mo = __uint_as_float(((ob << (31 - q)) & 0x80000000u) | __float_as_uint(mag));
                     fpar ^= lv[q] < 0.0f;
                     const float nu = clipl(lv[q] - mo, L);
                     const bool sn = nu < 0.0f;
                     neg ^= sn;
-                    nb |= sn ? bit : 0u;
-                    mask |= bit;
+                    nb8 |= sn ? 1u << q : 0u;
                     const float av = fabsf(nu);
-                    amin = av < m1 ? eq : amin;
+                    amin = av < m1 ? ec + q : amin;
                     m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
                     m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
                 }
+                nb |= nb8 << sh;
+                mask |= 0xffu << sh;  // padding slots belong to this row alone
             }
             flush();
             lds_b<float>(sa) = m1;
