@@ -161,7 +161,8 @@ constexpr int kLargeRounds = 4;       // checks per thread at most (M <= 4 * TPB
 constexpr int kLargeEdgeBits = 20;    // fault-side entries: check << 20 | sign-bit slot
 constexpr int kLargeGather = 8;       // row chunk and fault record length (table entries per load step)
 constexpr int kLargeBatch = 4;        // faults whose loads the fault pass issues together
-constexpr int kLargeSure = 4;         // fault entries read whatever the degree (padding included)
+constexpr int kLargeSure = 6;         // fault entries read whatever the degree (padding included;
+                                      // DEM columns have degree 2-6)
 
 struct LargeArgs {
     int32_t M, N;
