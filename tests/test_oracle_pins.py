@@ -424,3 +424,178 @@ def test_learned_gamma1_changes_the_first_leg_only():
         assert out["conv"][b] == (1 if ok.size else 0)
         np.testing.assert_array_equal(out["llr"][b], tr[b, t_stop])
         np.testing.assert_array_equal(out["corr"][b], (tr[b, t_stop] < 0).astype(np.uint8))
+
+
+# ------------------------------------------------ S > 1 solution selection
+
+
+def _events_from_s_runs(h, w32, syn, prm, k_max, **kw):
+    """Convergence events 1..k_max of every shot, read off decodes with
+    S = 1..k_max.  The trajectory of a decode does not depend on S until it
+    stops, so the run with S = k ends at the k-th convergence event, if there
+    is one, and its final marginals give that event's decision
+    F^(k) = [Lambda < 0].  Event k exists iff F^(k) satisfies the syndrome and
+    the S = k run went past where the S = k-1 run stopped.  Returns, per
+    shot, the list of (F^(k), W^(k)) with W^(k) = sum_j F^(k)_j w_j in FP64,
+    and the outputs of every run."""
+    outs = []
+    for k in range(1, k_max + 1):
+        outs.append(oracle.decode(h.shape[0], h.shape[1], *_coo(h), kw["prior"],
+                                  dict(prm, num_solutions=k), syn, want_llr=True))
+    hh = h.astype(np.int64)
+    events = []
+    for b in range(syn.shape[0]):
+        ev = []
+        for k in range(k_max):
+            f = (outs[k]["llr"][b] < 0).astype(np.uint8)
+            ok = ((hh @ f) % 2 == (syn[b] != 0)).all()
+            past = k == 0 or outs[k]["iters"][b] > outs[k - 1]["iters"][b]
+            if not (ok and past):
+                break
+            ev.append((f, float(np.sum(f.astype(np.float64) * w32.astype(np.float64)))))
+        events.append(ev)
+    return events, outs
+
+
+def _check_selection(events, outs, k_max):
+    """The S = k output is the earliest lowest-weight solution among events
+    1..k (reading R7: lowest W, ties kept by the earliest), at that weight;
+    the kept weight never increases with k.  Returns how many (shot, k) cases
+    distinguish 'keep the lowest' from 'keep the last' and 'earliest on ties'
+    from 'latest on ties'."""
+    n_last, n_tie = 0, 0
+    for b, ev in enumerate(events):
+        prev_w = np.inf
+        for k in range(1, k_max + 1):
+            out = outs[k - 1]
+            n_k = min(k, len(ev))
+            assert out["conv"][b] == (1 if n_k else 0)
+            if not n_k:
+                continue
+            ws = [e[1] for e in ev[:n_k]]
+            best = int(np.argmin(ws))                 # first index of the minimum
+            np.testing.assert_array_equal(out["corr"][b], ev[best][0])
+            assert out["weight"][b] == ws[best]
+            assert ws[best] <= prev_w
+            prev_w = ws[best]
+            if not np.array_equal(ev[best][0], ev[n_k - 1][0]):
+                n_last += 1
+            last_min = n_k - 1 - int(np.argmin(ws[::-1]))
+            if last_min != best and not np.array_equal(ev[best][0], ev[last_min][0]):
+                n_tie += 1
+    return n_last, n_tie
+
+
+def test_s_solutions_keep_the_earliest_lowest_weight_bb72():
+    """Selection among S > 1 solutions on [[72,12,6]], R = 20.  Under the
+    paper's chaining a leg that starts from the marginals of a converged leg
+    converges again, to the same decision, at its first iteration, so the
+    rule shows only where later legs find other solutions: with the prior
+    anchor at p = 0.08 both rival rules (keep the last solution; keep the
+    latest of equal weight) give a different output on some shot."""
+    for p_, anchor, shots in ((0.06, 0, 200), (0.08, 1, 800)):
+        p = codes.bb_problem("bb72", p_)
+        _, syn = sampling.sample_batch(p, (1 << 32) | 6, 0, shots)
+        w32 = np.full(p.n, np.float32(np.log((1 - p_) / p_)), np.float32)
+        events, outs = _events_from_s_runs(p.dense(), w32, syn, dict(RELAY_DEFAULT, anchor=anchor), 5,
+                                           prior=p.prior)
+        n_last, n_tie = _check_selection(events, outs, 5)
+        assert sum(len(e) == 5 for e in events) > shots // 2
+        if anchor == 1:
+            assert n_last > 0 and n_tie > 0
+
+
+def test_s_solutions_on_small_loopy_graphs():
+    """The same selection rule on random loopy graphs with unequal integer
+    weights and the prior anchor, where later legs often find other
+    solutions: both rival rules fail on some shot."""
+    tot_last, tot_tie = 0, 0
+    for seed in range(4):
+        rng = np.random.default_rng(100 + seed)
+        m, n = 8, 16
+        h = (rng.random((m, n)) < 0.3).astype(np.uint8)
+        for j in range(n):
+            if not h[:, j].any():
+                h[rng.integers(0, m), j] = 1
+        w = rng.integers(1, 5, n).astype(np.float64)
+        f = (rng.random((200, n)) < 0.2).astype(np.uint8)
+        syn = ((f.astype(np.int64) @ h.T) % 2).astype(np.uint8)
+        prm = dict(RELAY_DEFAULT, num_legs=12, iters_first=20, iters_leg=15, anchor=1)
+        events, outs = _events_from_s_runs(h, w.astype(np.float32), syn, prm, 4,
+                                           prior=_prior_from_llr(w))
+        n_last, n_tie = _check_selection(events, outs, 4)
+        tot_last += n_last
+        tot_tie += n_tie
+    assert tot_last > 20 and tot_tie > 10
+
+
+# ------------------------------------------------- weight <= 3 on [[72,12,6]]
+
+
+def test_weight_at_least_min_weight_bb72():
+    """Validity and weight against the exact minimum on [[72,12,6]]: for
+    syndromes of random faults of weight <= 3, every fault set of weight <= 3
+    is enumerated (1 + 72 + 2556 + 59640 sets), so the least weight among the
+    enumerated solutions is the minimum weight of the syndrome.  A converged
+    correction satisfies H F = sigma and weighs at least that much."""
+    from itertools import combinations
+
+    p = codes.bb_problem("bb72", 0.05)
+    h = p.dense().astype(np.int64)
+    colmask = (h * (1 << np.arange(p.m, dtype=np.int64))[:, None]).sum(0)   # syndrome bits per column
+    best = {0: 0}
+    for k in (1, 2, 3):
+        for cset in combinations(range(p.n), k):
+            s = 0
+            for j in cset:
+                s ^= int(colmask[j])
+            best.setdefault(s, k)
+    rng = np.random.default_rng(3)
+    f = np.zeros((600, p.n), np.uint8)
+    for b in range(600):
+        f[b, rng.choice(p.n, rng.integers(1, 4), replace=False)] = 1
+    syn = ((f.astype(np.int64) @ h.T) % 2).astype(np.uint8)
+    out = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, dict(RELAY_DEFAULT, num_solutions=3), syn)
+    assert out["conv"].mean() > 0.9
+    for b in range(600):
+        if not out["conv"][b]:
+            continue
+        assert ((h @ out["corr"][b]) % 2 == syn[b]).all()
+        s = int((syn[b].astype(np.int64) << np.arange(p.m, dtype=np.int64)).sum())
+        assert int(out["corr"][b].sum()) >= best[s]
+
+
+# ------------------------------------------------ BB translation symmetry
+
+
+@pytest.mark.parametrize("name", ["bb72", "bb90"])
+def test_bb_translation_equivariance(name):
+    """Translations (u, v) -> (u + a, v + b) of Z_l x Z_m commute with A and B
+    (polynomials in the commuting shifts x, y), so they permute the checks and
+    both halves of the faults of HX = [A | B] and leave H invariant.  With
+    integer channel LLRs (w = 3), gamma = 0 in every leg and the clip at
+    L = 2^20 (a marginal then stays below 4 L = 2^22 in magnitude) all
+    arithmetic is exact, so decoding commutes with the permutation bit for bit: the
+    decision, convergence, legs, iterations, weight and marginals of a
+    translated syndrome are the translated ones."""
+    code = codes.bb_code(name)
+    l, m = code.l, code.m
+    prior = 1.0 / (1.0 + np.exp(3.0))
+    p = codes.problem_from_dense(name, code.hx, prior, code.logical)
+    prm = dict(RELAY_DEFAULT, num_legs=6, num_solutions=2, gamma_first=0.0, gamma_lo=0.0, gamma_hi=0.0,
+               llr_clip=2.0 ** 20)
+    _, syn = sampling.sample_batch(codes.bb_problem(name, 0.08), 91, 0, 150)
+    base = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, prm, syn, want_llr=True)
+    assert np.all(np.isin(base["llr"], np.round(base["llr"])))        # exact integer arithmetic
+    for (a, b) in ((1, 0), (0, 1), (2, 1)):
+        q = np.arange(l * m)
+        t = ((q // m + a) % l) * m + (q % m + b) % m                   # check / half-column map
+        tcol = np.concatenate([t, l * m + t])
+        assert ((code.hx[np.ix_(t, tcol)] == code.hx)).all()
+        syn_t = np.zeros_like(syn)
+        syn_t[:, t] = syn
+        out = oracle.decode(p.m, p.n, p.rows, p.cols, p.prior, prm, syn_t, want_llr=True)
+        for key in ("conv", "legs", "iters", "weight"):
+            np.testing.assert_array_equal(out[key], base[key])
+        np.testing.assert_array_equal(out["corr"][:, tcol], base["corr"])
+        np.testing.assert_array_equal(out["llr"][:, tcol], base["llr"])
