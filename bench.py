@@ -1,16 +1,17 @@
 #!/usr/bin/env python3
 """Relay-BP decoding throughput on one MI355X.
 
-Default workload (--workload bb144): plain Relay-BP FP32 on the [[144,12,12]]
-bivariate-bicycle code (HX 72 x 144, E = 432 edges), i.i.d. code-capacity
-faults at p in {0.02, 0.04, 0.06, 0.08}, 10^5 syndromes per p, T_1 = 80,
-T_r = 60, R = 301 legs in total, S = 5 solutions kept (lowest weight output).
-One step decodes all 4 x 10^5 syndromes, already resident in HBM.
+Default workload (--workload dem, the headline): plain Relay-BP FP32 on the
+DEM-shaped synthetic 936 x 8785 matrix (13 rounds of 72 detectors, columns of
+weight 2-6, E = 27,617 edges, priors log-uniform in [1e-4, 1e-2]), 10^6
+syndromes per step already resident in HBM, T_1 = 80, T_r = 60, R = 20 legs,
+S = 1, memory strengths gamma_1 = 0.125 and U[-0.24, 0.66] after.  With the
+latency tail: completion and LER within FPGA-cycle budgets, epsilon(T_ref)
+and the latency-tail condition.
 
 Other workloads:
-  --workload dem          DEM-shaped 936 x 8785 matrix, 10^6 shots, R = 20, S = 1;
-                          with the latency tail: completion and LER within FPGA-cycle
-                          budgets, epsilon(T_ref) and the latency-tail condition
+  --workload bb144        [[144,12,12]] code capacity, p in {0.02, 0.04, 0.06, 0.08},
+                          10^5 syndromes per p in one launch, R = 301, S = 5
   --workload dem-2gross   two-gross-scale DEM-shaped 2736 x 26208 matrix (82.6K edges)
                           on the large-graph kernel, 2 x 10^5 shots, R = 20, S = 1
   --workload dem-window   the DEM-shaped matrix decoded in overlapping windows of
@@ -175,7 +176,39 @@ def head(args, value, elapsed, config):
 
 
 def oracle_threads():
-    return min(16, os.cpu_count() or 1)
+    return min(16, len(os.sched_getaffinity(0)) or 1)
+
+
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+
+
+def oracle_baseline(decode_sample, n_all, n_one, total, what):
+    """Times the oracle on the first n_all syndromes with oracle_threads()
+    threads and on the first n_one with one thread.  decode_sample(n, threads)
+    runs the oracle and returns whether its outputs equal the GPU's."""
+    threads = oracle_threads()
+    t1 = time.perf_counter()
+    agree = decode_sample(n_all, threads)
+    tc = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    agree1 = decode_sample(n_one, 1)
+    t_one = time.perf_counter() - t1
+    return {"value": n_all / tc, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_all} of {total} {what}, same inputs, {tc:.1f} s on {threads} threads; "
+                      f"first {n_one} on one thread, {t_one:.1f} s",
+            "one_core": {"value": n_one / t_one, "shots": n_one},
+            "host": host_cpu(),
+            "paired_with_gpu_bit_exact": bool(agree and agree1)}
 
 
 # --------------------------------------------------------------------------
@@ -293,6 +326,31 @@ def run_bb144(args, torch, rb, codes, sampling):
 # --------------------------------------------------------------------------
 
 
+def end_to_end(torch, dec, syn_np, out):
+    """One decode with the copies: syndromes from pinned host memory to the
+    device, the decode, and corrections, converged flags, legs and iterations
+    back to pinned host memory, timed by the wall clock around synchronised
+    copies (reported beside the HBM-resident rate, never as it)."""
+    dev = out["corr"].device
+    h_syn = torch.from_numpy(syn_np).pin_memory()
+    h_out = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True)
+             for k, v in out.items() if k in ("corr", "conv", "legs", "iters")}
+    d_syn = torch.empty(h_syn.shape, dtype=h_syn.dtype, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d_syn.copy_(h_syn, non_blocking=True)
+    dec.decode(d_syn, out=out)
+    for k, v in h_out.items():
+        v.copy_(out[k], non_blocking=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h2d = h_syn.numel() * h_syn.element_size()
+    d2h = sum(v.numel() * v.element_size() for v in h_out.values())
+    same = bool(torch.equal(h_out["corr"][:20000], out["corr"][:20000].cpu()))
+    return {"syndromes_per_s": syn_np.shape[0] / el, "ms": el * 1e3, "h2d_bytes": h2d, "d2h_bytes": d2h,
+            "first_20000_identical": same}
+
+
 def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     """DEM-shaped matrix: 936 x 8785 on the block kernel, or (two_gross) the
     two-gross-scale 2736 x 26208 on the large-graph kernel."""
@@ -348,18 +406,18 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     if not args.no_cpu_baseline:
         import oracle
 
-        threads = oracle_threads()
+        def decode_sample(n, threads):
+            ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n],
+                                threads=threads)
+            return bool(np.array_equal(ref["corr"], out["corr"][:n].cpu().numpy())
+                        and np.array_equal(ref["iters"], iters[:n])
+                        and np.array_equal(ref["legs"], out["legs"][:n].cpu().numpy())
+                        and np.array_equal(ref["conv"], conv[:n]))
+
         n_cpu = min(args.cpu_sample or (200 if two_gross else 20000), shots)
-        t1 = time.perf_counter()
-        ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n_cpu],
-                            threads=threads)
-        tc = time.perf_counter() - t1
-        agree = bool(np.array_equal(ref["corr"], out["corr"][:n_cpu].cpu().numpy())
-                     and np.array_equal(ref["iters"], iters[:n_cpu])
-                     and np.array_equal(ref["conv"], conv[:n_cpu]))
-        cpu = {"value": n_cpu / tc, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {n_cpu} of {shots} syndromes, same inputs, {tc:.1f} s",
-               "paired_with_gpu_bit_exact": agree}
+        cpu = oracle_baseline(decode_sample, n_cpu, max(1, n_cpu // (16 if two_gross else 40)), shots,
+                              "syndromes")
+    e2e = end_to_end(torch, dec, syn_np, out) if not two_gross else None
     line = head(args, shots * args.steps / elapsed, elapsed, {
         "workload": f"relay_bp_dem_{tag}", "matrix": f"DEM-shaped synthetic {tag}",
         "edges": E, "shots": shots, "T_first": 80, "T_leg": 60, "legs": 20, "solutions": 1,
@@ -377,7 +435,8 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
                  "ler": {"ler": k / shots, "wilson95": wilson(k, shots),
                          "conv": float(conv.mean()), "mean_iters": float(iters.mean()),
                          "max_iters": int(iters.max()), "faults_per_shot": f_shots.size / shots},
-                 "latency_tail": tail, "kernel_config": dec.info(), "cpu_baseline": cpu})
+                 "latency_tail": tail, "kernel_config": dec.info(), "end_to_end": e2e,
+                 "cpu_baseline": cpu})
     return line
 
 
@@ -736,7 +795,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["bb144", "dem", "dem-2gross", "dem-window", "mixed-codes", "learned",
                                            "bp-llr"],
-                    default="bb144")
+                    default="dem")
     ap.add_argument("--train-steps", type=int, default=0, help="learned: Adam steps (default 2000)")
     ap.add_argument("--shots", type=int, default=0,
                     help="syndromes per p (bb144) or in total (default per workload)")
@@ -773,6 +832,8 @@ def main():
            "mixed-codes": run_mixed_codes,
            "learned": run_learned, "bp-llr": run_bp_llr}[args.workload]
     line = run(args, torch, rb, codes, sampling)
+    if line.get("cpu_baseline") and "host" not in line["cpu_baseline"]:
+        line["cpu_baseline"]["host"] = host_cpu()
     if args.calibrate_copy > 0:
         n_el = args.calibrate_copy * (1 << 20) // 4
         src = torch.arange(n_el, dtype=torch.int32, device="cuda")
