@@ -323,6 +323,31 @@ rb_status rb_decode_multi(rb_ctx *ctx, int64_t B, const int32_t *d_code_id,
                           void *d_workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * rb_decode_multi without a workspace argument, for callers that cannot
+ * allocate device memory: code being captured into a hipGraph, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments (minus d_workspace
+ * and workspace_bytes), same results as rb_decode_multi.  The shot lists and
+ * queue counters live in a static device array of 8 MiB that the library
+ * holds on every GPU it runs on until the process ends; the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine), clears what
+ * must start at zero with small kernels (no memset), and only enqueues on
+ * `stream`.  The first call on a device looks up the array's address there.
+ * Every call on one GPU, from any context, uses that GPU's one array: calls
+ * that overlap on one GPU (concurrent streams, threads) race and give wrong
+ * results; serialise them.
+ *   returns RB_E_WORKSPACE if B > rb_noalloc_max_batch(ctx) (about 10^6
+ *   syndromes), before any GPU work; otherwise as rb_decode_multi.
+ */
+rb_status rb_decode_multi_noalloc(rb_ctx *ctx, int64_t B, const int32_t *d_code_id,
+                                  const uint8_t *d_syndromes, uint8_t *d_corr, uint8_t *d_conv,
+                                  int32_t *d_legs, int32_t *d_iters, double *d_weight,
+                                  float *d_final_llr, void *stream);
+
+/* Largest batch rb_decode_multi_noalloc accepts for a mixed context (0 for
+ * NULL or a single-code context); host-only. */
+int64_t rb_noalloc_max_batch(const rb_ctx *ctx);
+
+/*
  * Autotunes a mixed context: for every code k with sample_b[k] > 0, times each
  * tile of the mixed kernel that fits the code on d_samples[k] (uint8
  * [sample_b[k]][M_k], device) and keeps the fastest.  chosen_variants

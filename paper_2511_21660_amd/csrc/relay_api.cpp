@@ -2412,23 +2412,16 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
     return RB_OK;
 }
 
-rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn, uint8_t *d_corr,
-                          uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters, double *d_weight,
-                          float *d_final_llr, void *d_workspace, size_t workspace_bytes, void *stream) {
-    g_last_error.clear();
-    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
-    if (!c->multi) return fail(RB_E_INVALID_ARG, "not a mixed-code context");
-    if (B < 0) return fail(RB_E_INVALID_ARG, "B must be >= 0");
-    if (B == 0) return RB_OK;
-    if (B > INT32_MAX) return fail(RB_E_SHAPE, "B exceeds 2^31 - 1");
-    if (!d_code_id || !d_syn || !d_corr || !d_conv || !d_legs || !d_iters || !d_workspace)
-        return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
+// The mixed launch of rb_decode_multi: shot lists in `ws` (at least
+// shot_list_bytes(B, n_codes) bytes), one queue of kQueueWords counters per
+// code at `queues`.  Arguments are validated by the callers.
+static rb_status launch_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn,
+                                     uint8_t *d_corr, uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters,
+                                     double *d_weight, float *d_final_llr, void *ws_bytes,
+                                     unsigned long long *queues, hipStream_t s) {
     const int nc = (int)c->subs.size();
-    if (workspace_bytes < rb::shot_list_bytes(B, nc)) return fail(RB_E_WORKSPACE, "workspace too small");
-    hipStream_t s = (hipStream_t)stream;
-    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(rb::launch_shot_lists(B, d_syn, c->m_max, d_code_id, c->d_code_m, nc, c->d_code_fam, c->nfam,
-                                 d_workspace, c->d_queues, s),
+                                 ws_bytes, queues, s),
            "shot list kernels");
     rb::MixedArgs m{};
     m.run = base_args(c->subs[0], B, d_syn);
@@ -2446,17 +2439,79 @@ rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const 
     m.fam_rep = c->d_fam_rep;
     m.fam_size = c->d_fam_size;
     m.code_id = d_code_id;
-    const int32_t *ws = (const int32_t *)d_workspace;
+    const int32_t *ws = (const int32_t *)ws_bytes;
     m.seg_start = ws + (size_t)nc * rb::kWeightBinsHost;
     m.seg_count = m.seg_start + nc;
     m.order = m.seg_count + nc;
     m.list = ws + (size_t)nc * (rb::kWeightBinsHost + 3) + (size_t)B;
-    m.queues = c->d_queues;
+    m.queues = queues;
     const int64_t full = (int64_t)c->blocks_per_cu[0] * c->num_cu;
     const int grid = (int)std::max<int64_t>(1, full);
     RB_HIP(rb::launch_mixed(c->params.anchor == RB_ANCHOR_PRIOR, m, grid, (size_t)c->lds_bytes, s),
            "mixed kernel launch");
     return RB_OK;
+}
+
+static rb_status check_multi_args(const rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn,
+                                  const uint8_t *d_corr, const uint8_t *d_conv, const int32_t *d_legs,
+                                  const int32_t *d_iters) {
+    if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (!c->multi) return fail(RB_E_INVALID_ARG, "not a mixed-code context");
+    if (B < 0) return fail(RB_E_INVALID_ARG, "B must be >= 0");
+    if (B > INT32_MAX) return fail(RB_E_SHAPE, "B exceeds 2^31 - 1");
+    if (B > 0 && (!d_code_id || !d_syn || !d_corr || !d_conv || !d_legs || !d_iters))
+        return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
+    return RB_OK;
+}
+
+rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn, uint8_t *d_corr,
+                          uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters, double *d_weight,
+                          float *d_final_llr, void *d_workspace, size_t workspace_bytes, void *stream) {
+    g_last_error.clear();
+    rb_status st = check_multi_args(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters);
+    if (st != RB_OK || B == 0) return st;
+    if (!d_workspace) return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
+    const int nc = (int)c->subs.size();
+    if (workspace_bytes < rb::shot_list_bytes(B, nc)) return fail(RB_E_WORKSPACE, "workspace too small");
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    return launch_decode_multi(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters, d_weight, d_final_llr,
+                               d_workspace, c->d_queues, (hipStream_t)stream);
+}
+
+// Layout of the static scratch for a context of nc codes: nc queues, then
+// the shot lists at the next 256-byte boundary.
+static size_t noalloc_list_offset(int nc) {
+    const size_t q = sizeof(unsigned long long) * rb::kQueueWords * (size_t)nc;
+    return (q + 255) / 256 * 256;
+}
+
+int64_t rb_noalloc_max_batch(const rb_ctx *c) {
+    if (!c || !c->multi) return 0;
+    const int nc = (int)c->subs.size();
+    const size_t off = noalloc_list_offset(nc);
+    const size_t head = rb::shot_list_bytes(0, nc);
+    if (off + head > rb::kNoAllocScratchBytes) return 0;
+    return (int64_t)((rb::kNoAllocScratchBytes - off - head) / (2 * sizeof(int32_t)));
+}
+
+rb_status rb_decode_multi_noalloc(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn,
+                                  uint8_t *d_corr, uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters,
+                                  double *d_weight, float *d_final_llr, void *stream) {
+    g_last_error.clear();
+    rb_status st = check_multi_args(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters);
+    if (st != RB_OK || B == 0) return st;
+    const int64_t bmax = rb_noalloc_max_batch(c);
+    if (B > bmax)
+        return fail(RB_E_WORKSPACE, "B = " + std::to_string(B) + " exceeds the static scratch of " +
+                                        std::to_string(rb::kNoAllocScratchBytes) + " bytes (at most " +
+                                        std::to_string(bmax) + " syndromes for this context)");
+    RB_HIP(hipSetDevice(c->device), "hipSetDevice");
+    void *base = nullptr;
+    RB_HIP(rb::noalloc_scratch(c->device, &base), "static scratch address");
+    const int nc = (int)c->subs.size();
+    return launch_decode_multi(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters, d_weight, d_final_llr,
+                               (unsigned char *)base + noalloc_list_offset(nc), (unsigned long long *)base,
+                               (hipStream_t)stream);
 }
 
 rb_status rb_autotune_multi(rb_ctx *c, const int64_t *sample_b, const uint8_t *const *d_samples, int32_t reps,

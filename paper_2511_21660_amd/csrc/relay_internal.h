@@ -261,6 +261,12 @@ hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, 
                              const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam,
                              void *workspace, unsigned long long *queues, hipStream_t s);
 size_t shot_list_bytes(int64_t B, int ncodes);
+// Static scratch of the no-allocation mixed decode (queue counters of every
+// code, then the shot lists): its size, and its device address on `device`,
+// which must be the current device (looked up once per device, then cached).
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void **ptr);
 constexpr int kWeightBinsHost = 256;              // weight bins of the shot-list sort
 constexpr int kListHeader = kWeightBinsHost + 3;  // int32 words before key[] for one code
 

@@ -49,6 +49,8 @@
 // -ffp-contract=off): nu = clip(Lambda - mu); lambda = clip(a + b) with
 // a = (1 - gamma) * lambda(0), b = gamma * clip(Lambda); sums in ascending i.
 
+#include <mutex>
+
 #include "relay_internal.h"
 
 namespace rb {
@@ -783,6 +785,39 @@ hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowpt
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(kQueueSplit), 0, s, q);
     return hipGetLastError();
+}
+
+}  // namespace rb
+
+// ------------------------------------------------------------------------
+// Static scratch of rb_decode_multi_noalloc: the mixed launch's queue
+// counters and shot lists, for callers that cannot allocate.  Every GPU the
+// library runs on holds its own copy for the life of the process; all calls
+// on one GPU share it.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in for the symbol): it uses the device
+// address looked up below, once per device.
+// ------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[rb::kNoAllocScratchBytes];
+
+namespace rb {
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace rb

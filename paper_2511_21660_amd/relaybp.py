@@ -99,6 +99,9 @@ def load_library():
     L.rb_create_multi.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(RBCodeDesc),
                                   ctypes.POINTER(RBParams), i32]
     L.rb_decode_multi.argtypes = [P, i64, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+    L.rb_decode_multi_noalloc.argtypes = [P, i64, P, P, P, P, P, P, P, P, P]
+    L.rb_noalloc_max_batch.argtypes = [P]
+    L.rb_noalloc_max_batch.restype = i64
     L.rb_autotune_multi.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(P), i32,
                                     ctypes.POINTER(i32)]
     L.rb_train_tape_size.argtypes = [P, i64, i32, i32]
@@ -113,7 +116,7 @@ def load_library():
     L.rb_last_error_message.restype = ctypes.c_char_p
     for name in ("rb_params_default", "rb_create", "rb_decode", "rb_trace", "rb_get_llr",
                  "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status",
-                 "rb_autotune", "rb_reserve", "rb_create_multi", "rb_decode_multi",
+                 "rb_autotune", "rb_reserve", "rb_create_multi", "rb_decode_multi", "rb_decode_multi_noalloc",
                  "rb_autotune_multi", "rb_forward_train", "rb_backward", "rb_set_leg_gamma",
                  "rb_set_prior_scale", "rb_plan_check", "rb_syndrome"):
         getattr(L, name).restype = ctypes.c_int
@@ -426,6 +429,25 @@ class MultiDecoder:
             self._h, b, _ptr(code_id), _ptr(syndromes), _ptr(out["corr"]), _ptr(out["conv"]),
             _ptr(out["legs"]), _ptr(out["iters"]), _ptr(out.get("weight")), _ptr(out.get("llr")),
             _ptr(ws), ws.numel(), _stream(syndromes.device)))
+        return out
+
+    def noalloc_max_batch(self) -> int:
+        return int(load_library().rb_noalloc_max_batch(self._h))
+
+    def decode_noalloc(self, code_id, syndromes, out):
+        """rb_decode_multi_noalloc: the same decode with the library's static
+        scratch instead of a workspace (``out`` from alloc(); its workspace
+        is not used).  Enqueues on the current stream."""
+        import torch
+
+        if syndromes.dtype != torch.uint8 or syndromes.shape[1] != self.m_max:
+            raise ValueError(f"syndromes must be uint8 [B, {self.m_max}]")
+        if code_id.dtype != torch.int32 or code_id.shape[0] != syndromes.shape[0]:
+            raise ValueError("code_id must be int32 [B]")
+        _check(load_library().rb_decode_multi_noalloc(
+            self._h, syndromes.shape[0], _ptr(code_id), _ptr(syndromes), _ptr(out["corr"]),
+            _ptr(out["conv"]), _ptr(out["legs"]), _ptr(out["iters"]), _ptr(out.get("weight")),
+            _ptr(out.get("llr")), _stream(syndromes.device)))
         return out
 
     def autotune(self, samples, reps: int = 3):

@@ -110,4 +110,6 @@ def test_null_arguments(lib):
     assert lib.rb_get_info(None, None) == 1
     assert lib.rb_sync_status(None) == 1
     assert lib.rb_syndrome(None, 1, None, None, None, None) == 1
+    assert lib.rb_decode_multi_noalloc(None, 1, None, None, None, None, None, None, None, None, None) == 1
+    assert lib.rb_noalloc_max_batch(None) == 0
     lib.rb_destroy(None)
