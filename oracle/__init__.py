@@ -13,6 +13,7 @@ from .oracle import (  # noqa: F401
     lib,
     minsum_trace,
     philox4x32_10,
+    round_h16,
     sumproduct_trace,
     trace,
 )

@@ -73,6 +73,13 @@ def lib():
             f.restype = i32
         L.ro_sumproduct_trace.argtypes = [i32, i32, i64, P, P, P, i32, i64, P, P]
         L.ro_sumproduct_trace.restype = i32
+        L.ro_round_h16.argtypes = [ctypes.c_double]
+        L.ro_round_h16.restype = ctypes.c_double
+        L.ro_decode_h16.argtypes = [i32, i32, i64, P, P, P, ctypes.POINTER(OracleParams), P, i64, P, P,
+                                    P, P, P, P, P]
+        L.ro_decode_h16.restype = i32
+        L.ro_trace_h16.argtypes = [i32, i32, i64, P, P, P, P, i32, ctypes.c_double, i64, P, P]
+        L.ro_trace_h16.restype = i32
         _lib = L
     return _lib
 
@@ -97,13 +104,21 @@ def _coo(rows, cols):
     return (np.ascontiguousarray(rows, dtype=np.int32), np.ascontiguousarray(cols, dtype=np.int32))
 
 
+def round_h16(x: float) -> float:
+    """Nearest IEEE binary16 value (ties to even) of x, as the oracle's
+    binary16 mode rounds."""
+    return float(lib().ro_round_h16(float(x)))
+
+
 def decode(m, n, rows, cols, prior, params: dict, syn, precision="f32", threads=None,
            chunk=None, want_llr=False, gamma1=None, scale=1.0):
     """Relay-decode syndromes [B, M]; returns dict of corr/conv/legs/iters/weight
     (and final marginals ``llr`` [B, N] when ``want_llr``).  ``gamma1`` [N]
     replaces leg 1's uniform memory strength per column and ``scale``
     multiplies the initial channel LLRs (a learned first leg); the defaults are
-    the paper's decoder."""
+    the paper's decoder.  precision: "f32" (the decoder's arithmetic), "f64"
+    (its twin) or "h16" (binary16 messages and marginals; no scale; llr is
+    returned as float32)."""
     rows, cols = _coo(rows, cols)
     prior = np.ascontiguousarray(prior, dtype=np.float64)
     syn = np.ascontiguousarray(syn, dtype=np.uint8)
@@ -114,20 +129,25 @@ def decode(m, n, rows, cols, prior, params: dict, syn, precision="f32", threads=
     legs = np.zeros(b, np.int32)
     iters = np.zeros(b, np.int32)
     weight = np.zeros(b, np.float64)
-    llr = np.zeros((b, n), np.float32 if precision == "f32" else np.float64) if want_llr else None
+    llr = np.zeros((b, n), np.float64 if precision == "f64" else np.float32) if want_llr else None
     fn = getattr(lib(), f"ro_decode_{precision}")
     g1 = None
     if gamma1 is not None:
-        g1 = np.ascontiguousarray(gamma1, dtype=np.float32 if precision == "f32" else np.float64)
+        g1 = np.ascontiguousarray(gamma1, dtype=np.float64 if precision == "f64" else np.float32)
         if g1.shape != (n,):
             raise ValueError("gamma1 must have one entry per column")
+    if precision == "h16" and scale != 1.0:
+        raise ValueError("the binary16 mode has no prior scale")
     threads = threads or os.cpu_count() or 1
     chunk = chunk or max(1, min(256, (b + threads - 1) // max(threads, 1)))
 
     def run(s0):
         s1 = min(b, s0 + chunk)
-        rc = fn(m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(prior), ctypes.byref(p),
-                _ptr(g1) if g1 is not None else None, float(scale), s1 - s0,
+        lead = (m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(prior), ctypes.byref(p),
+                _ptr(g1) if g1 is not None else None)
+        if precision != "h16":
+            lead = lead + (float(scale),)
+        rc = fn(*lead, s1 - s0,
                 _ptr(syn[s0:s1]), _ptr(corr[s0:s1]), _ptr(conv[s0:s1]), _ptr(legs[s0:s1]),
                 _ptr(iters[s0:s1]), _ptr(weight[s0:s1]),
                 _ptr(llr[s0:s1]) if want_llr else None)
@@ -149,14 +169,23 @@ def decode(m, n, rows, cols, prior, params: dict, syn, precision="f32", threads=
 
 def trace(m, n, rows, cols, prior, gamma, t_iters, syn, scale=1.0, precision="f32",
           llr_clip=2.0 ** 64):
-    """Marginal trace [B, T+1, N] of one leg with per-column gamma, no early stop."""
+    """Marginal trace [B, T+1, N] of one leg with per-column gamma, no early stop
+    (precision "f32", "f64" or "h16")."""
     rows, cols = _coo(rows, cols)
     prior = np.ascontiguousarray(prior, dtype=np.float64)
-    dt = np.float32 if precision == "f32" else np.float64
+    dt = np.float64 if precision == "f64" else np.float32
     gamma = np.ascontiguousarray(np.broadcast_to(np.asarray(gamma, dtype=dt), (n,)))
     syn = np.ascontiguousarray(syn, dtype=np.uint8)
     b = syn.shape[0]
     out = np.zeros((b, t_iters + 1, n), dt)
+    if precision == "h16":
+        if scale != 1.0:
+            raise ValueError("the binary16 mode has no prior scale")
+        rc = lib().ro_trace_h16(m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(prior), _ptr(gamma),
+                                int(t_iters), float(llr_clip), b, _ptr(syn), _ptr(out))
+        if rc != 0:
+            raise ValueError(f"oracle trace failed with code {rc}")
+        return out
     rc = getattr(lib(), f"ro_trace_{precision}")(m, n, rows.size, _ptr(rows), _ptr(cols),
                                                  _ptr(prior), float(scale), _ptr(gamma),
                                                  int(t_iters), float(llr_clip), b, _ptr(syn),

@@ -213,6 +213,197 @@ typedef struct {
 #undef RINF
 
 /* ------------------------------------------------------------------------ */
+/* Reduced-precision mode: IEEE binary16 messages and marginals.             */
+/*                                                                          */
+/* The paper leaves the precision of Relay's messages open (its FPGA         */
+/* estimates state none).  This mode runs the same algorithm, in the same    */
+/* order, with every quantity of a shot (Lambda, lambda(0), the memory term, */
+/* nu, mu) held as a binary16 value and every arithmetic result rounded to   */
+/* binary16, nearest-even, with IEEE overflow to infinity:                   */
+/*   w16_j   = h16(log((1 - p_j) / p_j))       (rounded once from FP64)      */
+/*   g16_rj  = h16(gamma_rj) of the FP32 gamma of reading R5                 */
+/*   L16     = h16(min(L, 4096))               (the clip; 4096 keeps sums of */
+/*             up to 15 clipped terms finite)                                */
+/*   nu      = clip(h16(Lambda - mu))                                        */
+/*   mu      = sgn * min |nu| over the others  (selection only, no rounding) */
+/*   a       = h16(h16(1 - g16) * lambda(0)),  b = h16(g16 * clip(Lambda))   */
+/*   lambda  = clip(h16(a + b)),  Lambda = h16(... h16(lambda + mu_1) ...)   */
+/* in ascending check order.  The decision, the convergence test, the legs   */
+/* and the S-solution rule are those of the FP32 decoder; a solution's       */
+/* weight W sums the FP32 channel LLRs in FP64, as there.  Values are kept   */
+/* in doubles (every binary16 value is one), and a sum, difference or        */
+/* product of two binary16 values is exact in FP64, so rounding the FP64     */
+/* result once gives the correctly rounded binary16 operation.               */
+/* ------------------------------------------------------------------------ */
+
+/* Nearest binary16 value to x, ties to even (IEEE 754 roundTiesToEven), as
+ * a double: 11 significant bits for |x| >= 2^-14, a fixed quantum of 2^-24
+ * below (subnormals), infinity from 65520 = 65504 + half a unit up. */
+double ro_round_h16(double x) {
+    if (isnan(x)) return x;
+    double a = fabs(x);
+    if (a >= 65520.0) return copysign(INFINITY, x);
+    if (a == 0.0) return x;
+    int e;
+    frexp(a, &e);            /* a = m 2^e, m in [0.5, 1) */
+    int q = e - 11;          /* quantum of the binade [2^(e-1), 2^e) */
+    if (q < -24) q = -24;
+    double r = nearbyint(ldexp(a, -q));  /* default rounding mode: nearest, ties to even */
+    return copysign(ldexp(r, q), x);
+}
+
+static double clip_h(double x, double L) {
+    if (x > L) return L;
+    if (x < -L) return -L;
+    return x;
+}
+
+/* One DMem-BP iteration in binary16 (same steps as the FP32 iteration). */
+static void dmem_iteration_h16(const graph *g, const unsigned char *sigma, const double *gamma,
+                               const double *lam0, double *Lam, double *mu, double *nu,
+                               unsigned char *F, double L) {
+    for (int i = 0; i < g->M; ++i) {
+        for (int e = g->rowptr[i]; e < g->rowptr[i + 1]; ++e)
+            nu[e] = clip_h(ro_round_h16(Lam[g->col[e]] - mu[e]), L);
+        for (int e = g->rowptr[i]; e < g->rowptr[i + 1]; ++e) {
+            int negative = sigma[i] ? 1 : 0;
+            double mag = INFINITY;
+            for (int e2 = g->rowptr[i]; e2 < g->rowptr[i + 1]; ++e2) {
+                if (e2 == e) continue;
+                if (nu[e2] < 0) negative ^= 1;
+                if (fabs(nu[e2]) < mag) mag = fabs(nu[e2]);
+            }
+            mu[e] = clip_h(negative ? -mag : mag, L);
+        }
+    }
+    for (int j = 0; j < g->N; ++j) {
+        double one_minus = ro_round_h16(1.0 - gamma[j]);
+        double a = ro_round_h16(one_minus * lam0[j]);
+        double b = ro_round_h16(gamma[j] * clip_h(Lam[j], L));
+        double acc = clip_h(ro_round_h16(a + b), L);
+        for (int c = g->colptr[j]; c < g->colptr[j + 1]; ++c) acc = ro_round_h16(acc + mu[g->cedge[c]]);
+        Lam[j] = acc;
+        F[j] = acc < 0 ? 1 : 0;
+    }
+}
+
+/* Relay decoding in the binary16 mode; arguments as ro_decode_f32 (gamma1
+ * float [N] or NULL, rounded to binary16; final_llr as float, exact). */
+int ro_decode_h16(int M, int N, long nnz, const int *rows, const int *cols, const double *prior,
+                  const ro_params *prm, const float *gamma1, long B, const unsigned char *syn,
+                  unsigned char *corr, unsigned char *conv, int *legs, int *iters, double *weight,
+                  float *final_llr) {
+    if (prm->num_legs < 1 || prm->iters_first < 1 || prm->iters_leg < 1 || prm->num_solutions < 1)
+        return -5;
+    graph g;
+    int rc = graph_build(&g, M, N, nnz, rows, cols);
+    if (rc) return rc;
+    const double L = ro_round_h16(fmin(prm->llr_clip, 4096.0));
+    float *w32 = malloc(sizeof(float) * (size_t)N);
+    double *w16 = malloc(sizeof(double) * (size_t)N);
+    double *lam0 = malloc(sizeof(double) * (size_t)N);
+    double *Lam = malloc(sizeof(double) * (size_t)N);
+    double *mu = malloc(sizeof(double) * (size_t)(g.E ? g.E : 1));
+    double *nu = malloc(sizeof(double) * (size_t)(g.E ? g.E : 1));
+    double *gam = malloc(sizeof(double) * (size_t)N * (size_t)prm->num_legs);
+    unsigned char *F = malloc((size_t)N);
+    unsigned char *best = malloc((size_t)N);
+    for (int j = 0; j < N; ++j) {
+        double wd = log((1.0 - prior[j]) / prior[j]);
+        w32[j] = (float)wd;
+        w16[j] = ro_round_h16(wd);
+    }
+    for (int r = 1; r <= prm->num_legs; ++r)
+        for (int j = 0; j < N; ++j) {
+            float g32 = r == 1 ? (gamma1 ? gamma1[j] : prm->gamma_first)
+                               : ro_gamma_f32(prm->seed, r, j, prm->gamma_lo, prm->gamma_hi);
+            gam[(size_t)(r - 1) * N + j] = ro_round_h16((double)g32);
+        }
+    for (long b = 0; b < B; ++b) {
+        const unsigned char *sigma = syn + (size_t)b * M;
+        for (int j = 0; j < N; ++j) { Lam[j] = w16[j]; lam0[j] = w16[j]; }
+        for (int e = 0; e < g.E; ++e) mu[e] = 0;
+        int count = 0, total = 0, last_leg = 0, stop = 0;
+        double best_w = INFINITY;
+        for (int r = 1; r <= prm->num_legs && !stop; ++r) {
+            int T = (r == 1) ? prm->iters_first : prm->iters_leg;
+            if (r >= 2) {
+                for (int e = 0; e < g.E; ++e) mu[e] = 0;
+                for (int j = 0; j < N; ++j) lam0[j] = (prm->anchor == 0) ? clip_h(Lam[j], L) : w16[j];
+            }
+            const double *gr = gam + (size_t)(r - 1) * N;
+            for (int t = 1; t <= T; ++t) {
+                if (prm->max_total_iters > 0 && total >= prm->max_total_iters) { stop = 1; break; }
+                last_leg = r;
+                dmem_iteration_h16(&g, sigma, gr, lam0, Lam, mu, nu, F, L);
+                ++total;
+                if (syndrome_ok_f32(&g, sigma, F)) {
+                    ++count;
+                    double W = 0.0;
+                    for (int j = 0; j < N; ++j) if (F[j]) W += (double)w32[j];
+                    if (W < best_w) { best_w = W; memcpy(best, F, (size_t)N); }
+                    if (count >= prm->num_solutions) stop = 1;
+                    break;
+                }
+            }
+        }
+        unsigned char *out = corr + (size_t)b * N;
+        double W = best_w;
+        if (count > 0) {
+            memcpy(out, best, (size_t)N);
+        } else {
+            memcpy(out, F, (size_t)N);
+            W = 0.0;
+            for (int j = 0; j < N; ++j) if (F[j]) W += (double)w32[j];
+        }
+        conv[b] = count > 0 ? 1 : 0;
+        legs[b] = last_leg;
+        iters[b] = total;
+        if (weight) weight[b] = W;
+        if (final_llr)
+            for (int j = 0; j < N; ++j) final_llr[(size_t)b * N + j] = (float)Lam[j];
+    }
+    free(w32); free(w16); free(lam0); free(Lam); free(mu); free(nu); free(gam); free(F); free(best);
+    graph_free(&g);
+    return 0;
+}
+
+/* One leg in binary16 from the leg-1 initialisation for exactly T
+ * iterations with per-column gamma (float [N], rounded to binary16):
+ * trace[b][t][j] = Lambda_j(t) as float, t = 0..T. */
+int ro_trace_h16(int M, int N, long nnz, const int *rows, const int *cols, const double *prior,
+                 const float *gamma, int T, double llr_clip, long B, const unsigned char *syn,
+                 float *trace) {
+    graph g;
+    int rc = graph_build(&g, M, N, nnz, rows, cols);
+    if (rc) return rc;
+    const double L = ro_round_h16(fmin(llr_clip, 4096.0));
+    double *w = malloc(sizeof(double) * (size_t)N);
+    double *gm = malloc(sizeof(double) * (size_t)N);
+    double *Lam = malloc(sizeof(double) * (size_t)N);
+    double *mu = malloc(sizeof(double) * (size_t)(g.E ? g.E : 1));
+    double *nu = malloc(sizeof(double) * (size_t)(g.E ? g.E : 1));
+    unsigned char *F = malloc((size_t)N);
+    for (int j = 0; j < N; ++j) {
+        w[j] = ro_round_h16(log((1.0 - prior[j]) / prior[j]));
+        gm[j] = ro_round_h16((double)gamma[j]);
+    }
+    for (long b = 0; b < B; ++b) {
+        const unsigned char *sigma = syn + (size_t)b * M;
+        float *tr = trace + (size_t)b * (size_t)(T + 1) * N;
+        for (int j = 0; j < N; ++j) { Lam[j] = w[j]; tr[j] = (float)w[j]; }
+        for (int e = 0; e < g.E; ++e) mu[e] = 0;
+        for (int t = 1; t <= T; ++t) {
+            dmem_iteration_h16(&g, sigma, gm, w, Lam, mu, nu, F, L);
+            for (int j = 0; j < N; ++j) tr[(size_t)t * N + j] = (float)Lam[j];
+        }
+    }
+    free(w); free(gm); free(Lam); free(mu); free(nu); free(F);
+    graph_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sum-product BP (FP64), for exactness checks on trees.                     */
 /* Messages in the log-likelihood-ratio domain:                              */
 /*   check -> fault: mu = (-1)^sigma * 2 atanh(prod_{j'!=j} tanh(nu/2))      */
