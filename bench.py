@@ -5,8 +5,9 @@ Default workload (--workload dem, the headline): plain Relay-BP FP32 on the
 DEM-shaped synthetic 936 x 8785 matrix (13 rounds of 72 detectors, columns of
 weight 2-6, E = 27,617 edges, priors log-uniform in [1e-4, 1e-2]), 10^6
 syndromes per step already resident in HBM, T_1 = 80, T_r = 60, R = 20 legs,
-S = 1, memory strengths gamma_1 = 0.125 and U[-0.24, 0.66] after.  With the
-latency tail: completion and LER within FPGA-cycle budgets, epsilon(T_ref)
+S = 1, memory strengths gamma_1 = 0.125 and U[-0.24, 0.66] after; syndromes
+in and corrections out bit-packed in uint32 words (--io-layout bytes: one
+byte per entry).  With the latency tail: completion and LER within FPGA-cycle budgets, epsilon(T_ref)
 and the latency-tail condition.
 
 Other workloads:
@@ -364,11 +365,20 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     syn_np, (f_shots, f_cols) = sampling.sample_syndromes_sparse(prob, 0xDE3, shots)
     print(f"# dem {tag} inputs: {shots} shots, {f_shots.size} faults, "
           f"{time.perf_counter() - t_in:.1f} s", file=sys.stderr, flush=True)
-    dec = rb.Decoder.from_problem(prob, device=0, **RELAY_R20)
+    bits = args.io_layout == "bits32"
+    dec = rb.Decoder.from_problem(prob, device=0, **dict(RELAY_R20, io_layout=1 if bits else 0))
     if args.variant is not None:
         dec.set_variant(args.variant)
-    d_syn = torch.from_numpy(syn_np).to(dev)
+    d_syn = torch.from_numpy(rb.pack_bits(syn_np) if bits else syn_np).to(dev)
     out = dec.decode(d_syn)
+
+    def corr_bytes(s0, s1):
+        """Corrections of shots s0 .. s1 - 1 as uint8 [s1 - s0, N] on the device."""
+        c = out["corr"][s0:s1]
+        if not bits:
+            return c
+        sh = torch.arange(32, device=dev, dtype=torch.int32)
+        return ((c[:, :, None] >> sh) & 1).reshape(c.shape[0], -1)[:, :N].to(torch.uint8)
 
     def step(ev):
         if ev is not None:
@@ -386,8 +396,8 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     lds_b = lds_bytes_per_edge_update_large(M, N, E) if two_gross else lds_bytes_per_edge_update(M, N, E)
     roof, lds = roofline(kernel, kernel_ms, iters_launch * ops_per_iteration(M, N, E), iters_launch * E, lds_b,
                          stored_traffic(f"{kernel}_dem{tag}_hbm_traffic.txt"))
-    # logical failures on the GPU, so that the 8.8 GB correction array stays in
-    # HBM: A (F xor F_hat) = A F xor A F_hat over GF(2).
+    # logical failures on the GPU, so that the correction array stays in HBM:
+    # A (F xor F_hat) = A F xor A F_hat over GF(2).
     a = torch.from_numpy(prob.logical.astype(np.float32)).to(dev)
     af = torch.zeros((shots, a.shape[0]), dtype=torch.int32, device=dev)
     d_fs = torch.from_numpy(f_shots).to(dev)
@@ -398,7 +408,7 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     fail = torch.zeros(shots, dtype=torch.bool, device=dev)
     chunk = 50000
     for s0 in range(0, shots, chunk):
-        ah = torch.round(out["corr"][s0:s0 + chunk].float() @ a.T).to(torch.int32)
+        ah = torch.round(corr_bytes(s0, s0 + chunk).float() @ a.T).to(torch.int32)
         fail[s0:s0 + chunk] = ((ah + af[s0:s0 + chunk]) % 2).any(1)
     fail |= out["conv"] == 0
     k = int(fail.sum().item())
@@ -409,7 +419,7 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
         def decode_sample(n, threads):
             ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n],
                                 threads=threads)
-            return bool(np.array_equal(ref["corr"], out["corr"][:n].cpu().numpy())
+            return bool(np.array_equal(ref["corr"], corr_bytes(0, n).cpu().numpy())
                         and np.array_equal(ref["iters"], iters[:n])
                         and np.array_equal(ref["legs"], out["legs"][:n].cpu().numpy())
                         and np.array_equal(ref["conv"], conv[:n]))
@@ -417,12 +427,12 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
         n_cpu = min(args.cpu_sample or (200 if two_gross else 20000), shots)
         cpu = oracle_baseline(decode_sample, n_cpu, max(1, n_cpu // (16 if two_gross else 40)), shots,
                               "syndromes")
-    e2e = end_to_end(torch, dec, syn_np, out) if not two_gross else None
+    e2e = end_to_end(torch, dec, rb.pack_bits(syn_np) if bits else syn_np, out) if not two_gross else None
     line = head(args, shots * args.steps / elapsed, elapsed, {
         "workload": f"relay_bp_dem_{tag}", "matrix": f"DEM-shaped synthetic {tag}",
         "edges": E, "shots": shots, "T_first": 80, "T_leg": 60, "legs": 20, "solutions": 1,
         "gamma_first": 0.125, "gamma_range": [-0.24, 0.66], "anchor": "chain",
-        "parallelism": "single_gpu"})
+        "io_layout": args.io_layout, "parallelism": "single_gpu"})
     # latency tail (Sec. 7.2): completion within FPGA-cycle budgets (2 cycles
     # per iteration), LER at each budget, epsilon(T_ref = 500 cycles), and the
     # latency-tail condition for T_gen = 1000 cycles and C = 10 code blocks
@@ -803,6 +813,9 @@ def main():
                     help="oracle sample: syndromes per p (bb144) or in total (dem)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--io-layout", choices=["bits32", "bytes"], default="bits32",
+                    help="dem, dem-2gross: syndromes in and corrections out bit-packed in uint32 words "
+                         "(default) or one byte per entry")
     ap.add_argument("--schedule", choices=["per-p", "per-p-lpt", "mixed"], default="mixed",
                     help="bb144 only.  per-p: one launch per p in input order; per-p-lpt: one "
                          "launch per p, shots longest-first; mixed: all four p in one launch "

@@ -60,6 +60,15 @@ typedef enum {
     RB_E_INTERNAL = 10        /* the library's own tables failed a consistency check */
 } rb_status;
 
+/* Layout of syndromes and corrections in device memory (rb_params.io_layout).
+ * BYTES: one uint8 per check / fault, nonzero = 1 (syndromes; corrections are
+ * written as 0 / 1).  BITS32: bit-packed uint32 words, W_M = ceil(M / 32) per
+ * syndrome and W_N = ceil(N / 32) per correction, entry k in bit (k mod 32) of
+ * word floor(k / 32); input bits past M in the last word are ignored, output
+ * bits past N are written as 0.  Per-shot flags, counts, weights and
+ * marginals keep their layouts. */
+enum { RB_IO_BYTES = 0, RB_IO_BITS32 = 1 };
+
 /* Anchor of the memory term in legs r >= 2 (leg 1 always uses w_j). */
 enum { RB_ANCHOR_CHAIN = 0, /* lambda^{(r)}(0) = clip(Lambda^{(r-1)}(T_{r-1})), paper Sec. 2.3 */
        RB_ANCHOR_PRIOR = 1  /* lambda^{(r)}(0) = w_j = log((1-p_j)/p_j) in every leg */ };
@@ -77,11 +86,16 @@ enum { RB_ANCHOR_CHAIN = 0, /* lambda^{(r)}(0) = clip(Lambda^{(r-1)}(T_{r-1})), 
  *                   Philox4x32-10 (key = seed, counter = (floor(j/4), r, 0, 0), word j mod 4,
  *                   u = (word >> 8) 2^-24); the same Gamma_r for every shot
  *   llr_clip        L > 0: messages, marginals and the memory term saturate to [-L, L]
+ *                   (an FP32 value, like the messages)
  *   seed            64-bit Philox key for the memory strengths
  *   anchor          RB_ANCHOR_CHAIN or RB_ANCHOR_PRIOR
  *   max_total_iters total iteration cutoff per shot across legs (0 = none); a shot
  *                   that reaches it without S solutions stops (paper Sec. 7: runs
  *                   past the cycle cutoff count as failures)
+ *   io_layout       RB_IO_BYTES or RB_IO_BITS32: layout of the syndromes and
+ *                   corrections that rb_decode, rb_decode_multi(_noalloc),
+ *                   rb_autotune(_multi) and rb_syndrome take and return (rb_trace
+ *                   and the training calls always take uint8 syndromes)
  */
 typedef struct {
     int32_t num_legs;
@@ -95,6 +109,7 @@ typedef struct {
     uint64_t seed;
     int32_t anchor;
     int32_t max_total_iters;
+    int32_t io_layout;
 } rb_params;
 
 /* Kernel configuration chosen for a context (read-only diagnostics). */
@@ -114,7 +129,8 @@ typedef struct {
 
 /* Fills *out with the paper's parameters (R = 301 legs in total, T_1 = 80,
  * T_r = 60, S = 1, gamma_0 = 0.125, gamma in [-0.24, 0.66], L = 2^64,
- * anchor CHAIN, no cutoff, seed 0x52454C4159).  RB_E_INVALID_ARG if out is NULL. */
+ * anchor CHAIN, no cutoff, seed 0x52454C4159, RB_IO_BYTES).  RB_E_INVALID_ARG if
+ * out is NULL. */
 rb_status rb_params_default(rb_params *out);
 
 /*
@@ -148,9 +164,10 @@ void rb_destroy(rb_ctx *ctx);
 /*
  * Relay-decodes B syndromes (paper Sec. 2.3: Relay decoding, convergence
  * criterion, Relay chaining).
- *   d_syndromes  uint8 [B][M], nonzero = 1
- *   d_corr       uint8 [B][N] out: the lowest-weight converged solution, or the
- *                last hard decision (F_hat_j = 1 iff Lambda_j < 0) if no leg converged
+ *   d_syndromes  uint8 [B][M], nonzero = 1 (RB_IO_BITS32: uint32 [B][W_M])
+ *   d_corr       uint8 [B][N] out (RB_IO_BITS32: uint32 [B][W_N]): the lowest-weight
+ *                converged solution, or the last hard decision (F_hat_j = 1 iff
+ *                Lambda_j < 0) if no leg converged
  *   d_conv       uint8 [B] out: 1 iff at least one leg converged (H F_hat = sigma)
  *   d_legs       int32 [B] out: index (1-based) of the last leg started
  *   d_iters      int32 [B] out: iterations executed over all legs
@@ -180,9 +197,10 @@ rb_status rb_trace(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, const flo
 /*
  * Syndrome of a batch of corrections over F_2 (the decoding problem of paper
  * Sec. 2.1: sigma = H F), optionally added to a given syndrome:
- *   d_corr      uint8 [B][N], nonzero = 1 (device)
- *   d_syn_in    uint8 [B][M] or NULL (device); NULL reads as all zero
- *   d_syn_out   uint8 [B][M] out (device): d_syn_in XOR (H d_corr mod 2); may
+ *   d_corr      uint8 [B][N], nonzero = 1 (device; RB_IO_BITS32: uint32 [B][W_N])
+ *   d_syn_in    uint8 [B][M] or NULL (device; RB_IO_BITS32: uint32 [B][W_M]); NULL
+ *               reads as all zero
+ *   d_syn_out   out (device), layout of d_syn_in: d_syn_in XOR (H d_corr mod 2); may
  *               alias d_syn_in
  * Windowed decoding uses it to pass the residual syndrome of committed faults
  * to the next window; it also checks corrections.  Enqueues on `stream`; no
@@ -254,7 +272,7 @@ rb_status rb_plan_check(int32_t M, int32_t N, int64_t nnz, const int32_t *rows, 
 
 /*
  * Measures every built-in kernel configuration the graph fits on B syndromes
- * (d_syndromes, uint8 [B][M] on the device), `reps` timed launches each after
+ * (d_syndromes on the device, in the context's io_layout), `reps` timed launches each after
  * one warm-up, and keeps the fastest for later decodes.  Results do not
  * depend on the configuration (only speed does).  Allocates scratch outputs,
  * uses the null stream and synchronises the device: call it once after
@@ -305,7 +323,9 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
  *                list); a shot with an id outside [0, n_codes) is skipped and its
  *                outputs are left untouched
  *   d_syndromes  uint8 [B][M_max]: row b holds the code's M syndrome bits first
- *   d_corr       uint8 [B][N_max] out (first N entries of row b are meaningful);
+ *                (RB_IO_BITS32: uint32 [B][ceil(M_max / 32)], the code's bits first)
+ *   d_corr       uint8 [B][N_max] out (first N entries of row b are meaningful;
+ *                RB_IO_BITS32: uint32 [B][ceil(N_max / 32)], the first N bits);
  *   d_conv, d_legs, d_iters, d_weight, d_final_llr ([B][N_max]) as in rb_decode
  *   d_workspace  device buffer of at least rb_workspace_size(ctx, B) bytes, owned
  *                by the caller, not used concurrently by another call
@@ -350,7 +370,8 @@ int64_t rb_noalloc_max_batch(const rb_ctx *ctx);
 /*
  * Autotunes a mixed context: for every code k with sample_b[k] > 0, times each
  * tile of the mixed kernel that fits the code on d_samples[k] (uint8
- * [sample_b[k]][M_k], device) and keeps the fastest.  chosen_variants
+ * [sample_b[k]][M_k], or uint32 [sample_b[k]][ceil(M_k / 32)] under
+ * RB_IO_BITS32; device) and keeps the fastest.  chosen_variants
  * (nullable, int32 [n_codes]) receives the configuration kept per code.
  * Allocates scratch and synchronises the device.
  */

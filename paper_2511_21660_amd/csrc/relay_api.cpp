@@ -1508,6 +1508,8 @@ rb_status check_params(const rb_params *p) {
     if (p->gamma_lo > p->gamma_hi) return fail(RB_E_INVALID_ARG, "gamma_lo > gamma_hi");
     if (!std::isfinite(p->llr_clip) || !(p->llr_clip > 0.0f))
         return fail(RB_E_INVALID_ARG, "llr_clip must be finite and > 0");
+    if (p->io_layout != RB_IO_BYTES && p->io_layout != RB_IO_BITS32)
+        return fail(RB_E_INVALID_ARG, "io_layout must be RB_IO_BYTES or RB_IO_BITS32");
     return RB_OK;
 }
 
@@ -1636,6 +1638,7 @@ rb_status rb_params_default(rb_params *out) {
     out->seed = 0x52454C4159ull;
     out->anchor = RB_ANCHOR_CHAIN;
     out->max_total_iters = 0;
+    out->io_layout = RB_IO_BYTES;
     return RB_OK;
 }
 
@@ -1751,8 +1754,10 @@ static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     rb::GroupArgs a{};
     a.M = c->M;
     a.N = c->N;
-    a.syn_stride = c->M;
-    a.corr_stride = c->N;
+    a.io_bits = c->params.io_layout == RB_IO_BITS32 ? 1 : 0;
+    a.syn_stride = a.io_bits ? (c->M + 31) / 32 : c->M;
+    a.corr_stride = a.io_bits ? (c->N + 31) / 32 : c->N;
+    a.llr_stride = c->N;
     a.B = B;
     a.count = B;
     a.list = nullptr;
@@ -1780,6 +1785,9 @@ static rb::BlockArgs block_args(const rb::GroupArgs &g, const rb_ctx *c) {
     rb::BlockArgs b{};
     b.M = g.M;
     b.N = g.N;
+    b.syn_stride = g.syn_stride;
+    b.corr_stride = g.corr_stride;
+    b.io_bits = g.io_bits;
     b.B = g.B;
     b.syn = g.syn;
     b.corr = g.corr;
@@ -1822,6 +1830,9 @@ static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
     rb::LargeArgs b{};
     b.M = g.M;
     b.N = g.N;
+    b.syn_stride = g.syn_stride;
+    b.corr_stride = g.corr_stride;
+    b.io_bits = g.io_bits;
     b.B = g.B;
     b.syn = g.syn;
     b.corr = g.corr;
@@ -1909,7 +1920,8 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
         // longest-first order: shot list sorted by decreasing syndrome weight
         hipStream_t s = (hipStream_t)stream;
         RB_HIP(hipSetDevice(c->device), "hipSetDevice");
-        RB_HIP(rb::launch_shot_lists(B, d_syn, c->M, nullptr, c->d_code_m, 1, nullptr, 1, c->d_ws, c->d_queue, s),
+        RB_HIP(rb::launch_shot_lists(B, d_syn, a.syn_stride, a.io_bits != 0, nullptr, c->d_code_m, 1, nullptr, 1,
+                                     c->d_ws, c->d_queue, s),
                "shot list kernels");
         a.list = (const int32_t *)c->d_ws + (size_t)(rb::kListHeader + B);
         RB_HIP(rb::launch_group(c->variant, c->params.anchor == RB_ANCHOR_PRIOR, false, a,
@@ -1931,7 +1943,7 @@ rb_status rb_syndrome(const rb_ctx *c, int64_t B, const uint8_t *d_corr, const u
     if (B > INT64_MAX / ((int64_t)c->M + 1)) return fail(RB_E_SHAPE, "B * M overflows");
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(rb::launch_syndrome(B, c->M, c->N, c->d_rowptr, c->d_colidx, d_corr, d_syn_in, d_syn_out,
-                               (hipStream_t)stream),
+                               c->params.io_layout == RB_IO_BITS32, (hipStream_t)stream),
            "syndrome kernel launch");
     return RB_OK;
 }
@@ -1946,6 +1958,9 @@ rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_ga
     if (B == 0) return RB_OK;
     if (!d_syn || !d_gamma || !d_trace) return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
     rb::GroupArgs a = base_args(c, B, d_syn);
+    a.io_bits = 0;  // the trace hook takes uint8 syndromes in either layout
+    a.syn_stride = c->M;
+    a.corr_stride = c->N;
     a.trace_gamma = d_gamma;
     a.scale = scale;
     a.trace_T = T;
@@ -2105,7 +2120,8 @@ static rb_status time_variant(rb_ctx *c, int64_t B, const uint8_t *d_syn, int32_
         if (e1) (void)hipEventDestroy(e1);
     };
     hipError_t e;
-    if ((e = hipMalloc(&corr, (size_t)B * c->N)) != hipSuccess || (e = hipMalloc(&conv, (size_t)B)) != hipSuccess ||
+    const size_t corr_row = std::max<size_t>((size_t)c->N, 4 * (((size_t)c->N + 31) / 32));  // either layout
+    if ((e = hipMalloc(&corr, (size_t)B * corr_row)) != hipSuccess || (e = hipMalloc(&conv, (size_t)B)) != hipSuccess ||
         (e = hipMalloc(&legs, (size_t)B * 4)) != hipSuccess || (e = hipMalloc(&iters, (size_t)B * 4)) != hipSuccess ||
         (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
         cleanup();
@@ -2149,7 +2165,8 @@ rb_status rb_autotune(rb_ctx *c, int64_t B, const uint8_t *d_syn, int32_t reps,
         if (e1) (void)hipEventDestroy(e1);
     };
     hipError_t e;
-    if ((e = hipMalloc(&corr, (size_t)B * c->N)) != hipSuccess || (e = hipMalloc(&conv, (size_t)B)) != hipSuccess ||
+    const size_t corr_row = std::max<size_t>((size_t)c->N, 4 * (((size_t)c->N + 31) / 32));  // either layout
+    if ((e = hipMalloc(&corr, (size_t)B * corr_row)) != hipSuccess || (e = hipMalloc(&conv, (size_t)B)) != hipSuccess ||
         (e = hipMalloc(&legs, (size_t)B * 4)) != hipSuccess || (e = hipMalloc(&iters, (size_t)B * 4)) != hipSuccess ||
         (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
         cleanup();
@@ -2420,13 +2437,16 @@ static rb_status launch_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code
                                      double *d_weight, float *d_final_llr, void *ws_bytes,
                                      unsigned long long *queues, hipStream_t s) {
     const int nc = (int)c->subs.size();
-    RB_HIP(rb::launch_shot_lists(B, d_syn, c->m_max, d_code_id, c->d_code_m, nc, c->d_code_fam, c->nfam,
+    const bool bits = c->params.io_layout == RB_IO_BITS32;
+    const int32_t syn_stride = bits ? (c->m_max + 31) / 32 : c->m_max;
+    RB_HIP(rb::launch_shot_lists(B, d_syn, syn_stride, bits, d_code_id, c->d_code_m, nc, c->d_code_fam, c->nfam,
                                  ws_bytes, queues, s),
            "shot list kernels");
     rb::MixedArgs m{};
     m.run = base_args(c->subs[0], B, d_syn);
-    m.run.syn_stride = c->m_max;
-    m.run.corr_stride = c->n_max;
+    m.run.syn_stride = syn_stride;
+    m.run.corr_stride = bits ? (c->n_max + 31) / 32 : c->n_max;
+    m.run.llr_stride = c->n_max;
     m.run.corr = d_corr;
     m.run.conv = d_conv;
     m.run.legs = d_legs;

@@ -137,7 +137,7 @@ void relay_block_kernel(BlockArgs a) {
         count = 0;
         best_w = __longlong_as_double(0x7ff0000000000000ll);
         best_mask = 0;
-        sig = myrow >= 0 && a.syn[(size_t)shot * a.M + myrow] != 0;
+        sig = myrow >= 0 && syn_bit(a.syn, (size_t)shot, a.syn_stride, myrow, a.io_bits);
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const uint32_t sl = tl + TPB * v;
@@ -313,10 +313,31 @@ void relay_block_kernel(BlockArgs a) {
                         const uint32_t sl = tl + TPB * v;
                         const int j = jv[v];
                         if (j >= 0) {
-                            a.corr[(size_t)shot * a.N + j] = (uint8_t)((out >> v) & 1u);
+                            if (!a.io_bits) a.corr[(size_t)shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
                             if (a.final_llr)
                                 a.final_llr[(size_t)shot * a.N + j] = lds_b<float>(4u * sl);
                         }
+                    }
+                    if (a.io_bits) {
+                        // slots hold faults in degree order, so the packed words are
+                        // assembled in LDS: the first ceil(N/32) words of the Lambda
+                        // region (read above for the marginals; the next fetch
+                        // rewrites every Lambda word) are cleared, each fault ORs its
+                        // bit into word j / 32, and the words go out coalesced
+                        const int nw = (a.N + 31) >> 5;
+                        __syncthreads();
+                        for (int q = t; q < nw; q += TPB) lds_b<uint32_t>(4u * (uint32_t)q) = 0u;
+                        __syncthreads();
+#pragma unroll
+                        for (int v = 0; v < VPT; ++v) {
+                            const int j = jv[v];
+                            if (j >= 0 && ((out >> v) & 1u))
+                                __hip_atomic_fetch_or(&lds_b<uint32_t>(4u * (uint32_t)(j >> 5)), 1u << (j & 31),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        __syncthreads();
+                        uint32_t *c32 = reinterpret_cast<uint32_t *>(a.corr) + (size_t)shot * a.corr_stride;
+                        for (int q = t; q < nw; q += TPB) c32[q] = lds_b<uint32_t>(4u * (uint32_t)q);
                     }
                     if (t == 0) {
                         a.conv[shot] = count > 0 ? 1 : 0;

@@ -28,14 +28,25 @@ constexpr int kQueueSplit = 8;
 constexpr int kQueueStride = 32;
 constexpr int kQueueWords = kQueueSplit * kQueueStride;
 
+// Bit-packed I/O (RB_IO_BITS32): syndromes and corrections as uint32 words,
+// entry k in bit k % 32 of word k / 32.  The kernels read a syndrome bit
+// with syn_bit and the strides below count elements of the layout in use
+// (bytes, or words when io_bits is set).
+__device__ __forceinline__ bool syn_bit(const void *syn, size_t row, int32_t stride, int i, bool bits) {
+    if (bits) return (static_cast<const uint32_t *>(syn)[row * stride + (i >> 5)] >> (i & 31)) & 1u;
+    return static_cast<const uint8_t *>(syn)[row * stride + i] != 0;
+}
+
 struct GroupArgs {
     int32_t M, N;
-    int32_t syn_stride, corr_stride;  // bytes per syndrome row, entries per correction row
+    int32_t syn_stride, corr_stride;  // elements (bytes or words) per syndrome / correction row
+    int32_t llr_stride;               // floats per marginal row
+    int32_t io_bits;                  // 1: bit-packed syndromes and corrections
     int64_t B;
     int64_t count;        // queue positions to decode
     const int32_t *list;  // [count] shot of queue position k, or null (shot = k)
     const uint8_t *syn;   // [B][syn_stride]
-    uint8_t *corr;        // [B][N]
+    uint8_t *corr;        // [B][corr_stride]
     uint8_t *conv;        // [B]
     int32_t *legs;        // [B]
     int32_t *iters;       // [B]
@@ -105,6 +116,8 @@ constexpr int kBlockChunk = 8;
 
 struct BlockArgs {
     int32_t M, N;
+    int32_t syn_stride, corr_stride;  // elements (bytes or words) per syndrome / correction row
+    int32_t io_bits;                  // 1: bit-packed syndromes and corrections
     int64_t B;
     const uint8_t *syn;
     uint8_t *corr;
@@ -133,6 +146,13 @@ struct BlockArgs {
     float scale;
     int32_t trace_T;
     float *trace;
+    // binary16 mode (relay_block16_kernel): w and Gamma by slot as binary16
+    // bits, the clip L as binary16 bits, and an LDS region of ceil(TPB*VPT/32)
+    // words where packed corrections are assembled
+    const uint16_t *w16_slot;      // [TPB*VPT]
+    const uint16_t *gamma16_slot;  // [R][TPB*VPT]
+    uint32_t L16;
+    uint32_t stage_off;
 };
 
 // Largest static LDS of a variant's kernels.  The kernels address LDS by
@@ -152,6 +172,19 @@ hipError_t launch_gather_slots(const float *src, int64_t src_stride, const int32
 hipError_t launch_block(int v, bool prior_anchor, bool trace, const BlockArgs &a, int grid,
                         size_t lds, hipStream_t s);
 
+// The binary16 block kernel (two syndromes per workgroup, one in each half of
+// every LDS word and register): configuration v has the shape of block
+// variant v.
+int num_block16_variants();
+BlockShape block16_variant_shape(int v);
+hipError_t block16_static_lds(int v, size_t *bytes);
+hipError_t block16_variant_occupancy(int v, bool prior_anchor, bool trace, size_t lds, int *blocks);
+hipError_t block16_prepare(int v, size_t lds);
+hipError_t launch_block16(int v, bool prior_anchor, bool trace, const BlockArgs &a, int grid, size_t lds,
+                          hipStream_t s);
+// dst[k] = binary16 bits of src[k] (round to nearest even), k < n
+hipError_t launch_to_half(const float *src, int64_t n, uint16_t *dst, hipStream_t s);
+
 // Shape of a large-graph configuration: TPB threads decode one syndrome;
 // thread t owns faults t + TPB*v (v < VR) and up to kLargeRounds checks.
 struct LargeShape {
@@ -166,6 +199,8 @@ constexpr int kLargeSure = 6;         // fault entries read whatever the degree 
 
 struct LargeArgs {
     int32_t M, N;
+    int32_t syn_stride, corr_stride;  // elements (bytes or words) per syndrome / correction row
+    int32_t io_bits;                  // 1: bit-packed syndromes and corrections
     int64_t B;
     const uint8_t *syn;
     uint8_t *corr;
@@ -248,8 +283,10 @@ hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_f
                               float hi, hipStream_t s);
 hipError_t launch_reset_queue(unsigned long long *q, hipStream_t s);
 // syn_out[b][i] = (syn_in ? syn_in[b][i] : 0) XOR parity of corr[b][j] over row i (CSR rowptr / colidx)
+// (bits: corr, syn_in and syn_out bit-packed, ceil(N/32) and ceil(M/32) words per shot)
 hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowptr, const int32_t *colidx,
-                           const uint8_t *corr, const uint8_t *syn_in, uint8_t *syn_out, hipStream_t s);
+                           const uint8_t *corr, const uint8_t *syn_in, uint8_t *syn_out, bool bits,
+                           hipStream_t s);
 // Builds per-code shot lists in `workspace` (shot_list_bytes(B, ncodes) bytes):
 // positions sorted by (family, decreasing syndrome weight), the family of
 // code c being code_fam[c] (identity when code_fam is null); the list of
@@ -257,7 +294,8 @@ hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowpt
 // zeroes the per-family queue counters.  Layout (sized for ncodes >= nfam):
 // hist[ncodes*256], seg_start[ncodes], seg_count[ncodes], order[ncodes],
 // key[B], list[B] (int32).
-hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
+// (syn_stride in elements of the layout: bytes, or words when bits is set)
+hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, bool bits, const int32_t *code_id,
                              const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam,
                              void *workspace, unsigned long long *queues, hipStream_t s);
 size_t shot_list_bytes(int64_t B, int ncodes);

@@ -280,10 +280,9 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         best_w = __longlong_as_double(0x7ff0000000000000ll);  // +inf
         best_mask = 0;
         sig = 0;
-        const uint8_t *s = a.syn + (size_t)shot * a.syn_stride;
-        uint8_t sb[CPT];
+        bool sb[CPT];
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) sb[c] = s[min((int)gl + G * c, a.M - 1)];
+        for (int c = 0; c < CPT; ++c) sb[c] = syn_bit(a.syn, (size_t)shot, a.syn_stride, min((int)gl + G * c, a.M - 1), a.io_bits);
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int i = (int)gl + G * c;
@@ -414,12 +413,32 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                     uint32_t fm = 0;
                     const double Wlast = count > 0 ? best_w : weight_of(fm);
                     const uint32_t out = count > 0 ? best_mask : fm;
+                    if (a.io_bits) {
+                        // word q of the packed correction holds faults 32q .. 32q+31;
+                        // lane g of the slot assembles word g (ceil(N/32) <= G words,
+                        // as N <= G * VPT and VPT <= 32) from one ballot per fault
+                        // round v, whose slot bits are faults G*v .. G*v+G-1
+                        uint32_t word = 0;
 #pragma unroll
-                    for (int v = 0; v < VPT; ++v) {
-                        const int j = (int)gl + G * v;
-                        if (j < a.N) {
-                            a.corr[(size_t)shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
-                            if (a.final_llr) a.final_llr[(size_t)shot * a.corr_stride + j] = Lr[v];
+                        for (int v = 0; v < VPT; ++v) {
+                            const unsigned long long bal = __ballot((out >> v) & 1u);
+                            const unsigned long long sb = G == 64 ? bal : (bal >> (slot * G)) & ((1ull << (G % 64)) - 1ull);
+                            const int d = G * v - 32 * (int)gl;  // bit of word gl where fault G*v lands
+                            if (d > -64 && d < 32) word |= (uint32_t)(d >= 0 ? sb << d : sb >> -d);
+                        }
+                        if ((int)gl * 32 < a.N) reinterpret_cast<uint32_t *>(a.corr)[(size_t)shot * a.corr_stride + gl] = word;
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VPT; ++v) {
+                            const int j = (int)gl + G * v;
+                            if (j < a.N) a.corr[(size_t)shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
+                        }
+                    }
+                    if (a.final_llr) {
+#pragma unroll
+                        for (int v = 0; v < VPT; ++v) {
+                            const int j = (int)gl + G * v;
+                            if (j < a.N) a.final_llr[(size_t)shot * a.llr_stride + j] = Lr[v];
                         }
                     }
                     if (g == 0) {
@@ -522,15 +541,23 @@ __global__ void list_zero_kernel(int32_t *p, int n, unsigned long long *queues, 
 constexpr int kListThreads = 256;
 
 // Key of shot b: family-major, then decreasing syndrome weight (bin), or -1.
-__device__ __forceinline__ int shot_key(int64_t b, const uint8_t *syn, int32_t syn_stride,
+__device__ __forceinline__ int shot_key(int64_t b, const uint8_t *syn, int32_t syn_stride, bool bits,
                                         const int32_t *code_id, const int32_t *code_m, int ncodes,
                                         const int32_t *code_fam) {
     const int c = code_id ? code_id[b] : 0;
     if (c < 0 || c >= ncodes) return -1;  // invalid code id: shot skipped, outputs untouched
     const int m = code_m[c];
-    const uint8_t *s = syn + (size_t)b * syn_stride;
     int wgt = 0;
-    for (int i = 0; i < m; ++i) wgt += s[i] != 0;
+    if (bits) {
+        const uint32_t *s = reinterpret_cast<const uint32_t *>(syn) + (size_t)b * syn_stride;
+        for (int q = 0; q * 32 < m; ++q) {
+            const int left = m - 32 * q;  // bits of word q inside the code's M
+            wgt += __popc(left >= 32 ? s[q] : s[q] & ((1u << left) - 1u));
+        }
+    } else {
+        const uint8_t *s = syn + (size_t)b * syn_stride;
+        for (int i = 0; i < m; ++i) wgt += s[i] != 0;
+    }
     const int f = code_fam ? code_fam[c] : c;
     return f * kWeightBins + (kWeightBins - 1 - min(wgt, kWeightBins - 1));
 }
@@ -538,14 +565,14 @@ __device__ __forceinline__ int shot_key(int64_t b, const uint8_t *syn, int32_t s
 // Block-local histogram in LDS (dynamic LDS: nbins words), then one global
 // atomic per nonzero (block, bin).
 __global__ __launch_bounds__(kListThreads) void list_key_kernel(
-        int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
+        int64_t B, const uint8_t *syn, int32_t syn_stride, bool bits, const int32_t *code_id,
         const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam, int32_t *key, int32_t *hist) {
     const int nb = nfam * kWeightBins;
     for (int k = threadIdx.x; k < nb; k += kListThreads) *(__attribute__((address_space(3))) int32_t *)(size_t)(4u * k) = 0;
     __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * kListThreads + threadIdx.x;
     if (b < B) {
-        const int k = shot_key(b, syn, syn_stride, code_id, code_m, ncodes, code_fam);
+        const int k = shot_key(b, syn, syn_stride, bits, code_id, code_m, ncodes, code_fam);
         key[b] = k;
         if (k >= 0)
             __hip_atomic_fetch_add((__attribute__((address_space(3))) int32_t *)(size_t)(4u * k), 1,
@@ -678,6 +705,28 @@ __global__ __launch_bounds__(256) void syndrome_kernel(int64_t B, int32_t M, int
     syn_out[idx] = (uint8_t)par;
 }
 
+// The same on bit-packed rows: one thread per (shot, syndrome word), the 32
+// checks of word q (bits past M are written as 0).
+__global__ __launch_bounds__(256) void syndrome_bits_kernel(int64_t B, int32_t M, int32_t N, const int32_t *rowptr,
+                                                            const int32_t *colidx, const uint32_t *corr,
+                                                            const uint32_t *syn_in, uint32_t *syn_out) {
+    const int32_t WM = (M + 31) / 32, WN = (N + 31) / 32;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * (int64_t)WM) return;
+    const int64_t b = idx / WM;
+    const int q = (int)(idx % WM);
+    const uint32_t *f = corr + (size_t)b * WN;
+    uint32_t word = 0;
+    for (int k = 0; k < 32 && 32 * q + k < M; ++k) {
+        const int i = 32 * q + k;
+        uint32_t par = 0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) par ^= (f[colidx[e] >> 5] >> (colidx[e] & 31)) & 1u;
+        word |= par << k;
+    }
+    if (syn_in) word ^= syn_in[idx] & (32 * q + 32 <= M ? 0xffffffffu : (1u << (M - 32 * q)) - 1u);
+    syn_out[idx] = word;
+}
+
 }  // namespace
 
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
@@ -749,7 +798,7 @@ hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_f
     return hipGetLastError();
 }
 
-hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, const int32_t *code_id,
+hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, bool bits, const int32_t *code_id,
                              const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam,
                              void *workspace, unsigned long long *queues, hipStream_t s) {
     int32_t *hist = (int32_t *)workspace;                       // ncodes * bins
@@ -762,7 +811,7 @@ hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, 
     hipLaunchKernelGGL(list_zero_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, hist, nh, queues, nfam);
     const int blocks = (int)((B + kListThreads - 1) / kListThreads);
     hipLaunchKernelGGL(list_key_kernel, dim3(blocks), dim3(kListThreads), 4u * (size_t)nh, s, B, syn, syn_stride,
-                       code_id, code_m, ncodes, code_fam, nfam, key, hist);
+                       bits, code_id, code_m, ncodes, code_fam, nfam, key, hist);
     hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, nfam, hist, seg_start, seg_count, order);
     hipLaunchKernelGGL(list_scatter_kernel, dim3(blocks), dim3(kListThreads), 8u * (size_t)nh, s, B, nh, key, hist,
                        list);
@@ -774,7 +823,16 @@ size_t shot_list_bytes(int64_t B, int ncodes) {
 }
 
 hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowptr, const int32_t *colidx,
-                           const uint8_t *corr, const uint8_t *syn_in, uint8_t *syn_out, hipStream_t s) {
+                           const uint8_t *corr, const uint8_t *syn_in, uint8_t *syn_out, bool bits,
+                           hipStream_t s) {
+    if (bits) {
+        const int64_t n = B * (int64_t)((M + 31) / 32);
+        if (n == 0) return hipSuccess;
+        hipLaunchKernelGGL(syndrome_bits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B, M, N, rowptr,
+                           colidx, reinterpret_cast<const uint32_t *>(corr),
+                           reinterpret_cast<const uint32_t *>(syn_in), reinterpret_cast<uint32_t *>(syn_out));
+        return hipGetLastError();
+    }
     const int64_t n = B * (int64_t)M;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(syndrome_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B, M, N, rowptr, colidx,

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         sig = 0;
 #pragma unroll
         for (int c = 0; c < kLargeRounds; ++c)
-            if (ci[c] >= 0 && a.syn[(size_t)shot * a.M + ci[c]] != 0) sig |= 1u << c;
+            if (ci[c] >= 0 && syn_bit(a.syn, (size_t)shot, a.syn_stride, ci[c], a.io_bits)) sig |= 1u << c;
 #pragma unroll
         for (int v = 0; v < VR; ++v) {
             const int j = (int)tl + TPB * v;
@@ -280,8 +280,22 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                     for (int v = 0; v < VR; ++v) {
                         const int j = (int)tl + TPB * v;
                         if (j < N) {
-                            a.corr[(size_t)shot * N + j] = (uint8_t)((out >> v) & 1u);
+                            if (!a.io_bits) a.corr[(size_t)shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
                             if (a.final_llr) a.final_llr[(size_t)shot * N + j] = lds_b<float>(4u * (uint32_t)j);
+                        }
+                    }
+                    if (a.io_bits) {
+                        // fault j = t + TPB*v: the 64 faults of a wave in round v
+                        // are words (TPB*v + 64*wave) / 32 and the next one, taken
+                        // from one ballot (bits of faults >= N are 0)
+                        uint32_t *c32 = reinterpret_cast<uint32_t *>(a.corr) + (size_t)shot * a.corr_stride;
+                        const int lane = t & 63;
+#pragma unroll
+                        for (int v = 0; v < VR; ++v) {
+                            const unsigned long long bal = __ballot((out >> v) & 1u);
+                            const int j0 = TPB * v + (t & ~63) + (lane & 32);  // first fault of this lane's word
+                            if ((lane & 31) == 0 && j0 < N)
+                                c32[j0 >> 5] = (uint32_t)(lane & 32 ? bal >> 32 : bal);
                         }
                     }
                     if (t == 0) {

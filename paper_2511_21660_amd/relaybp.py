@@ -23,6 +23,26 @@ STATUS = {
     8: "RB_E_UNSUPPORTED", 9: "RB_E_NONFINITE", 10: "RB_E_INTERNAL",
 }
 ANCHOR_CHAIN, ANCHOR_PRIOR = 0, 1
+IO_BYTES, IO_BITS32 = 0, 1
+
+
+def pack_bits(a) -> np.ndarray:
+    """uint8 0/1 array [B, K] -> int32 words [B, ceil(K / 32)], entry k in bit
+    k % 32 of word k // 32 (the RB_IO_BITS32 layout)."""
+    a = np.ascontiguousarray(np.asarray(a) != 0)
+    b, k = a.shape
+    w = (k + 31) // 32
+    pad = np.zeros((b, 32 * w), dtype=bool)
+    pad[:, :k] = a
+    by = np.packbits(pad, axis=1, bitorder="little")          # [B, 4w] bytes, little-endian bits
+    return np.ascontiguousarray(by).view("<u4").astype(np.uint32).view(np.int32).reshape(b, w)
+
+
+def unpack_bits(words, k: int) -> np.ndarray:
+    """Inverse of pack_bits: int32 / uint32 words [B, W] -> uint8 0/1 [B, k]."""
+    w = np.ascontiguousarray(np.asarray(words)).astype(np.uint32).astype("<u4")
+    by = w.view(np.uint8).reshape(w.shape[0], -1)
+    return np.unpackbits(by, axis=1, bitorder="little")[:, :k].astype(np.uint8)
 
 
 class RelayError(RuntimeError):
@@ -44,6 +64,7 @@ class RBParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("anchor", ctypes.c_int32),
         ("max_total_iters", ctypes.c_int32),
+        ("io_layout", ctypes.c_int32),
     ]
 
 
@@ -196,6 +217,8 @@ class Decoder:
         elif isinstance(params, dict):
             params = default_params(**params, **overrides)
         self.params = params
+        self.bits = params.io_layout == IO_BITS32
+        self.wm, self.wn = (self.m + 31) // 32, (self.n + 31) // 32
         rows = np.ascontiguousarray(rows, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
         prior = np.ascontiguousarray(np.broadcast_to(np.asarray(prior, np.float64), (self.n,)))
@@ -226,14 +249,22 @@ class Decoder:
 
         return torch.device("cuda", self.device)
 
-    def decode(self, syndromes, want_weight=True, want_llr=False, out=None):
-        """syndromes: uint8 CUDA tensor [B, M].  Returns a dict of CUDA tensors
-        corr [B, N] u8, conv [B] u8, legs [B] i32, iters [B] i32, and optionally
-        weight [B] f64 and llr [B, N] f32.  Work is enqueued on the current stream."""
+    def _io(self):
+        """(dtype, syndrome row length, correction row length) of the context's layout."""
         import torch
 
-        if syndromes.dtype != torch.uint8 or syndromes.dim() != 2 or syndromes.shape[1] != self.m:
-            raise ValueError(f"syndromes must be uint8 [B, {self.m}]")
+        return (torch.int32, self.wm, self.wn) if self.bits else (torch.uint8, self.m, self.n)
+
+    def decode(self, syndromes, want_weight=True, want_llr=False, out=None):
+        """syndromes: uint8 CUDA tensor [B, M] (bit-packed layout: int32 [B, ceil(M/32)]).
+        Returns a dict of CUDA tensors corr [B, N] u8 (bit-packed: int32 [B, ceil(N/32)]),
+        conv [B] u8, legs [B] i32, iters [B] i32, and optionally weight [B] f64 and
+        llr [B, N] f32.  Work is enqueued on the current stream."""
+        import torch
+
+        dt, sw, cw = self._io()
+        if syndromes.dtype != dt or syndromes.dim() != 2 or syndromes.shape[1] != sw:
+            raise ValueError(f"syndromes must be {dt} [B, {sw}]")
         if not syndromes.is_cuda:
             raise ValueError("syndromes must be a CUDA (HIP) tensor")
         syndromes = syndromes.contiguous()
@@ -241,7 +272,7 @@ class Decoder:
         dev = syndromes.device
         if out is None:
             out = {
-                "corr": torch.empty((b, self.n), dtype=torch.uint8, device=dev),
+                "corr": torch.empty((b, cw), dtype=dt, device=dev),
                 "conv": torch.empty(b, dtype=torch.uint8, device=dev),
                 "legs": torch.empty(b, dtype=torch.int32, device=dev),
                 "iters": torch.empty(b, dtype=torch.int32, device=dev),
@@ -258,18 +289,20 @@ class Decoder:
 
     def syndrome(self, corr, syn_in=None, out=None):
         """(syn_in XOR H corr) mod 2 for corr uint8 [B, N] on the device: uint8 [B, M]
-        (syn_in None reads as zero; out may be syn_in).  Enqueued on the current stream."""
+        (bit-packed layout: int32 [B, ceil(N/32)] -> int32 [B, ceil(M/32)]; syn_in None
+        reads as zero; out may be syn_in).  Enqueued on the current stream."""
         import torch
 
-        if corr.dtype != torch.uint8 or corr.dim() != 2 or corr.shape[1] != self.n or not corr.is_cuda:
-            raise ValueError(f"corr must be a uint8 CUDA tensor [B, {self.n}]")
+        dt, sw, cw = self._io()
+        if corr.dtype != dt or corr.dim() != 2 or corr.shape[1] != cw or not corr.is_cuda:
+            raise ValueError(f"corr must be a {dt} CUDA tensor [B, {cw}]")
         corr = corr.contiguous()
         b = corr.shape[0]
-        if syn_in is not None and (syn_in.dtype != torch.uint8 or tuple(syn_in.shape) != (b, self.m)
+        if syn_in is not None and (syn_in.dtype != dt or tuple(syn_in.shape) != (b, sw)
                                    or not syn_in.is_contiguous()):
-            raise ValueError(f"syn_in must be a contiguous uint8 CUDA tensor [{b}, {self.m}]")
+            raise ValueError(f"syn_in must be a contiguous {dt} CUDA tensor [{b}, {sw}]")
         if out is None:
-            out = torch.empty((b, self.m), dtype=torch.uint8, device=corr.device)
+            out = torch.empty((b, sw), dtype=dt, device=corr.device)
         _check(load_library().rb_syndrome(self._h, b, _ptr(corr), _ptr(syn_in), _ptr(out), _stream(corr.device)))
         return out
 
@@ -360,6 +393,7 @@ class MultiDecoder:
         elif isinstance(params, dict):
             params = default_params(**params, **overrides)
         self.params = params
+        self.bits = params.io_layout == IO_BITS32
         self.ms = [int(p.m) for p in problems]
         self.ns = [int(p.n) for p in problems]
         self.m_max, self.n_max = max(self.ms), max(self.ns)
@@ -398,8 +432,9 @@ class MultiDecoder:
         import torch
 
         dev = torch.device("cuda", self.device)
+        dt, _, cw = self._io()
         out = {
-            "corr": torch.empty((b, self.n_max), dtype=torch.uint8, device=dev),
+            "corr": torch.empty((b, cw), dtype=dt, device=dev),
             "conv": torch.empty(b, dtype=torch.uint8, device=dev),
             "legs": torch.empty(b, dtype=torch.int32, device=dev),
             "iters": torch.empty(b, dtype=torch.int32, device=dev),
@@ -412,13 +447,22 @@ class MultiDecoder:
             out["llr"] = torch.empty((b, self.n_max), dtype=torch.float32, device=dev)
         return out
 
-    def decode(self, code_id, syndromes, out=None, want_weight=True, want_llr=False):
-        """code_id int32 [B], syndromes uint8 [B, M_max] (CUDA).  Enqueues on the
-        current stream; returns the dict of output tensors."""
+    def _io(self):
         import torch
 
-        if syndromes.dtype != torch.uint8 or syndromes.shape[1] != self.m_max:
-            raise ValueError(f"syndromes must be uint8 [B, {self.m_max}]")
+        if self.bits:
+            return torch.int32, (self.m_max + 31) // 32, (self.n_max + 31) // 32
+        return torch.uint8, self.m_max, self.n_max
+
+    def decode(self, code_id, syndromes, out=None, want_weight=True, want_llr=False):
+        """code_id int32 [B], syndromes uint8 [B, M_max] (bit-packed layout: int32
+        [B, ceil(M_max/32)]; CUDA).  Enqueues on the current stream; returns the dict
+        of output tensors."""
+        import torch
+
+        dt, sw, _ = self._io()
+        if syndromes.dtype != dt or syndromes.shape[1] != sw:
+            raise ValueError(f"syndromes must be {dt} [B, {sw}]")
         if code_id.dtype != torch.int32 or code_id.shape[0] != syndromes.shape[0]:
             raise ValueError("code_id must be int32 [B]")
         b = syndromes.shape[0]
@@ -440,8 +484,9 @@ class MultiDecoder:
         is not used).  Enqueues on the current stream."""
         import torch
 
-        if syndromes.dtype != torch.uint8 or syndromes.shape[1] != self.m_max:
-            raise ValueError(f"syndromes must be uint8 [B, {self.m_max}]")
+        dt, sw, _ = self._io()
+        if syndromes.dtype != dt or syndromes.shape[1] != sw:
+            raise ValueError(f"syndromes must be {dt} [B, {sw}]")
         if code_id.dtype != torch.int32 or code_id.shape[0] != syndromes.shape[0]:
             raise ValueError("code_id must be int32 [B]")
         _check(load_library().rb_decode_multi_noalloc(

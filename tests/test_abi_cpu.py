@@ -37,6 +37,7 @@ def test_params_default_matches_paper(lib):
     assert p.gamma_first == np.float32(0.125)
     assert (p.gamma_lo, p.gamma_hi) == (np.float32(-0.24), np.float32(0.66))
     assert p.llr_clip == 2.0 ** 64
+    assert p.io_layout == rb.IO_BYTES
     assert lib.rb_params_default(None) == 1
 
 
@@ -75,7 +76,7 @@ def test_create_rejects_bad_input_before_device_use():
         assert _create(p.m, p.n, p.rows, p.cols, prior)[0] == 4
     for field, val in (("num_legs", 0), ("iters_first", 0), ("iters_leg", -1),
                        ("num_solutions", 0), ("anchor", 2), ("max_total_iters", -1),
-                       ("llr_clip", 0.0), ("gamma_lo", 1.0)):
+                       ("llr_clip", 0.0), ("gamma_lo", 1.0), ("io_layout", 2), ("io_layout", -1)):
         assert _create(p.m, p.n, p.rows, p.cols, p.prior, rb.default_params(**{field: val}))[0] == 1
     assert _create(p.m, p.n, p.rows, p.cols, p.prior,
                    rb.default_params(gamma_first=float("nan")))[0] == 9
