@@ -52,7 +52,13 @@ sys.path.insert(0, ROOT)
 
 # MI355X peaks (published): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3 T lane-ops/s (non-packed FP32 / int)
-PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 78.6 TB/s at 128 B/clk/CU
+# LDS read bandwidth of gfx950, measured by paper_2511_21660_amd/ldspeak.py:
+# conflict-free ds_read_b128 and _b64 reach 234 and 228 B/clk/CU, so the peak
+# is taken as 256 B/clk/CU (CDNA3's 128 B/clk is half of it); ds_read_b32
+# reaches 117 of its 128 B/clk (256 bytes per wave every two clocks), the
+# ceiling for the 4-byte gathers the decoders issue.
+PEAK_LDS_TBS = 256 * 256 * 2.4e9 / 1e12       # 157.3 TB/s at 256 B/clk/CU
+PEAK_LDS_B32_TBS = 256 * 128 * 2.4e9 / 1e12   # 78.6 TB/s for 4-byte reads
 
 # Relay parameters of the paper's appendix on Relay resources (T = 80, then
 # 60; gamma_0 = 0.125, gamma ~ U[-0.24, 0.66]); R counts every leg.
@@ -141,6 +147,7 @@ def roofline(kernel, kernel_ms, ops_launch, eu_launch, lds_b_per_eu, traffic):
              "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic, "kernel": kernel,
              "kernel_ms_per_launch": kernel_ms, "ops_per_edge_update": ops_launch / eu_launch},
             {"achieved": lds, "peak": PEAK_LDS_TBS, "unit": "TB/s", "frac": lds / PEAK_LDS_TBS,
+             "frac_of_b32_read_peak": lds / PEAK_LDS_B32_TBS,
              "bytes_per_edge_update": lds_b_per_eu})
 
 
@@ -213,7 +220,7 @@ def oracle_baseline(decode_sample, n_all, n_one, total, what):
 
 
 # --------------------------------------------------------------------------
-# [[144,12,12]] at four p values, S = 5 (the headline)
+# [[144,12,12]] at four p values, S = 5
 # --------------------------------------------------------------------------
 
 
@@ -310,6 +317,29 @@ def run_bb144(args, torch, rb, codes, sampling):
                "sample": f"first {n_cpu} syndromes of each of the 4 p values "
                          f"({len(ps) * n_cpu} of {n_shots}), same inputs, {tc:.1f} s",
                "paired_with_gpu_bit_exact": agree}
+    f16 = None
+    if args.f16_steps > 0:
+        # the same syndromes with binary16 messages (block kernel, two syndromes
+        # per workgroup): LER per p beside FP32's, and the bit-exact pairing
+        # with the oracle's binary16 mode on the first 2000 syndromes of each p
+        f16 = {}
+        for q, p in enumerate(ps):
+            dec16 = rb.Decoder.from_problem(probs[q], device=0, **dict(RELAY, precision=1))
+            o = {k: v.cpu().numpy() for k, v in dec16.decode(torch.from_numpy(syns[q]).to(dev)).items()}
+            fail = logical_failures(probs[q], faults[q], o["corr"], o["conv"])
+            kf = int(fail.sum())
+            ent = {"ler": kf / len(fail), "wilson95": wilson(kf, len(fail)), "mean_iters": float(o["iters"].mean()),
+                   "same_correction_as_fp32": float((o["corr"] == res[q]["corr"][:, :N]).all(1).mean())}
+            if not args.no_cpu_baseline:
+                import oracle
+
+                n = min(2000, len(fail))
+                ref = oracle.decode(probs[q].m, probs[q].n, probs[q].rows, probs[q].cols, probs[q].prior, RELAY,
+                                    syns[q][:n], precision="h16", threads=oracle_threads())
+                ent["oracle_h16_paired_bit_exact"] = bool(np.array_equal(ref["corr"], o["corr"][:n])
+                                                          and np.array_equal(ref["iters"], o["iters"][:n]))
+            f16[str(p)] = ent
+            dec16.close()
     line = head(args, n_shots * args.steps / elapsed, elapsed, {
         "workload": "relay_bp_bb144_code_capacity", "code": "[[144,12,12]] HX 72x144",
         "edges": E, "p": ps, "syndromes_per_p": shots, "syndromes_per_step": n_shots,
@@ -318,7 +348,7 @@ def run_bb144(args, torch, rb, codes, sampling):
         "parallelism": "single_gpu"})
     line.update({"edge_updates_per_s": iters_step * E * args.steps / elapsed,
                  "launch_ms": launch_means(per_launch), "roofline": roof, "lds_roofline": lds,
-                 "ler": ler, "kernel_config": info, "cpu_baseline": cpu})
+                 "ler": ler, "binary16": f16, "kernel_config": info, "cpu_baseline": cpu})
     return line
 
 
@@ -352,6 +382,61 @@ def end_to_end(torch, dec, syn_np, out):
             "first_20000_identical": same}
 
 
+def measure_h16(args, torch, rb, prob, d_syn, syn_np, bits, failures, corr_bytes, out32, stream):
+    """The same syndromes decoded with binary16 messages (two syndromes per
+    workgroup): throughput, the packed-FP16 ALU roofline, LER with its Wilson
+    interval beside FP32's, agreement with the FP32 decisions, and bit-exact
+    pairing with the oracle's binary16 mode on a sample."""
+    M, N, E = prob.m, prob.n, prob.nnz
+    shots = syn_np.shape[0]
+    dec = rb.Decoder.from_problem(prob, device=0, **dict(RELAY_R20, io_layout=1 if bits else 0, precision=1))
+    o = dec.decode(d_syn)
+
+    def step(ev):
+        if ev is not None:
+            ev[0][0].record(stream)
+        dec.decode(d_syn, out=o)
+        if ev is not None:
+            ev[0][1].record(stream)
+
+    elapsed, per_launch = timed(torch, step, 1, args.f16_steps, 1)
+    kernel_ms = float(np.mean(per_launch))
+    iters = o["iters"].cpu().numpy()
+    it = int(iters.astype(np.int64).sum())
+    achieved = it * ops_per_iteration(M, N, E) / (kernel_ms * 1e-3) / 1e12
+    fail = failures(o)
+    k = int(fail.sum().item())
+    same = 0
+    for s0 in range(0, shots, 50000):
+        same += int((corr_bytes(s0, s0 + 50000, o) == corr_bytes(s0, s0 + 50000)).all(1).sum().item())
+    res = {"syndromes_per_s": shots * args.f16_steps / elapsed, "launch_ms": kernel_ms,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": 2 * PEAK_VALU_TOPS, "unit": "Tops/s",
+                        "frac": achieved / (2 * PEAK_VALU_TOPS), "kernel": "relay_block16_kernel",
+                        "peak_note": "packed binary16: two lane-ops per lane per cycle"},
+           "lds_roofline": {"achieved": it * E * lds_bytes_per_edge_update(M, N, E) / 2 / (kernel_ms * 1e-3) / 1e12,
+                            "peak": PEAK_LDS_TBS, "unit": "TB/s",
+                            "note": "algorithmic bytes of binary16 messages: half of the FP32 figure"},
+           "ler": k / shots, "wilson95": wilson(k, shots), "conv": float(o["conv"].float().mean().item()),
+           "mean_iters": float(iters.mean()), "same_correction_as_fp32": same / shots,
+           "clip": "min(L, 4096)", "steps": args.f16_steps}
+    res["lds_roofline"]["frac"] = res["lds_roofline"]["achieved"] / PEAK_LDS_TBS
+    if not args.no_cpu_baseline:
+        import oracle
+
+        n = min(1000, shots)
+        t1 = time.perf_counter()
+        ref = oracle.decode(M, N, prob.rows, prob.cols, prob.prior, RELAY_R20, syn_np[:n], precision="h16",
+                            threads=oracle_threads())
+        tc = time.perf_counter() - t1
+        res["oracle_h16"] = {"shots": n, "syndromes_per_s": n / tc,
+                             "paired_with_gpu_bit_exact": bool(
+                                 np.array_equal(ref["corr"], corr_bytes(0, n, o).cpu().numpy())
+                                 and np.array_equal(ref["iters"], iters[:n])
+                                 and np.array_equal(ref["conv"], o["conv"][:n].cpu().numpy()))}
+    dec.close()
+    return res
+
+
 def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     """DEM-shaped matrix: 936 x 8785 on the block kernel, or (two_gross) the
     two-gross-scale 2736 x 26208 on the large-graph kernel."""
@@ -372,9 +457,10 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     d_syn = torch.from_numpy(rb.pack_bits(syn_np) if bits else syn_np).to(dev)
     out = dec.decode(d_syn)
 
-    def corr_bytes(s0, s1):
-        """Corrections of shots s0 .. s1 - 1 as uint8 [s1 - s0, N] on the device."""
-        c = out["corr"][s0:s1]
+    def corr_bytes(s0, s1, o=None):
+        """Corrections of shots s0 .. s1 - 1 (of `o`, default the FP32 decode) as
+        uint8 [s1 - s0, N] on the device."""
+        c = (out if o is None else o)["corr"][s0:s1]
         if not bits:
             return c
         sh = torch.arange(32, device=dev, dtype=torch.int32)
@@ -405,13 +491,18 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     for c0 in range(0, d_fs.numel(), 1 << 22):
         af.index_add_(0, d_fs[c0:c0 + (1 << 22)],
                       a[:, d_fc[c0:c0 + (1 << 22)]].T.contiguous().to(torch.int32))
-    fail = torch.zeros(shots, dtype=torch.bool, device=dev)
-    chunk = 50000
-    for s0 in range(0, shots, chunk):
-        ah = torch.round(corr_bytes(s0, s0 + chunk).float() @ a.T).to(torch.int32)
-        fail[s0:s0 + chunk] = ((ah + af[s0:s0 + chunk]) % 2).any(1)
-    fail |= out["conv"] == 0
+    def failures(o):
+        bad = torch.zeros(shots, dtype=torch.bool, device=dev)
+        for s0 in range(0, shots, 50000):
+            ah = torch.round(corr_bytes(s0, s0 + 50000, o).float() @ a.T).to(torch.int32)
+            bad[s0:s0 + 50000] = ((ah + af[s0:s0 + 50000]) % 2).any(1)
+        return bad | (o["conv"] == 0)
+
+    fail = failures(out)
     k = int(fail.sum().item())
+    f16 = None
+    if not two_gross and args.f16_steps > 0:
+        f16 = measure_h16(args, torch, rb, prob, d_syn, syn_np, bits, failures, corr_bytes, out, stream)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -446,7 +537,7 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
                          "conv": float(conv.mean()), "mean_iters": float(iters.mean()),
                          "max_iters": int(iters.max()), "faults_per_shot": f_shots.size / shots},
                  "latency_tail": tail, "kernel_config": dec.info(), "end_to_end": e2e,
-                 "cpu_baseline": cpu})
+                 "binary16": f16, "cpu_baseline": cpu})
     return line
 
 
@@ -631,6 +722,22 @@ def run_mixed_codes(args, torch, rb, codes, sampling):
 
     el_mixed, pl_mixed = timed(torch, step_mixed, 1, args.steps, args.warmup)
     host = {k: v.cpu().numpy() for k, v in mout.items() if k != "workspace"}
+    # per-shot fixed cost: an all-zero syndrome converges at the first
+    # iteration, so a batch of them costs one fetch, one check pass and one
+    # convergence event per shot
+    d_zero = torch.zeros_like(d_syn)
+    zout = mdec.alloc(shots)
+
+    def step_zero(ev):
+        if ev is not None:
+            ev[0][0].record(stream)
+        mdec.decode(d_code, d_zero, out=zout)
+        if ev is not None:
+            ev[0][1].record(stream)
+
+    _, pl_zero = timed(torch, step_zero, 1, max(2, args.steps // 2), 1)
+    assert int(zout["iters"].max().item()) == 1
+    del zout
     # the same launch captured in a hipGraph and replayed
     gout = mdec.alloc(shots)
     side = torch.cuda.Stream()
@@ -722,6 +829,10 @@ def run_mixed_codes(args, torch, rb, codes, sampling):
         "per_code_launches": {"value": shots * args.steps / el_per,
                               "launch_ms": launch_means(pl_per),
                               "results_identical": same},
+        "per_shot_fixed_cost": {"zero_syndrome_launch_ms": float(np.mean(pl_zero)),
+                                "ns_per_shot": float(np.mean(pl_zero)) * 1e6 / shots,
+                                "share_of_launch": float(np.mean(pl_zero)) / kernel_ms,
+                                "mean_iters": float(host["iters"].mean())},
         "tiles_chosen": chosen, "ler": ler, "cpu_baseline": cpu})
     return line
 
@@ -813,6 +924,9 @@ def main():
                     help="oracle sample: syndromes per p (bb144) or in total (dem)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--f16-steps", type=int, default=3,
+                    help="dem: timed launches of the binary16 decoder on the same syndromes; bb144: "
+                         "decode them with binary16 messages for the LER comparison (0: skip)")
     ap.add_argument("--io-layout", choices=["bits32", "bytes"], default="bits32",
                     help="dem, dem-2gross: syndromes in and corrections out bit-packed in uint32 words "
                          "(default) or one byte per entry")

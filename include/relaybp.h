@@ -69,6 +69,22 @@ typedef enum {
  * marginals keep their layouts. */
 enum { RB_IO_BYTES = 0, RB_IO_BITS32 = 1 };
 
+/* Arithmetic of the messages (rb_params.precision).  F32: IEEE binary32, the
+ * decoder of paper Sec. 2.3 in canonical FP32 order.  F16: every per-shot
+ * quantity (marginals Lambda, lambda(0), the memory term, nu and mu) held in
+ * IEEE binary16 and every arithmetic result rounded to binary16 (nearest
+ * even), in the same order: w16_j = binary16(log((1-p_j)/p_j)) rounded once
+ * from FP64, gamma16 = binary16 of the FP32 memory strength, clip L16 =
+ * binary16(min(llr_clip, 4096)) (so sums of up to 15 clipped terms stay
+ * finite).  The paper does not state the precision of Relay's messages (its
+ * FPGA resource estimates in the appendix on Relay resources give none).
+ * Decisions, the convergence test, legs, S solutions and the weight W (FP64
+ * sum of the FP32 w_j) are those of F32; final marginals are returned as
+ * float.  F16 contexts run graphs that fit a block shape (two syndromes per
+ * workgroup), no prior scale, no training calls and no mixed launch
+ * (RB_E_UNSUPPORTED). */
+enum { RB_PREC_F32 = 0, RB_PREC_F16 = 1 };
+
 /* Anchor of the memory term in legs r >= 2 (leg 1 always uses w_j). */
 enum { RB_ANCHOR_CHAIN = 0, /* lambda^{(r)}(0) = clip(Lambda^{(r-1)}(T_{r-1})), paper Sec. 2.3 */
        RB_ANCHOR_PRIOR = 1  /* lambda^{(r)}(0) = w_j = log((1-p_j)/p_j) in every leg */ };
@@ -96,6 +112,7 @@ enum { RB_ANCHOR_CHAIN = 0, /* lambda^{(r)}(0) = clip(Lambda^{(r-1)}(T_{r-1})), 
  *                   corrections that rb_decode, rb_decode_multi(_noalloc),
  *                   rb_autotune(_multi) and rb_syndrome take and return (rb_trace
  *                   and the training calls always take uint8 syndromes)
+ *   precision       RB_PREC_F32 or RB_PREC_F16 (see above)
  */
 typedef struct {
     int32_t num_legs;
@@ -110,6 +127,7 @@ typedef struct {
     int32_t anchor;
     int32_t max_total_iters;
     int32_t io_layout;
+    int32_t precision;
 } rb_params;
 
 /* Kernel configuration chosen for a context (read-only diagnostics). */
@@ -129,8 +147,8 @@ typedef struct {
 
 /* Fills *out with the paper's parameters (R = 301 legs in total, T_1 = 80,
  * T_r = 60, S = 1, gamma_0 = 0.125, gamma in [-0.24, 0.66], L = 2^64,
- * anchor CHAIN, no cutoff, seed 0x52454C4159, RB_IO_BYTES).  RB_E_INVALID_ARG if
- * out is NULL. */
+ * anchor CHAIN, no cutoff, seed 0x52454C4159, RB_IO_BYTES, RB_PREC_F32).
+ * RB_E_INVALID_ARG if out is NULL. */
 rb_status rb_params_default(rb_params *out);
 
 /*

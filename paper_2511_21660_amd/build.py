@@ -1,4 +1,5 @@
-"""Builds the HIP library ``librelaybp.so`` in-tree for gfx950.
+"""Builds the HIP library ``librelaybp.so`` in-tree for gfx950, and the LDS
+bandwidth probe ``liblds_peak.so`` that measures the LDS roofline's peak.
 
 Flags: -ffp-contract=off keeps the canonical FP32 operation order (no fused
 multiply-add); the packed-FP32 target feature is switched off so the compiler
@@ -12,7 +13,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librelaybp.so")
-SOURCES = ["relay_kernels.hip", "relay_block.hip", "relay_large.hip", "relay_train.hip", "relay_api.cpp"]
+LDS_PEAK_LIB = os.path.join(HERE, "liblds_peak.so")
+SOURCES = ["relay_kernels.hip", "relay_block.hip", "relay_block16.hip", "relay_large.hip", "relay_train.hip",
+           "relay_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -25,18 +28,23 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def _hipcc(out: str, sources, verbose: bool) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-shared", "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, "-shared", "-o", tmp] + [os.path.join(CSRC, s) for s in sources]
     res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
     if verbose or res.returncode != 0:
         print(res.stdout)
         print(res.stderr)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed ({res.returncode}): {' '.join(cmd)}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(LDS_PEAK_LIB, ["lds_peak.hip"], verbose)
+    return _hipcc(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

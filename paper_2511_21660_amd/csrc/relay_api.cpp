@@ -56,6 +56,7 @@ struct rb_ctx {
     std::vector<int32_t> rowidx;  // [E], ascending within a column
     std::vector<int32_t> cpos;    // [E] position of edge (rowidx, j) inside its CSR row
     std::vector<float> w;         // [N]
+    std::vector<double> w64;      // [N] log((1-p)/p) in FP64 (the binary16 mode rounds it once)
     // device
     float *d_w = nullptr;
     float *d_gamma = nullptr;        // [R][N]
@@ -72,6 +73,11 @@ struct rb_ctx {
     int32_t *d_slot_col = nullptr, *d_chk_split = nullptr;
     float *d_w_slot = nullptr;      // [TPB*VPT] w by fault slot (block kernel)
     float *d_gamma_slot = nullptr;  // [R][TPB*VPT] gamma by fault slot (block kernel)
+    // binary16 mode (rb_params.precision = RB_PREC_F16): binary16 block kernel
+    bool h16 = false;
+    uint16_t *d_w16_slot = nullptr;      // [TPB*VPT] w by slot, binary16 bits
+    uint16_t *d_gamma16_slot = nullptr;  // [R][TPB*VPT] gamma by slot, binary16 bits
+    uint32_t L16 = 0, stage_off = 0;
     float prior_scale = 1.0f;       // s in Lambda(0) = s * w (rb_set_prior_scale)
     // longest-first shot lists for single-code decodes (rb_reserve)
     void *d_ws = nullptr;
@@ -557,7 +563,27 @@ bool large_fits(const rb_ctx *c, const rb::LargeShape &s) {
     return large_layout(c, s).lds_bytes <= 160 * 1024;
 }
 
+// Staging words of the binary16 kernel's packed corrections, after the
+// block layout (16-byte aligned).
+uint32_t block16_stage_off(int lds_bytes) { return ((uint32_t)lds_bytes + 15u) & ~15u; }
+int block16_lds_bytes(const rb::BlockShape &s, int lds_bytes) {
+    return (int)block16_stage_off(lds_bytes) + 4 * ((s.TPB * s.VPT + 31) / 32);
+}
+
+bool block16_fits(const rb_ctx *c, const rb::BlockShape &s) {
+    if (!block_fits(c, s)) return false;
+    std::vector<LaneSeg> lanes;
+    std::vector<int32_t> wdeg, wbase;
+    int64_t words = 0;
+    block_order(c, s, lanes, wdeg, wbase, words);
+    return block16_lds_bytes(s, block_layout(s, words).lds_bytes) <= 160 * 1024;
+}
+
 bool any_fits(const rb_ctx *c, int v) {
+    if (c->params.precision == RB_PREC_F16) {
+        v -= rb::num_variants();
+        return v >= 0 && v < rb::num_block_variants() && block16_fits(c, rb::block_variant_shape(v));
+    }
     if (v < rb::num_variants()) return variant_fits(c, rb::variant_shape(v));
     v -= rb::num_variants();
     if (v < rb::num_block_variants()) return block_fits(c, rb::block_variant_shape(v));
@@ -860,6 +886,7 @@ std::vector<int32_t> place_faults(const rb_ctx *c, const rb::BlockShape &s, cons
                         over = std::max(over, ld + 1 - (long long)wdeg[lane_of_edge[(size_t)e] / 64]);
                         sum += ld;
                     }
+                    if (c->colptr[j] == c->colptr[j + 1]) over = 0;  // an empty column loads no bank
                     const long long key = over * (1ll << 32) + sum;
                     if (best < 0 || key < bkey) {
                         best = l;
@@ -1485,6 +1512,56 @@ rb_status build_large_plan(rb_ctx *c, int lv) {
     return RB_OK;
 }
 
+// The binary16 kernel on block shape bv (after build_block_plan(c, bv)):
+// w and Gamma by slot as binary16 (w rounded once from FP64, Gamma from its
+// FP32 value), the clip L16 = min(L, 4096), the staging words, and the
+// kernel's LDS allowance and occupancy.
+rb_status build_block16_extras(rb_ctx *c, int bv) {
+    if (bv >= rb::num_block16_variants()) return fail(RB_E_INTERNAL, "no binary16 kernel for this block shape");
+    const rb::BlockShape s = rb::block_variant_shape(bv), s16 = rb::block16_variant_shape(bv);
+    if (s.TPB != s16.TPB || s.DCMAX != s16.DCMAX || s.VPT != s16.VPT || s.prof != s16.prof || s.waves != s16.waves)
+        return fail(RB_E_INTERNAL, "binary16 block shape differs from the FP32 one");
+    const int npad = s.TPB * s.VPT, R = c->params.num_legs;
+    std::vector<int32_t> slot_col((size_t)npad);
+    RB_HIP(hipMemcpy(slot_col.data(), c->d_slot_col, sizeof(int32_t) * (size_t)npad, hipMemcpyDeviceToHost),
+           "read slot map");
+    std::vector<uint16_t> w16((size_t)npad, 0);
+    for (int q = 0; q < npad; ++q)
+        if (slot_col[q] >= 0) {
+            const _Float16 h = (_Float16)c->w64[(size_t)slot_col[q]];  // one rounding, nearest even
+            std::memcpy(&w16[q], &h, 2);
+        }
+    rb_status st;
+    if ((st = upload(&c->d_w16_slot, w16, "upload binary16 w by slot")) != RB_OK) return st;
+    (void)hipFree(c->d_gamma16_slot);
+    c->d_gamma16_slot = nullptr;
+    RB_HIP(hipMalloc(&c->d_gamma16_slot, sizeof(uint16_t) * (size_t)npad * (size_t)R), "hipMalloc(binary16 gamma)");
+    RB_HIP(rb::launch_to_half(c->d_gamma_slot, (int64_t)npad * R, c->d_gamma16_slot, nullptr), "binary16 gamma");
+    RB_HIP(hipDeviceSynchronize(), "binary16 gamma");
+    const _Float16 lh = (_Float16)std::min(c->params.llr_clip, 4096.0f);
+    uint16_t lb;
+    std::memcpy(&lb, &lh, 2);
+    c->L16 = lb;
+    c->stage_off = block16_stage_off(c->lds_bytes);
+    c->lds_bytes = block16_lds_bytes(s, c->lds_bytes);
+    if (c->lds_bytes > 160 * 1024) return fail(RB_E_UNSUPPORTED, "binary16 LDS image exceeds a CU");
+    {
+        size_t st_lds = 0;
+        RB_HIP(rb::block16_static_lds(bv, &st_lds), "kernel attributes");
+        if (st_lds != 0) return fail(RB_E_DEVICE, "internal: binary16 block kernel uses static LDS");
+    }
+    RB_HIP(rb::block16_prepare(bv, (size_t)c->lds_bytes), "allow dynamic LDS");
+    const bool prior = c->params.anchor == RB_ANCHOR_PRIOR;
+    for (int tr = 0; tr < 2; ++tr) {
+        int blocks = 0;
+        RB_HIP(rb::block16_variant_occupancy(bv, prior, tr != 0, (size_t)c->lds_bytes, &blocks), "occupancy query");
+        if (blocks < 1) return fail(RB_E_UNSUPPORTED, "binary16 block configuration does not fit on a CU");
+        c->blocks_per_cu[tr] = blocks;
+    }
+    c->h16 = true;
+    return RB_OK;
+}
+
 rb_status plan(rb_ctx *c, int v) {
     c->large = false;
     if (v < rb::num_variants()) {
@@ -1492,7 +1569,11 @@ rb_status plan(rb_ctx *c, int v) {
         return build_plan(c, v);
     }
     v -= rb::num_variants();
-    if (v < rb::num_block_variants()) return build_block_plan(c, v);
+    if (v < rb::num_block_variants()) {
+        rb_status st = build_block_plan(c, v);
+        if (st == RB_OK && c->params.precision == RB_PREC_F16) st = build_block16_extras(c, v);
+        return st;
+    }
     return build_large_plan(c, v - rb::num_block_variants());
 }
 
@@ -1510,6 +1591,8 @@ rb_status check_params(const rb_params *p) {
         return fail(RB_E_INVALID_ARG, "llr_clip must be finite and > 0");
     if (p->io_layout != RB_IO_BYTES && p->io_layout != RB_IO_BITS32)
         return fail(RB_E_INVALID_ARG, "io_layout must be RB_IO_BYTES or RB_IO_BITS32");
+    if (p->precision != RB_PREC_F32 && p->precision != RB_PREC_F16)
+        return fail(RB_E_INVALID_ARG, "precision must be RB_PREC_F32 or RB_PREC_F16");
     return RB_OK;
 }
 
@@ -1569,7 +1652,11 @@ rb_status host_graph(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int3
     for (int32_t i = 0; i < M; ++i) c->max_row = std::max<int32_t>(c->max_row, (int32_t)(c->rowptr[i + 1] - c->rowptr[i]));
     for (int32_t j = 0; j < N; ++j) c->max_col = std::max<int32_t>(c->max_col, (int32_t)(c->colptr[j + 1] - c->colptr[j]));
     c->w.assign((size_t)N, 0.0f);
-    for (int32_t j = 0; prior_p && j < N; ++j) c->w[j] = (float)std::log((1.0 - prior_p[j]) / prior_p[j]);
+    c->w64.assign((size_t)N, 0.0);
+    for (int32_t j = 0; prior_p && j < N; ++j) {
+        c->w64[j] = std::log((1.0 - prior_p[j]) / prior_p[j]);
+        c->w[j] = (float)c->w64[j];
+    }
     *out = c;
     return RB_OK;
 }
@@ -1577,6 +1664,11 @@ rb_status host_graph(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int3
 // The cheapest built-in group-kernel tile the graph fits; for larger graphs
 // the first block-kernel shape that fits; -1 if none.
 int choose_variant(const rb_ctx *c) {
+    if (c->params.precision == RB_PREC_F16) {
+        for (int bv = 0; bv < rb::num_block_variants(); ++bv)
+            if (any_fits(c, rb::num_variants() + bv)) return rb::num_variants() + bv;
+        return -1;
+    }
     int best = -1;
     double best_cost = 0.0;
     for (int v = 0; v < rb::num_variants(); ++v) {
@@ -1639,6 +1731,7 @@ rb_status rb_params_default(rb_params *out) {
     out->anchor = RB_ANCHOR_CHAIN;
     out->max_total_iters = 0;
     out->io_layout = RB_IO_BYTES;
+    out->precision = RB_PREC_F32;
     return RB_OK;
 }
 
@@ -1718,6 +1811,8 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_chk_split);
         (void)hipFree(c->d_w_slot);
         (void)hipFree(c->d_gamma_slot);
+        (void)hipFree(c->d_w16_slot);
+        (void)hipFree(c->d_gamma16_slot);
         (void)hipFree(c->d_chk_of);
         (void)hipFree(c->d_lrowptr);
         (void)hipFree(c->d_lcolptr);
@@ -1823,6 +1918,10 @@ static rb::BlockArgs block_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.scale = g.scale;
     b.trace_T = g.trace_T;
     b.trace = g.trace;
+    b.w16_slot = c->d_w16_slot;
+    b.gamma16_slot = c->d_gamma16_slot;
+    b.L16 = c->L16;
+    b.stage_off = c->stage_off;
     return b;
 }
 
@@ -1870,7 +1969,10 @@ static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
     return b;
 }
 
-static int shots_per_block(const rb_ctx *c) { return (c->block || c->large) ? 1 : 64 / c->shape.G; }
+static int shots_per_block(const rb_ctx *c) {
+    if (c->h16) return 2;  // one syndrome in each half of the binary16 words
+    return (c->block || c->large) ? 1 : 64 / c->shape.G;
+}
 
 static int grid_for(const rb_ctx *c, int64_t B, int trace) {
     const int spb = shots_per_block(c);
@@ -1888,6 +1990,10 @@ static rb_status launch(rb_ctx *c, const rb::GroupArgs &a, bool trace, hipStream
         RB_HIP(rb::launch_large(c->variant - rb::num_variants() - rb::num_block_variants(), prior, trace,
                                 large_args(a, c), grid, (size_t)c->lds_bytes, s),
                "relay large-graph kernel launch");
+    } else if (c->h16) {
+        RB_HIP(rb::launch_block16(c->variant - rb::num_variants(), prior, trace, block_args(a, c), grid,
+                                  (size_t)c->lds_bytes, s),
+               "relay binary16 block kernel launch");
     } else if (c->block) {
         RB_HIP(rb::launch_block(c->variant - rb::num_variants(), prior, trace, block_args(a, c), grid,
                                 (size_t)c->lds_bytes, s),
@@ -1955,6 +2061,7 @@ rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_ga
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: trace one code's own context");
     if (B < 0 || T < 0) return fail(RB_E_INVALID_ARG, "B and T must be >= 0");
     if (!std::isfinite(scale)) return fail(RB_E_NONFINITE, "scale must be finite");
+    if (c->h16 && scale != 1.0f) return fail(RB_E_UNSUPPORTED, "the binary16 mode has no prior scale");
     if (B == 0) return RB_OK;
     if (!d_syn || !d_gamma || !d_trace) return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
     rb::GroupArgs a = base_args(c, B, d_syn);
@@ -1985,6 +2092,10 @@ rb_status rb_set_leg_gamma(rb_ctx *c, int32_t leg, const float *host_gamma) {
         RB_HIP(rb::launch_gather_slots(c->d_gamma + (size_t)(leg - 1) * c->N, c->N, c->d_slot_col, npad, 1,
                                        c->d_gamma_slot + (size_t)(leg - 1) * npad, nullptr),
                "gamma by slot");
+        if (c->h16)
+            RB_HIP(rb::launch_to_half(c->d_gamma_slot + (size_t)(leg - 1) * npad, npad,
+                                      c->d_gamma16_slot + (size_t)(leg - 1) * npad, nullptr),
+                   "binary16 gamma");
         RB_HIP(hipDeviceSynchronize(), "gamma by slot");
     }
     return RB_OK;
@@ -1995,6 +2106,7 @@ rb_status rb_set_prior_scale(rb_ctx *c, float scale) {
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: set the scale of a single-code context");
     if (!std::isfinite(scale)) return fail(RB_E_NONFINITE, "scale must be finite");
+    if (c->h16 && scale != 1.0f) return fail(RB_E_UNSUPPORTED, "the binary16 mode has no prior scale");
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(hipDeviceSynchronize(), "synchronise before scale update");
     c->prior_scale = scale;
@@ -2255,6 +2367,7 @@ rb_status rb_forward_train(rb_ctx *c, int64_t B, const uint8_t *d_syn, const flo
                            void *stream) {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (c->h16) return fail(RB_E_UNSUPPORTED, "training runs in FP32: create the context with RB_PREC_F32");
     rb::TrainArgs a{};
     rb_status st = train_args(c, B, d_syn, d_gamma, d_scale, T, ckpt_every, d_tape, tape_bytes, &a);
     if (st != RB_OK) return st;
@@ -2271,6 +2384,7 @@ rb_status rb_backward(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d
                       float *d_dgamma, float *d_dscale, void *stream) {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
+    if (c->h16) return fail(RB_E_UNSUPPORTED, "training runs in FP32: create the context with RB_PREC_F32");
     rb::TrainArgs a{};
     rb_status st = train_args(c, B, d_syn, d_gamma, d_scale, T, ckpt_every, d_tape, tape_bytes, &a);
     if (st != RB_OK) return st;
@@ -2374,6 +2488,8 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
     if (n_codes < 1 || n_codes > 64 || !codes) return fail(RB_E_INVALID_ARG, "need 1..64 code descriptors");
     rb_status st = check_params(params);
     if (st != RB_OK) return st;
+    if (params->precision != RB_PREC_F32)
+        return fail(RB_E_UNSUPPORTED, "the mixed launch decodes in FP32 (RB_PREC_F32)");
     rb_ctx *m = new (std::nothrow) rb_ctx();
     if (!m) return fail(RB_E_OOM, "host allocation failed");
     m->multi = true;

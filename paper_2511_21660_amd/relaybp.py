@@ -24,6 +24,7 @@ STATUS = {
 }
 ANCHOR_CHAIN, ANCHOR_PRIOR = 0, 1
 IO_BYTES, IO_BITS32 = 0, 1
+PREC_F32, PREC_F16 = 0, 1
 
 
 def pack_bits(a) -> np.ndarray:
@@ -65,6 +66,7 @@ class RBParams(ctypes.Structure):
         ("anchor", ctypes.c_int32),
         ("max_total_iters", ctypes.c_int32),
         ("io_layout", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
     ]
 
 

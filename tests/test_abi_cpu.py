@@ -76,10 +76,25 @@ def test_create_rejects_bad_input_before_device_use():
         assert _create(p.m, p.n, p.rows, p.cols, prior)[0] == 4
     for field, val in (("num_legs", 0), ("iters_first", 0), ("iters_leg", -1),
                        ("num_solutions", 0), ("anchor", 2), ("max_total_iters", -1),
-                       ("llr_clip", 0.0), ("gamma_lo", 1.0), ("io_layout", 2), ("io_layout", -1)):
+                       ("llr_clip", 0.0), ("gamma_lo", 1.0), ("io_layout", 2), ("io_layout", -1),
+                       ("precision", 2), ("precision", -1)):
         assert _create(p.m, p.n, p.rows, p.cols, p.prior, rb.default_params(**{field: val}))[0] == 1
     assert _create(p.m, p.n, p.rows, p.cols, p.prior,
                    rb.default_params(gamma_first=float("nan")))[0] == 9
+
+
+def test_mixed_launch_rejects_binary16_before_device_use():
+    p = codes.bb_problem("bb72", 0.05)
+    rows = np.ascontiguousarray(p.rows, np.int32)
+    cols = np.ascontiguousarray(p.cols, np.int32)
+    prior = np.ascontiguousarray(p.prior, np.float64)
+    desc = (rb.RBCodeDesc * 1)(rb.RBCodeDesc(p.m, p.n, rows.size, rows.ctypes.data_as(ctypes.c_void_p),
+                                             cols.ctypes.data_as(ctypes.c_void_p),
+                                             prior.ctypes.data_as(ctypes.c_void_p)))
+    h = ctypes.c_void_p()
+    lib = rb.load_library()
+    st = lib.rb_create_multi(ctypes.byref(h), 1, desc, ctypes.byref(rb.default_params(precision=rb.PREC_F16)), 0)
+    assert st == 8 and b"FP32" in lib.rb_last_error_message()
 
 
 def test_create_on_gpu_less_host_reports_device_error():
