@@ -226,7 +226,7 @@ def sumproduct_trace(m, n, rows, cols, llr, t_iters, syn):
 def decode_windowed(m, n, rows, cols, prior, params: dict, syn, band, first_round, t_commit, t_overlap,
                     threads=None):
     """Windowed Relay decoding over detector rounds (the overlapping windows of
-    T_commit + T_overlap rounds of the paper's closing caveat), written from
+    T_commit + T_overlap rounds of the caveat in Sec. 7.3), written from
     the definition with boolean masks:
 
       rounds R = ceil(m / band); window k covers detector rounds

@@ -1,5 +1,5 @@
 """Windowed Relay decoding over detector rounds (the overlapping windows of
-T_commit + T_overlap rounds that the paper's closing caveat describes:
+T_commit + T_overlap rounds that the caveat of the paper's Sec. 7.3 describes:
 decode a window, commit the faults of its first T_commit rounds, advance by
 T_commit).
 

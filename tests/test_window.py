@@ -1,5 +1,5 @@
 """Windowed decoding over detector rounds (the overlapping windows of
-T_commit + T_overlap rounds of the paper's closing caveat, Sec. 8).
+T_commit + T_overlap rounds of the caveat in the paper's Sec. 7.3, future directions).
 
 CPU: the oracle's windowed decoder against properties its definition fixes,
 and the GPU driver's window plan (host logic).  GPU: the driver against the
