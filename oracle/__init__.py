@@ -15,5 +15,6 @@ from .oracle import (  # noqa: F401
     philox4x32_10,
     round_h16,
     sumproduct_trace,
+    tangent,
     trace,
 )

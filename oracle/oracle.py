@@ -80,6 +80,9 @@ def lib():
         L.ro_decode_h16.restype = i32
         L.ro_trace_h16.argtypes = [i32, i32, i64, P, P, P, P, i32, ctypes.c_double, i64, P, P]
         L.ro_trace_h16.restype = i32
+        L.ro_tangent_f32.argtypes = [i32, i32, i64, P, P, P, ctypes.c_float, P, i32, ctypes.c_double, i64,
+                                     P, P, ctypes.c_double, P, P, P]
+        L.ro_tangent_f32.restype = i32
         _lib = L
     return _lib
 
@@ -193,6 +196,33 @@ def trace(m, n, rows, cols, prior, gamma, t_iters, syn, scale=1.0, precision="f3
     if rc != 0:
         raise ValueError(f"oracle trace failed with code {rc}")
     return out
+
+
+def tangent(m, n, rows, cols, prior, gamma, t_iters, syn, dgamma, dscale=0.0, scale=1.0,
+            llr_clip=2.0 ** 64, dwprime=None):
+    """Forward-mode derivative of one leg's Lambda(T) along its FP32 trajectory.
+
+    The leg is the one ``trace`` runs (FP32, per-column gamma, channel LLRs
+    w' = scale * w, no early stop); the direction is (dgamma [N], dscale), plus
+    dwprime [N] on w' itself if given.  Returns
+    (Lambda(T) float32 [B, N], dLambda(T) float64 [B, N]).
+    """
+    rows, cols = _coo(rows, cols)
+    prior = np.ascontiguousarray(prior, dtype=np.float64)
+    gamma = np.ascontiguousarray(np.broadcast_to(np.asarray(gamma, dtype=np.float32), (n,)))
+    dgamma = np.ascontiguousarray(np.broadcast_to(np.asarray(dgamma, dtype=np.float64), (n,)))
+    syn = np.ascontiguousarray(syn, dtype=np.uint8)
+    b = syn.shape[0]
+    lam = np.zeros((b, n), np.float32)
+    dlam = np.zeros((b, n), np.float64)
+    dwp = None if dwprime is None else np.ascontiguousarray(np.broadcast_to(
+        np.asarray(dwprime, dtype=np.float64), (n,)))
+    rc = lib().ro_tangent_f32(m, n, rows.size, _ptr(rows), _ptr(cols), _ptr(prior), float(scale),
+                              _ptr(gamma), int(t_iters), float(llr_clip), b, _ptr(syn), _ptr(dgamma),
+                              float(dscale), None if dwp is None else _ptr(dwp), _ptr(lam), _ptr(dlam))
+    if rc != 0:
+        raise ValueError(f"oracle tangent failed with code {rc}")
+    return lam, dlam
 
 
 def minsum_trace(m, n, rows, cols, llr, t_iters, syn, precision="f32"):

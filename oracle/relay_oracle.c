@@ -454,3 +454,106 @@ int ro_sumproduct_trace(int M, int N, long nnz, const int *rows, const int *cols
     graph_free(&g);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Tangent (forward-mode derivative) of one leg, along its FP32 trajectory.  */
+/*                                                                           */
+/* The FP32 values follow ro_trace_f32 operation for operation (same         */
+/* readings R1-R3, R8), so Lambda(T) is that function's last row.  Beside    */
+/* them, FP64 tangents d(.) of every quantity in a direction (dgamma, dscale)*/
+/* of the memory strengths and the channel-LLR scale (plus, optionally, a    */
+/* direction dwprime [N] of the scaled LLRs w' themselves), by the chain rule on */
+/* the update equations of paper Sec. 2.3 with the trajectory's discrete     */
+/* choices held fixed:                                                       */
+/*   w'       = s w                      dw'     = ds w                      */
+/*   nu_e     = clip(Lambda_j - mu_e)    dnu_e   = dLambda_j - dmu_e inside  */
+/*                                                 (-L, L), else 0           */
+/*   mu_e     = S_e min_{e' != e} |nu_e'|  dmu_e = S_e sgn(nu_k) dnu_k, k the */
+/*              first edge of the check (ascending) attaining that minimum;  */
+/*              0 if the minimum is clipped (>= L) or the set is empty       */
+/*   lambda_j = clip((1-g) w' + g clip(Lambda_j))                            */
+/*            dlambda = (1-g) dw' + dg (clip(Lambda_j) - w')                 */
+/*                      + g dLambda_j [Lambda_j inside]  inside (-L, L)      */
+/*   Lambda_j = lambda_j + sum mu_e       dLambda = dlambda + sum dmu_e      */
+/* sgn(0) = 0 (|x| has no slope there).  The sign product S_e is piecewise   */
+/* constant and carries no tangent.  Writes Lambda(T) [B][N] (float) and     */
+/* dLambda(T) [B][N] (double).                                               */
+/* ------------------------------------------------------------------------ */
+
+int ro_tangent_f32(int M, int N, long nnz, const int *rows, const int *cols, const double *prior,
+                   float scale, const float *gamma, int T, double llr_clip, long B,
+                   const unsigned char *syn, const double *dgamma, double dscale,
+                   const double *dwprime, float *lam_out, double *dlam_out) {
+    graph g;
+    int rc = graph_build(&g, M, N, nnz, rows, cols);
+    if (rc) return rc;
+    const float L = (float)llr_clip;
+    const size_t ne = (size_t)(g.E ? g.E : 1);
+    float *w = malloc(sizeof(float) * (size_t)N), *wp = malloc(sizeof(float) * (size_t)N);
+    float *Lam = malloc(sizeof(float) * (size_t)N), *mu = malloc(sizeof(float) * ne);
+    float *nu = malloc(sizeof(float) * ne);
+    double *dwp = malloc(sizeof(double) * (size_t)N), *dLam = malloc(sizeof(double) * (size_t)N);
+    double *dmu = malloc(sizeof(double) * ne), *dnu = malloc(sizeof(double) * ne);
+    for (int j = 0; j < N; ++j) {
+        w[j] = (float)log((1.0 - prior[j]) / prior[j]);
+        wp[j] = scale * w[j];
+        dwp[j] = dscale * (double)w[j] + (dwprime ? dwprime[j] : 0.0);
+    }
+    for (long b = 0; b < B; ++b) {
+        const unsigned char *sigma = syn + (size_t)b * M;
+        for (int j = 0; j < N; ++j) { Lam[j] = wp[j]; dLam[j] = dwp[j]; }
+        for (int e = 0; e < g.E; ++e) { mu[e] = 0.0f; dmu[e] = 0.0; }
+        for (int t = 1; t <= T; ++t) {
+            for (int i = 0; i < M; ++i) {
+                for (int e = g.rowptr[i]; e < g.rowptr[i + 1]; ++e) {
+                    const float pre = Lam[g.col[e]] - mu[e];
+                    nu[e] = pre > L ? L : (pre < -L ? -L : pre);
+                    dnu[e] = (pre > -L && pre < L) ? dLam[g.col[e]] - dmu[e] : 0.0;
+                }
+                for (int e = g.rowptr[i]; e < g.rowptr[i + 1]; ++e) {
+                    int negative = sigma[i] ? 1 : 0, k = -1;
+                    float mag = INFINITY;
+                    for (int e2 = g.rowptr[i]; e2 < g.rowptr[i + 1]; ++e2) {
+                        if (e2 == e) continue;
+                        if (nu[e2] < 0) negative ^= 1;
+                        if (fabsf(nu[e2]) < mag) { mag = fabsf(nu[e2]); k = e2; }
+                    }
+                    const float m = negative ? -mag : mag;
+                    mu[e] = m > L ? L : (m < -L ? -L : m);
+                    if (k < 0 || !(mag < L)) {
+                        dmu[e] = 0.0;
+                    } else {
+                        const double sg = nu[k] > 0 ? 1.0 : (nu[k] < 0 ? -1.0 : 0.0);
+                        dmu[e] = (negative ? -1.0 : 1.0) * sg * dnu[k];
+                    }
+                }
+            }
+            for (int j = 0; j < N; ++j) {
+                const float gj = gamma[j];
+                const float cl = Lam[j] > L ? L : (Lam[j] < -L ? -L : Lam[j]);
+                const float a = (1.0f - gj) * wp[j];
+                const float bb = gj * cl;
+                const float pre = a + bb;
+                float acc = pre > L ? L : (pre < -L ? -L : pre);
+                double dacc = 0.0;
+                if (pre > -L && pre < L) {
+                    dacc = (1.0 - (double)gj) * dwp[j] + dgamma[j] * ((double)cl - (double)wp[j]);
+                    if (Lam[j] > -L && Lam[j] < L) dacc += (double)gj * dLam[j];
+                }
+                for (int c = g.colptr[j]; c < g.colptr[j + 1]; ++c) {
+                    acc += mu[g.cedge[c]];
+                    dacc += dmu[g.cedge[c]];
+                }
+                Lam[j] = acc;
+                dLam[j] = dacc;
+            }
+        }
+        for (int j = 0; j < N; ++j) {
+            lam_out[(size_t)b * N + j] = Lam[j];
+            dlam_out[(size_t)b * N + j] = dLam[j];
+        }
+    }
+    free(w); free(wp); free(Lam); free(mu); free(nu); free(dwp); free(dLam); free(dmu); free(dnu);
+    graph_free(&g);
+    return 0;
+}
