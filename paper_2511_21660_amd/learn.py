@@ -102,20 +102,37 @@ def soft_decoding_loss_np(llr, syndromes, faults, h, logical, eps=1e-7):
 
 
 def train_first_leg(decoder, problem, sample, steps=2000, t_iters=60, ckpt_every=10, lr=1e-2,
-                    gamma_init=0.125, scale_init=1.0, log_every=100, log=None):
+                    gamma_init=0.125, scale_init=1.0, log_every=100, log=None, gamma_range=None,
+                    learn_scale=True):
     """Adam on (gamma_j, s) through the unrolled first leg.
 
     decoder: a relaybp.Decoder for `problem`; sample(step) -> (faults, syndromes)
     uint8 numpy arrays [B, N], [B, M] of freshly drawn errors.  t_iters: the
     unrolled depth, or a tuple of depths whose losses are averaged (each depth
-    is one forward / adjoint pass from the initial LLRs).  Returns (gamma
+    is one forward / adjoint pass from the initial LLRs).  gamma_range (lo, hi):
+    learn gamma_j = lo + (hi - lo) sigmoid(theta_j) instead of gamma_j itself,
+    which keeps every strength inside the range the paper draws later legs
+    from (the adjoint gives dLoss/dgamma; torch applies the chain rule through
+    the sigmoid).  learn_scale=False holds s at scale_init.  Returns (gamma
     float32 [N], scale float, history list of (step, loss)).
     """
     depths = (t_iters,) if isinstance(t_iters, int) else tuple(t_iters)
     dev = torch.device("cuda", decoder.device)
-    gamma = torch.full((problem.n,), gamma_init, dtype=torch.float32, device=dev, requires_grad=True)
-    scale = torch.tensor([scale_init], dtype=torch.float32, device=dev, requires_grad=True)
-    opt = torch.optim.Adam([gamma, scale], lr=lr)
+    if gamma_range is None:
+        theta = torch.full((problem.n,), gamma_init, dtype=torch.float32, device=dev, requires_grad=True)
+
+        def gamma_of(th):
+            return th
+    else:
+        lo, hi = (float(x) for x in gamma_range)
+        u0 = (gamma_init - lo) / (hi - lo)
+        theta = torch.full((problem.n,), float(np.log(u0 / (1.0 - u0))), dtype=torch.float32, device=dev,
+                           requires_grad=True)
+
+        def gamma_of(th):
+            return lo + (hi - lo) * torch.sigmoid(th)
+    scale = torch.tensor([scale_init], dtype=torch.float32, device=dev, requires_grad=learn_scale)
+    opt = torch.optim.Adam([theta, scale] if learn_scale else [theta], lr=lr)
     h = incidence(problem.rows, problem.cols, problem.m, problem.n, dev)
     lg = torch.from_numpy(problem.logical.astype(np.float32)).to(dev)
     history = []
@@ -124,6 +141,7 @@ def train_first_leg(decoder, problem, sample, steps=2000, t_iters=60, ckpt_every
         d_syn = torch.from_numpy(s).to(dev)
         d_f = torch.from_numpy(f).to(dev)
         loss = 0.0
+        gamma = gamma_of(theta)
         for t in depths:
             llr = RelayUnroll.apply(decoder, d_syn, gamma, scale, t, ckpt_every)
             loss = loss + soft_decoding_loss(llr, d_syn, d_f, h, lg)
@@ -135,4 +153,4 @@ def train_first_leg(decoder, problem, sample, steps=2000, t_iters=60, ckpt_every
             history.append((step, float(loss.item())))
             if log is not None:
                 log(f"step {step} loss {history[-1][1]:.5f} scale {float(scale.item()):.4f}")
-    return gamma.detach().cpu().numpy(), float(scale.item()), history
+    return gamma_of(theta).detach().cpu().numpy(), float(scale.item()), history

@@ -93,6 +93,65 @@ def test_adjoint_matches_fp64_finite_differences(rb):
     assert abs(s_gpu - cen) <= 1e-3 * abs(cen), (s_gpu, cen)
 
 
+def _setup_range(b, seed, lo, hi, p=0.04, name="bb144"):
+    prob = codes.bb_problem(name, p)
+    faults, syn = sampling.sample_batch(prob, (5 << 32) | seed, 0, b)
+    gamma = np.random.default_rng(seed).uniform(lo, hi, prob.n).astype(np.float32)
+    return prob, faults, syn, gamma
+
+
+def test_adjoint_at_full_depth_matches_oracle_tangents(rb):
+    """The adjoint at the training depth: T = 60 unrolled iterations with
+    checkpoints every 10, 64 shots of [[144,12,12]] at p = 0.04, gamma_j drawn
+    around the first-leg value (U(0.05, 0.2)).  Finite differences carry no
+    information at this depth (Lambda grows to ~1e19 and the loss has a kink
+    within 1e-10 of almost every point), so the reference is the oracle's
+    forward-mode tangent along the same FP32 trajectory: for 40 coordinates
+    with the largest |g_j|, g_j must equal sum_b <dL/dLambda_b(T),
+    dLambda_b(T)/dgamma_j> with dL/dLambda in FP64, rel. tol. 1e-3; the scale
+    to within the FP32 bound of its (ill-conditioned) sum."""
+    from paper_2511_21660_amd import learn
+
+    prob, faults, syn, gamma = _setup_range(64, 13, 0.05, 0.2)
+    T, C, scale = 60, 10, 1.0
+    llr, g_gpu, s_gpu, _ = _gpu_forward_backward(rb, prob, faults, syn, gamma, scale, T, C)
+    ref = oracle.trace(prob.m, prob.n, prob.rows, prob.cols, prob.prior, gamma, T, syn, scale=scale)[:, T]
+    np.testing.assert_array_equal(llr, ref)
+    lam = torch.from_numpy(llr.astype(np.float64)).requires_grad_(True)
+    h = learn.incidence(prob.rows, prob.cols, prob.m, prob.n, "cpu")
+    lg = torch.from_numpy(prob.logical.astype(np.float32))
+    loss = learn.soft_decoding_loss(lam, torch.from_numpy(syn), torch.from_numpy(faults), h, lg)
+    loss.backward()
+    dl = lam.grad.numpy()
+    assert np.abs(g_gpu).max() > 0.0
+    order = np.argsort(-np.abs(g_gpu))[:40]
+    for j in order:
+        d = np.zeros(prob.n)
+        d[j] = 1.0
+        _, tan = oracle.tangent(prob.m, prob.n, prob.rows, prob.cols, prob.prior, gamma, T, syn, d, 0.0,
+                                scale=scale)
+        expect = float((dl * tan).sum())
+        assert abs(g_gpu[j] - expect) <= 1e-3 * abs(expect), (j, g_gpu[j], expect)
+    # The scale: dL/ds = sum_k d0_k w_k with d0_k = dL/dw'_k.  At this depth the
+    # sum cancels to ~1e-8 of sum_k |d0_k w_k| (the shots that carry the loss
+    # are chaotic), so FP32 can hold it only to eps32 * kappa; check the
+    # oracle's two routes agree, and the GPU to within that bound.
+    w = np.log((1.0 - prob.prior) / prob.prior).astype(np.float32).astype(np.float64)
+    d0 = np.zeros(prob.n)
+    for k in range(prob.n):
+        d = np.zeros(prob.n)
+        d[k] = 1.0
+        _, tan = oracle.tangent(prob.m, prob.n, prob.rows, prob.cols, prob.prior, gamma, T, syn,
+                                np.zeros(prob.n), 0.0, scale=scale, dwprime=d)
+        d0[k] = float((dl * tan).sum())
+    _, tan = oracle.tangent(prob.m, prob.n, prob.rows, prob.cols, prob.prior, gamma, T, syn,
+                            np.zeros(prob.n), 1.0, scale=scale)
+    expect = float((dl * tan).sum())
+    kappa = float(np.abs(d0 * w).sum())
+    assert abs(expect - float((d0 * w).sum())) <= 1e-9 * kappa
+    assert abs(s_gpu - expect) <= 1e-3 * abs(expect) + 2.0 ** -23 * kappa, (s_gpu, expect, kappa)
+
+
 def test_adjoint_deterministic_and_checkpoint_invariant(rb):
     prob, faults, syn, gamma = _setup(b=64, seed=5)
     runs = [_gpu_forward_backward(rb, prob, faults, syn, gamma, 1.0, 30, c) for c in (10, 10, 7, 30)]
