@@ -7,10 +7,25 @@
   bytes each way; stamped with a hash of the kernel sources so that a stale
   figure is recognised after the kernels change.
 
+* ``counters``: VALU and LDS activity of a kernel from one ``--pmc`` run of
+  SQ counters (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_INSTS_LDS,
+  SQ_LDS_BANK_CONFLICT, SQ_LDS_IDX_ACTIVE, SQ_WAIT_INST_LDS, SQ_BUSY_CU_CYCLES,
+  GRBM_GUI_ACTIVE), normalised by the edge-updates of one launch:
+    - cycles of a launch: GRBM_GUI_ACTIVE / XCDs (the counter sums the XCDs);
+    - VALU busy: 4 SQ_ACTIVE_INST_VALU / (SIMDs x cycles) (quad-cycles, one
+      per wave64 VALU instruction on a 16-lane SIMD);
+    - lane-ops per edge-update: 64 SQ_INSTS_VALU / edge-updates (against the
+      algorithmic count of the update rules);
+    - LDS instructions per edge-update: 64 SQ_INSTS_LDS / edge-updates;
+    - LDS active: SQ_LDS_IDX_ACTIVE / (CUs x cycles); bank-conflict share:
+      SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.
+
 Usage (after the rocprofv3 runs):
     python -m paper_2511_21660_amd.profiling stats KERNEL_STATS_CSV
     python -m paper_2511_21660_amd.profiling traffic --fetch FETCH_CSV --write WRITE_CSV \
         --kernel relay_mixed_kernel --copy-kernel elementwise --copy-bytes N --out OUT_JSON
+    python -m paper_2511_21660_amd.profiling counters --sq SQ_CSV --kernel relay_block_kernel \
+        --edge-updates EU --ops-per-edge-update OPS [--launches-skip 0]
 """
 from __future__ import annotations
 
@@ -72,6 +87,37 @@ def traffic(fetch_csv, write_csv, kernel, copy_kernel, copy_bytes):
             "write_scale": write_scale, "source_hash": source_hash()}
 
 
+def _counter_rows(path: str, kernel: str):
+    """{counter: [value per dispatch]} of the dispatches whose kernel name
+    contains `kernel` (rows of one dispatch share its Dispatch_Id)."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if kernel not in r["Kernel_Name"]:
+            continue
+        per.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    return [per[k] for k in sorted(per, key=int)]
+
+
+def counters(sq_csv, kernel, edge_updates, ops_per_eu, cus=256, simds_per_cu=4, xcds=8, skip=0):
+    """Derived VALU / LDS activity per launch, averaged over the dispatches
+    (after `skip`), for a launch of `edge_updates` edge-updates."""
+    rows = _counter_rows(sq_csv, kernel)[skip:]
+    if not rows:
+        raise SystemExit(f"no dispatch of {kernel!r} in {sq_csv}")
+    mean = {k: sum(r[k] for r in rows) / len(rows) for k in rows[0]}
+    cyc = mean["GRBM_GUI_ACTIVE"] / xcds
+    out = {"kernel": kernel, "dispatches": len(rows), "cycles_per_launch": cyc,
+           "valu_busy": 4.0 * mean["SQ_ACTIVE_INST_VALU"] / (cus * simds_per_cu * cyc),
+           "lane_ops_per_edge_update": 64.0 * mean["SQ_INSTS_VALU"] / edge_updates,
+           "algorithmic_ops_per_edge_update": ops_per_eu,
+           "lds_instructions_per_edge_update": 64.0 * mean["SQ_INSTS_LDS"] / edge_updates,
+           "lds_active": mean["SQ_LDS_IDX_ACTIVE"] / (cus * cyc),
+           "lds_bank_conflict_share": mean["SQ_LDS_BANK_CONFLICT"] / max(1.0, mean["SQ_LDS_IDX_ACTIVE"]),
+           "raw_means": mean, "source_hash": source_hash()}
+    out["algorithmic_share_of_valu"] = ops_per_eu / out["lane_ops_per_edge_update"]
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -84,7 +130,17 @@ def main(argv=None):
     t.add_argument("--copy-kernel", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--sq", required=True)
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--edge-updates", type=float, required=True)
+    c.add_argument("--ops-per-edge-update", type=float, required=True)
+    c.add_argument("--launches-skip", type=int, default=0)
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        print(json.dumps(counters(a.sq, a.kernel, a.edge_updates, a.ops_per_edge_update, skip=a.launches_skip),
+                         indent=1))
+        return 0
     if a.cmd == "stats":
         print(stats_table(a.csv))
     else:
