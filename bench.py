@@ -119,13 +119,24 @@ def logical_failures(prob, faults, corr, conv):
     return (~conv.astype(bool)) | bad
 
 
+WARM_SECONDS = 0.3  # the GPU's clocks ramp up over the first ~0.1-0.3 s of load
+
+
 def timed(torch, step, n_launch, steps, warmup):
-    """warmup untimed steps, then `steps` steps bracketed by device
-    synchronisation.  step(ev) records ev[k] = (start, end) HIP events on the
-    launch stream around launch k (ev is None during warm-up)."""
+    """warmup untimed steps (continued, up to 1000 steps, until WARM_SECONDS
+    have passed, so that short launches are not timed at idle clocks), then
+    `steps` steps bracketed by device synchronisation.  step(ev) records ev[k]
+    = (start, end) HIP events on the launch stream around launch k (ev is None
+    during warm-up)."""
+    t_warm = time.perf_counter()
     for _ in range(warmup):
         step(None)
     torch.cuda.synchronize()
+    extra = 0
+    while time.perf_counter() - t_warm < WARM_SECONDS and extra < 1000:
+        step(None)
+        torch.cuda.synchronize()
+        extra += 1
     evs = []
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -176,6 +187,8 @@ def head(args, value, elapsed, config):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_note": f"each timed loop runs its warmup steps, then untimed steps until {WARM_SECONDS} s "
+                       "of load have passed (clock ramp-up)",
         "ms_per_step": elapsed * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",

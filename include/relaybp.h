@@ -192,7 +192,8 @@ void rb_destroy(rb_ctx *ctx);
  *   d_weight     double [B] out or NULL: sum_j F_hat_j w_j of d_corr
  *   d_final_llr  float [B][N] out or NULL: marginals Lambda after the last iteration
  * B == 0 is a no-op.  Returns RB_E_INVALID_ARG for null required pointers or
- * B < 0.  Enqueues on `stream`; no allocation, no synchronisation.
+ * B < 0, RB_E_SHAPE for B >= 2^31 (shots are indexed in 32 bits).  Enqueues
+ * on `stream`; no allocation, no synchronisation.
  */
 rb_status rb_decode(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, uint8_t *d_corr,
                     uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters, double *d_weight,
@@ -208,6 +209,7 @@ rb_status rb_decode(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, uint8_t 
  *   T            >= 0 iterations
  *   d_trace      float [B][T+1][N] out: Lambda_j(t) for t = 0..T
  * Same kernels as rb_decode (message-level parity hook).  Enqueues on `stream`.
+ * RB_E_SHAPE for B >= 2^31.
  */
 rb_status rb_trace(rb_ctx *ctx, int64_t B, const uint8_t *d_syndromes, const float *d_gamma,
                    float scale, int32_t T, float *d_trace, void *stream);
@@ -365,7 +367,7 @@ rb_status rb_decode_multi(rb_ctx *ctx, int64_t B, const int32_t *d_code_id,
  * allocate device memory: code being captured into a hipGraph, tight serving
  * loops, harnesses that forbid hipMalloc.  Same arguments (minus d_workspace
  * and workspace_bytes), same results as rb_decode_multi.  The shot lists and
- * queue counters live in a static device array of 8 MiB that the library
+ * queue counters live in a static device array of 12 MiB that the library
  * holds on every GPU it runs on until the process ends; the call allocates
  * nothing (no hipMalloc, hipFree or allocating library routine), clears what
  * must start at zero with small kernels (no memset), and only enqueues on

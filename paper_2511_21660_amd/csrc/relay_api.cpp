@@ -91,6 +91,10 @@ struct rb_ctx {
     // families: codes with the same graph and tile (one shot list each)
     int32_t nfam = 0;
     int32_t *d_code_fam = nullptr, *d_fam_rep = nullptr, *d_fam_size = nullptr;
+    // w and gamma of every code, the members of each family stored contiguously,
+    // and each code's member index within its family
+    float *d_wcat = nullptr, *d_gcat = nullptr;
+    int32_t *d_code_member = nullptr;
     int32_t m_max = 0, n_max = 0;
     // large-graph kernel (compressed messages): CSR / CSC copies and tables
     bool large = false;
@@ -1841,6 +1845,13 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_fam_rep);
         (void)hipFree(c->d_fam_size);
     }
+    if (c->d_wcat || c->d_gcat || c->d_code_member) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(c->d_wcat);
+        (void)hipFree(c->d_gcat);
+        (void)hipFree(c->d_code_member);
+    }
     for (rb_ctx *s : c->subs) rb_destroy(s);
     delete c;
 }
@@ -2012,6 +2023,7 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (B < 0) return fail(RB_E_INVALID_ARG, "B must be >= 0");
     if (B == 0) return RB_OK;
+    if (B > INT32_MAX) return fail(RB_E_SHAPE, "B exceeds 2^31 - 1");
     if (!d_syn || !d_corr || !d_conv || !d_legs || !d_iters)
         return fail(RB_E_INVALID_ARG, "a required device pointer is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use rb_decode_multi");
@@ -2027,7 +2039,7 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
         hipStream_t s = (hipStream_t)stream;
         RB_HIP(hipSetDevice(c->device), "hipSetDevice");
         RB_HIP(rb::launch_shot_lists(B, d_syn, a.syn_stride, a.io_bits != 0, nullptr, c->d_code_m, 1, nullptr, 1,
-                                     c->d_ws, c->d_queue, s),
+                                     nullptr, c->d_ws, c->d_queue, s),
                "shot list kernels");
         a.list = (const int32_t *)c->d_ws + (size_t)(rb::kListHeader + B);
         RB_HIP(rb::launch_group(c->variant, c->params.anchor == RB_ANCHOR_PRIOR, false, a,
@@ -2060,6 +2072,7 @@ rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_ga
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: trace one code's own context");
     if (B < 0 || T < 0) return fail(RB_E_INVALID_ARG, "B and T must be >= 0");
+    if (B > INT32_MAX) return fail(RB_E_SHAPE, "B exceeds 2^31 - 1");
     if (!std::isfinite(scale)) return fail(RB_E_NONFINITE, "scale must be finite");
     if (c->h16 && scale != 1.0f) return fail(RB_E_UNSUPPORTED, "the binary16 mode has no prior scale");
     if (B == 0) return RB_OK;
@@ -2427,15 +2440,14 @@ namespace {
 
 // per-code data the mixed kernel reads
 rb_status upload_codes(rb_ctx *m) {
-    std::vector<rb::CodeStatic> cs(m->subs.size());
+    const size_t nc = m->subs.size();
+    std::vector<rb::CodeStatic> cs(nc);
     int lds = 0;
-    for (size_t k = 0; k < m->subs.size(); ++k) {
+    for (size_t k = 0; k < nc; ++k) {
         const rb_ctx *s = m->subs[k];
         cs[k].M = s->M;
         cs[k].N = s->N;
         cs[k].tile = rb::mixed_tile_of_variant(s->variant);
-        cs[k].w = s->d_w;
-        cs[k].gamma = s->d_gamma;
         cs[k].lam_off = s->d_lam_off;
         cs[k].mu_off = s->d_mu_off;
         cs[k].lampad_off = s->lampad_off;
@@ -2445,19 +2457,17 @@ rb_status upload_codes(rb_ctx *m) {
         lds = std::max(lds, s->lds_bytes);
         if (cs[k].tile < 0) return fail(RB_E_UNSUPPORTED, "code planned outside the mixed tile set");
     }
-    rb_status st = upload(&m->d_codes, cs, "upload code table");
-    if (st != RB_OK) return st;
     // families: same tile and the same graph (identical CSR), hence identical
     // gather tables and LDS layout; members differ only in w and gamma
-    std::vector<int32_t> fam(m->subs.size(), -1), rep, size;
-    for (size_t k = 0; k < m->subs.size(); ++k) {
+    std::vector<int32_t> fam(nc, -1), member(nc, 0), rep, size;
+    for (size_t k = 0; k < nc; ++k) {
         const rb_ctx *a = m->subs[k];
         for (size_t f = 0; f < rep.size() && fam[k] < 0; ++f) {
             const rb_ctx *b = m->subs[(size_t)rep[f]];
             if (cs[k].tile == cs[(size_t)rep[f]].tile && a->M == b->M && a->N == b->N && a->rowptr == b->rowptr &&
                 a->colidx == b->colidx) {
                 fam[k] = (int32_t)f;
-                ++size[f];
+                member[k] = size[f]++;
             }
         }
         if (fam[k] < 0) {
@@ -2466,6 +2476,36 @@ rb_status upload_codes(rb_ctx *m) {
             size.push_back(1);
         }
     }
+    // w and gamma of all codes, family by family, members in order
+    const int R = m->params.num_legs;
+    std::vector<size_t> woff(nc), goff(nc);
+    size_t wtot = 0, gtot = 0;
+    for (size_t f = 0; f < rep.size(); ++f)
+        for (size_t k = 0; k < nc; ++k)
+            if (fam[k] == (int32_t)f) {
+                woff[k] = wtot;
+                goff[k] = gtot;
+                wtot += (size_t)m->subs[k]->N;
+                gtot += (size_t)R * m->subs[k]->N;
+            }
+    std::vector<float> wcat(wtot), gcat(gtot);
+    for (size_t k = 0; k < nc; ++k) {
+        const rb_ctx *s = m->subs[k];
+        RB_HIP(hipMemcpy(wcat.data() + woff[k], s->d_w, sizeof(float) * (size_t)s->N, hipMemcpyDeviceToHost),
+               "read code w");
+        RB_HIP(hipMemcpy(gcat.data() + goff[k], s->d_gamma, sizeof(float) * (size_t)R * s->N,
+                         hipMemcpyDeviceToHost),
+               "read code gamma");
+    }
+    rb_status st = upload(&m->d_wcat, wcat, "upload code w");
+    if (st != RB_OK) return st;
+    if ((st = upload(&m->d_gcat, gcat, "upload code gamma")) != RB_OK) return st;
+    for (size_t k = 0; k < nc; ++k) {
+        cs[k].w = m->d_wcat + woff[k];
+        cs[k].gamma = m->d_gcat + goff[k];
+    }
+    if ((st = upload(&m->d_codes, cs, "upload code table")) != RB_OK) return st;
+    if ((st = upload(&m->d_code_member, member, "upload code members")) != RB_OK) return st;
     m->nfam = (int32_t)rep.size();
     if ((st = upload(&m->d_code_fam, fam, "upload code families")) != RB_OK) return st;
     if ((st = upload(&m->d_fam_rep, rep, "upload family members")) != RB_OK) return st;
@@ -2556,7 +2596,7 @@ static rb_status launch_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code
     const bool bits = c->params.io_layout == RB_IO_BITS32;
     const int32_t syn_stride = bits ? (c->m_max + 31) / 32 : c->m_max;
     RB_HIP(rb::launch_shot_lists(B, d_syn, syn_stride, bits, d_code_id, c->d_code_m, nc, c->d_code_fam, c->nfam,
-                                 ws_bytes, queues, s),
+                                 c->d_code_member, ws_bytes, queues, s),
            "shot list kernels");
     rb::MixedArgs m{};
     m.run = base_args(c->subs[0], B, d_syn);
@@ -2574,12 +2614,12 @@ static rb_status launch_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code
     m.nfam = c->nfam;
     m.fam_rep = c->d_fam_rep;
     m.fam_size = c->d_fam_size;
-    m.code_id = d_code_id;
     const int32_t *ws = (const int32_t *)ws_bytes;
     m.seg_start = ws + (size_t)nc * rb::kWeightBinsHost;
     m.seg_count = m.seg_start + nc;
     m.order = m.seg_count + nc;
     m.list = ws + (size_t)nc * (rb::kWeightBinsHost + 3) + (size_t)B;
+    m.list_cid = m.list + B;
     m.queues = queues;
     const int64_t full = (int64_t)c->blocks_per_cu[0] * c->num_cu;
     const int grid = (int)std::max<int64_t>(1, full);
@@ -2627,7 +2667,7 @@ int64_t rb_noalloc_max_batch(const rb_ctx *c) {
     const size_t off = noalloc_list_offset(nc);
     const size_t head = rb::shot_list_bytes(0, nc);
     if (off + head > rb::kNoAllocScratchBytes) return 0;
-    return (int64_t)((rb::kNoAllocScratchBytes - off - head) / (2 * sizeof(int32_t)));
+    return (int64_t)((rb::kNoAllocScratchBytes - off - head) / (3 * sizeof(int32_t)));
 }
 
 rb_status rb_decode_multi_noalloc(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn,

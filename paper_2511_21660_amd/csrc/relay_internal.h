@@ -22,9 +22,11 @@ struct CodeStatic;
 // Work queues of the group kernels: kQueueSplit counters, kQueueStride
 // unsigned long longs (256 bytes) apart; slot s claims positions
 // s % kQueueSplit + kQueueSplit * n from counter s % kQueueSplit, which spreads
-// the claims of thousands of slots over several L2 atomic units.  The block
-// kernel uses counter 0 alone.  A queue occupies kQueueWords words.
-constexpr int kQueueSplit = 8;
+// the claims of thousands of slots over many addresses: device-scope atomics
+// on one address serialise (with 8 counters the claims alone took ~1 ms per
+// 4 x 10^5 syndromes; 64 counters cut that 4-fold, more gain little).  The
+// block kernel uses counter 0 alone.  A queue occupies kQueueWords words.
+constexpr int kQueueSplit = 64;
 constexpr int kQueueStride = 32;
 constexpr int kQueueWords = kQueueSplit * kQueueStride;
 
@@ -54,10 +56,10 @@ struct GroupArgs {
     float *final_llr;     // [B][N] or null
     const float *w;       // [N] channel LLRs
     const float *gamma;   // [R][N] memory strengths, row r-1 = leg r
-    // codes sharing one graph (mixed launch): when code_id is set, the shot's
-    // own code, codes[code_id[shot]], supplies w and gamma
-    const int32_t *code_id;
-    const CodeStatic *codes;
+    // codes sharing one graph (mixed launch): when list_cid is set, queue
+    // position k belongs to family member list_cid[k], whose w and gamma
+    // follow member 0's at w + list_cid[k] * N and gamma + list_cid[k] * R * N
+    const int32_t *list_cid;
     // per-lane gather tables, two 16-bit slot-relative LDS byte offsets per
     // word: lane g's entries e = c*DC + k (Lambda of check edge) and
     // e = v*DV + k (mu of fault edge) at word g*ceil(n/2) + e/2, half e%2
@@ -244,6 +246,9 @@ hipError_t launch_large(int v, bool prior_anchor, bool trace, const LargeArgs &a
 struct CodeStatic {
     int32_t M, N;
     int32_t tile;  // index into the mixed tile switch
+    // w [N] and gamma [R][N]; the members of a family are stored one after
+    // another in member order, so member i's follow member 0's by i * N and
+    // i * R * N floats
     const float *w;
     const float *gamma;
     const uint32_t *lam_off;
@@ -261,8 +266,8 @@ struct MixedArgs {
     int32_t nfam;
     const int32_t *fam_rep;
     const int32_t *fam_size;
-    const int32_t *code_id;    // [B] code of each shot
     const int32_t *list;       // shot lists, all codes
+    const int32_t *list_cid;   // family member of each list position
     const int32_t *seg_start;  // [nfam] (device, written by the list kernels)
     const int32_t *seg_count;  // [nfam]
     const int32_t *order;      // [nfam] family visiting order (device, written by the list kernels)
@@ -291,18 +296,20 @@ hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowpt
 // positions sorted by (family, decreasing syndrome weight), the family of
 // code c being code_fam[c] (identity when code_fam is null); the list of
 // family f starts at list + seg_start[f] and holds seg_count[f] shots.  Also
-// zeroes the per-family queue counters.  Layout (sized for ncodes >= nfam):
-// hist[ncodes*256], seg_start[ncodes], seg_count[ncodes], order[ncodes],
-// key[B], list[B] (int32).
+// zeroes the per-family queue counters.  With code_member (member index of
+// each code within its family), list_cid[p] = code_member[code_id[list[p]]].
+// Layout (sized for ncodes >= nfam): hist[ncodes*256], seg_start[ncodes],
+// seg_count[ncodes], order[ncodes], key[B], list[B], list_cid[B] (int32).
 // (syn_stride in elements of the layout: bytes, or words when bits is set)
 hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, bool bits, const int32_t *code_id,
                              const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam,
-                             void *workspace, unsigned long long *queues, hipStream_t s);
+                             const int32_t *code_member, void *workspace, unsigned long long *queues,
+                             hipStream_t s);
 size_t shot_list_bytes(int64_t B, int ncodes);
 // Static scratch of the no-allocation mixed decode (queue counters of every
 // code, then the shot lists): its size, and its device address on `device`,
 // which must be the current device (looked up once per device, then cached).
-constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+constexpr size_t kNoAllocScratchBytes = size_t(12) << 20;
 constexpr int kMaxDevices = 64;
 hipError_t noalloc_scratch(int device, void **ptr);
 constexpr int kWeightBinsHost = 256;              // weight bins of the shot-list sort

@@ -206,7 +206,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     uint32_t sig = 0;        // sigma bits of the lane's checks
     uint32_t best_mask = 0;  // best solution bits of the lane's faults
     double best_w = 0.0;
-    long long shot = -1;
+    int shot = -1;  // shots are indexed in 32 bits (B < 2^31)
     int r = 0, t = 0, total = 0, count = 0;
     bool active = false;
 
@@ -217,23 +217,19 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
             for (int k = 0; k < DC; ++k) lds_at<float>(lds, mu_row0 + c * ROW_STRIDE + KSTRIDE * k) = 0.0f;
     };
 
-    // w and gamma of the code of the slot's shot: the launch's own, or (MULTI,
-    // codes sharing one graph) those of codes[cid], cid = code_id[shot] set by
-    // fetch; the pointers are looked up where used (event paths only), so
-    // the loop carries one index rather than two pointers
+    // w and gamma of a code: the launch's own, or (MULTI, codes sharing one
+    // graph) those of family member cid, stored contiguously after member 0
+    // (w at a.w + cid * N, memory strengths at a.gamma + cid * R * N)
     int cid = 0;
-    auto code_w = [&]() -> const float * { return (MULTI && a.code_id) ? a.codes[cid].w : a.w; };
-    auto code_gamma = [&]() -> const float * { return (MULTI && a.code_id) ? a.codes[cid].gamma : a.gamma; };
+    auto code_w = [&](int c) -> const float * { return (MULTI && a.list_cid) ? a.w + (size_t)c * a.N : a.w; };
+    auto code_gamma = [&](int c) -> const float * {
+        return (MULTI && a.list_cid) ? a.gamma + (size_t)c * a.num_legs * a.N : a.gamma;
+    };
 
-    // sum of w_j over the lane's faults with Lambda_j < 0 (FP64, over the
-    // slot's G lanes) and the decision bits; the loads are unconditional
-    // (indices clamped) so they issue together, and adding +0 for the other
-    // faults leaves the sum's bits unchanged
-    auto weight_of = [&](uint32_t &fm) -> double {
-        float wv[VPT];
-        const float *cw = code_w();
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) wv[v] = cw[min((int)gl + G * v, a.N - 1)];
+    // sum of wv_j over the lane's faults with Lambda_j < 0 (FP64, over the
+    // slot's G lanes) and the decision bits; adding +0 for the other faults
+    // leaves the sum's bits unchanged
+    auto weight_of = [&](const float (&wv)[VPT], uint32_t &fm) -> double {
         double part = 0.0;
         fm = 0;
 #pragma unroll
@@ -245,67 +241,87 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         return group_sum<G>(part);
     };
 
-    // Take the next syndrome for this slot and initialise leg 1.  The slot
-    // draws positions sq + kQueueSplit * n from sub-counter sq, claimed one
-    // ahead: lane 0 of the slot holds the position claimed at the previous
-    // fetch (its atomic has long completed) and claims the following one, so
-    // no fetch waits on the queue atomic.
+    // The queue.  The slot draws positions sq + kQueueSplit * n from
+    // sub-counter sq and works one position ahead: nx_shot / nx_cid hold the
+    // shot (or -1: the queue is exhausted) and family member at the position
+    // it will take next, loaded when the previous syndrome started, and lane 0
+    // holds the n claimed for the position after that, so starting a syndrome
+    // waits on neither the queue atomic nor the list.
     const unsigned sq = (blockIdx.x * (unsigned)NS + (unsigned)slot) % (unsigned)kQueueSplit;
     unsigned long long *const qk = a.queue + (size_t)sq * kQueueStride;
-    unsigned long long claim = 0;
-    if (g == 0) claim = atomicAdd(qk, 1ull);
-    auto fetch = [&]() {
-        const unsigned long long nxt = (unsigned long long)sq + kQueueSplit * __shfl(claim, 0, G);
-        if (nxt >= (unsigned long long)a.count) {
-            active = false;
-            return;
+    unsigned claim = 0;
+    int nx_shot = -1;
+    int nx_cid = 0;
+    auto prefetch = [&]() {
+        const unsigned long long p = (unsigned long long)sq + kQueueSplit * (unsigned long long)__shfl(claim, 0, G);
+        nx_shot = -1;
+        if (p < (unsigned long long)a.count) {
+            nx_shot = a.list ? a.list[p] : (int)p;
+            if (MULTI && a.list_cid) nx_cid = a.list_cid[p];
+            if (g == 0) claim = (unsigned)atomicAdd(qk, 1ull);
         }
-        if (g == 0) claim = atomicAdd(qk, 1ull);
-        active = true;
-        shot = a.list ? (long long)a.list[nxt] : (long long)nxt;
-        if (MULTI && a.code_id) cid = a.code_id[shot];
-        const float *cw = code_w(), *cgam = code_gamma();
-        // loads unconditional (indices clamped, so in bounds): they issue together
-        float wv[VPT], gv[VPT];
+    };
+
+    // Loads that start the prefetched syndrome (indices clamped, so in bounds,
+    // and unconditional: they issue together): the leg-1 memory strengths of
+    // its code into gm and, when the code is not the launch's own, its w into
+    // xl (both arrays are dead once a syndrome is done); then its syndrome
+    // bits, folded into a mask (the first use: one wait covers every load).
+    auto load_start = [&](bool own_w) -> uint32_t {
+        const float *cg = TRACE ? a.trace_gamma : code_gamma(nx_cid);
 #pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int j = min((int)gl + G * v, a.N - 1);
-            wv[v] = cw[j];
-            gv[v] = TRACE ? a.trace_gamma[j] : cgam[j];
+        for (int v = 0; v < VPT; ++v) gm[v] = cg[min((int)gl + G * v, a.N - 1)];
+        if (!own_w) {
+            const float *cw = code_w(nx_cid);
+#pragma unroll
+            for (int v = 0; v < VPT; ++v) xl[v] = cw[min((int)gl + G * v, a.N - 1)];
         }
+        bool sb[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+            sb[c] = syn_bit(a.syn, (size_t)nx_shot, a.syn_stride, min((int)gl + G * c, a.M - 1), a.io_bits);
+        uint32_t m = 0;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+            if ((int)gl + G * c < a.M && sb[c]) m |= 1u << c;
+        return m;
+    };
+    // leg 1 of the prefetched syndrome (channel LLRs wn, gm as loaded), then
+    // the prefetch of the next position
+    auto begin = [&](const float (&wn)[VPT], uint32_t nsig) {
+        shot = nx_shot;
+        cid = nx_cid;
+        active = true;
         r = 1;
         t = 0;
         total = 0;
         count = 0;
         best_w = __longlong_as_double(0x7ff0000000000000ll);  // +inf
         best_mask = 0;
-        sig = 0;
-        bool sb[CPT];
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) sb[c] = syn_bit(a.syn, (size_t)shot, a.syn_stride, min((int)gl + G * c, a.M - 1), a.io_bits);
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int i = (int)gl + G * c;
-            if (i < a.M && sb[c]) sig |= 1u << c;
-        }
+        sig = nsig;
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const int j = (int)gl + G * v;
-            float wj = 0.0f, gj = 0.0f;
-            if (j < a.N) {
-                wj = a.scale * wv[v];
-                gj = gv[v];
-                lds_at<float>(lds, base + WORD * j) = wj;
-                if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
-            }
+            const bool in = j < a.N;
+            const float wj = in ? a.scale * wn[v] : 0.0f;
+            const float gj = in ? gm[v] : 0.0f;
+            // columns j >= N own spare words of the padded Lambda region
+            lds_at<float>(lds, base + WORD * j) = wj;
+            if (TRACE && in) a.trace[(size_t)shot * (a.trace_T + 1) * a.N + j] = wj;
             Lr[v] = wj;
             xl[v] = (1.0f - gj) * wj;
             gm[v] = gj;
         }
         zero_rows();
+        prefetch();
     };
 
-    fetch();
+    if (g == 0) claim = (unsigned)atomicAdd(qk, 1ull);
+    prefetch();
+    if (nx_shot >= 0) {
+        const uint32_t nsig = load_start(false);
+        begin(xl, nsig);
+    }
     wave_sync();
 
     while (__any(active)) {
@@ -369,50 +385,75 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         const bool event = conv_ev || leg_ev;
         if (event) {
             bool done = true;
-            uint32_t fm_conv = 0;
-            if (!TRACE) {
-                if (conv_ev) {
-                    ++count;
-                    const double W = weight_of(fm_conv);
-                    if (W < best_w) {
-                        best_w = W;
-                        best_mask = fm_conv;
-                    }
-                    done = count >= a.num_solutions || r >= a.num_legs || cut;
-                } else {
-                    done = r >= a.num_legs || cut;
+            if (!TRACE) done = (conv_ev && count + 1 >= a.num_solutions) || r >= a.num_legs || cut;
+            const bool start = done && nx_shot >= 0;
+            // One round of loads for the whole event, issued before any store:
+            // w of the shot's code (solution weights, the prior anchor); the
+            // memory strengths of leg r+1 into gm, or those of leg 1 of the
+            // prefetched syndrome with its bits and (codes sharing a graph) w.
+            float wv[VPT];
+            uint32_t nsig = 0;
+            {
+                const float *cw = code_w(cid);
+#pragma unroll
+                for (int v = 0; v < VPT; ++v) wv[v] = cw[min((int)gl + G * v, a.N - 1)];
+            }
+            if (!done) {
+                // lanes past N load column N-1's: their words are never read
+                const float *gr = code_gamma(cid) + (size_t)r * a.N;
+#pragma unroll
+                for (int v = 0; v < VPT; ++v) gm[v] = gr[min((int)gl + G * v, a.N - 1)];
+            } else if (start) {
+                nsig = load_start(!(MULTI && a.list_cid));
+            }
+            if (!TRACE && conv_ev) {
+                ++count;
+                uint32_t fm_conv = 0;
+                const double W = weight_of(wv, fm_conv);
+                if (W < best_w) {
+                    best_w = W;
+                    best_mask = fm_conv;
                 }
             }
             if (!done) {
-                // chain to leg r+1: restart check messages, new Gamma, new anchor
+                // chain to leg r+1: restart check messages, new Gamma (in gm),
+                // new anchor
                 ++r;
                 t = 0;
-                // (indices clamped so every load is in bounds and all issue
-                // together; lanes past N keep their values)
-                const float *gr = code_gamma() + (size_t)(r - 1) * a.N;
-                const float *cw = code_w();
-                float gv[VPT], wv[VPT];
 #pragma unroll
-                for (int v = 0; v < VPT; ++v) {
-                    const int j = min((int)gl + G * v, a.N - 1);
-                    gv[v] = gr[j];
-                    wv[v] = PRIOR ? cw[j] : 0.0f;
-                }
-#pragma unroll
-                for (int v = 0; v < VPT; ++v) {
-                    if ((int)gl + G * v < a.N) {
-                        gm[v] = gv[v];
-                        xl[v] = (1.0f - gv[v]) * (PRIOR ? a.scale * wv[v] : clipf(Lr[v], L));
-                    }
-                }
+                for (int v = 0; v < VPT; ++v) xl[v] = (1.0f - gm[v]) * (PRIOR ? a.scale * wv[v] : clipf(Lr[v], L));
                 zero_rows();
             } else {
+                // the last decision and its weight are the output only when no
+                // leg converged; the outputs are stored after the next syndrome
+                // has started, so its loads are consumed first
+                uint32_t out = 0;
+                double w_out = 0.0;
                 if (!TRACE) {
-                    // the last decision and its weight are the output only when
-                    // no leg converged
                     uint32_t fm = 0;
-                    const double Wlast = count > 0 ? best_w : weight_of(fm);
-                    const uint32_t out = count > 0 ? best_mask : fm;
+                    const double Wlast = count > 0 ? best_w : weight_of(wv, fm);
+                    out = count > 0 ? best_mask : fm;
+                    w_out = count > 0 ? best_w : Wlast;
+                    if (a.final_llr) {
+#pragma unroll
+                        for (int v = 0; v < VPT; ++v) {
+                            const int j = (int)gl + G * v;
+                            if (j < a.N) a.final_llr[(size_t)shot * a.llr_stride + j] = Lr[v];
+                        }
+                    }
+                }
+                const int o_shot = shot;
+                const int o_legs = r, o_iters = total;
+                const bool o_conv = count > 0;
+                if (start) {
+                    if (MULTI && a.list_cid)
+                        begin(xl, nsig);
+                    else
+                        begin(wv, nsig);
+                } else {
+                    active = false;
+                }
+                if (!TRACE) {
                     if (a.io_bits) {
                         // word q of the packed correction holds faults 32q .. 32q+31;
                         // lane g of the slot assembles word g (ceil(N/32) <= G words,
@@ -422,33 +463,25 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
                         for (int v = 0; v < VPT; ++v) {
                             const unsigned long long bal = __ballot((out >> v) & 1u);
-                            const unsigned long long sb = G == 64 ? bal : (bal >> (slot * G)) & ((1ull << (G % 64)) - 1ull);
+                            const unsigned long long sbits = G == 64 ? bal : (bal >> (slot * G)) & ((1ull << (G % 64)) - 1ull);
                             const int d = G * v - 32 * (int)gl;  // bit of word gl where fault G*v lands
-                            if (d > -64 && d < 32) word |= (uint32_t)(d >= 0 ? sb << d : sb >> -d);
+                            if (d > -64 && d < 32) word |= (uint32_t)(d >= 0 ? sbits << d : sbits >> -d);
                         }
-                        if ((int)gl * 32 < a.N) reinterpret_cast<uint32_t *>(a.corr)[(size_t)shot * a.corr_stride + gl] = word;
+                        if ((int)gl * 32 < a.N) reinterpret_cast<uint32_t *>(a.corr)[(size_t)o_shot * a.corr_stride + gl] = word;
                     } else {
 #pragma unroll
                         for (int v = 0; v < VPT; ++v) {
                             const int j = (int)gl + G * v;
-                            if (j < a.N) a.corr[(size_t)shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
-                        }
-                    }
-                    if (a.final_llr) {
-#pragma unroll
-                        for (int v = 0; v < VPT; ++v) {
-                            const int j = (int)gl + G * v;
-                            if (j < a.N) a.final_llr[(size_t)shot * a.llr_stride + j] = Lr[v];
+                            if (j < a.N) a.corr[(size_t)o_shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
                         }
                     }
                     if (g == 0) {
-                        a.conv[shot] = count > 0 ? 1 : 0;
-                        a.legs[shot] = r;
-                        a.iters[shot] = total;
-                        if (a.weight) a.weight[shot] = count > 0 ? best_w : Wlast;
+                        a.conv[o_shot] = o_conv ? 1 : 0;
+                        a.legs[o_shot] = o_legs;
+                        a.iters[o_shot] = o_iters;
+                        if (a.weight) a.weight[o_shot] = w_out;
                     }
                 }
-                fetch();
             }
         }
         wave_sync();
@@ -488,7 +521,8 @@ void relay_group_kernel(GroupArgs a) {
 // Mixed-code launch: each wave decodes one family at a time (the codes that
 // share a graph and a tile, e.g. one code at several noise rates) with the
 // family's compiled tile, drains the family's queue (one longest-first list
-// over all its codes; every slot takes w and gamma from its shot's own code),
+// over all its codes; every slot takes w and gamma from its shot's own code,
+// the member index of each list position standing beside the list),
 // then moves on to the next family in the order the list kernels set.
 // Only tiles within a 128-VGPR budget take part, so mixing never lowers
 // occupancy below what the largest code needs on its own.
@@ -511,10 +545,9 @@ void relay_mixed_kernel(MixedArgs m) {
         a.mu0_off = cs.mu0_off;
         a.half_off = cs.half_off;
         a.list = m.list + m.seg_start[f];
+        a.list_cid = m.fam_size[f] > 1 ? m.list_cid + m.seg_start[f] : nullptr;
         a.count = m.seg_count[f];
         a.queue = m.queues + (size_t)f * kQueueWords;
-        a.code_id = m.fam_size[f] > 1 ? m.code_id : nullptr;
-        a.codes = m.codes;
         switch (cs.tile) {
             case 0: group_loop<8, 5, 6, 9, 3, PRIOR, false, true>(a); break;
             case 1: group_loop<16, 3, 6, 6, 3, PRIOR, false, true>(a); break;
@@ -630,9 +663,13 @@ __global__ void list_scan_kernel(int ncodes, int32_t *hist, int32_t *seg_start, 
 
 // Each block reserves one contiguous range per nonzero (block, bin) and
 // places its shots inside it (order within a bin is irrelevant: every shot's
-// result depends on its own syndrome only).
+// result depends on its own syndrome only); with code_member, also the
+// family member of each placed shot's code.
 __global__ __launch_bounds__(kListThreads) void list_scatter_kernel(int64_t B, int nb, const int32_t *key,
-                                                                    int32_t *pos, int32_t *list) {
+                                                                    int32_t *pos, int32_t *list,
+                                                                    const int32_t *code_id,
+                                                                    const int32_t *code_member,
+                                                                    int32_t *list_cid) {
     // LDS: count[nb], then base[nb]
     const uint32_t cnt0 = 0u, base0 = 4u * (uint32_t)nb;
     for (int k = threadIdx.x; k < nb; k += kListThreads) *(__attribute__((address_space(3))) int32_t *)(size_t)(cnt0 + 4u * k) = 0;
@@ -651,7 +688,11 @@ __global__ __launch_bounds__(kListThreads) void list_scatter_kernel(int64_t B, i
         *(__attribute__((address_space(3))) int32_t *)(size_t)(base0 + 4u * q) = n ? atomicAdd(&pos[q], n) : 0;
     }
     __syncthreads();
-    if (k >= 0) list[*(__attribute__((address_space(3))) int32_t *)(size_t)(base0 + 4u * k) + local] = (int32_t)b;
+    if (k >= 0) {
+        const int32_t p = *(__attribute__((address_space(3))) int32_t *)(size_t)(base0 + 4u * k) + local;
+        list[p] = (int32_t)b;
+        if (list_cid) list_cid[p] = code_member[code_id[b]];
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -800,13 +841,15 @@ hipError_t launch_gamma_table(float *tab, int R, int N, uint64_t seed, float g_f
 
 hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, bool bits, const int32_t *code_id,
                              const int32_t *code_m, int ncodes, const int32_t *code_fam, int nfam,
-                             void *workspace, unsigned long long *queues, hipStream_t s) {
+                             const int32_t *code_member, void *workspace, unsigned long long *queues,
+                             hipStream_t s) {
     int32_t *hist = (int32_t *)workspace;                       // ncodes * bins
     int32_t *seg_start = hist + (size_t)ncodes * kWeightBins;   // ncodes
     int32_t *seg_count = seg_start + ncodes;                    // ncodes
     int32_t *order = seg_count + ncodes;                        // ncodes
     int32_t *key = order + ncodes;                              // B
     int32_t *list = key + B;                                    // B
+    int32_t *list_cid = list + B;                               // B (written with code_member)
     const int nh = nfam * kWeightBins;
     hipLaunchKernelGGL(list_zero_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, hist, nh, queues, nfam);
     const int blocks = (int)((B + kListThreads - 1) / kListThreads);
@@ -814,12 +857,12 @@ hipError_t launch_shot_lists(int64_t B, const uint8_t *syn, int32_t syn_stride, 
                        bits, code_id, code_m, ncodes, code_fam, nfam, key, hist);
     hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, nfam, hist, seg_start, seg_count, order);
     hipLaunchKernelGGL(list_scatter_kernel, dim3(blocks), dim3(kListThreads), 8u * (size_t)nh, s, B, nh, key, hist,
-                       list);
+                       list, code_id, code_member, code_member ? list_cid : nullptr);
     return hipGetLastError();
 }
 
 size_t shot_list_bytes(int64_t B, int ncodes) {
-    return sizeof(int32_t) * ((size_t)ncodes * (kWeightBins + 3) + 2 * (size_t)B);
+    return sizeof(int32_t) * ((size_t)ncodes * (kWeightBins + 3) + 3 * (size_t)B);
 }
 
 hipError_t launch_syndrome(int64_t B, int32_t M, int32_t N, const int32_t *rowptr, const int32_t *colidx,
