@@ -399,6 +399,16 @@ rb_status rb_autotune_multi(rb_ctx *ctx, const int64_t *sample_b, const uint8_t 
                             int32_t reps, int32_t *chosen_variants);
 
 /*
+ * Sets the tile code k of a mixed context decodes with (a configuration index
+ * as in rb_info).  RB_E_INVALID_ARG for a single-code context or k outside
+ * [0, n_codes); RB_E_UNSUPPORTED if the configuration is not a tile of the
+ * mixed kernel or the code does not fit it.  Codes with the same graph share
+ * one shot list and queue while they also share a tile.  Rebuilds the gather
+ * tables (allocates and synchronises).
+ */
+rb_status rb_set_code_variant(rb_ctx *ctx, int32_t k, int32_t variant);
+
+/*
  * Differentiable decoding (learned memory strengths).  The forward pass is one
  * DMem-BP leg from the leg-1 initialisation (paper Sec. 2.3) run for exactly T
  * iterations with learnable per-column memory strengths gamma_j and channel

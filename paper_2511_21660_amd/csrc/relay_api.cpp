@@ -2722,6 +2722,19 @@ rb_status rb_autotune_multi(rb_ctx *c, const int64_t *sample_b, const uint8_t *c
     return upload_codes(c);
 }
 
+rb_status rb_set_code_variant(rb_ctx *c, int32_t k, int32_t variant) {
+    g_last_error.clear();
+    if (!c || !c->multi) return fail(RB_E_INVALID_ARG, "not a mixed-code context");
+    if (k < 0 || k >= (int32_t)c->subs.size()) return fail(RB_E_INVALID_ARG, "code index out of range");
+    if (variant < 0 || variant >= rb::num_variants() || rb::mixed_tile_of_variant(variant) < 0)
+        return fail(RB_E_UNSUPPORTED, "not a tile of the mixed kernel");
+    if (!variant_fits(c->subs[(size_t)k], rb::variant_shape(variant)))
+        return fail(RB_E_UNSUPPORTED, "the code does not fit the tile");
+    rb_status st = rb_set_variant(c->subs[(size_t)k], variant);
+    if (st != RB_OK) return st;
+    return upload_codes(c);
+}
+
 rb_status rb_sync_status(rb_ctx *c) {
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");

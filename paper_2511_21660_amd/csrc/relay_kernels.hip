@@ -154,6 +154,11 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     constexpr uint32_t WORD = 4u * SPH;            // bytes between consecutive words of a slot
     constexpr uint32_t ROW_STRIDE = WORD * G;      // bytes between the messages of checks c, c+1
     constexpr uint32_t KSTRIDE = WORD * G * CPT;   // bytes between the messages of steps k, k+1
+    // checks / faults per batch of the two passes: whole passes when their
+    // gathered operands fit in a few dozen registers, else one check and three
+    // faults at a time
+    constexpr int CB = 2 * CPT * DC <= 40 ? CPT : 1;
+    constexpr int FB = VPT * DV <= 16 ? VPT : 3;
 
     uint32_t lane_rt = threadIdx.x;
     opaque(lane_rt);  // keeps lane-derived constants inside this tile's code path
@@ -276,14 +281,26 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
             for (int v = 0; v < VPT; ++v) xl[v] = cw[min((int)gl + G * v, a.N - 1)];
         }
-        bool sb[CPT];
+        // (the layout test is uniform over the launch: taken once, so the
+        // loads of either layout issue together)
+        uint32_t raw[CPT];
+        if (a.io_bits) {
+            const uint32_t *sw = static_cast<const uint32_t *>(static_cast<const void *>(a.syn)) +
+                                 (size_t)nx_shot * a.syn_stride;
 #pragma unroll
-        for (int c = 0; c < CPT; ++c)
-            sb[c] = syn_bit(a.syn, (size_t)nx_shot, a.syn_stride, min((int)gl + G * c, a.M - 1), a.io_bits);
+            for (int c = 0; c < CPT; ++c) {
+                const int i = min((int)gl + G * c, a.M - 1);
+                raw[c] = (sw[i >> 5] >> (i & 31)) & 1u;
+            }
+        } else {
+            const uint8_t *sb = a.syn + (size_t)nx_shot * a.syn_stride;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) raw[c] = sb[min((int)gl + G * c, a.M - 1)];
+        }
         uint32_t m = 0;
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
-            if ((int)gl + G * c < a.M && sb[c]) m |= 1u << c;
+            if ((int)gl + G * c < a.M && raw[c] != 0u) m |= 1u << c;
         return m;
     };
     // leg 1 of the prefetched syndrome (channel LLRs wn, gm as loaded), then
@@ -332,46 +349,55 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         opaque(gl);
         opaque(mu_row0);
         // ---------------- check pass: mu(t+1) from Lambda(t), mu(t); parity of F(t)
+        // Checks are processed in batches of CB: every gather of a batch is
+        // issued before its first message store (a store might alias a later
+        // gather as far as the compiler knows, so an interleaved order would
+        // serialise the LDS round trips); batches are fenced from each other
+        // to keep live ranges inside the register budget.
         bool mism = false;
         if (active) {
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const uint32_t row = mu_row0 + c * ROW_STRIDE;
-                float mo[DC], lv[DC];
+            for (int c0 = 0; c0 < CPT; c0 += CB) {
+                float mo[CB][DC], lv[CB][DC];
 #pragma unroll
-                for (int k = 0; k < DC; ++k) mo[k] = lds_at<float>(lds, row + KSTRIDE * k);
+                for (int c = c0; c < c0 + CB && c < CPT; ++c) {
+                    const uint32_t row = mu_row0 + c * ROW_STRIDE;
 #pragma unroll
-                for (int k = 0; k < DC; ++k) lv[k] = lds_at<float>(lds, lam_addr(c, k));
-                const bool sc = (sig >> c) & 1u;
-                bool fpar = sc;  // sigma_i + parity of F(t) over the check
-                bool neg = sc;   // sigma_i + parity of the signs of nu
-                bool sk[DC];
-                float av[DC];
-                float m1 = L, m2 = L;
+                    for (int k = 0; k < DC; ++k) mo[c - c0][k] = lds_at<float>(lds, row + KSTRIDE * k);
 #pragma unroll
-                for (int k = 0; k < DC; ++k) {
-                    fpar ^= lv[k] < 0.0f;
-                    const float nu = clipf(lv[k] - mo[k], L);
-                    sk[k] = nu < 0.0f;
-                    neg ^= sk[k];
-                    av[k] = fabsf(nu);
-                    // two smallest magnitudes: with m1 <= m2, min(m2, max(m1, av)) is the
-                    // median of (m1, av, m2)
-                    m2 = __builtin_amdgcn_fmed3f(m1, av[k], m2);
-                    // min(m1, av) as med3(m1, av, -1) (both are >= +0): one VOP3 op
-                    // taking |nu| as a source modifier (a -inf bound would be
-                    // rewritten into a VOP2 min that needs |nu| in a register)
-                    m1 = __builtin_amdgcn_fmed3f(m1, av[k], -1.0f);
+                    for (int k = 0; k < DC; ++k) lv[c - c0][k] = lds_at<float>(lds, lam_addr(c, k));
                 }
-                mism |= fpar;
 #pragma unroll
-                for (int k = 0; k < DC; ++k) {
-                    const float mag = (av[k] == m1) ? m2 : m1;
-                    lds_at<float>(lds, row + KSTRIDE * k) = (neg ^ sk[k]) ? -mag : mag;
+                for (int c = c0; c < c0 + CB && c < CPT; ++c) {
+                    const uint32_t row = mu_row0 + c * ROW_STRIDE;
+                    const bool sc = (sig >> c) & 1u;
+                    bool fpar = sc;  // sigma_i + parity of F(t) over the check
+                    bool neg = sc;   // sigma_i + parity of the signs of nu
+                    bool sk[DC];
+                    float av[DC];
+                    float m1 = L, m2 = L;
+#pragma unroll
+                    for (int k = 0; k < DC; ++k) {
+                        fpar ^= lv[c - c0][k] < 0.0f;
+                        const float nu = clipf(lv[c - c0][k] - mo[c - c0][k], L);
+                        sk[k] = nu < 0.0f;
+                        neg ^= sk[k];
+                        av[k] = fabsf(nu);
+                        // two smallest magnitudes: with m1 <= m2, min(m2, max(m1, av)) is the
+                        // median of (m1, av, m2)
+                        m2 = __builtin_amdgcn_fmed3f(m1, av[k], m2);
+                        // min(m1, av) as med3(m1, av, -1) (both are >= +0): one VOP3 op
+                        // taking |nu| as a source modifier (a -inf bound would be
+                        // rewritten into a VOP2 min that needs |nu| in a register)
+                        m1 = __builtin_amdgcn_fmed3f(m1, av[k], -1.0f);
+                    }
+                    mism |= fpar;
+#pragma unroll
+                    for (int k = 0; k < DC; ++k) {
+                        const float mag = (av[k] == m1) ? m2 : m1;
+                        lds_at<float>(lds, row + KSTRIDE * k) = (neg ^ sk[k]) ? -mag : mag;
+                    }
                 }
-                // keep the scheduler from hoisting the next check's gathers above
-                // this one: bounded live ranges keep the kernel inside its
-                // register budget
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -487,22 +513,31 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         wave_sync();
 
         // ---------------- fault pass: memory term, marginals, Lambda(t+1)
+        // (faults in batches of FB, gathers before stores, as in the check pass)
         if (active && !event) {
 #pragma unroll
-            for (int v = 0; v < VPT; ++v) {
-                const float y = gm[v] * clipf(Lr[v], L);
-                float acc = clipf(xl[v] + y, L);
+            for (int v0 = 0; v0 < VPT; v0 += FB) {
+                float mv[FB][DV];
 #pragma unroll
-                for (int k = 0; k < DV; ++k) acc += lds_at<float>(lds, mu_addr(v, k));
-                Lr[v] = acc;
-                // columns j >= N of the last row of lanes own spare words of the
-                // padded Lambda region, so the write needs no bound check
-                lds_at<float>(lds, lam_w0 + WORD * G * v) = acc;
-                if (v % 3 == 2) __builtin_amdgcn_sched_barrier(0);
-                if (TRACE) {
-                    const int j = (int)gl + G * v;
-                    if (j < a.N) a.trace[((size_t)shot * (a.trace_T + 1) + t + 1) * a.N + j] = acc;
+                for (int v = v0; v < v0 + FB && v < VPT; ++v)
+#pragma unroll
+                    for (int k = 0; k < DV; ++k) mv[v - v0][k] = lds_at<float>(lds, mu_addr(v, k));
+#pragma unroll
+                for (int v = v0; v < v0 + FB && v < VPT; ++v) {
+                    const float y = gm[v] * clipf(Lr[v], L);
+                    float acc = clipf(xl[v] + y, L);
+#pragma unroll
+                    for (int k = 0; k < DV; ++k) acc += mv[v - v0][k];
+                    Lr[v] = acc;
+                    // columns j >= N of the last row of lanes own spare words of the
+                    // padded Lambda region, so the write needs no bound check
+                    lds_at<float>(lds, lam_w0 + WORD * G * v) = acc;
+                    if (TRACE) {
+                        const int j = (int)gl + G * v;
+                        if (j < a.N) a.trace[((size_t)shot * (a.trace_T + 1) + t + 1) * a.N + j] = acc;
+                    }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
             ++t;
             ++total;
@@ -553,6 +588,9 @@ void relay_mixed_kernel(MixedArgs m) {
             case 1: group_loop<16, 3, 6, 6, 3, PRIOR, false, true>(a); break;
             case 2: group_loop<16, 5, 6, 9, 3, PRIOR, false, true>(a); break;
             case 3: group_loop<32, 5, 6, 9, 3, PRIOR, false, true>(a); break;
+            case 4: group_loop<64, 1, 6, 2, 3, PRIOR, false, true>(a); break;
+            case 5: group_loop<64, 2, 6, 3, 3, PRIOR, false, true>(a); break;
+            case 6: group_loop<64, 3, 6, 5, 3, PRIOR, false, true>(a); break;
             default: break;
         }
     }
@@ -725,6 +763,13 @@ const Variant kVariants[] = {
     // irregular small graphs
     RB_VARIANT(16, 4, 16, 8, 8, 2),   // M <= 64,  N <= 128
     RB_VARIANT(64, 4, 16, 8, 8, 2),   // M <= 256, N <= 512
+    // degree-(6, 3) graphs, one syndrome per wave: the shortest iteration for
+    // a single syndrome (fewest checks and faults per lane), at more
+    // lane-operations per edge than the tiles above; the choice for codes
+    // whose launch time is set by a few long-running syndromes
+    RB_VARIANT(64, 1, 6, 2, 3, 4),    // M <= 64,  N <= 128
+    RB_VARIANT(64, 2, 6, 3, 3, 4),    // M <= 128, N <= 192
+    RB_VARIANT(64, 3, 6, 5, 3, 4),    // M <= 192, N <= 320
 };
 
 // ------------------------------------------------------------------------
@@ -773,7 +818,7 @@ __global__ __launch_bounds__(256) void syndrome_bits_kernel(int64_t B, int32_t M
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 
 // group variants usable in the mixed launch, in the order of its tile switch
-const int kMixedVariants[] = {1, 3, 5, 8};
+const int kMixedVariants[] = {1, 3, 5, 8, 11, 12, 13};
 
 int mixed_tile_of_variant(int v) {
     for (int t = 0; t < (int)(sizeof(kMixedVariants) / sizeof(kMixedVariants[0])); ++t)

@@ -127,6 +127,7 @@ def load_library():
     L.rb_noalloc_max_batch.restype = i64
     L.rb_autotune_multi.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(P), i32,
                                     ctypes.POINTER(i32)]
+    L.rb_set_code_variant.argtypes = [P, i32, i32]
     L.rb_train_tape_size.argtypes = [P, i64, i32, i32]
     L.rb_train_tape_size.restype = ctypes.c_size_t
     L.rb_forward_train.argtypes = [P, i64, P, P, P, i32, i32, P, P, ctypes.c_size_t, P]
@@ -140,7 +141,7 @@ def load_library():
     for name in ("rb_params_default", "rb_create", "rb_decode", "rb_trace", "rb_get_llr",
                  "rb_get_gamma_table", "rb_get_info", "rb_set_variant", "rb_sync_status",
                  "rb_autotune", "rb_reserve", "rb_create_multi", "rb_decode_multi", "rb_decode_multi_noalloc",
-                 "rb_autotune_multi", "rb_forward_train", "rb_backward", "rb_set_leg_gamma",
+                 "rb_autotune_multi", "rb_set_code_variant", "rb_forward_train", "rb_backward", "rb_set_leg_gamma",
                  "rb_set_prior_scale", "rb_plan_check", "rb_syndrome"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -505,3 +506,7 @@ class MultiDecoder:
         chosen = (ctypes.c_int32 * k)()
         _check(load_library().rb_autotune_multi(self._h, bs, ptrs, int(reps), chosen))
         return list(chosen)
+
+    def set_code_variant(self, k: int, variant: int):
+        """Decode code k with the mixed-kernel tile `variant` (rb_set_code_variant)."""
+        _check(load_library().rb_set_code_variant(self._h, int(k), int(variant)))

@@ -128,4 +128,5 @@ def test_null_arguments(lib):
     assert lib.rb_syndrome(None, 1, None, None, None, None) == 1
     assert lib.rb_decode_multi_noalloc(None, 1, None, None, None, None, None, None, None, None, None) == 1
     assert lib.rb_noalloc_max_batch(None) == 0
+    assert lib.rb_set_code_variant(None, 0, 0) == 1
     lib.rb_destroy(None)

@@ -365,6 +365,47 @@ def test_mixed_batch_parity(rb):
     dec.close()
 
 
+def test_mixed_batch_every_tile(rb):
+    """Every tile of the mixed kernel that fits a code, forced per code
+    (rb_set_code_variant), in rounds that give each code its next fitting
+    tile: every shot equals the oracle's decode of its own code."""
+    b = 700
+    probs, code_id, syn, per_code = _mixed_inputs(b, p=0.05, key=11 << 32)
+    dec = rb.MultiDecoder(probs, **RELAY_DEFAULT)
+    nvar = rb.Decoder.from_problem(probs[0], **RELAY_DEFAULT).info()["num_variants"]
+    fits = []
+    for k in range(len(probs)):
+        ok = []
+        for v in range(nvar):
+            try:
+                dec.set_code_variant(k, v)
+            except rb.RelayError as e:
+                assert e.status == 8  # RB_E_UNSUPPORTED
+                continue
+            ok.append(v)
+        assert ok, MIX_CODES[k]
+        fits.append(ok)
+    assert any(max(ok) >= 11 for ok in fits)  # the one-syndrome-per-wave tiles take part
+    refs = [oracle.decode(pr.m, pr.n, pr.rows, pr.cols, pr.prior, RELAY_DEFAULT, per_code[k][1], want_llr=True)
+            for k, pr in enumerate(probs)]
+    d_code, d_syn = torch.from_numpy(code_id).cuda(), torch.from_numpy(syn).cuda()
+    for rnd in range(max(len(ok) for ok in fits)):
+        tiles = [ok[rnd % len(ok)] for ok in fits]
+        for k, v in enumerate(tiles):
+            dec.set_code_variant(k, v)
+        print(f"[parity] mixed tiles {tiles}", flush=True)
+        out = dec.decode(d_code, d_syn, want_llr=True)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items() if k != "workspace"}
+        for k, pr in enumerate(probs):
+            idx, s = per_code[k]
+            sub = {"corr": g["corr"][idx, :pr.n], "conv": g["conv"][idx], "legs": g["legs"][idx],
+                   "iters": g["iters"][idx], "weight": g["weight"][idx], "llr": g["llr"][idx, :pr.n],
+                   "info": {"variant": f"mixed tile {tiles[k]}"}}
+            assert_parity(sub, refs[k], s, pr, f"mixed code {MIX_CODES[k]} tile {tiles[k]}")
+    dec.close()
+
+
 def _defined(out, code_id, ns):
     """Outputs with the padding of each row (entries >= N of its code) zeroed."""
     cid = torch.as_tensor(code_id, device="cuda").long()
