@@ -1856,6 +1856,14 @@ void rb_destroy(rb_ctx *c) {
     delete c;
 }
 
+// Every w_j bit-identical (uniform priors): the group kernel then takes a
+// solution's weight as a count times w_0.
+static bool w_is_uniform(const rb_ctx *c) {
+    for (size_t j = 1; j < c->w.size(); ++j)
+        if (std::memcmp(&c->w[j], &c->w[0], sizeof(float)) != 0) return false;
+    return true;
+}
+
 static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     rb::GroupArgs a{};
     a.M = c->M;
@@ -1884,6 +1892,8 @@ static rb::GroupArgs base_args(const rb_ctx *c, int64_t B, const uint8_t *syn) {
     a.mu0_off = c->mu0_off;
     a.half_off = c->half_off;
     a.scale = c->prior_scale;
+    a.w_uniform = w_is_uniform(c) ? 1 : 0;
+    a.w0 = c->w.empty() ? 0.0f : c->w[0];
     return a;
 }
 
@@ -2500,9 +2510,14 @@ rb_status upload_codes(rb_ctx *m) {
     rb_status st = upload(&m->d_wcat, wcat, "upload code w");
     if (st != RB_OK) return st;
     if ((st = upload(&m->d_gcat, gcat, "upload code gamma")) != RB_OK) return st;
+    std::vector<int32_t> fam_uniform(rep.size(), 1);
+    for (size_t k = 0; k < nc; ++k)
+        if (!w_is_uniform(m->subs[k])) fam_uniform[(size_t)fam[k]] = 0;
     for (size_t k = 0; k < nc; ++k) {
         cs[k].w = m->d_wcat + woff[k];
         cs[k].gamma = m->d_gcat + goff[k];
+        cs[k].w_uniform = fam_uniform[(size_t)fam[k]];
+        cs[k].w0 = m->subs[k]->w.empty() ? 0.0f : m->subs[k]->w[0];
     }
     if ((st = upload(&m->d_codes, cs, "upload code table")) != RB_OK) return st;
     if ((st = upload(&m->d_code_member, member, "upload code members")) != RB_OK) return st;

@@ -56,6 +56,8 @@ struct GroupArgs {
     float *final_llr;     // [B][N] or null
     const float *w;       // [N] channel LLRs
     const float *gamma;   // [R][N] memory strengths, row r-1 = leg r
+    int32_t w_uniform;    // 1: every w_j of the code (of every family member) is equal
+    float w0;             // w_0 of the code (of member 0)
     // codes sharing one graph (mixed launch): when list_cid is set, queue
     // position k belongs to family member list_cid[k], whose w and gamma
     // follow member 0's at w + list_cid[k] * N and gamma + list_cid[k] * R * N
@@ -251,6 +253,8 @@ struct CodeStatic {
     // i * R * N floats
     const float *w;
     const float *gamma;
+    int32_t w_uniform;  // 1: every w_j of every member of the code's family is equal
+    float w0;           // w_0 of the code
     const uint32_t *lam_off;
     const uint32_t *mu_off;
     uint32_t lampad_off, mupad_off, mu0_off, half_off;

@@ -138,6 +138,13 @@ __device__ __forceinline__ double group_sum(double x) {
     return x;
 }
 
+template <int G>
+__device__ __forceinline__ int group_isum(int x) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
+    return x;
+}
+
 // ------------------------------------------------------------------------
 // The group kernel
 // ------------------------------------------------------------------------
@@ -231,6 +238,14 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         return (MULTI && a.list_cid) ? a.gamma + (size_t)c * a.num_legs * a.N : a.gamma;
     };
 
+    // Uniform priors (every w_j of a code equal, as under code-capacity
+    // noise): w0 is the w of the current syndrome's code, and a solution's
+    // weight is (number of faults set) x w0 -- exactly the FP64 sum, which
+    // adds at most 2^9 copies of one 24-bit value -- so the event paths load
+    // no w at all.
+    const bool wu = a.w_uniform != 0;
+    float w0 = a.w0;
+
     // sum of wv_j over the lane's faults with Lambda_j < 0 (FP64, over the
     // slot's G lanes) and the decision bits; adding +0 for the other faults
     // leaves the sum's bits unchanged
@@ -243,6 +258,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
             fm |= f ? 1u << v : 0u;
             part += (double)(f ? wv[v] : 0.0f);
         }
+        if (wu) return (double)group_isum<G>(__popc(fm)) * (double)w0;
         return group_sum<G>(part);
     };
 
@@ -272,11 +288,14 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     // its code into gm and, when the code is not the launch's own, its w into
     // xl (both arrays are dead once a syndrome is done); then its syndrome
     // bits, folded into a mask (the first use: one wait covers every load).
-    auto load_start = [&](bool own_w) -> uint32_t {
+    auto load_start = [&](bool own_w, float &w0n) -> uint32_t {
         const float *cg = TRACE ? a.trace_gamma : code_gamma(nx_cid);
 #pragma unroll
         for (int v = 0; v < VPT; ++v) gm[v] = cg[min((int)gl + G * v, a.N - 1)];
-        if (!own_w) {
+        w0n = a.w0;
+        if (wu) {
+            if (!own_w) w0n = code_w(nx_cid)[0];
+        } else if (!own_w) {
             const float *cw = code_w(nx_cid);
 #pragma unroll
             for (int v = 0; v < VPT; ++v) xl[v] = cw[min((int)gl + G * v, a.N - 1)];
@@ -305,9 +324,10 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     };
     // leg 1 of the prefetched syndrome (channel LLRs wn, gm as loaded), then
     // the prefetch of the next position
-    auto begin = [&](const float (&wn)[VPT], uint32_t nsig) {
+    auto begin = [&](const float (&wn)[VPT], uint32_t nsig, float w0n) {
         shot = nx_shot;
         cid = nx_cid;
+        w0 = w0n;
         active = true;
         r = 1;
         t = 0;
@@ -320,7 +340,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         for (int v = 0; v < VPT; ++v) {
             const int j = (int)gl + G * v;
             const bool in = j < a.N;
-            const float wj = in ? a.scale * wn[v] : 0.0f;
+            const float wj = in ? a.scale * (wu ? w0n : wn[v]) : 0.0f;
             const float gj = in ? gm[v] : 0.0f;
             // columns j >= N own spare words of the padded Lambda region
             lds_at<float>(lds, base + WORD * j) = wj;
@@ -336,8 +356,9 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     if (g == 0) claim = (unsigned)atomicAdd(qk, 1ull);
     prefetch();
     if (nx_shot >= 0) {
-        const uint32_t nsig = load_start(false);
-        begin(xl, nsig);
+        float w0n;
+        const uint32_t nsig = load_start(false, w0n);
+        begin(xl, nsig, w0n);
     }
     wave_sync();
 
@@ -419,7 +440,11 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
             // prefetched syndrome with its bits and (codes sharing a graph) w.
             float wv[VPT];
             uint32_t nsig = 0;
-            {
+            float w0n = w0;
+            if (wu) {
+#pragma unroll
+                for (int v = 0; v < VPT; ++v) wv[v] = w0;
+            } else {
                 const float *cw = code_w(cid);
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) wv[v] = cw[min((int)gl + G * v, a.N - 1)];
@@ -430,7 +455,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) gm[v] = gr[min((int)gl + G * v, a.N - 1)];
             } else if (start) {
-                nsig = load_start(!(MULTI && a.list_cid));
+                nsig = load_start(!(MULTI && a.list_cid), w0n);
             }
             if (!TRACE && conv_ev) {
                 ++count;
@@ -473,9 +498,9 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 const bool o_conv = count > 0;
                 if (start) {
                     if (MULTI && a.list_cid)
-                        begin(xl, nsig);
+                        begin(xl, nsig, w0n);
                     else
-                        begin(wv, nsig);
+                        begin(wv, nsig, w0n);
                 } else {
                     active = false;
                 }
@@ -573,6 +598,8 @@ void relay_mixed_kernel(MixedArgs m) {
         a.N = cs.N;
         a.w = cs.w;
         a.gamma = cs.gamma;
+        a.w_uniform = cs.w_uniform;
+        a.w0 = cs.w0;
         a.lam_off = cs.lam_off;
         a.mu_off = cs.mu_off;
         a.lampad_off = cs.lampad_off;

@@ -135,6 +135,31 @@ def test_every_fitting_variant_agrees(rb):
     assert tested >= 3
 
 
+def test_every_fitting_variant_nonuniform_priors(rb):
+    """A BB graph with a different prior on every column (the kernels' general
+    solution-weight path; uniform priors take a count x w path): every
+    fitting configuration against the oracle, two solutions per shot."""
+    base = codes.bb_problem("bb144", 0.05)
+    rng = np.random.default_rng(31)
+    prior = rng.uniform(0.02, 0.09, base.n)
+    prob = codes.problem_from_dense("bb144-nonuniform", base.dense(), prior, base.logical)
+    faults = (rng.random((300, prob.n)) < prior[None, :]).astype(np.uint8)
+    syn = ((faults.astype(np.int64) @ base.dense().T.astype(np.int64)) % 2).astype(np.uint8)
+    prm = dict(RELAY_DEFAULT, num_legs=40, num_solutions=2)
+    ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, prm, syn, want_llr=True)
+    nvar = gpu_decode(rb, prob, prm, syn[:1])["info"]["num_variants"]
+    tested = 0
+    for v in range(nvar):
+        try:
+            gpu = gpu_decode(rb, prob, prm, syn, variant=v)
+        except rb.RelayError as e:
+            assert e.status == 8
+            continue
+        assert_parity(gpu, ref, syn, prob, f"non-uniform priors variant {v}")
+        tested += 1
+    assert tested >= 3
+
+
 def _irregular_problem(seed, m=40, n=90):
     rng = np.random.default_rng(seed)
     h = (rng.random((m, n)) < 0.06).astype(np.uint8)
