@@ -812,7 +812,8 @@ def run_mixed_codes(args, torch, rb, codes, sampling):
     lds_b = sum(int(host["iters"][per[k][0]].astype(np.int64).sum()) * pr.nnz *
                 lds_bytes_per_edge_update(pr.m, pr.n, pr.nnz)
                 for k, pr in enumerate(probs)) / eu_launch
-    roof, lds = roofline("relay_mixed_kernel", kernel_ms, ops_launch, eu_launch, lds_b, None)
+    roof, lds = roofline("relay_mixed_kernel", kernel_ms, ops_launch, eu_launch, lds_b,
+                         stored_traffic("relay_mixed_kernel_mixed_bb_codes_hbm_traffic.txt"))
     cpu = None
     if not args.no_cpu_baseline:
         import oracle

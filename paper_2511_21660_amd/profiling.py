@@ -98,12 +98,16 @@ def _counter_rows(path: str, kernel: str):
     return [per[k] for k in sorted(per, key=int)]
 
 
-def counters(sq_csv, kernel, edge_updates, ops_per_eu, cus=256, simds_per_cu=4, xcds=8, skip=0):
+def counters(sq_csv, kernel, edge_updates, ops_per_eu, cus=256, simds_per_cu=4, xcds=8, skip=0, near_max=0.9):
     """Derived VALU / LDS activity per launch, averaged over the dispatches
-    (after `skip`), for a launch of `edge_updates` edge-updates."""
+    (after `skip`) whose SQ_INSTS_VALU is at least `near_max` of the largest
+    (the workload's own launches, not autotuning trials or smaller probes),
+    for a launch of `edge_updates` edge-updates."""
     rows = _counter_rows(sq_csv, kernel)[skip:]
     if not rows:
         raise SystemExit(f"no dispatch of {kernel!r} in {sq_csv}")
+    top = max(r["SQ_INSTS_VALU"] for r in rows)
+    rows = [r for r in rows if r["SQ_INSTS_VALU"] >= near_max * top]
     mean = {k: sum(r[k] for r in rows) / len(rows) for k in rows[0]}
     cyc = mean["GRBM_GUI_ACTIVE"] / xcds
     out = {"kernel": kernel, "dispatches": len(rows), "cycles_per_launch": cyc,
@@ -136,10 +140,11 @@ def main(argv=None):
     c.add_argument("--edge-updates", type=float, required=True)
     c.add_argument("--ops-per-edge-update", type=float, required=True)
     c.add_argument("--launches-skip", type=int, default=0)
+    c.add_argument("--near-max", type=float, default=0.9)
     a = ap.parse_args(argv)
     if a.cmd == "counters":
-        print(json.dumps(counters(a.sq, a.kernel, a.edge_updates, a.ops_per_edge_update, skip=a.launches_skip),
-                         indent=1))
+        print(json.dumps(counters(a.sq, a.kernel, a.edge_updates, a.ops_per_edge_update, skip=a.launches_skip,
+                                  near_max=a.near_max), indent=1))
         return 0
     if a.cmd == "stats":
         print(stats_table(a.csv))
