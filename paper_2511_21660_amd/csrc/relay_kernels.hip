@@ -340,7 +340,8 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         for (int v = 0; v < VPT; ++v) {
             const int j = (int)gl + G * v;
             const bool in = j < a.N;
-            const float wj = in ? a.scale * (wu ? w0n : wn[v]) : 0.0f;
+            // (+ 0 turns a -0 channel LLR, s * w with s or w zero, into +0)
+            const float wj = in ? a.scale * (wu ? w0n : wn[v]) + 0.0f : 0.0f;
             const float gj = in ? gm[v] : 0.0f;
             // columns j >= N own spare words of the padded Lambda region
             lds_at<float>(lds, base + WORD * j) = wj;
@@ -391,18 +392,27 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
                 for (int c = c0; c < c0 + CB && c < CPT; ++c) {
                     const uint32_t row = mu_row0 + c * ROW_STRIDE;
-                    const bool sc = (sig >> c) & 1u;
-                    bool fpar = sc;  // sigma_i + parity of F(t) over the check
-                    bool neg = sc;   // sigma_i + parity of the signs of nu
-                    bool sk[DC];
+                    // Signs as bit 31 of the words: sgn(x) = -1 iff x < 0 is the
+                    // sign bit because no marginal is ever -0 (channel LLRs are
+                    // taken +0 for -0 when a syndrome starts; a memory term is -0
+                    // only from two -0 operands; a sum with a nonzero or a +0 term
+                    // is not -0), hence no nu = clip(Lambda - mu) is -0 either.
+                    // The parities are XORs of whole words (bit 31 is read); a
+                    // message is its magnitude with the sign bit set by a mask:
+                    // no lane masks pass through scalar registers, which shortens
+                    // one syndrome's iteration by about a fifth.
+                    const uint32_t sc = ((sig >> c) & 1u) << 31;
+                    uint32_t fpar = sc;  // bit 31: sigma_i + parity of F(t) over the check
+                    uint32_t neg = sc;   // bit 31: sigma_i + parity of the signs of nu
+                    uint32_t nb[DC];
                     float av[DC];
                     float m1 = L, m2 = L;
 #pragma unroll
                     for (int k = 0; k < DC; ++k) {
-                        fpar ^= lv[c - c0][k] < 0.0f;
+                        fpar ^= __float_as_uint(lv[c - c0][k]);
                         const float nu = clipf(lv[c - c0][k] - mo[c - c0][k], L);
-                        sk[k] = nu < 0.0f;
-                        neg ^= sk[k];
+                        nb[k] = __float_as_uint(nu);
+                        neg ^= nb[k];
                         av[k] = fabsf(nu);
                         // two smallest magnitudes: with m1 <= m2, min(m2, max(m1, av)) is the
                         // median of (m1, av, m2)
@@ -412,11 +422,12 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                         // rewritten into a VOP2 min that needs |nu| in a register)
                         m1 = __builtin_amdgcn_fmed3f(m1, av[k], -1.0f);
                     }
-                    mism |= fpar;
+                    mism |= (fpar >> 31) != 0u;
 #pragma unroll
                     for (int k = 0; k < DC; ++k) {
-                        const float mag = (av[k] == m1) ? m2 : m1;
-                        lds_at<float>(lds, row + KSTRIDE * k) = (neg ^ sk[k]) ? -mag : mag;
+                        const float mag = (av[k] == m1) ? m2 : m1;  // >= +0: bit 31 clear
+                        lds_at<uint32_t>(lds, row + KSTRIDE * k) =
+                            ((neg ^ nb[k]) & 0x80000000u) | __float_as_uint(mag);
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -472,7 +483,8 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                 ++r;
                 t = 0;
 #pragma unroll
-                for (int v = 0; v < VPT; ++v) xl[v] = (1.0f - gm[v]) * (PRIOR ? a.scale * wv[v] : clipf(Lr[v], L));
+                for (int v = 0; v < VPT; ++v)
+                    xl[v] = (1.0f - gm[v]) * (PRIOR ? a.scale * wv[v] + 0.0f : clipf(Lr[v], L));
                 zero_rows();
             } else {
                 // the last decision and its weight are the output only when no

@@ -260,6 +260,47 @@ def test_learned_first_leg_parity(rb, name, anchor):
     assert_parity(gpu, ref, syn, prob, f"learned first leg {name} anchor {anchor}")
 
 
+@pytest.mark.parametrize("scale", [0.0, -1.0])
+def test_signed_zero_channel_llrs(rb, scale):
+    """Channel LLRs s * w that are -0 (s = 0 with priors above 1/2, s = -1 with
+    priors of exactly 1/2) on every configuration that fits, both anchors:
+    the kernels take such a zero as +0 when a syndrome starts (the group
+    kernel reads signs as sign bits), which must leave every output equal to
+    the oracle's, whose sign test is x < 0."""
+    prob = _irregular_problem(23)
+    prior = prob.prior.copy()
+    rng = np.random.default_rng(5)
+    prior[rng.integers(0, prob.n, 8)] = 0.5
+    prior[rng.integers(0, prob.n, 8)] = 0.7
+    prob = codes.problem_from_dense("irr23-zeros", prob.dense(), prior, prob.logical)
+    _, syn = sampling.sample_batch(prob, 41, 0, 200)
+    for anchor in (0, 1):
+        prm = dict(RELAY_DEFAULT, anchor=anchor, num_legs=8, num_solutions=2)
+        ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, prm, syn, want_llr=True,
+                            scale=scale)
+        probe = rb.Decoder.from_problem(prob, **prm)
+        nvar = probe.info()["num_variants"]
+        probe.close()
+        tested = 0
+        for v in range(nvar):
+            dec = rb.Decoder.from_problem(prob, **prm)
+            try:
+                dec.set_variant(v)
+            except rb.RelayError as e:
+                assert e.status == 8
+                dec.close()
+                continue
+            dec.set_prior_scale(scale)
+            out = dec.decode(torch.from_numpy(syn).cuda(), want_llr=True)
+            torch.cuda.synchronize()
+            gpu = {k: x.cpu().numpy() for k, x in out.items()}
+            gpu["info"] = dec.info()
+            dec.close()
+            assert_parity(gpu, ref, syn, prob, f"scale {scale} anchor {anchor} variant {v}")
+            tested += 1
+        assert tested >= 3
+
+
 def test_unsatisfiable_syndrome_runs_full_budget(rb):
     code = codes.bb_code("bb72")
     h = np.vstack([code.hx, np.zeros((1, 72), np.uint8)])
