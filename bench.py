@@ -339,9 +339,32 @@ def run_bb144(args, torch, rb, codes, sampling):
         # per workgroup): LER per p beside FP32's, and the bit-exact pairing
         # with the oracle's binary16 mode on the first 2000 syndromes of each p
         f16 = {}
+        decs16 = [rb.Decoder.from_problem(pr, device=0, **dict(RELAY, precision=1)) for pr in probs]
+        d16 = [torch.from_numpy(s).to(dev) for s in syns]
+        outs16 = [decs16[q].decode(d16[q]) for q in range(len(ps))]
+
+        def step16(ev):
+            for q in range(len(ps)):
+                if ev is not None:
+                    ev[q][0].record(stream)
+                decs16[q].decode(d16[q], out=outs16[q])
+                if ev is not None:
+                    ev[q][1].record(stream)
+
+        el16, pl16 = timed(torch, step16, len(ps), args.f16_steps, 1)
+        it16 = sum(int(o["iters"].to(torch.int64).sum().item()) for o in outs16)
+        ms16 = float(np.sum(launch_means(pl16)))
+        roof16 = {"bound": "alu", "achieved": it16 * ops_per_iteration(M, N, E) / (ms16 * 1e-3) / 1e12,
+                  "peak": 2 * PEAK_VALU_TOPS, "unit": "Tops/s", "kernel": "relay_block16_kernel",
+                  "peak_note": "packed binary16: two lane-ops per lane per cycle"}
+        roof16["frac"] = roof16["achieved"] / roof16["peak"]
+        f16["throughput"] = {"syndromes_per_s": n_shots * args.f16_steps / el16,
+                             "kernel_ms_per_step": ms16, "roofline": roof16,
+                             "note": "four per-p launches of the block kernel's binary16 form (two syndromes "
+                                     "per workgroup); FP32 above runs the group kernel"}
         for q, p in enumerate(ps):
-            dec16 = rb.Decoder.from_problem(probs[q], device=0, **dict(RELAY, precision=1))
-            o = {k: v.cpu().numpy() for k, v in dec16.decode(torch.from_numpy(syns[q]).to(dev)).items()}
+            dec16 = decs16[q]
+            o = {k: v.cpu().numpy() for k, v in outs16[q].items()}
             fail = logical_failures(probs[q], faults[q], o["corr"], o["conv"])
             kf = int(fail.sum())
             ent = {"ler": kf / len(fail), "wilson95": wilson(kf, len(fail)), "mean_iters": float(o["iters"].mean()),
