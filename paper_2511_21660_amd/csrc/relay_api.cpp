@@ -1771,9 +1771,14 @@ rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32
     if (e != hipSuccess) return bail(hip_fail(e, "hipGetDeviceProperties"));
     c->num_cu = prop.multiProcessorCount;
     const int R = params->num_legs;
-    if ((e = hipMalloc(&c->d_w, sizeof(float) * (size_t)N)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(w)"));
-    if ((e = hipMalloc(&c->d_gamma, sizeof(float) * (size_t)N * (size_t)R)) != hipSuccess)
+    // (both tables end in kGroupReadPad floats of zeros: see relay_internal.h)
+    if ((e = hipMalloc(&c->d_w, sizeof(float) * ((size_t)N + rb::kGroupReadPad))) != hipSuccess)
+        return bail(hip_fail(e, "hipMalloc(w)"));
+    if ((e = hipMalloc(&c->d_gamma, sizeof(float) * ((size_t)N * (size_t)R + rb::kGroupReadPad))) != hipSuccess)
         return bail(hip_fail(e, "hipMalloc(gamma)"));
+    if ((e = hipMemset(c->d_w + N, 0, sizeof(float) * rb::kGroupReadPad)) != hipSuccess ||
+        (e = hipMemset(c->d_gamma + (size_t)N * R, 0, sizeof(float) * rb::kGroupReadPad)) != hipSuccess)
+        return bail(hip_fail(e, "clear table padding"));
     if ((e = hipMalloc(&c->d_queue, sizeof(unsigned long long) * rb::kQueueWords)) != hipSuccess)
         return bail(hip_fail(e, "hipMalloc(queue)"));
     if ((e = hipMemcpy(c->d_w, c->w.data(), sizeof(float) * (size_t)N, hipMemcpyHostToDevice)) != hipSuccess)
@@ -2498,7 +2503,7 @@ rb_status upload_codes(rb_ctx *m) {
                 wtot += (size_t)m->subs[k]->N;
                 gtot += (size_t)R * m->subs[k]->N;
             }
-    std::vector<float> wcat(wtot), gcat(gtot);
+    std::vector<float> wcat(wtot + rb::kGroupReadPad, 0.0f), gcat(gtot + rb::kGroupReadPad, 0.0f);
     for (size_t k = 0; k < nc; ++k) {
         const rb_ctx *s = m->subs[k];
         RB_HIP(hipMemcpy(wcat.data() + woff[k], s->d_w, sizeof(float) * (size_t)s->N, hipMemcpyDeviceToHost),

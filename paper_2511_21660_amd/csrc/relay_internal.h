@@ -27,6 +27,11 @@ struct CodeStatic;
 // 4 x 10^5 syndromes; 64 counters cut that 4-fold, more gain little).  The
 // block kernel uses counter 0 alone.  A queue occupies kQueueWords words.
 constexpr int kQueueSplit = 64;
+// Floats of zero padding after a code's w [N] and memory-strength table
+// [R][N]: a group-kernel lane reads entries gl + G*v (v < VPT) of a row
+// without clamping to N - 1, so reads past the last row stay in bounds
+// (G * VPT <= kGroupReadPad for every tile); lanes past N never use them.
+constexpr int kGroupReadPad = 512;
 constexpr int kQueueStride = 32;
 constexpr int kQueueWords = kQueueSplit * kQueueStride;
 

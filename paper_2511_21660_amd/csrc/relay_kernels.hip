@@ -155,6 +155,7 @@ template <int G, int CPT, int DC, int VPT, int DV, bool PRIOR, bool TRACE, bool 
 __device__ __forceinline__ void group_loop(const GroupArgs a) {
     static_assert(64 % G == 0, "G must divide the wave");
     static_assert(CPT <= 32 && VPT <= 32, "per-lane bit masks are 32 bits");
+    static_assert(G * VPT <= kGroupReadPad, "unclamped w / gamma reads stay inside the padded tables");
     char *lds = nullptr;  // LDS is addressed by absolute byte offsets
     constexpr int NS = 64 / G;                     // slots per wave
     constexpr int SPH = G >= 32 ? 1 : 32 / G;      // slots per half-wave region
@@ -245,20 +246,24 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     // no w at all.
     const bool wu = a.w_uniform != 0;
     float w0 = a.w0;
+    uint32_t in_n = 0;
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) in_n |= (int)gl + G * v < a.N ? 1u << v : 0u;
 
     // sum of wv_j over the lane's faults with Lambda_j < 0 (FP64, over the
     // slot's G lanes) and the decision bits; adding +0 for the other faults
     // leaves the sum's bits unchanged
+    // (decision bits: the sign bits of the marginals, Lambda never being -0,
+    // shifted in from the top fault down; in_n masks the lane's faults < N)
     auto weight_of = [&](const float (&wv)[VPT], uint32_t &fm) -> double {
-        double part = 0.0;
         fm = 0;
 #pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const bool f = (int)gl + G * v < a.N && Lr[v] < 0.0f;
-            fm |= f ? 1u << v : 0u;
-            part += (double)(f ? wv[v] : 0.0f);
-        }
+        for (int v = VPT - 1; v >= 0; --v) fm = __builtin_amdgcn_alignbit(fm, __float_as_uint(Lr[v]), 31);
+        fm &= in_n;
         if (wu) return (double)group_isum<G>(__popc(fm)) * (double)w0;
+        double part = 0.0;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) part += (double)(((fm >> v) & 1u) ? wv[v] : 0.0f);
         return group_sum<G>(part);
     };
 
@@ -289,16 +294,23 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
     // xl (both arrays are dead once a syndrome is done); then its syndrome
     // bits, folded into a mask (the first use: one wait covers every load).
     auto load_start = [&](bool own_w, float &w0n) -> uint32_t {
-        const float *cg = TRACE ? a.trace_gamma : code_gamma(nx_cid);
+        // (the caller's trace gamma has N entries: clamped; the library's
+        // padded tables are read at gl + G*v, one base address per load round)
+        if (TRACE) {
 #pragma unroll
-        for (int v = 0; v < VPT; ++v) gm[v] = cg[min((int)gl + G * v, a.N - 1)];
+            for (int v = 0; v < VPT; ++v) gm[v] = a.trace_gamma[min((int)gl + G * v, a.N - 1)];
+        } else {
+            const float *cg = code_gamma(nx_cid) + gl;
+#pragma unroll
+            for (int v = 0; v < VPT; ++v) gm[v] = cg[G * v];
+        }
         w0n = a.w0;
         if (wu) {
             if (!own_w) w0n = code_w(nx_cid)[0];
         } else if (!own_w) {
-            const float *cw = code_w(nx_cid);
+            const float *cw = code_w(nx_cid) + gl;
 #pragma unroll
-            for (int v = 0; v < VPT; ++v) xl[v] = cw[min((int)gl + G * v, a.N - 1)];
+            for (int v = 0; v < VPT; ++v) xl[v] = cw[G * v];
         }
         // (the layout test is uniform over the launch: taken once, so the
         // loads of either layout issue together)
@@ -456,15 +468,16 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) wv[v] = w0;
             } else {
-                const float *cw = code_w(cid);
+                const float *cw = code_w(cid) + gl;
 #pragma unroll
-                for (int v = 0; v < VPT; ++v) wv[v] = cw[min((int)gl + G * v, a.N - 1)];
+                for (int v = 0; v < VPT; ++v) wv[v] = cw[G * v];
             }
             if (!done) {
-                // lanes past N load column N-1's: their words are never read
-                const float *gr = code_gamma(cid) + (size_t)r * a.N;
+                // lanes past N load the next row's or the padding: their words
+                // are never read
+                const float *gr = code_gamma(cid) + (size_t)r * a.N + gl;
 #pragma unroll
-                for (int v = 0; v < VPT; ++v) gm[v] = gr[min((int)gl + G * v, a.N - 1)];
+                for (int v = 0; v < VPT; ++v) gm[v] = gr[G * v];
             } else if (start) {
                 nsig = load_start(!(MULTI && a.list_cid), w0n);
             }
