@@ -250,11 +250,12 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
     for (int v = 0; v < VPT; ++v) in_n |= (int)gl + G * v < a.N ? 1u << v : 0u;
 
-    // sum of wv_j over the lane's faults with Lambda_j < 0 (FP64, over the
-    // slot's G lanes) and the decision bits; adding +0 for the other faults
-    // leaves the sum's bits unchanged
-    // (decision bits: the sign bits of the marginals, Lambda never being -0,
-    // shifted in from the top fault down; in_n masks the lane's faults < N)
+    // Decision bits and weight of the current marginals: bit v of fm is
+    // F = [Lambda < 0] of fault gl + G*v, i.e. the marginal's sign bit
+    // (Lambda is never -0), shifted in from the top fault down and masked to
+    // faults < N by in_n; the weight is the FP64 sum of w_j over the faults
+    // set, over the slot's G lanes (adding +0 for the others leaves the sum's
+    // bits unchanged), or the count times w0 under uniform priors.
     auto weight_of = [&](const float (&wv)[VPT], uint32_t &fm) -> double {
         fm = 0;
 #pragma unroll
@@ -288,14 +289,15 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
         }
     };
 
-    // Loads that start the prefetched syndrome (indices clamped, so in bounds,
-    // and unconditional: they issue together): the leg-1 memory strengths of
-    // its code into gm and, when the code is not the launch's own, its w into
-    // xl (both arrays are dead once a syndrome is done); then its syndrome
-    // bits, folded into a mask (the first use: one wait covers every load).
+    // Loads that start the prefetched syndrome, all unconditional so they
+    // issue together: the leg-1 memory strengths of its code into gm and,
+    // when the code is not the launch's own, its w into xl (both arrays are
+    // dead once a syndrome is done) or, under uniform priors, its w0; then its
+    // syndrome bits, folded into a mask (the first use: one wait covers every
+    // load).  The library's padded tables are read at gl + G*v from one base
+    // address; the caller's trace gamma and syndromes have exactly N and M
+    // entries, so those indices are clamped.
     auto load_start = [&](bool own_w, float &w0n) -> uint32_t {
-        // (the caller's trace gamma has N entries: clamped; the library's
-        // padded tables are read at gl + G*v, one base address per load round)
         if (TRACE) {
 #pragma unroll
             for (int v = 0; v < VPT; ++v) gm[v] = a.trace_gamma[min((int)gl + G * v, a.N - 1)];
@@ -312,8 +314,8 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
 #pragma unroll
             for (int v = 0; v < VPT; ++v) xl[v] = cw[G * v];
         }
-        // (the layout test is uniform over the launch: taken once, so the
-        // loads of either layout issue together)
+        // (the layout test is uniform over the launch: taken once, outside the
+        // loads)
         uint32_t raw[CPT];
         if (a.io_bits) {
             const uint32_t *sw = static_cast<const uint32_t *>(static_cast<const void *>(a.syn)) +
