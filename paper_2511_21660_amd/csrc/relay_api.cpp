@@ -71,8 +71,8 @@ struct rb_ctx {
     uint32_t red_off = 0, slack_off = 0;
     int32_t *d_chk_row = nullptr, *d_wave_deg = nullptr, *d_wave_base = nullptr;
     int32_t *d_slot_col = nullptr, *d_chk_split = nullptr;
-    float *d_w_slot = nullptr;      // [TPB*VPT] w by fault slot (block kernel)
-    float *d_gamma_slot = nullptr;  // [R][TPB*VPT] gamma by fault slot (block kernel)
+    float *d_w_slot = nullptr;      // [TPB*VPT] w by fault slot (block and large-graph kernels)
+    float *d_gamma_slot = nullptr;  // [R][TPB*VPT] gamma by fault slot (block and large-graph kernels)
     // binary16 mode (rb_params.precision = RB_PREC_F16): binary16 block kernel
     bool h16 = false;
     uint16_t *d_w16_slot = nullptr;      // [TPB*VPT] w by slot, binary16 bits
@@ -101,9 +101,10 @@ struct rb_ctx {
     rb::LargeShape lshape{};
     int32_t lrounds = 0, nsw = 0;
     uint32_t chk_off = 0, sgn_off = 0;
-    int32_t *d_lrowptr = nullptr, *d_lcolptr = nullptr, *d_chk_of = nullptr;
+    int32_t *d_lrowptr = nullptr, *d_chk_of = nullptr;
+    int2 *d_fcol = nullptr;      // [TPB*VR] (first entry, degree) per fault slot
     float *d_lambda0 = nullptr;  // [blocks_per_cu * num_cu][N] large-graph kernel workspace
-    uint16_t *d_col16 = nullptr;            // row chunks of fault indices
+    uint16_t *d_col16 = nullptr;            // row chunks of fault slots
     int32_t *d_rbase = nullptr;
     uint32_t *d_fedge = nullptr, *d_frec = nullptr;
     // CSR / CSC on the device (training kernels)
@@ -1348,18 +1349,27 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
 // Host tables of the large-graph kernel (no device work).  Checks sorted by
 // decreasing degree are dealt round by round (round r takes the next TPB of
 // them, thread t the t-th), so the 64 checks a wave handles in one round have
-// nearly the same length; fault-side entries pack each CSC entry's check and
-// the slot of its edge in the padded row table (which indexes its sign bit).
+// nearly the same length.  Faults are renumbered into slots by decreasing
+// column degree (ties by index), so the 64 slots of a wave in one round
+// nearly always share a degree.  Row chunks hold fault slots; each fault-side
+// entry is the code of its edge: check << kLargeEdgeBits | (slot ^ 24), the
+// slot being the edge's position in the padded row table (a row's chunk of 8
+// entries is one byte of sign bits, entry q in bit 7 - q: slot s's bit is bit
+// (s & 31) ^ 7 of word s >> 5, moved to bit 31 by a left shift of (s ^ 24) & 31).
 struct LargeTables {
     LargeLayout lay{};
     int32_t rounds = 0;
-    std::vector<int32_t> chk_of, rowptr, colptr, rbase;
+    std::vector<int32_t> chk_of, rowptr, rbase, slot_col;
+    std::vector<int2> fcol;      // per slot: first entry in fedge, column degree
     std::vector<uint16_t> ctab;  // rows padded to multiples of kLargeGather entries, + one zero chunk
     std::vector<uint32_t> frec, fedge;
 };
 
+uint32_t large_code(int32_t i, int64_t slot) { return ((uint32_t)i << rb::kLargeEdgeBits) | ((uint32_t)slot ^ 24u); }
+
 LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     constexpr int G = rb::kLargeGather;
+    const int npad = s.TPB * s.VR;
     LargeTables T;
     T.lay = large_layout(c, s);
     T.rounds = (c->M + s.TPB - 1) / s.TPB;
@@ -1370,8 +1380,18 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     });
     T.chk_of.assign((size_t)rb::kLargeRounds * s.TPB, -1);
     for (int32_t q = 0; q < c->M; ++q) T.chk_of[(size_t)q] = order[(size_t)q];
+    std::vector<int32_t> fo((size_t)c->N);
+    for (int32_t j = 0; j < c->N; ++j) fo[(size_t)j] = j;
+    std::stable_sort(fo.begin(), fo.end(), [&](int32_t x, int32_t y) {
+        return c->colptr[x + 1] - c->colptr[x] > c->colptr[y + 1] - c->colptr[y];
+    });
+    T.slot_col.assign((size_t)npad, -1);
+    std::vector<int32_t> slot_of((size_t)c->N);
+    for (int32_t p = 0; p < c->N; ++p) {
+        T.slot_col[(size_t)p] = fo[(size_t)p];
+        slot_of[(size_t)fo[(size_t)p]] = p;
+    }
     T.rowptr.assign(c->rowptr.begin(), c->rowptr.end());
-    T.colptr.assign(c->colptr.begin(), c->colptr.end());
     T.rbase.resize((size_t)c->M);
     int64_t chunks = 0;
     for (int32_t i = 0; i < c->M; ++i) {
@@ -1384,55 +1404,91 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     for (int32_t i = 0; i < c->M; ++i) {
         const int64_t d = c->rowptr[i + 1] - c->rowptr[i];
         for (int64_t k = d; k < (d + G - 1) / G * G; ++k) T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)k] = (uint16_t)c->N;
-    }
-    for (int32_t i = 0; i < c->M; ++i)
         for (int64_t e = c->rowptr[i]; e < c->rowptr[i + 1]; ++e)
-            T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)(e - c->rowptr[i])] = (uint16_t)c->colidx[(size_t)e];
-    T.fedge.resize((size_t)std::max<int64_t>(1, c->E), 0u);
-    for (int64_t q = 0; q < c->E; ++q) {
-        const int32_t i = c->rowidx[(size_t)q];
-        const int64_t e = (int64_t)T.rbase[(size_t)i] * G + c->cpos[(size_t)q];  // sign-bit slot
-        T.fedge[(size_t)q] = ((uint32_t)i << rb::kLargeEdgeBits) | (uint32_t)e;
+            T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)(e - c->rowptr[i])] =
+                (uint16_t)slot_of[(size_t)c->colidx[(size_t)e]];
     }
-    T.frec.assign((size_t)c->N * G, 0u);
-    for (int32_t j = 0; j < c->N; ++j)
-        for (int64_t q = c->colptr[j]; q < c->colptr[j + 1] && q - c->colptr[j] < G; ++q)
-            T.frec[(size_t)j * G + (size_t)(q - c->colptr[j])] = T.fedge[(size_t)q];
+    T.fedge.assign((size_t)std::max<int64_t>(1, c->E), 0u);
+    T.fcol.assign((size_t)npad, int2{0, 0});
+    T.frec.assign((size_t)npad * G, 0u);
+    int64_t q = 0;
+    for (int32_t p = 0; p < c->N; ++p) {
+        const int32_t j = T.slot_col[(size_t)p];
+        T.fcol[(size_t)p] = int2{(int)q, (int)(c->colptr[j + 1] - c->colptr[j])};
+        for (int64_t e = c->colptr[j]; e < c->colptr[j + 1]; ++e, ++q) {
+            const int32_t i = c->rowidx[(size_t)e];
+            const uint32_t code = large_code(i, (int64_t)T.rbase[(size_t)i] * G + c->cpos[(size_t)e]);
+            T.fedge[(size_t)q] = code;
+            if (e - c->colptr[j] < G) T.frec[(size_t)p * G + (size_t)(e - c->colptr[j])] = code;
+        }
+    }
     return T;
 }
 
 // Independent reading of the large-graph tables: every check on exactly one
 // (round, thread); rounds in use hold the checks (kernel reads rounds <
-// ceil(M/TPB)); each CSR edge's fault and each CSC entry's (check, slot) agree
-// with H; slots start rows on whole chunks and their sign bits lie inside the
-// LDS sign words; the LDS image fits.
+// ceil(M/TPB)); the slots a permutation of the faults; each CSR edge's row
+// entry the slot of its fault; each slot's entries, decoded, exactly its
+// column's edges in ascending check order, each naming the row slot that
+// holds it (so every message is rebuilt from its own check's state and sign
+// bit); sign bits inside the LDS sign words; the LDS image fits.
 std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const LargeTables &T, rb_plan_report *r) {
     if (T.lay.lds_bytes > 160 * 1024) return "LDS image exceeds a CU";
     if (T.rounds < 1 || T.rounds > rb::kLargeRounds || (int64_t)T.rounds * s.TPB < c->M) return "check rounds";
     // the kernel loads whole chunks of kLargeGather entries: a row's chunk
     // past its last edge holds N (the +inf entry of Lambda, which must not
-    // overlap the check states), a record past a column's last entry holds
+    // overlap the check states), a record past a slot's last entry holds
     // zeros (valid addresses), and every chunk lies inside the table
     if (T.lay.chk_off < 4u * (uint32_t)c->N + 4u) return "Lambda[N] overlaps the check states";
     constexpr int G = rb::kLargeGather;
-    if (T.frec.size() != (size_t)c->N * G) return "fault records";
-    auto slot_of_edge = [&](int32_t i, int64_t e) -> int64_t {  // table slot of CSR edge e of row i
-        return (int64_t)T.rbase[(size_t)i] * G + (e - T.rowptr[(size_t)i]);
-    };
-    auto col_of_slot = [&](int64_t at) -> int64_t {
-        return at >= 0 && (size_t)at < T.ctab.size() ? (int64_t)T.ctab[(size_t)at] : -1;
+    const int npad = s.TPB * s.VR;
+    if (T.frec.size() != (size_t)npad * G || T.fcol.size() != (size_t)npad || T.slot_col.size() != (size_t)npad)
+        return "slot tables";
+    std::vector<int32_t> slot_of((size_t)c->N, -1);
+    for (int p = 0; p < npad; ++p) {
+        const int32_t j = T.slot_col[(size_t)p];
+        if (p >= c->N) {
+            if (j != -1) return "spare slot " + std::to_string(p) + " holds a fault";
+            continue;
+        }
+        if (j < 0 || j >= c->N || slot_of[(size_t)j] >= 0) return "slot " + std::to_string(p) + ": not a permutation";
+        slot_of[(size_t)j] = p;
+    }
+    auto col_of_slot = [&](int64_t at) -> int64_t {  // fault in table slot `at`
+        if (at < 0 || (size_t)at >= T.ctab.size() || T.ctab[(size_t)at] >= (uint32_t)c->N) return -1;
+        return T.slot_col[T.ctab[(size_t)at]];
     };
     for (int32_t i = 0; i < c->M; ++i) {
         const int64_t d = T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i];
         if ((size_t)(T.rbase[(size_t)i] + (d + G - 1) / G) * G > T.ctab.size()) return "row chunks past the table";
         for (int64_t k = d; k < (d + G - 1) / G * G; ++k)
             if (T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)k] != (uint32_t)c->N) return "row padding values";
+        for (int64_t e = T.rowptr[(size_t)i]; e < T.rowptr[(size_t)i + 1]; ++e) {
+            const int64_t at = (int64_t)T.rbase[(size_t)i] * G + (e - T.rowptr[(size_t)i]);
+            if (col_of_slot(at) != c->colidx[(size_t)e]) return "edge " + std::to_string(e) + ": wrong fault slot";
+            if (at >= 32 * (int64_t)T.lay.nsw) return "edge " + std::to_string(e) + ": sign bit past the sign words";
+        }
     }
-    for (int32_t j = 0; j < c->N; ++j) {
-        const int64_t d = T.colptr[(size_t)j + 1] - T.colptr[(size_t)j];
+    for (int p = 0; p < c->N; ++p) {
+        const int32_t j = T.slot_col[(size_t)p];
+        const int64_t d = c->colptr[j + 1] - c->colptr[j];
+        const int2 fc = T.fcol[(size_t)p];
+        if (fc.y != d || fc.x < 0 || (int64_t)fc.x + d > (int64_t)T.fedge.size())
+            return "slot " + std::to_string(p) + ": entry range";
+        int32_t prev = -1;
+        for (int64_t k = 0; k < d; ++k) {
+            const uint32_t code = T.fedge[(size_t)(fc.x + k)];
+            const int32_t i = (int32_t)(code >> rb::kLargeEdgeBits);
+            const int64_t at = (int64_t)((code & ((1u << rb::kLargeEdgeBits) - 1u)) ^ 24u);
+            if (i <= prev || i >= c->M) return "slot " + std::to_string(p) + ": checks not ascending";
+            const int64_t pos = at - (int64_t)T.rbase[(size_t)i] * G;  // position in the row
+            if (pos < 0 || pos >= T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i] || col_of_slot(at) != j)
+                return "slot " + std::to_string(p) + ": entry " + std::to_string(k) + " is not its edge";
+            prev = i;
+        }
         for (int k = 0; k < G; ++k) {
-            const uint32_t want = k < d ? T.fedge[(size_t)(T.colptr[(size_t)j] + k)] : 0u;
-            if (T.frec[(size_t)j * G + k] != want) return "fault " + std::to_string(j) + ": record entry " + std::to_string(k);
+            const uint32_t want = k < d ? T.fedge[(size_t)(fc.x + k)] : 0u;
+            if (T.frec[(size_t)p * G + k] != want) return "slot " + std::to_string(p) + ": record entry " + std::to_string(k);
         }
     }
     std::vector<int> seen((size_t)c->M, 0);
@@ -1445,30 +1501,6 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
     }
     for (int32_t i = 0; i < c->M; ++i)
         if (!seen[(size_t)i]) return "check " + std::to_string(i) + " not placed";
-    for (int32_t i = 0; i < c->M; ++i)
-        for (int64_t e = T.rowptr[(size_t)i]; e < T.rowptr[(size_t)i + 1]; ++e) {
-            const int64_t at = slot_of_edge(i, e);
-            const int64_t j = col_of_slot(at);
-            if (j < 0 || j >= c->N) return "edge " + std::to_string(e) + ": fault out of range";
-            if (at >= 32 * (int64_t)T.lay.nsw) return "edge " + std::to_string(e) + ": sign bit past the sign words";
-            bool hit = false;  // (i, slot) must be a column entry of fault j
-            for (int64_t q = T.colptr[(size_t)j]; q < T.colptr[(size_t)j + 1] && !hit; ++q)
-                hit = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits) == i &&
-                      (int64_t)(T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u)) == at;
-            if (!hit) return "edge " + std::to_string(e) + " missing from its fault's entries";
-        }
-    for (int32_t j = 0; j < c->N; ++j) {
-        int32_t prev = -1;
-        for (int64_t q = T.colptr[(size_t)j]; q < T.colptr[(size_t)j + 1]; ++q) {
-            const int32_t i = (int32_t)(T.fedge[(size_t)q] >> rb::kLargeEdgeBits);
-            const int64_t e = T.fedge[(size_t)q] & ((1u << rb::kLargeEdgeBits) - 1u);
-            if (i <= prev) return "fault " + std::to_string(j) + ": checks not ascending";
-            const int64_t k = e - (int64_t)T.rbase[(size_t)i] * G;  // position in the row
-            if (k < 0 || k >= T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i] || col_of_slot(e) != j)
-                return "fault " + std::to_string(j) + ": entry " + std::to_string(q) + " is not its edge";
-            prev = i;
-        }
-    }
     r->lds_bytes = (int32_t)T.lay.lds_bytes;
     return "";
 }
@@ -1479,7 +1511,20 @@ rb_status build_large_plan(rb_ctx *c, int lv) {
     rb_status st;
     if ((st = upload(&c->d_chk_of, T.chk_of, "upload check placement")) != RB_OK) return st;
     if ((st = upload(&c->d_lrowptr, T.rowptr, "upload rowptr")) != RB_OK) return st;
-    if ((st = upload(&c->d_lcolptr, T.colptr, "upload colptr")) != RB_OK) return st;
+    if ((st = upload(&c->d_fcol, T.fcol, "upload slot entry ranges")) != RB_OK) return st;
+    if ((st = upload(&c->d_slot_col, T.slot_col, "upload slot map")) != RB_OK) return st;
+    {
+        const int npad = s.TPB * s.VR, R = c->params.num_legs;
+        std::vector<float> w_slot((size_t)npad, 0.0f);
+        for (int32_t p = 0; p < c->N; ++p) w_slot[(size_t)p] = c->w[(size_t)T.slot_col[(size_t)p]];
+        if ((st = upload(&c->d_w_slot, w_slot, "upload w by slot")) != RB_OK) return st;
+        (void)hipFree(c->d_gamma_slot);
+        c->d_gamma_slot = nullptr;
+        RB_HIP(hipMalloc(&c->d_gamma_slot, sizeof(float) * (size_t)npad * (size_t)R), "hipMalloc(gamma by slot)");
+        RB_HIP(rb::launch_gather_slots(c->d_gamma, c->N, c->d_slot_col, npad, R, c->d_gamma_slot, nullptr),
+               "gamma by slot");
+        RB_HIP(hipDeviceSynchronize(), "gamma by slot");
+    }
     if ((st = upload(&c->d_col16, T.ctab, "upload row chunks")) != RB_OK) return st;
     if ((st = upload(&c->d_rbase, T.rbase, "upload row bases")) != RB_OK) return st;
     if ((st = upload(&c->d_frec, T.frec, "upload fault records")) != RB_OK) return st;
@@ -1824,7 +1869,7 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_gamma16_slot);
         (void)hipFree(c->d_chk_of);
         (void)hipFree(c->d_lrowptr);
-        (void)hipFree(c->d_lcolptr);
+        (void)hipFree(c->d_fcol);
         (void)hipFree(c->d_col16);
         (void)hipFree(c->d_rbase);
         (void)hipFree(c->d_fedge);
@@ -1966,13 +2011,14 @@ static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.iters = g.iters;
     b.weight = g.weight;
     b.final_llr = g.final_llr;
-    b.w = g.w;
-    b.gamma = g.gamma;
+    b.slot_col = c->d_slot_col;
+    b.w_slot = c->d_w_slot;
+    b.gamma_slot = c->d_gamma_slot;
     b.lambda0 = c->d_lambda0;
     b.rowptr = c->d_lrowptr;
     b.ctab = c->d_col16;
     b.rbase = c->d_rbase;
-    b.colptr = c->d_lcolptr;
+    b.fcol = c->d_fcol;
     b.frec = c->d_frec;
     b.fedge = c->d_fedge;
     b.chk_of = c->d_chk_of;
@@ -2115,8 +2161,8 @@ rb_status rb_set_leg_gamma(rb_ctx *c, int32_t leg, const float *host_gamma) {
     RB_HIP(hipMemcpy(c->d_gamma + (size_t)(leg - 1) * c->N, host_gamma, sizeof(float) * (size_t)c->N,
                      hipMemcpyHostToDevice),
            "copy gamma row");
-    if (c->block) {
-        const int npad = c->bshape.TPB * c->bshape.VPT;
+    if (c->block || c->large) {
+        const int npad = c->block ? c->bshape.TPB * c->bshape.VPT : c->lshape.TPB * c->lshape.VR;
         RB_HIP(rb::launch_gather_slots(c->d_gamma + (size_t)(leg - 1) * c->N, c->N, c->d_slot_col, npad, 1,
                                        c->d_gamma_slot + (size_t)(leg - 1) * npad, nullptr),
                "gamma by slot");

@@ -195,16 +195,15 @@ hipError_t launch_block16(int v, bool prior_anchor, bool trace, const BlockArgs 
 hipError_t launch_to_half(const float *src, int64_t n, uint16_t *dst, hipStream_t s);
 
 // Shape of a large-graph configuration: TPB threads decode one syndrome;
-// thread t owns faults t + TPB*v (v < VR) and up to kLargeRounds checks.
+// thread t owns the fault slots t + TPB*v (v < VR) and up to kLargeRounds
+// checks.
 struct LargeShape {
     int TPB, VR;
 };
 constexpr int kLargeRounds = 4;       // checks per thread at most (M <= 4 * TPB)
-constexpr int kLargeEdgeBits = 20;    // fault-side entries: check << 20 | sign-bit slot
-constexpr int kLargeGather = 8;       // row chunk and fault record length (table entries per load step)
-constexpr int kLargeBatch = 4;        // faults whose loads the fault pass issues together
-constexpr int kLargeSure = 6;         // fault entries read whatever the degree (padding included;
-                                      // DEM columns have degree 2-6)
+constexpr int kLargeEdgeBits = 20;    // fault-side entry codes: check << 20 | (sign-bit slot ^ 24)
+constexpr int kLargeGather = 8;       // row chunk length (one byte of sign bits) and fault record length
+constexpr int kLargeBatch = 4;        // fault slots whose loads the fault pass issues together
 
 struct LargeArgs {
     int32_t M, N;
@@ -218,24 +217,27 @@ struct LargeArgs {
     int32_t *iters;
     double *weight;
     float *final_llr;
-    const float *w;            // [N]
-    const float *gamma;        // [R][N]
-    float *lambda0;            // [grid][N] workspace: lambda(0) of the current chained leg per workgroup
+    // fault slots: faults in order of decreasing column degree, slot p holds
+    // fault slot_col[p] (-1 for the TPB*VR - N spare slots)
+    const int32_t *slot_col;   // [TPB*VR]
+    const float *w_slot;       // [TPB*VR] w by slot (0 for spare slots)
+    const float *gamma_slot;   // [R][TPB*VR] gamma by slot
+    float *lambda0;            // [grid][N] workspace: lambda(0) of the current chained leg per workgroup, by slot
     const int32_t *rowptr;     // [M+1] CSR
-    const uint16_t *ctab;      // row i's fault indices from entry 8 * rbase[i], padded with 0 to a
-                               // multiple of kLargeGather (16-byte aligned chunks)
+    const uint16_t *ctab;      // row i's fault slots from entry 8 * rbase[i], padded with N to a
+                               // multiple of kLargeGather (16-byte aligned chunks), + one zero chunk
     const int32_t *rbase;      // [M] first chunk of row i in ctab
-    const int32_t *colptr;     // [N+1] CSC
-    const uint32_t *frec;      // [N][kLargeGather] first entries of each column (padding: 0)
-    const uint32_t *fedge;     // [E] CSC order (ascending check): check << kLargeEdgeBits | slot
+    const int2 *fcol;          // [TPB*VR] (first entry in fedge, column degree) of each slot
+    const uint32_t *frec;      // [TPB*VR][kLargeGather] the first entry codes of each slot (padding: 0)
+    const uint32_t *fedge;     // [E] entry codes by slot, each column's in ascending check order
     const int32_t *chk_of;     // [kLargeRounds][TPB] check of thread t in round c, or -1
     int32_t rounds;            // check rounds in use (<= kLargeRounds)
-    int32_t nsw;               // words of edge sign bits (ceil(E / 32))
+    int32_t nsw;               // words of edge sign bits
     unsigned long long *queue;
     int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
     float L;
     uint32_t chk_off, sgn_off, red_off;  // LDS byte offsets: check states, sign bits, scratch
-    const float *trace_gamma;
+    const float *trace_gamma;  // [N] by fault (trace runs)
     float scale;
     int32_t trace_T;
     float *trace;

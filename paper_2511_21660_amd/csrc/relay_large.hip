@@ -12,27 +12,37 @@
 // sign sign(nu_e) XOR neg_i, where neg_i is the parity of sigma_i and of the
 // signs of all nu of the check.  A check's messages are therefore fixed by
 // the state (m1, m2, position of the minimum, neg) plus one sign bit per edge.
-// LDS holds Lambda[0..N-1] and one more entry, Lambda[N] = +inf, that row
-// padding reads; one 16-byte state per check; the sign bits of nu, one per
-// slot of the padded row table.  A fault rebuilds each message it sums
-// from the state of its check, bit for bit the message the other kernels
-// store.  A 2736 x 26208 matrix with 82.6K edges takes about 156 KiB.
+// LDS holds Lambda by fault slot and one more entry, Lambda[N] = +inf, that
+// row padding reads; one 16-byte state per check, (m1, m2) carrying neg as
+// their sign bit and the position as the code of the edge's fault-side entry;
+// the sign bits of nu, one byte per chunk of eight row entries.  A fault
+// rebuilds each message it sums from its check's state and its edge's sign
+// bit, bit for bit the message the other kernels store.  A 2736 x 26208
+// matrix with 82.6K edges takes about 157 KiB.
 //
-// Roles.  Thread t owns the faults j = t + TPB*v (v < VR) and the checks
-// chk_of[c][t] (c < rounds): checks sorted by degree and dealt round by round,
-// so the 64 rows a wave handles in one round have nearly the same length.
-// The graph tables stay in global memory, shared by all workgroups and
-// L2-resident: each row's fault indices padded to a multiple of 8 (one
-// aligned 16-byte load per 8 edges) and one 32-byte record per fault with its
-// first 8 (check, slot) entries (the records of a wave's lanes contiguous),
-// the slot being the edge's position in the padded row table.
-// A 32-bit word of sign bits can hold edges of two checks owned by different
-// threads, so a check writes its bits of a shared word with two LDS atomics
-// (clear, then set its own bits).
+// Fault slots.  Faults are renumbered in order of decreasing column degree
+// (slot p holds fault slot_col[p]); thread t owns the slots t + TPB*v
+// (v < VR), so the 64 faults a wave handles in one round nearly always share
+// their degree and the fault pass runs no entries past it.  Lambda, w, gamma
+// and the chained lambda(0) are all kept by slot; corrections and marginals
+// go out by fault.
+//
+// Roles.  Thread t owns its slots and the checks chk_of[c][t] (c < rounds):
+// checks sorted by degree and dealt round by round, so the 64 rows a wave
+// handles in one round have nearly the same length.  The graph tables stay in
+// global memory, shared by all workgroups and L2-resident: each row's fault
+// slots padded to a multiple of 8 (one aligned 16-byte load per 8 edges), and
+// per slot (first entry, degree) and a 32-byte record of its first 8 entry
+// codes.  An entry code (check << 20 | (s ^ 24)) names the check's state
+// (bits 20..31), the word of its sign bit (s >> 5) and, in its low five bits,
+// the left shift that moves that bit to bit 31 (chunk entry q's bit is bit
+// 7 - q of the chunk's byte).
 //
 // Iteration (as in the block kernel): the check pass of iteration t+1 reads
 // Lambda(t) for every edge, so the parity of F(t) per check is folded into it
 // and reduced with one barrier; leg and shot events are block-uniform.
+// Lambda, nu and every lambda(0) are never -0 (channel LLRs enter as
+// s * w + 0), so sign bits are the signs the min-sum update tests with x < 0.
 
 #include <algorithm>
 
@@ -44,24 +54,37 @@ namespace {
 
 __device__ __forceinline__ float clipl(float x, float L) { return __builtin_amdgcn_fmed3f(x, -L, L); }
 
-// four words in one LDS access (a plain vector type: the LDS helpers take no
-// class types)
+// three or four words in one LDS access (plain vector types: the LDS helpers
+// take no class types)
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void lds_and(uint32_t byte_addr, uint32_t v) {
-    __hip_atomic_fetch_and((__attribute__((address_space(3))) uint32_t *)(size_t)byte_addr, v, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
 __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
     __hip_atomic_fetch_or((__attribute__((address_space(3))) uint32_t *)(size_t)byte_addr, v, __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// bits 5..19 of an entry code (its sign word), as one instruction: written
+// as shifts and a mask, the compiler folds the word's scaling by 4 into them
+// and needs three
+__device__ __forceinline__ uint32_t bfe_word(uint32_t pk) {
+    uint32_t r;
+    asm("v_bfe_u32 %0, %1, 5, 15" : "=v"(r) : "v"(pk));
+    return r;
+}
+
+// 4 * (x & 0xffff) as one instruction (a 16 x 16-bit multiply-add)
+__device__ __forceinline__ uint32_t lo16_x4(uint32_t x) {
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, 4, 0" : "=v"(r) : "v"(x));
+    return r;
+}
+
 template <int TPB, int VR, bool PRIOR, bool TRACE>
 __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     static_assert(VR <= 32 && VR % kLargeBatch == 0 && TPB % 256 == 0, "shape");
-    static_assert(32 % kLargeGather == 0, "a row chunk lies in one sign word");
+    static_assert(kLargeGather == 8, "a row chunk is one byte of sign bits");
+    constexpr int NP = TPB * VR;                          // slots (row stride of gamma_slot)
     const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
     const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 bytes (block OR), 16-byte aligned
     const uint32_t shot_sh = flags + 4u * (TPB / 64);     // claimed shot index
@@ -70,8 +93,8 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     const float L = a.L;
     const int N = a.N;
     // thread index made opaque at the top of every iteration, so that the
-    // per-fault addresses are recomputed where used instead of being hoisted
-    // out of the persistent loop (2 * VR 64-bit pointers would spill)
+    // per-slot addresses are recomputed where used instead of being hoisted
+    // out of the persistent loop
     uint32_t tl = (uint32_t)t;
 
     // this thread's checks, their degrees and first row chunks
@@ -86,32 +109,23 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
     if (t == 0) lds_b<float>(4u * (uint32_t)N) = __builtin_inff();  // target of row padding entries
 
-    // (1 - gamma) * lambda(0) is formed each iteration from two values per
-    // fault, read each iteration (coalesced: a wave's lanes own
-    // consecutive faults), which keeps the registers for the loads in flight:
-    // gamma of the current leg from the table; lambda(0) from w in leg 1 and
-    // under the prior anchor, else (chained legs) from this workgroup's slice
-    // of global memory, written at each leg change
+    // lambda(0) is s * w in leg 1 and under the prior anchor (from the shared,
+    // L2-resident w by slot), else (chained legs) this workgroup's slice of
+    // global memory, written at each leg change
     float *l0w = a.lambda0 + (size_t)blockIdx.x * N;
-    const float *gcur = a.gamma;
+    const float *gcur = a.gamma_slot;
     uint32_t sig = 0;  // bit c: syndrome bit of check ci[c]
     uint32_t best_mask = 0;
     double best_w = 0.0;
     long long shot = -1;
     int r = 0, tt = 0, total = 0, count = 0;
 
-    // messages restart at zero: states (0, 0, 0, 0) and all sign bits clear
+    // messages restart at zero: states (+0, +0, 0) and all sign bits clear
     // rebuild +0 on every edge
     auto zero_messages = [&]() {
 #pragma unroll
         for (int c = 0; c < kLargeRounds; ++c)
-            if (ci[c] >= 0) {
-                const uint32_t sa = chk + 16u * (uint32_t)ci[c];
-                lds_b<uint32_t>(sa) = 0u;
-                lds_b<uint32_t>(sa + 4u) = 0u;
-                lds_b<uint32_t>(sa + 8u) = 0u;
-                lds_b<uint32_t>(sa + 12u) = 0u;
-            }
+            if (ci[c] >= 0) lds_b<u32x4>(chk + 16u * (uint32_t)ci[c]) = u32x4{0u, 0u, 0u, 0u};
         for (int q = t; q < a.nsw; q += TPB) lds_b<uint32_t>(sgn + 4u * (uint32_t)q) = 0u;
     };
 
@@ -134,14 +148,14 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             if (ci[c] >= 0 && syn_bit(a.syn, (size_t)shot, a.syn_stride, ci[c], a.io_bits)) sig |= 1u << c;
 #pragma unroll
         for (int v = 0; v < VR; ++v) {
-            const int j = (int)tl + TPB * v;
-            if (j < N) {
-                const float wj = a.scale * a.w[j];
-                lds_b<float>(4u * (uint32_t)j) = wj;
-                if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * N + j] = wj;
+            const int p = (int)tl + TPB * v;
+            if (p < N) {
+                const float wj = a.scale * a.w_slot[p] + 0.0f;  // -0 enters as +0
+                lds_b<float>(4u * (uint32_t)p) = wj;
+                if (TRACE) a.trace[(size_t)shot * (a.trace_T + 1) * N + a.slot_col[p]] = wj;
             }
         }
-        gcur = TRACE ? a.trace_gamma : a.gamma;
+        gcur = a.gamma_slot;
         zero_messages();
         return true;
     };
@@ -153,96 +167,72 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         asm volatile("" : "+v"(tl));
         // ---------------- check pass: new states from Lambda(t) and the old
         // messages; parity of F(t) per check
-        bool unsat_local = false;
+        uint32_t unsat_bits = 0;
 #pragma unroll
         for (int c = 0; c < kLargeRounds; ++c) {
             const int i = ci[c];
             if (i < 0) continue;
             const uint32_t sa = chk + 16u * (uint32_t)i;
             const u32x4 sto = lds_b<u32x4>(sa);
-            const float m1o = __uint_as_float(sto.x);
-            const float m2o = __uint_as_float(sto.y);
-            const int amo = (int)sto.z;
-            const uint32_t flipo = sto.w ? 0xffffffffu : 0u;
-            const bool sc = (sig >> c) & 1u;
-            bool fpar = sc, neg = sc;
+            const uint32_t m1o = sto.x, m2o = sto.y;          // old magnitudes, signed with the old neg
+            const int amo = (int)((sto.z & 0xfffffu) ^ 24u);  // slot of the old minimum
+            const uint32_t sc = ((sig >> c) & 1u) << 31;
+            uint32_t fpar = sc;  // bit 31: sigma_i XOR the signs of Lambda over the row
+            uint32_t negp = 0;   // XOR of the row's bytes of nu signs (neg from its popcount)
             float m1 = L, m2 = L;
             // edge k of the row has the sign-bit slot e0 + k, its position in
-            // the padded row table: rows start on multiples of kLargeGather,
-            // so a chunk of kLargeGather edges never straddles a sign word
+            // the padded row table: rows start on multiples of 8 slots, so a
+            // chunk of 8 edges is one byte of sign bits, read (old signs) and
+            // written (new signs) whole
             const int e0 = crb[c] * kLargeGather, deg = cd[c];
             int amin = e0;
-            // sign bits of the word being filled: old message signs, new nu
-            // signs and the row's bits in it; a word shared with another
-            // check is written with two atomics
-            int cw = e0 >> 5;
-            uint32_t osg = lds_b<uint32_t>(sgn + 4u * (uint32_t)cw) ^ flipo, nb = 0u, mask = 0u;
-            auto flush = [&]() {
-                const uint32_t wa = sgn + 4u * (uint32_t)cw;
-                if (mask == 0xffffffffu) {
-                    lds_b<uint32_t>(wa) = nb;
-                } else if (mask != 0u) {
-                    lds_and(wa, ~mask);
-                    lds_or(wa, nb);
-                }
-            };
             // eight edges per step from one aligned 16-byte load of the row's
-            // padded fault indices; the Lambda gathers are issued together
+            // padded fault slots; the Lambda gathers are issued together and
             // the next chunk is loaded one step ahead (the table ends with a
             // zero chunk, so the load past a row's last chunk stays inside it).
             // Padding entries of a row's last chunk address Lambda[N] = +inf:
             // their nu is clip(inf - mu) = L, which leaves m1 <= m2 <= L, the
             // position of the minimum, both parities and the sign bits as
             // they are, so all eight entries run without a per-edge test.
-            // A chunk is one byte of a sign word (its slot is a multiple of
-            // 8): old signs are read and new ones collected per byte.
             const uint4 *rt = reinterpret_cast<const uint4 *>(a.ctab) + crb[c];
             uint4 cur = rt[0];
             for (int k = 0; k < deg; k += kLargeGather) {
                 const uint4 pk = cur;
                 cur = rt[k / kLargeGather + 1];
                 const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
+                const int ec = e0 + k;  // slot of the chunk's first entry
+                const uint32_t ba = sgn + ((uint32_t)ec >> 3);
+                const uint32_t ob = lds_b<uint8_t>(ba);  // old signs of nu, entry q in bit 7 - q
                 float lv[kLargeGather];
 #pragma unroll
                 for (int q = 0; q < kLargeGather; ++q)
-                    lv[q] = lds_b<float>(4u * ((q & 1) ? (pw[q >> 1] >> 16) : (pw[q >> 1] & 0xffffu)));
-                const int ec = e0 + k;  // slot of the chunk's first entry
-                if ((ec >> 5) != cw) {  // the row enters the next word of sign bits
-                    flush();
-                    cw = ec >> 5;
-                    osg = lds_b<uint32_t>(sgn + 4u * (uint32_t)cw) ^ flipo;
-                    nb = 0u;
-                    mask = 0u;
-                }
-                const uint32_t sh = (uint32_t)ec & 31u;
-                const uint32_t ob = osg >> sh;  // old message signs, entry q in bit q
-                const int am = amo - ec;        // entry of the old minimum, if in 0..7
-                uint32_t nb8 = 0u;
+                    lv[q] = lds_b<float>((q & 1) ? 4u * (pw[q >> 1] >> 16) : lo16_x4(pw[q >> 1]));
+                int am = amo - ec;  // entry of the old minimum, if in 0..7
+                asm volatile("" : "+v"(am));  // compared with each entry's constant
+                int aq = -1;                  // entry of a new minimum in this chunk
+                uint32_t nb = 0u;
 #pragma unroll
                 for (int q = 0; q < kLargeGather; ++q) {
-                    const float mag = am == q ? m2o : m1o;
-                    const float mo = __uint_as_float(((ob << (31 - q)) & 0x80000000u) | __float_as_uint(mag));
-                    fpar ^= lv[q] < 0.0f;
+                    const uint32_t mag = am == q ? m2o : m1o;
+                    const float mo = __uint_as_float(((ob << (24 + q)) & 0x80000000u) ^ mag);
+                    fpar ^= __float_as_uint(lv[q]);
                     const float nu = clipl(lv[q] - mo, L);
-                    const bool sn = nu < 0.0f;
-                    neg ^= sn;
-                    nb8 |= sn ? 1u << q : 0u;
+                    nb = __builtin_amdgcn_alignbit(nb, __float_as_uint(nu), 31);  // sign of nu -> bit 7 - q
                     const float av = fabsf(nu);
-                    amin = av < m1 ? ec + q : amin;
+                    aq = av < m1 ? q : aq;
                     m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
                     m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
                 }
-                nb |= nb8 << sh;
-                mask |= 0xffu << sh;  // padding slots belong to this row alone
+                amin = aq >= 0 ? ec + aq : amin;
+                negp ^= nb;
+                lds_b<uint8_t>(ba) = (uint8_t)nb;
             }
-            flush();
-            lds_b<float>(sa) = m1;
-            lds_b<float>(sa + 4u) = m2;
-            lds_b<int>(sa + 8u) = amin;
-            lds_b<uint32_t>(sa + 12u) = neg ? 1u : 0u;
-            unsat_local |= fpar;
+            const uint32_t neg = sc ^ ((uint32_t)__popc(negp) << 31);
+            lds_b<u32x4>(sa) = u32x4{__float_as_uint(m1) | neg, __float_as_uint(m2) | neg,
+                                     ((uint32_t)i << kLargeEdgeBits) | ((uint32_t)amin ^ 24u), 0u};
+            unsat_bits |= fpar;
         }
-        const bool unsat = block_or<TPB>(unsat_local, flags);
+        const bool unsat = block_or<TPB>((unsat_bits >> 31) != 0u, flags);
 
         // ---------------- leg scheduler (block-uniform)
         const bool cut = a.max_total_iters > 0 && total >= a.max_total_iters;
@@ -256,11 +246,11 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 double part = 0.0;
 #pragma unroll
                 for (int v = 0; v < VR; ++v) {
-                    const int j = (int)tl + TPB * v;
-                    if (j < N) {
-                        const bool f = lds_b<float>(4u * (uint32_t)j) < 0.0f;
+                    const int p = (int)tl + TPB * v;
+                    if (p < N) {
+                        const bool f = lds_b<float>(4u * (uint32_t)p) < 0.0f;
                         fm |= f ? 1u << v : 0u;
-                        part += (double)(f ? a.w[j] : 0.0f);  // + 0 leaves the sum's bits unchanged
+                        part += (double)(f ? a.w_slot[p] : 0.0f);  // + 0 leaves the sum's bits unchanged
                     }
                 }
                 const double W = block_sum<TPB>(part, red);
@@ -278,25 +268,34 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                     const uint32_t out = count > 0 ? best_mask : fm;
 #pragma unroll
                     for (int v = 0; v < VR; ++v) {
-                        const int j = (int)tl + TPB * v;
-                        if (j < N) {
+                        const int p = (int)tl + TPB * v;
+                        if (p < N) {
+                            const int j = a.slot_col[p];
                             if (!a.io_bits) a.corr[(size_t)shot * a.corr_stride + j] = (uint8_t)((out >> v) & 1u);
-                            if (a.final_llr) a.final_llr[(size_t)shot * N + j] = lds_b<float>(4u * (uint32_t)j);
+                            if (a.final_llr) a.final_llr[(size_t)shot * N + j] = lds_b<float>(4u * (uint32_t)p);
                         }
                     }
                     if (a.io_bits) {
-                        // fault j = t + TPB*v: the 64 faults of a wave in round v
-                        // are words (TPB*v + 64*wave) / 32 and the next one, taken
-                        // from one ballot (bits of faults >= N are 0)
-                        uint32_t *c32 = reinterpret_cast<uint32_t *>(a.corr) + (size_t)shot * a.corr_stride;
-                        const int lane = t & 63;
+                        // slots hold faults in degree order, so the packed words are
+                        // assembled in LDS: the first ceil(N/32) words of the Lambda
+                        // region (read above; the next fetch rewrites every Lambda
+                        // word below N) are cleared, each set fault ORs its bit into
+                        // word j / 32, and the words go out coalesced
+                        const int nw = (N + 31) >> 5;
+                        __syncthreads();
+                        for (int q = t; q < nw; q += TPB) lds_b<uint32_t>(4u * (uint32_t)q) = 0u;
+                        __syncthreads();
 #pragma unroll
                         for (int v = 0; v < VR; ++v) {
-                            const unsigned long long bal = __ballot((out >> v) & 1u);
-                            const int j0 = TPB * v + (t & ~63) + (lane & 32);  // first fault of this lane's word
-                            if ((lane & 31) == 0 && j0 < N)
-                                c32[j0 >> 5] = (uint32_t)(lane & 32 ? bal >> 32 : bal);
+                            const int p = (int)tl + TPB * v;
+                            if (p < N && ((out >> v) & 1u)) {
+                                const int j = a.slot_col[p];
+                                lds_or(4u * (uint32_t)(j >> 5), 1u << (j & 31));
+                            }
                         }
+                        __syncthreads();
+                        uint32_t *c32 = reinterpret_cast<uint32_t *>(a.corr) + (size_t)shot * a.corr_stride;
+                        for (int q = t; q < nw; q += TPB) c32[q] = lds_b<uint32_t>(4u * (uint32_t)q);
                     }
                     if (t == 0) {
                         a.conv[shot] = count > 0 ? 1 : 0;
@@ -309,12 +308,11 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             if (!done) {
                 ++r;
                 tt = 0;
-                const float *gr = a.gamma + (size_t)(r - 1) * N;
-                gcur = gr;
+                gcur = a.gamma_slot + (size_t)(r - 1) * NP;
 #pragma unroll
                 for (int v = 0; v < VR; ++v) {
-                    const int j = (int)tl + TPB * v;
-                    if (!PRIOR && j < N) l0w[j] = clipl(lds_b<float>(4u * (uint32_t)j), L);
+                    const int p = (int)tl + TPB * v;
+                    if (!PRIOR && p < N) l0w[p] = clipl(lds_b<float>(4u * (uint32_t)p), L);
                 }
                 zero_messages();
             } else {
@@ -325,69 +323,83 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         }
 
         // ---------------- fault pass: memory term, then the messages of the
-        // fault's checks in ascending check order, each rebuilt from its
-        // check's state and its edge's sign bit.  Faults go in batches of
-        // kLargeBatch whose loads (column range, the 32-byte record of its
-        // first kLargeGather entries, gamma, Lambda) are all issued first;
-        // indices are clamped so every load is in bounds.
-        // message of one (check, edge) entry, from the check's 16-byte state
-        // (one LDS load) and the edge's sign word
-        auto msg_of = [&](uint32_t pk) -> float {
-            const uint32_t e = pk & ((1u << kLargeEdgeBits) - 1u);
-            const u32x4 st = lds_b<u32x4>(chk + 16u * (pk >> kLargeEdgeBits));
-            const uint32_t sw = lds_b<uint32_t>(sgn + 4u * (e >> 5));
-            const uint32_t mag = e == st.z ? st.y : st.x;
-            const uint32_t sb = ((sw >> (e & 31u)) ^ st.w) & 1u;
-            return __uint_as_float((sb << 31) | mag);
+        // slot's checks in ascending check order, each rebuilt from its
+        // check's state and its edge's sign bit.  Slots go in batches of
+        // kLargeBatch whose loads (first entry and degree, the first four
+        // entry codes, gamma, lambda(0), Lambda) are all issued first; slots
+        // are clamped so every load is in bounds.  Entries go in pairs whose
+        // state and sign-word loads issue together: the first pair whatever
+        // the degree (a record's padding entries name check 0, a valid
+        // address; the sum skips them with a select, not an added 0, which
+        // would turn -0 into +0), later pairs only where the degree reaches
+        // them (the lanes of a wave nearly always share it, so the pair
+        // drops out for the whole wave).
+        // (the state's three words in use are read as one access: a fourth,
+        // unused register would still be written by the load and could not
+        // take the next address until it lands)
+        auto st_of = [&](uint32_t pk) -> u32x3 { return lds_b<u32x3>(chk + ((pk >> 16) & 0xfff0u)); };
+        auto sw_of = [&](uint32_t pk) -> uint32_t { return lds_b<uint32_t>(sgn + (bfe_word(pk) << 2)); };
+        auto msg = [&](uint32_t pk, const u32x3 &st, uint32_t sw) -> float {
+            const uint32_t mag = pk == st.z ? st.y : st.x;  // signed with the check's neg
+            return __uint_as_float(((sw << (pk & 31u)) & 0x80000000u) ^ mag);
         };
+        // entries k and k + 1 of codes c0, c1 (the second only if k + 1 < deg)
+        auto pair = [&](float acc, uint32_t c0, uint32_t c1, int k, int deg, bool first_checked) -> float {
+            const u32x3 s0 = st_of(c0), s1 = st_of(c1);
+            const uint32_t w0 = sw_of(c0), w1 = sw_of(c1);
+            const float m0 = msg(c0, s0, w0), m1 = msg(c1, s1, w1);
+            acc = (first_checked || k < deg) ? acc + m0 : acc;
+            return k + 1 < deg ? acc + m1 : acc;
+        };
+        // lambda(0): s * w + 0 (leg 1, prior anchor) or the chained anchor
+        // (x * 1 + 0 = x: a chained anchor is never -0)
+        const bool from_w = PRIOR || r == 1;
+        const float *l0src = from_w ? a.w_slot : l0w;
+        const float l0mul = from_w ? a.scale : 1.0f;
+        const char *gsrc = reinterpret_cast<const char *>(gcur);
 #pragma unroll
         for (int vb = 0; vb < VR; vb += kLargeBatch) {
-            // this thread's faults of this and every later batch lie past N
+            // this thread's slots of this and every later batch lie past N
             if ((int)tl + TPB * vb >= N) break;
-            int qa[kLargeBatch], qb[kLargeBatch];
-            uint4 ra[kLargeBatch], rc[kLargeBatch];
+            int2 fc[kLargeBatch];
+            uint4 ra[kLargeBatch];
             float gv[kLargeBatch], l0[kLargeBatch], lam[kLargeBatch];
 #pragma unroll
             for (int f = 0; f < kLargeBatch; ++f) {
-                const int j = min((int)tl + TPB * (vb + f), N - 1);
-                qa[f] = a.colptr[j];
-                qb[f] = a.colptr[j + 1];
-                const uint4 *fr = reinterpret_cast<const uint4 *>(a.frec) + 2 * (size_t)j;
-                ra[f] = fr[0];
-                rc[f] = fr[1];
-                gv[f] = gcur[j];
-                // lambda(0) is s * w in leg 1 and under the prior anchor (read
-                // from the shared, L2-resident w), else the chained anchor
-                l0[f] = (PRIOR || r == 1) ? a.scale * a.w[j] : l0w[j];
-                lam[f] = lds_b<float>(4u * (uint32_t)j);
+                const uint32_t p = (uint32_t)min((int)tl + TPB * (vb + f), N - 1);
+                const uint32_t o4 = 4u * p;  // byte offsets from 32-bit products (tables < 4 GiB)
+                fc[f] = *reinterpret_cast<const int2 *>(reinterpret_cast<const char *>(a.fcol) + 2u * o4);
+                ra[f] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(a.frec) + 8u * o4);
+                gv[f] = TRACE ? a.trace_gamma[a.slot_col[p]] : *reinterpret_cast<const float *>(gsrc + o4);
+                l0[f] = l0mul * *reinterpret_cast<const float *>(reinterpret_cast<const char *>(l0src) + o4) + 0.0f;
+                lam[f] = lds_b<float>(o4);
             }
+            // whole records: the compiler would otherwise split a record into
+            // loads issued where its entries are used
+#pragma unroll
+            for (int f = 0; f < kLargeBatch; ++f) asm volatile("" : "+v"(ra[f].x), "+v"(ra[f].y), "+v"(ra[f].z), "+v"(ra[f].w));
 #pragma unroll
             for (int f = 0; f < kLargeBatch; ++f) {
-                const int j = (int)tl + TPB * (vb + f);
-                if (j >= N) continue;
+                const int p = (int)tl + TPB * (vb + f);
+                if (p >= N) continue;
                 const float y = gv[f] * clipl(lam[f], L);
                 const float x = (1.0f - gv[f]) * l0[f];  // (1 - gamma) lambda(0)
                 float acc = clipl(x + y, L);
-                const uint32_t pk[kLargeGather] = {ra[f].x, ra[f].y, ra[f].z, ra[f].w,
-                                                   rc[f].x, rc[f].y, rc[f].z, rc[f].w};
-                // the first kLargeSure entries are read whatever the degree
-                // (padding entries address check 0 and sign word 0), so their
-                // loads issue together; the sum skips the padding (a select,
-                // not an added 0, which would turn -0 into +0)
-                const int deg = qb[f] - qa[f];
-                float mv[kLargeSure];
-#pragma unroll
-                for (int k = 0; k < kLargeSure; ++k) mv[k] = msg_of(pk[k]);
-#pragma unroll
-                for (int k = 0; k < kLargeSure; ++k) acc = k < deg ? acc + mv[k] : acc;
-#pragma unroll
-                for (int k = kLargeSure; k < kLargeGather; ++k) {
-                    if (k >= deg) break;
-                    acc += msg_of(pk[k]);
+                const int deg = fc[f].y;
+                acc = pair(acc, ra[f].x, ra[f].y, 0, deg, false);
+                if (deg > 2) acc = pair(acc, ra[f].z, ra[f].w, 2, deg, true);
+                if (deg > 4) {
+                    const uint4 rc =
+                        *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(a.frec) + 32u * (uint32_t)p + 16u);
+                    acc = pair(acc, rc.x, rc.y, 4, deg, true);
+                    if (deg > 6) acc = pair(acc, rc.z, rc.w, 6, deg, true);
+                    for (int q = fc[f].x + kLargeGather; q < fc[f].x + deg; ++q) {
+                        const uint32_t pq = a.fedge[q];
+                        acc += msg(pq, st_of(pq), sw_of(pq));
+                    }
                 }
-                for (int q = qa[f] + kLargeGather; q < qb[f]; ++q) acc += msg_of(a.fedge[q]);
-                lds_b<float>(4u * (uint32_t)j) = acc;
-                if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + j] = acc;
+                lds_b<float>(4u * (uint32_t)p) = acc;
+                if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + a.slot_col[p]] = acc;
             }
         }
         ++tt;
