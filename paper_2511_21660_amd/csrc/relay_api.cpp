@@ -99,13 +99,13 @@ struct rb_ctx {
     // large-graph kernel (compressed messages): CSR / CSC copies and tables
     bool large = false;
     rb::LargeShape lshape{};
-    int32_t lrounds = 0, nsw = 0;
-    uint32_t chk_off = 0, sgn_off = 0;
+    int32_t lrounds = 0, nrec = 0;
+    uint32_t chk_off = 0;
     int32_t *d_lrowptr = nullptr, *d_chk_of = nullptr;
     int2 *d_fcol = nullptr;      // [TPB*VR] (first entry, degree) per fault slot
     float *d_lambda0 = nullptr;  // [blocks_per_cu * num_cu][N] large-graph kernel workspace
     uint16_t *d_col16 = nullptr;            // row chunks of fault slots
-    int32_t *d_rbase = nullptr;
+    int32_t *d_rbase = nullptr, *d_rrec = nullptr;
     uint32_t *d_fedge = nullptr, *d_frec = nullptr;
     // CSR / CSC on the device (training kernels)
     int32_t *d_rowptr = nullptr, *d_colidx = nullptr, *d_colptr = nullptr, *d_cedge = nullptr;
@@ -532,39 +532,35 @@ bool block_fits(const rb_ctx *c, const rb::BlockShape &s) {
     return l.lds_bytes <= 160 * 1024;
 }
 
-// Slots of the large-graph kernel's padded row table: each row rounded up to
-// whole chunks of kLargeGather entries.  Slot rbase*kLargeGather + k holds the
-// fault of edge k of a row and indexes that edge's sign bit.
-int64_t large_slots(const rb_ctx *c) {
+// 16-byte check records of the large-graph kernel: one per 32 positions of a
+// row (at least one per row), each holding the check's state and the sign
+// bits of its 32 positions.
+int64_t large_records(const rb_ctx *c) {
     int64_t n = 0;
-    for (int32_t i = 0; i < c->M; ++i)
-        n += (c->rowptr[i + 1] - c->rowptr[i] + rb::kLargeGather - 1) / rb::kLargeGather * rb::kLargeGather;
+    for (int32_t i = 0; i < c->M; ++i) n += std::max<int64_t>(1, (c->rowptr[i + 1] - c->rowptr[i] + 31) / 32);
     return n;
 }
 
 // Large-graph kernel LDS: Lambda[N + 1] (entry N = +inf is the target of row
-// padding), one 16-byte state per check, one sign bit per slot, reduction
-// scratch.
+// padding), the check records, reduction scratch.
 struct LargeLayout {
-    uint32_t chk_off, sgn_off, red_off;
-    int32_t nsw;
+    uint32_t chk_off, red_off;
+    int32_t nrec;
     int64_t lds_bytes;
 };
 
 LargeLayout large_layout(const rb_ctx *c, const rb::LargeShape &s) {
     LargeLayout l{};
-    l.nsw = (int32_t)((large_slots(c) + 31) / 32);
+    l.nrec = (int32_t)std::min<int64_t>(large_records(c), INT32_MAX);
     l.chk_off = ((4u * (uint32_t)c->N + 4u) + 15u) & ~15u;
-    l.sgn_off = l.chk_off + 16u * (uint32_t)c->M;
-    l.red_off = (l.sgn_off + 4u * (uint32_t)l.nsw + 15u) & ~15u;
+    l.red_off = l.chk_off + 16u * (uint32_t)std::min(l.nrec, rb::kLargeMaxRecords);
     l.lds_bytes = (int64_t)l.red_off + 12 * (s.TPB / 64) + 8;
     return l;
 }
 
 bool large_fits(const rb_ctx *c, const rb::LargeShape &s) {
     if (c->M > rb::kLargeRounds * s.TPB || c->N > s.TPB * s.VR) return false;
-    if (c->N > 65535 || c->M > (1 << (32 - rb::kLargeEdgeBits)) || large_slots(c) >= (int64_t)1 << rb::kLargeEdgeBits)
-        return false;
+    if (c->N > 65535 || large_records(c) > rb::kLargeMaxRecords) return false;
     return large_layout(c, s).lds_bytes <= 160 * 1024;
 }
 
@@ -1351,21 +1347,25 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
 // them, thread t the t-th), so the 64 checks a wave handles in one round have
 // nearly the same length.  Faults are renumbered into slots by decreasing
 // column degree (ties by index), so the 64 slots of a wave in one round
-// nearly always share a degree.  Row chunks hold fault slots; each fault-side
-// entry is the code of its edge: check << kLargeEdgeBits | (slot ^ 24), the
-// slot being the edge's position in the padded row table (a row's chunk of 8
-// entries is one byte of sign bits, entry q in bit 7 - q: slot s's bit is bit
-// (s & 31) ^ 7 of word s >> 5, moved to bit 31 by a left shift of (s ^ 24) & 31).
+// nearly always share a degree.  Row chunks (8 entries, rows padded with N)
+// hold fault slots.  Row i owns records rrec[i] .. rrec[i] + ceil(deg/32) - 1;
+// position k of the row is bit (k & 31) ^ 7 of word 3 of record
+// rrec[i] + k / 32 (a chunk of 8 positions is one byte, entry q in bit
+// 7 - q).  Each fault-side entry is the code of its edge: record << 20 |
+// ((k & 31) ^ 24), the low five bits being the left shift that moves the
+// edge's sign bit to bit 31.
 struct LargeTables {
     LargeLayout lay{};
     int32_t rounds = 0;
-    std::vector<int32_t> chk_of, rowptr, rbase, slot_col;
+    std::vector<int32_t> chk_of, rowptr, rbase, rrec, slot_col;
     std::vector<int2> fcol;      // per slot: first entry in fedge, column degree
     std::vector<uint16_t> ctab;  // rows padded to multiples of kLargeGather entries, + one zero chunk
     std::vector<uint32_t> frec, fedge;
 };
 
-uint32_t large_code(int32_t i, int64_t slot) { return ((uint32_t)i << rb::kLargeEdgeBits) | ((uint32_t)slot ^ 24u); }
+uint32_t large_code(int32_t rec0, int64_t k) {
+    return ((uint32_t)(rec0 + k / 32) << rb::kLargeEdgeBits) | ((uint32_t)(k & 31) ^ 24u);
+}
 
 LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     constexpr int G = rb::kLargeGather;
@@ -1393,10 +1393,14 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     }
     T.rowptr.assign(c->rowptr.begin(), c->rowptr.end());
     T.rbase.resize((size_t)c->M);
-    int64_t chunks = 0;
+    T.rrec.resize((size_t)c->M);
+    int64_t chunks = 0, recs = 0;
     for (int32_t i = 0; i < c->M; ++i) {
+        const int64_t d = c->rowptr[i + 1] - c->rowptr[i];
         T.rbase[(size_t)i] = (int32_t)chunks;
-        chunks += (c->rowptr[i + 1] - c->rowptr[i] + G - 1) / G;
+        T.rrec[(size_t)i] = (int32_t)recs;
+        chunks += (d + G - 1) / G;
+        recs += std::max<int64_t>(1, (d + 31) / 32);
     }
     // padding entries of a row's last chunk hold N (the +inf entry of Lambda);
     // the closing chunk, only ever prefetched, holds zeros
@@ -1417,7 +1421,7 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
         T.fcol[(size_t)p] = int2{(int)q, (int)(c->colptr[j + 1] - c->colptr[j])};
         for (int64_t e = c->colptr[j]; e < c->colptr[j + 1]; ++e, ++q) {
             const int32_t i = c->rowidx[(size_t)e];
-            const uint32_t code = large_code(i, (int64_t)T.rbase[(size_t)i] * G + c->cpos[(size_t)e]);
+            const uint32_t code = large_code(T.rrec[(size_t)i], c->cpos[(size_t)e]);
             T.fedge[(size_t)q] = code;
             if (e - c->colptr[j] < G) T.frec[(size_t)p * G + (size_t)(e - c->colptr[j])] = code;
         }
@@ -1428,18 +1432,21 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
 // Independent reading of the large-graph tables: every check on exactly one
 // (round, thread); rounds in use hold the checks (kernel reads rounds <
 // ceil(M/TPB)); the slots a permutation of the faults; each CSR edge's row
-// entry the slot of its fault; each slot's entries, decoded, exactly its
-// column's edges in ascending check order, each naming the row slot that
-// holds it (so every message is rebuilt from its own check's state and sign
-// bit); sign bits inside the LDS sign words; the LDS image fits.
+// entry the slot of its fault; rows' records disjoint and inside the LDS
+// record region; each slot's entries, decoded (record -> its row, position
+// from the record and the bit), exactly its column's edges in ascending
+// check order, so every message is rebuilt from its own check's state and
+// sign bit; the LDS image fits.
 std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const LargeTables &T, rb_plan_report *r) {
     if (T.lay.lds_bytes > 160 * 1024) return "LDS image exceeds a CU";
     if (T.rounds < 1 || T.rounds > rb::kLargeRounds || (int64_t)T.rounds * s.TPB < c->M) return "check rounds";
     // the kernel loads whole chunks of kLargeGather entries: a row's chunk
     // past its last edge holds N (the +inf entry of Lambda, which must not
-    // overlap the check states), a record past a slot's last entry holds
+    // overlap the check records), a record past a slot's last entry holds
     // zeros (valid addresses), and every chunk lies inside the table
-    if (T.lay.chk_off < 4u * (uint32_t)c->N + 4u) return "Lambda[N] overlaps the check states";
+    if (T.lay.chk_off < 4u * (uint32_t)c->N + 4u) return "Lambda[N] overlaps the check records";
+    if (T.lay.nrec > rb::kLargeMaxRecords || T.lay.red_off < T.lay.chk_off + 16u * (uint32_t)T.lay.nrec)
+        return "check records past their region";
     constexpr int G = rb::kLargeGather;
     const int npad = s.TPB * s.VR;
     if (T.frec.size() != (size_t)npad * G || T.fcol.size() != (size_t)npad || T.slot_col.size() != (size_t)npad)
@@ -1454,19 +1461,22 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
         if (j < 0 || j >= c->N || slot_of[(size_t)j] >= 0) return "slot " + std::to_string(p) + ": not a permutation";
         slot_of[(size_t)j] = p;
     }
-    auto col_of_slot = [&](int64_t at) -> int64_t {  // fault in table slot `at`
-        if (at < 0 || (size_t)at >= T.ctab.size() || T.ctab[(size_t)at] >= (uint32_t)c->N) return -1;
-        return T.slot_col[T.ctab[(size_t)at]];
-    };
+    std::vector<int32_t> row_of_rec((size_t)T.lay.nrec, -1);
     for (int32_t i = 0; i < c->M; ++i) {
         const int64_t d = T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i];
+        const int64_t nr = std::max<int64_t>(1, (d + 31) / 32);
+        for (int64_t k = 0; k < nr; ++k) {
+            const int64_t rec = (int64_t)T.rrec[(size_t)i] + k;
+            if (rec < 0 || rec >= T.lay.nrec || row_of_rec[(size_t)rec] >= 0) return "row " + std::to_string(i) + ": records";
+            row_of_rec[(size_t)rec] = i;
+        }
         if ((size_t)(T.rbase[(size_t)i] + (d + G - 1) / G) * G > T.ctab.size()) return "row chunks past the table";
         for (int64_t k = d; k < (d + G - 1) / G * G; ++k)
             if (T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)k] != (uint32_t)c->N) return "row padding values";
         for (int64_t e = T.rowptr[(size_t)i]; e < T.rowptr[(size_t)i + 1]; ++e) {
-            const int64_t at = (int64_t)T.rbase[(size_t)i] * G + (e - T.rowptr[(size_t)i]);
-            if (col_of_slot(at) != c->colidx[(size_t)e]) return "edge " + std::to_string(e) + ": wrong fault slot";
-            if (at >= 32 * (int64_t)T.lay.nsw) return "edge " + std::to_string(e) + ": sign bit past the sign words";
+            const uint32_t sl = T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)(e - T.rowptr[(size_t)i])];
+            if (sl >= (uint32_t)c->N || T.slot_col[sl] != c->colidx[(size_t)e])
+                return "edge " + std::to_string(e) + ": wrong fault slot";
         }
     }
     for (int p = 0; p < c->N; ++p) {
@@ -1478,11 +1488,14 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
         int32_t prev = -1;
         for (int64_t k = 0; k < d; ++k) {
             const uint32_t code = T.fedge[(size_t)(fc.x + k)];
-            const int32_t i = (int32_t)(code >> rb::kLargeEdgeBits);
-            const int64_t at = (int64_t)((code & ((1u << rb::kLargeEdgeBits) - 1u)) ^ 24u);
-            if (i <= prev || i >= c->M) return "slot " + std::to_string(p) + ": checks not ascending";
-            const int64_t pos = at - (int64_t)T.rbase[(size_t)i] * G;  // position in the row
-            if (pos < 0 || pos >= T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i] || col_of_slot(at) != j)
+            const int64_t rec = code >> rb::kLargeEdgeBits;
+            if ((code & ((1u << rb::kLargeEdgeBits) - 32u)) != 0u || rec >= T.lay.nrec)
+                return "slot " + std::to_string(p) + ": entry " + std::to_string(k) + " malformed";
+            const int32_t i = row_of_rec[(size_t)rec];
+            if (i <= prev) return "slot " + std::to_string(p) + ": checks not ascending";
+            const int64_t pos = 32 * (rec - T.rrec[(size_t)i]) + (int64_t)((code & 31u) ^ 24u);  // position in the row
+            const int64_t di = T.rowptr[(size_t)i + 1] - T.rowptr[(size_t)i];
+            if (pos >= di || T.ctab[(size_t)T.rbase[(size_t)i] * G + (size_t)pos] != (uint32_t)p)
                 return "slot " + std::to_string(p) + ": entry " + std::to_string(k) + " is not its edge";
             prev = i;
         }
@@ -1527,6 +1540,7 @@ rb_status build_large_plan(rb_ctx *c, int lv) {
     }
     if ((st = upload(&c->d_col16, T.ctab, "upload row chunks")) != RB_OK) return st;
     if ((st = upload(&c->d_rbase, T.rbase, "upload row bases")) != RB_OK) return st;
+    if ((st = upload(&c->d_rrec, T.rrec, "upload row records")) != RB_OK) return st;
     if ((st = upload(&c->d_frec, T.frec, "upload fault records")) != RB_OK) return st;
     if ((st = upload(&c->d_fedge, T.fedge, "upload fault entries")) != RB_OK) return st;
     {
@@ -1540,9 +1554,8 @@ rb_status build_large_plan(rb_ctx *c, int lv) {
     c->large = true;
     c->lshape = s;
     c->lrounds = T.rounds;
-    c->nsw = T.lay.nsw;
+    c->nrec = T.lay.nrec;
     c->chk_off = T.lay.chk_off;
-    c->sgn_off = T.lay.sgn_off;
     c->red_off = T.lay.red_off;
     c->lds_bytes = (int)T.lay.lds_bytes;
     const bool prior = c->params.anchor == RB_ANCHOR_PRIOR;
@@ -1872,6 +1885,7 @@ void rb_destroy(rb_ctx *c) {
         (void)hipFree(c->d_fcol);
         (void)hipFree(c->d_col16);
         (void)hipFree(c->d_rbase);
+        (void)hipFree(c->d_rrec);
         (void)hipFree(c->d_fedge);
         (void)hipFree(c->d_frec);
         (void)hipFree(c->d_lambda0);
@@ -2023,7 +2037,8 @@ static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.fedge = c->d_fedge;
     b.chk_of = c->d_chk_of;
     b.rounds = c->lrounds;
-    b.nsw = c->nsw;
+    b.nrec = c->nrec;
+    b.rrec = c->d_rrec;
     b.queue = g.queue;
     b.num_legs = g.num_legs;
     b.iters_first = g.iters_first;
@@ -2032,7 +2047,6 @@ static rb::LargeArgs large_args(const rb::GroupArgs &g, const rb_ctx *c) {
     b.max_total_iters = g.max_total_iters;
     b.L = g.L;
     b.chk_off = c->chk_off;
-    b.sgn_off = c->sgn_off;
     b.red_off = c->red_off;
     b.trace_gamma = g.trace_gamma;
     b.scale = g.scale;

@@ -201,7 +201,8 @@ struct LargeShape {
     int TPB, VR;
 };
 constexpr int kLargeRounds = 4;       // checks per thread at most (M <= 4 * TPB)
-constexpr int kLargeEdgeBits = 20;    // fault-side entry codes: check << 20 | (sign-bit slot ^ 24)
+constexpr int kLargeEdgeBits = 20;    // fault-side entry codes: record << 20 | sign-bit shift
+constexpr int kLargeMaxRecords = 4096;  // 16-byte check records (record << 4 fits 16 bits)
 constexpr int kLargeGather = 8;       // row chunk length (one byte of sign bits) and fault record length
 constexpr int kLargeBatch = 4;        // fault slots whose loads the fault pass issues together
 
@@ -227,16 +228,17 @@ struct LargeArgs {
     const uint16_t *ctab;      // row i's fault slots from entry 8 * rbase[i], padded with N to a
                                // multiple of kLargeGather (16-byte aligned chunks), + one zero chunk
     const int32_t *rbase;      // [M] first chunk of row i in ctab
+    const int32_t *rrec;       // [M] first LDS record of row i (one per 32 row positions)
     const int2 *fcol;          // [TPB*VR] (first entry in fedge, column degree) of each slot
     const uint32_t *frec;      // [TPB*VR][kLargeGather] the first entry codes of each slot (padding: 0)
     const uint32_t *fedge;     // [E] entry codes by slot, each column's in ascending check order
     const int32_t *chk_of;     // [kLargeRounds][TPB] check of thread t in round c, or -1
     int32_t rounds;            // check rounds in use (<= kLargeRounds)
-    int32_t nsw;               // words of edge sign bits
+    int32_t nrec;              // 16-byte check records
     unsigned long long *queue;
     int32_t num_legs, iters_first, iters_leg, num_solutions, max_total_iters;
     float L;
-    uint32_t chk_off, sgn_off, red_off;  // LDS byte offsets: check states, sign bits, scratch
+    uint32_t chk_off, red_off;  // LDS byte offsets: check records, scratch
     const float *trace_gamma;  // [N] by fault (trace runs)
     float scale;
     int32_t trace_T;

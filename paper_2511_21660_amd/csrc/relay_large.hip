@@ -13,12 +13,14 @@
 // signs of all nu of the check.  A check's messages are therefore fixed by
 // the state (m1, m2, position of the minimum, neg) plus one sign bit per edge.
 // LDS holds Lambda by fault slot and one more entry, Lambda[N] = +inf, that
-// row padding reads; one 16-byte state per check, (m1, m2) carrying neg as
-// their sign bit and the position as the code of the edge's fault-side entry;
-// the sign bits of nu, one byte per chunk of eight row entries.  A fault
-// rebuilds each message it sums from its check's state and its edge's sign
-// bit, bit for bit the message the other kernels store.  A 2736 x 26208
-// matrix with 82.6K edges takes about 157 KiB.
+// row padding reads, and 16-byte check records: a row has one record per 32
+// positions, each holding the state -- m1 and m2 carrying neg as their sign
+// bit, the position of the minimum as the code of its edge's fault-side
+// entry -- and, in its last word, the sign bits of nu at its 32 positions
+// (one byte per chunk of eight).  A fault rebuilds each message it sums from
+// one 16-byte read of the record holding its edge, bit for bit the message
+// the other kernels store.  A 2736 x 26208 matrix with 82.6K edges takes
+// about 158 KiB.
 //
 // Fault slots.  Faults are renumbered in order of decreasing column degree
 // (slot p holds fault slot_col[p]); thread t owns the slots t + TPB*v
@@ -33,10 +35,10 @@
 // global memory, shared by all workgroups and L2-resident: each row's fault
 // slots padded to a multiple of 8 (one aligned 16-byte load per 8 edges), and
 // per slot (first entry, degree) and a 32-byte record of its first 8 entry
-// codes.  An entry code (check << 20 | (s ^ 24)) names the check's state
-// (bits 20..31), the word of its sign bit (s >> 5) and, in its low five bits,
-// the left shift that moves that bit to bit 31 (chunk entry q's bit is bit
-// 7 - q of the chunk's byte).
+// codes.  An entry code (record << 20 | ((k & 31) ^ 24) for row position k)
+// names the record (bits 20..31) and, in its low five bits, the left shift
+// that moves the edge's sign bit to bit 31 (chunk entry q's bit is bit 7 - q
+// of the chunk's byte).
 //
 // Iteration (as in the block kernel): the check pass of iteration t+1 reads
 // Lambda(t) for every edge, so the parity of F(t) per check is folded into it
@@ -64,15 +66,6 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// bits 5..19 of an entry code (its sign word), as one instruction: written
-// as shifts and a mask, the compiler folds the word's scaling by 4 into them
-// and needs three
-__device__ __forceinline__ uint32_t bfe_word(uint32_t pk) {
-    uint32_t r;
-    asm("v_bfe_u32 %0, %1, 5, 15" : "=v"(r) : "v"(pk));
-    return r;
-}
-
 // 4 * (x & 0xffff) as one instruction (a 16 x 16-bit multiply-add)
 __device__ __forceinline__ uint32_t lo16_x4(uint32_t x) {
     uint32_t r;
@@ -88,7 +81,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
     const uint32_t flags = a.red_off + 8u * (TPB / 64);   // TPB/64 bytes (block OR), 16-byte aligned
     const uint32_t shot_sh = flags + 4u * (TPB / 64);     // claimed shot index
-    const uint32_t chk = a.chk_off, sgn = a.sgn_off;
+    const uint32_t chk = a.chk_off;
     const int t = threadIdx.x;
     const float L = a.L;
     const int N = a.N;
@@ -97,14 +90,15 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     // out of the persistent loop
     uint32_t tl = (uint32_t)t;
 
-    // this thread's checks, their degrees and first row chunks
-    int ci[kLargeRounds], cd[kLargeRounds], crb[kLargeRounds];
+    // this thread's checks, their degrees, first row chunks and first records
+    int ci[kLargeRounds], cd[kLargeRounds], crb[kLargeRounds], crec[kLargeRounds];
 #pragma unroll
     for (int c = 0; c < kLargeRounds; ++c) {
         const int i = c < a.rounds ? a.chk_of[c * TPB + t] : -1;
         ci[c] = i;
         cd[c] = i >= 0 ? a.rowptr[i + 1] - a.rowptr[i] : 0;
         crb[c] = i >= 0 ? a.rbase[i] : 0;
+        crec[c] = i >= 0 ? a.rrec[i] : 0;
     }
     if (t < TPB / 256) lds_b<uint32_t>(flags + 4u * (uint32_t)t) = 0u;
     if (t == 0) lds_b<float>(4u * (uint32_t)N) = __builtin_inff();  // target of row padding entries
@@ -120,13 +114,10 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
     long long shot = -1;
     int r = 0, tt = 0, total = 0, count = 0;
 
-    // messages restart at zero: states (+0, +0, 0) and all sign bits clear
-    // rebuild +0 on every edge
+    // messages restart at zero: records of zeros (states (+0, +0, 0), sign
+    // bits clear) rebuild +0 on every edge
     auto zero_messages = [&]() {
-#pragma unroll
-        for (int c = 0; c < kLargeRounds; ++c)
-            if (ci[c] >= 0) lds_b<u32x4>(chk + 16u * (uint32_t)ci[c]) = u32x4{0u, 0u, 0u, 0u};
-        for (int q = t; q < a.nsw; q += TPB) lds_b<uint32_t>(sgn + 4u * (uint32_t)q) = 0u;
+        for (int q = t; q < a.nrec; q += TPB) lds_b<u32x4>(chk + 16u * (uint32_t)q) = u32x4{0u, 0u, 0u, 0u};
     };
 
     auto fetch = [&]() -> bool {
@@ -172,20 +163,21 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         for (int c = 0; c < kLargeRounds; ++c) {
             const int i = ci[c];
             if (i < 0) continue;
-            const uint32_t sa = chk + 16u * (uint32_t)i;
-            const u32x4 sto = lds_b<u32x4>(sa);
-            const uint32_t m1o = sto.x, m2o = sto.y;          // old magnitudes, signed with the old neg
-            const int amo = (int)((sto.z & 0xfffffu) ^ 24u);  // slot of the old minimum
+            const uint32_t ra0 = chk + 16u * (uint32_t)crec[c];  // the row's first record
+            const u32x3 sto = lds_b<u32x3>(ra0);
+            const uint32_t m1o = sto.x, m2o = sto.y;  // old magnitudes, signed with the old neg
+            // position of the old minimum (of another row, for a record of
+            // zeros: out of this row, or position 24 of row 0 whose m1 and m2
+            // are both +0)
+            const int amo = 32 * ((int)(sto.z >> kLargeEdgeBits) - crec[c]) + (int)((sto.z & 31u) ^ 24u);
             const uint32_t sc = ((sig >> c) & 1u) << 31;
             uint32_t fpar = sc;  // bit 31: sigma_i XOR the signs of Lambda over the row
             uint32_t negp = 0;   // XOR of the row's bytes of nu signs (neg from its popcount)
             float m1 = L, m2 = L;
-            // edge k of the row has the sign-bit slot e0 + k, its position in
-            // the padded row table: rows start on multiples of 8 slots, so a
-            // chunk of 8 edges is one byte of sign bits, read (old signs) and
-            // written (new signs) whole
-            const int e0 = crb[c] * kLargeGather, deg = cd[c];
-            int amin = e0;
+            // a chunk of 8 positions is one byte of sign bits, read (old
+            // signs) and written (new signs) whole
+            const int deg = cd[c];
+            int amin = 0;
             // eight edges per step from one aligned 16-byte load of the row's
             // padded fault slots; the Lambda gathers are issued together and
             // the next chunk is loaded one step ahead (the table ends with a
@@ -200,14 +192,15 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 const uint4 pk = cur;
                 cur = rt[k / kLargeGather + 1];
                 const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
-                const int ec = e0 + k;  // slot of the chunk's first entry
-                const uint32_t ba = sgn + ((uint32_t)ec >> 3);
-                const uint32_t ob = lds_b<uint8_t>(ba);  // old signs of nu, entry q in bit 7 - q
+                // byte (k / 8) & 3 of word 3 of record k / 32: old signs of nu,
+                // entry q in bit 7 - q
+                const uint32_t ba = ra0 + 16u * (uint32_t)(k >> 5) + 12u + (uint32_t)((k >> 3) & 3);
+                const uint32_t ob = lds_b<uint8_t>(ba);
                 float lv[kLargeGather];
 #pragma unroll
                 for (int q = 0; q < kLargeGather; ++q)
                     lv[q] = lds_b<float>((q & 1) ? 4u * (pw[q >> 1] >> 16) : lo16_x4(pw[q >> 1]));
-                int am = amo - ec;  // entry of the old minimum, if in 0..7
+                int am = amo - k;  // entry of the old minimum, if in 0..7
                 asm volatile("" : "+v"(am));  // compared with each entry's constant
                 int aq = -1;                  // entry of a new minimum in this chunk
                 uint32_t nb = 0u;
@@ -223,13 +216,16 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                     m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
                     m1 = __builtin_amdgcn_fmed3f(m1, av, -1.0f);  // = min(m1, av): both are >= +0
                 }
-                amin = aq >= 0 ? ec + aq : amin;
+                amin = aq >= 0 ? k + aq : amin;
                 negp ^= nb;
                 lds_b<uint8_t>(ba) = (uint8_t)nb;
             }
             const uint32_t neg = sc ^ ((uint32_t)__popc(negp) << 31);
-            lds_b<u32x4>(sa) = u32x4{__float_as_uint(m1) | neg, __float_as_uint(m2) | neg,
-                                     ((uint32_t)i << kLargeEdgeBits) | ((uint32_t)amin ^ 24u), 0u};
+            // the state goes to every record of the row (three-word writes
+            // leave the sign bits)
+            const u32x3 st = u32x3{__float_as_uint(m1) | neg, __float_as_uint(m2) | neg,
+                                   ((uint32_t)(crec[c] + (amin >> 5)) << kLargeEdgeBits) | ((uint32_t)(amin & 31) ^ 24u)};
+            for (int rr = 0; rr == 0 || 32 * rr < deg; ++rr) lds_b<u32x3>(ra0 + 16u * (uint32_t)rr) = st;
             unsat_bits |= fpar;
         }
         const bool unsat = block_or<TPB>((unsat_bits >> 31) != 0u, flags);
@@ -324,32 +320,29 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
 
         // ---------------- fault pass: memory term, then the messages of the
         // slot's checks in ascending check order, each rebuilt from its
-        // check's state and its edge's sign bit.  Slots go in batches of
+        // check's state and its edge's sign bit (one read of the record that
+        // holds both).  Slots go in batches of
         // kLargeBatch whose loads (first entry and degree, the first four
         // entry codes, gamma, lambda(0), Lambda) are all issued first; slots
-        // are clamped so every load is in bounds.  Entries go in pairs whose
-        // state and sign-word loads issue together: the first pair whatever
-        // the degree (a record's padding entries name check 0, a valid
-        // address; the sum skips them with a select, not an added 0, which
-        // would turn -0 into +0), later pairs only where the degree reaches
-        // them (the lanes of a wave nearly always share it, so the pair
-        // drops out for the whole wave).
-        // (the state's three words in use are read as one access: a fourth,
-        // unused register would still be written by the load and could not
-        // take the next address until it lands)
-        auto st_of = [&](uint32_t pk) -> u32x3 { return lds_b<u32x3>(chk + ((pk >> 16) & 0xfff0u)); };
-        auto sw_of = [&](uint32_t pk) -> uint32_t { return lds_b<uint32_t>(sgn + (bfe_word(pk) << 2)); };
-        auto msg = [&](uint32_t pk, const u32x3 &st, uint32_t sw) -> float {
+        // are clamped so every load is in bounds.  The first two entries are
+        // read whatever the degree (a record's padding entries name record 0,
+        // a valid address; the sum skips them with a select, not an added 0,
+        // which would turn -0 into +0); later entries in pairs or singly,
+        // exactly as far as the degree reaches (the lanes of a wave nearly
+        // always share it, so the other branches drop out for the whole wave).
+        auto st_of = [&](uint32_t pk) -> u32x4 { return lds_b<u32x4>(chk + ((pk >> 16) & 0xfff0u)); };
+        auto msg = [&](uint32_t pk, const u32x4 &st) -> float {
             const uint32_t mag = pk == st.z ? st.y : st.x;  // signed with the check's neg
-            return __uint_as_float(((sw << (pk & 31u)) & 0x80000000u) ^ mag);
+            return __uint_as_float(((st.w << (pk & 31u)) & 0x80000000u) ^ mag);
         };
-        // entries k and k + 1 of codes c0, c1 (the second only if k + 1 < deg)
-        auto pair = [&](float acc, uint32_t c0, uint32_t c1, int k, int deg, bool first_checked) -> float {
-            const u32x3 s0 = st_of(c0), s1 = st_of(c1);
-            const uint32_t w0 = sw_of(c0), w1 = sw_of(c1);
-            const float m0 = msg(c0, s0, w0), m1 = msg(c1, s1, w1);
-            acc = (first_checked || k < deg) ? acc + m0 : acc;
-            return k + 1 < deg ? acc + m1 : acc;
+        auto two = [&](float acc, uint32_t c0, uint32_t c1) -> float {
+            const u32x4 s0 = st_of(c0), s1 = st_of(c1);
+            return (acc + msg(c0, s0)) + msg(c1, s1);
+        };
+        auto one = [&](float acc, uint32_t c0) -> float { return acc + msg(c0, st_of(c0)); };
+        // entries k and k + 1 of codes c0, c1 where k + 2 <= deg or deg == k + 1
+        auto upto_two = [&](float acc, uint32_t c0, uint32_t c1, int k, int deg) -> float {
+            return deg > k + 1 ? two(acc, c0, c1) : one(acc, c0);
         };
         // lambda(0): s * w + 0 (leg 1, prior anchor) or the chained anchor
         // (x * 1 + 0 = x: a chained anchor is never -0)
@@ -386,17 +379,19 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 const float x = (1.0f - gv[f]) * l0[f];  // (1 - gamma) lambda(0)
                 float acc = clipl(x + y, L);
                 const int deg = fc[f].y;
-                acc = pair(acc, ra[f].x, ra[f].y, 0, deg, false);
-                if (deg > 2) acc = pair(acc, ra[f].z, ra[f].w, 2, deg, true);
+                {
+                    const u32x4 s0 = st_of(ra[f].x), s1 = st_of(ra[f].y);
+                    const float m0 = msg(ra[f].x, s0), m1 = msg(ra[f].y, s1);
+                    acc = deg > 0 ? acc + m0 : acc;
+                    acc = deg > 1 ? acc + m1 : acc;
+                }
+                if (deg > 2) acc = upto_two(acc, ra[f].z, ra[f].w, 2, deg);
                 if (deg > 4) {
                     const uint4 rc =
                         *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(a.frec) + 32u * (uint32_t)p + 16u);
-                    acc = pair(acc, rc.x, rc.y, 4, deg, true);
-                    if (deg > 6) acc = pair(acc, rc.z, rc.w, 6, deg, true);
-                    for (int q = fc[f].x + kLargeGather; q < fc[f].x + deg; ++q) {
-                        const uint32_t pq = a.fedge[q];
-                        acc += msg(pq, st_of(pq), sw_of(pq));
-                    }
+                    acc = upto_two(acc, rc.x, rc.y, 4, deg);
+                    if (deg > 6) acc = upto_two(acc, rc.z, rc.w, 6, deg);
+                    for (int q = fc[f].x + kLargeGather; q < fc[f].x + deg; ++q) acc = one(acc, a.fedge[q]);
                 }
                 lds_b<float>(4u * (uint32_t)p) = acc;
                 if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + a.slot_col[p]] = acc;
