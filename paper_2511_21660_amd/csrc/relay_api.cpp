@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -1347,7 +1348,8 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
 // them, thread t the t-th), so the 64 checks a wave handles in one round have
 // nearly the same length.  Faults are renumbered into slots by decreasing
 // column degree (ties by index), so the 64 slots of a wave in one round
-// nearly always share a degree.  Row chunks (8 entries, rows padded with N)
+// nearly always share a degree (the dealing of degree groups to rounds is
+// below).  Row chunks (8 entries, rows padded with N)
 // hold fault slots.  Row i owns records rrec[i] .. rrec[i] + ceil(deg/32) - 1;
 // position k of the row is bit (k & 31) ^ 7 of word 3 of record
 // rrec[i] + k / 32 (a chunk of 8 positions is one byte, entry q in bit
@@ -1385,12 +1387,26 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     std::stable_sort(fo.begin(), fo.end(), [&](int32_t x, int32_t y) {
         return c->colptr[x + 1] - c->colptr[x] > c->colptr[y + 1] - c->colptr[y];
     });
+    // groups of 64 faults in that order are dealt to (round v, wave w) slot
+    // groups, each wave's rounds taken from a different starting round, so
+    // the waves reach the highest degrees (the entries read one by one) at
+    // different times
+    const int nw = s.TPB / 64, nv = (c->N + s.TPB - 1) / s.TPB;
+    std::vector<std::array<int, 3>> groups;  // (rotated round, wave, round)
+    for (int v = 0; v < nv; ++v)
+        for (int w = 0; w < nw; ++w)
+            if ((int64_t)s.TPB * v + 64 * w < c->N) groups.push_back({(v - w * nv / nw + nv) % nv, w, v});
+    std::sort(groups.begin(), groups.end());
     T.slot_col.assign((size_t)npad, -1);
     std::vector<int32_t> slot_of((size_t)c->N);
-    for (int32_t p = 0; p < c->N; ++p) {
-        T.slot_col[(size_t)p] = fo[(size_t)p];
-        slot_of[(size_t)fo[(size_t)p]] = p;
-    }
+    int32_t next = 0;
+    for (const auto &g : groups)
+        for (int lane = 0; lane < 64; ++lane) {
+            const int64_t p = (int64_t)s.TPB * g[2] + 64 * g[1] + lane;
+            if (p >= c->N) break;
+            T.slot_col[(size_t)p] = fo[(size_t)next];
+            slot_of[(size_t)fo[(size_t)next++]] = (int32_t)p;
+        }
     T.rowptr.assign(c->rowptr.begin(), c->rowptr.end());
     T.rbase.resize((size_t)c->M);
     T.rrec.resize((size_t)c->M);
@@ -1414,7 +1430,8 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     }
     T.fedge.assign((size_t)std::max<int64_t>(1, c->E), 0u);
     T.fcol.assign((size_t)npad, int2{0, 0});
-    T.frec.assign((size_t)npad * G, 0u);
+    constexpr int RC = rb::kLargeRec;
+    T.frec.assign((size_t)npad * RC, 0u);
     int64_t q = 0;
     for (int32_t p = 0; p < c->N; ++p) {
         const int32_t j = T.slot_col[(size_t)p];
@@ -1423,7 +1440,7 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
             const int32_t i = c->rowidx[(size_t)e];
             const uint32_t code = large_code(T.rrec[(size_t)i], c->cpos[(size_t)e]);
             T.fedge[(size_t)q] = code;
-            if (e - c->colptr[j] < G) T.frec[(size_t)p * G + (size_t)(e - c->colptr[j])] = code;
+            if (e - c->colptr[j] < RC) T.frec[(size_t)p * RC + (size_t)(e - c->colptr[j])] = code;
         }
     }
     return T;
@@ -1449,7 +1466,8 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
         return "check records past their region";
     constexpr int G = rb::kLargeGather;
     const int npad = s.TPB * s.VR;
-    if (T.frec.size() != (size_t)npad * G || T.fcol.size() != (size_t)npad || T.slot_col.size() != (size_t)npad)
+    constexpr int RC = rb::kLargeRec;
+    if (T.frec.size() != (size_t)npad * RC || T.fcol.size() != (size_t)npad || T.slot_col.size() != (size_t)npad)
         return "slot tables";
     std::vector<int32_t> slot_of((size_t)c->N, -1);
     for (int p = 0; p < npad; ++p) {
@@ -1499,9 +1517,9 @@ std::string check_large_tables(const rb_ctx *c, const rb::LargeShape &s, const L
                 return "slot " + std::to_string(p) + ": entry " + std::to_string(k) + " is not its edge";
             prev = i;
         }
-        for (int k = 0; k < G; ++k) {
+        for (int k = 0; k < RC; ++k) {
             const uint32_t want = k < d ? T.fedge[(size_t)(fc.x + k)] : 0u;
-            if (T.frec[(size_t)p * G + k] != want) return "slot " + std::to_string(p) + ": record entry " + std::to_string(k);
+            if (T.frec[(size_t)p * RC + k] != want) return "slot " + std::to_string(p) + ": record entry " + std::to_string(k);
         }
     }
     std::vector<int> seen((size_t)c->M, 0);

@@ -203,8 +203,9 @@ struct LargeShape {
 constexpr int kLargeRounds = 4;       // checks per thread at most (M <= 4 * TPB)
 constexpr int kLargeEdgeBits = 20;    // fault-side entry codes: record << 20 | sign-bit shift
 constexpr int kLargeMaxRecords = 4096;  // 16-byte check records (record << 4 fits 16 bits)
-constexpr int kLargeGather = 8;       // row chunk length (one byte of sign bits) and fault record length
-constexpr int kLargeBatch = 4;        // fault slots whose loads the fault pass issues together
+constexpr int kLargeGather = 8;       // row chunk length (one byte of sign bits)
+constexpr int kLargeRec = 4;          // entry codes per fault record (one 16-byte load)
+constexpr int kLargeAhead = 2;        // fault-pass rounds whose slot loads are in flight ahead of use
 
 struct LargeArgs {
     int32_t M, N;
@@ -230,7 +231,7 @@ struct LargeArgs {
     const int32_t *rbase;      // [M] first chunk of row i in ctab
     const int32_t *rrec;       // [M] first LDS record of row i (one per 32 row positions)
     const int2 *fcol;          // [TPB*VR] (first entry in fedge, column degree) of each slot
-    const uint32_t *frec;      // [TPB*VR][kLargeGather] the first entry codes of each slot (padding: 0)
+    const uint32_t *frec;      // [TPB*VR][kLargeRec] the first entry codes of each slot (padding: 0)
     const uint32_t *fedge;     // [E] entry codes by slot, each column's in ascending check order
     const int32_t *chk_of;     // [kLargeRounds][TPB] check of thread t in round c, or -1
     int32_t rounds;            // check rounds in use (<= kLargeRounds)

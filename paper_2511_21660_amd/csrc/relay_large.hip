@@ -66,6 +66,15 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// what the fault pass loads for one slot
+struct SlotLoads {
+    int2 fc;    // first entry in fedge, degree
+    uint4 ra;   // first four entry codes
+    float gv;   // gamma
+    float w0;   // w (lambda(0) = s * w + 0) or the chained anchor
+    float lam;  // Lambda
+};
+
 // 4 * (x & 0xffff) as one instruction (a 16 x 16-bit multiply-add)
 __device__ __forceinline__ uint32_t lo16_x4(uint32_t x) {
     uint32_t r;
@@ -75,7 +84,7 @@ __device__ __forceinline__ uint32_t lo16_x4(uint32_t x) {
 
 template <int TPB, int VR, bool PRIOR, bool TRACE>
 __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
-    static_assert(VR <= 32 && VR % kLargeBatch == 0 && TPB % 256 == 0, "shape");
+    static_assert(VR <= 32 && TPB % 256 == 0, "shape");
     static_assert(kLargeGather == 8, "a row chunk is one byte of sign bits");
     constexpr int NP = TPB * VR;                          // slots (row stride of gamma_slot)
     const uint32_t red = a.red_off;                       // TPB/64 doubles (block sums)
@@ -228,6 +237,35 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             for (int rr = 0; rr == 0 || 32 * rr < deg; ++rr) lds_b<u32x3>(ra0 + 16u * (uint32_t)rr) = st;
             unsat_bits |= fpar;
         }
+        // the fault pass's first kLargeAhead slot loads go out before the
+        // barrier (they read no state the check pass writes; after a leg or
+        // shot event they are dropped)
+        const bool from_w = PRIOR || r == 1;
+        const float *l0src = from_w ? a.w_slot : l0w;
+        const float l0mul = from_w ? a.scale : 1.0f;
+        const char *gsrc = reinterpret_cast<const char *>(gcur);
+        // slot loads: (first entry, degree), the first kLargeRec entry codes,
+        // gamma, lambda(0) (s * w + 0 in leg 1 and under the prior anchor,
+        // else the chained anchor: x * 1 + 0 = x, a chained anchor is never
+        // -0) and Lambda, for round v (slot clamped so every load is in bounds)
+        auto issue = [&](int v) -> SlotLoads {
+            SlotLoads o;
+            const uint32_t p = (uint32_t)min((int)tl + TPB * v, N - 1);
+            const uint32_t o4 = 4u * p;  // byte offsets from 32-bit products (tables < 4 GiB)
+            o.fc = *reinterpret_cast<const int2 *>(reinterpret_cast<const char *>(a.fcol) + 2u * o4);
+            o.ra = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(a.frec) + 4u * o4);
+            o.gv = TRACE ? a.trace_gamma[a.slot_col[p]] : *reinterpret_cast<const float *>(gsrc + o4);
+            o.w0 = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(l0src) + o4);
+            o.lam = lds_b<float>(o4);
+            // the whole record: the compiler would otherwise split it into
+            // loads issued where its entries are used
+            asm volatile("" : "+v"(o.ra.x), "+v"(o.ra.y), "+v"(o.ra.z), "+v"(o.ra.w));
+            return o;
+        };
+        SlotLoads ring[kLargeAhead + 1];
+#pragma unroll
+        for (int v = 0; v < kLargeAhead && v < VR; ++v) ring[v] = issue(v);
+
         const bool unsat = block_or<TPB>((unsat_bits >> 31) != 0u, flags);
 
         // ---------------- leg scheduler (block-uniform)
@@ -321,81 +359,59 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         // ---------------- fault pass: memory term, then the messages of the
         // slot's checks in ascending check order, each rebuilt from its
         // check's state and its edge's sign bit (one read of the record that
-        // holds both).  Slots go in batches of
-        // kLargeBatch whose loads (first entry and degree, the first four
-        // entry codes, gamma, lambda(0), Lambda) are all issued first; slots
-        // are clamped so every load is in bounds.  The first two entries are
-        // read whatever the degree (a record's padding entries name record 0,
-        // a valid address; the sum skips them with a select, not an added 0,
-        // which would turn -0 into +0); later entries in pairs or singly,
-        // exactly as far as the degree reaches (the lanes of a wave nearly
-        // always share it, so the other branches drop out for the whole wave).
+        // holds both).  Slot loads run kLargeAhead rounds ahead of their use.
+        // The first two entries are read whatever the degree (a record's
+        // padding entries name record 0, a valid address; the sum skips them
+        // with a select, not an added 0, which would turn -0 into +0), the
+        // next two where the degree exceeds 2 (the lanes of a wave nearly
+        // always share it, so the branch drops out for the whole wave), any
+        // further ones one by one from fedge (slots of such degrees are dealt
+        // to different rounds in different waves, so few waves wait on them
+        // at a time).
         auto st_of = [&](uint32_t pk) -> u32x4 { return lds_b<u32x4>(chk + ((pk >> 16) & 0xfff0u)); };
         auto msg = [&](uint32_t pk, const u32x4 &st) -> float {
             const uint32_t mag = pk == st.z ? st.y : st.x;  // signed with the check's neg
             return __uint_as_float(((st.w << (pk & 31u)) & 0x80000000u) ^ mag);
         };
-        auto two = [&](float acc, uint32_t c0, uint32_t c1) -> float {
-            const u32x4 s0 = st_of(c0), s1 = st_of(c1);
-            return (acc + msg(c0, s0)) + msg(c1, s1);
-        };
         auto one = [&](float acc, uint32_t c0) -> float { return acc + msg(c0, st_of(c0)); };
-        // entries k and k + 1 of codes c0, c1 where k + 2 <= deg or deg == k + 1
-        auto upto_two = [&](float acc, uint32_t c0, uint32_t c1, int k, int deg) -> float {
-            return deg > k + 1 ? two(acc, c0, c1) : one(acc, c0);
+        // round v: the slot's sum from loads `o`; the loads of round
+        // v + kLargeAhead go out into `ahead` (a set whose round is done)
+        // unconditionally (clamped), so the count of loads in flight is the
+        // same on every path and each round waits only for its own
+        const int wbase = __builtin_amdgcn_readfirstlane(t & ~63);  // the wave's first thread
+        auto step = [&](int v, const SlotLoads &o, SlotLoads &ahead) {
+            const int p = (int)tl + TPB * v;
+            // everything taken from `o` first, so its waits come before the
+            // next loads go out: the empty asm takes the values as inputs and
+            // keeps the loads after it
+            const float y = o.gv * clipl(o.lam, L);
+            const float x = (1.0f - o.gv) * (l0mul * o.w0 + 0.0f);  // (1 - gamma) lambda(0)
+            float acc = clipl(x + y, L);
+            int deg = o.fc.y, q0 = o.fc.x;
+            uint32_t e0 = o.ra.x, e1 = o.ra.y, e2 = o.ra.z, e3 = o.ra.w;
+            asm volatile("" : "+v"(acc), "+v"(deg), "+v"(q0), "+v"(e0), "+v"(e1), "+v"(e2), "+v"(e3) : : "memory");
+            const u32x4 s0 = st_of(e0), s1 = st_of(e1);
+            if (v + kLargeAhead < VR) ahead = issue(v + kLargeAhead);
+            if (p >= N) return;
+            const float m0 = msg(e0, s0), m1 = msg(e1, s1);
+            acc = deg > 0 ? acc + m0 : acc;
+            acc = deg > 1 ? acc + m1 : acc;
+            if (deg > 2) {  // both loads issue together; the fourth entry is read even at degree 3
+                const u32x4 s2 = st_of(e2), s3 = st_of(e3);
+                const float m2 = msg(e2, s2), m3 = msg(e3, s3);
+                acc += m2;
+                acc = deg > 3 ? acc + m3 : acc;
+            }
+            for (int q = q0 + kLargeRec; q < q0 + deg; ++q) acc = one(acc, a.fedge[q]);
+            lds_b<float>(4u * (uint32_t)p) = acc;
+            if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + a.slot_col[p]] = acc;
         };
-        // lambda(0): s * w + 0 (leg 1, prior anchor) or the chained anchor
-        // (x * 1 + 0 = x: a chained anchor is never -0)
-        const bool from_w = PRIOR || r == 1;
-        const float *l0src = from_w ? a.w_slot : l0w;
-        const float l0mul = from_w ? a.scale : 1.0f;
-        const char *gsrc = reinterpret_cast<const char *>(gcur);
 #pragma unroll
-        for (int vb = 0; vb < VR; vb += kLargeBatch) {
-            // this thread's slots of this and every later batch lie past N
-            if ((int)tl + TPB * vb >= N) break;
-            int2 fc[kLargeBatch];
-            uint4 ra[kLargeBatch];
-            float gv[kLargeBatch], l0[kLargeBatch], lam[kLargeBatch];
-#pragma unroll
-            for (int f = 0; f < kLargeBatch; ++f) {
-                const uint32_t p = (uint32_t)min((int)tl + TPB * (vb + f), N - 1);
-                const uint32_t o4 = 4u * p;  // byte offsets from 32-bit products (tables < 4 GiB)
-                fc[f] = *reinterpret_cast<const int2 *>(reinterpret_cast<const char *>(a.fcol) + 2u * o4);
-                ra[f] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(a.frec) + 8u * o4);
-                gv[f] = TRACE ? a.trace_gamma[a.slot_col[p]] : *reinterpret_cast<const float *>(gsrc + o4);
-                l0[f] = l0mul * *reinterpret_cast<const float *>(reinterpret_cast<const char *>(l0src) + o4) + 0.0f;
-                lam[f] = lds_b<float>(o4);
-            }
-            // whole records: the compiler would otherwise split a record into
-            // loads issued where its entries are used
-#pragma unroll
-            for (int f = 0; f < kLargeBatch; ++f) asm volatile("" : "+v"(ra[f].x), "+v"(ra[f].y), "+v"(ra[f].z), "+v"(ra[f].w));
-#pragma unroll
-            for (int f = 0; f < kLargeBatch; ++f) {
-                const int p = (int)tl + TPB * (vb + f);
-                if (p >= N) continue;
-                const float y = gv[f] * clipl(lam[f], L);
-                const float x = (1.0f - gv[f]) * l0[f];  // (1 - gamma) lambda(0)
-                float acc = clipl(x + y, L);
-                const int deg = fc[f].y;
-                {
-                    const u32x4 s0 = st_of(ra[f].x), s1 = st_of(ra[f].y);
-                    const float m0 = msg(ra[f].x, s0), m1 = msg(ra[f].y, s1);
-                    acc = deg > 0 ? acc + m0 : acc;
-                    acc = deg > 1 ? acc + m1 : acc;
-                }
-                if (deg > 2) acc = upto_two(acc, ra[f].z, ra[f].w, 2, deg);
-                if (deg > 4) {
-                    const uint4 rc =
-                        *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(a.frec) + 32u * (uint32_t)p + 16u);
-                    acc = upto_two(acc, rc.x, rc.y, 4, deg);
-                    if (deg > 6) acc = upto_two(acc, rc.z, rc.w, 6, deg);
-                    for (int q = fc[f].x + kLargeGather; q < fc[f].x + deg; ++q) acc = one(acc, a.fedge[q]);
-                }
-                lds_b<float>(4u * (uint32_t)p) = acc;
-                if (TRACE) a.trace[((size_t)shot * (a.trace_T + 1) + tt + 1) * N + a.slot_col[p]] = acc;
-            }
+        for (int v = 0; v < VR; ++v) {
+            // wave-uniform exit (lane-varying exits would nest the rounds'
+            // exec masks): no slot of this wave in this or a later round
+            if (wbase + TPB * v >= N) break;
+            step(v, ring[v % (kLargeAhead + 1)], ring[(v + kLargeAhead) % (kLargeAhead + 1)]);
         }
         ++tt;
         ++total;
