@@ -1344,9 +1344,8 @@ rb_status build_block_plan(rb_ctx *c, int bv) {
 }
 
 // Host tables of the large-graph kernel (no device work).  Checks sorted by
-// decreasing degree are dealt round by round (round r takes the next TPB of
-// them, thread t the t-th), so the 64 checks a wave handles in one round have
-// nearly the same length.  Faults are renumbered into slots by decreasing
+// decreasing degree form groups of 64 of nearly the same length, dealt to the
+// waves' rounds so the waves' row work is balanced (below).  Faults are renumbered into slots by decreasing
 // column degree (ties by index), so the 64 slots of a wave in one round
 // nearly always share a degree (the dealing of degree groups to rounds is
 // below).  Row chunks (8 entries, rows padded with N)
@@ -1374,14 +1373,38 @@ LargeTables large_tables(const rb_ctx *c, const rb::LargeShape &s) {
     const int npad = s.TPB * s.VR;
     LargeTables T;
     T.lay = large_layout(c, s);
-    T.rounds = (c->M + s.TPB - 1) / s.TPB;
     std::vector<int32_t> order((size_t)c->M);
     for (int32_t i = 0; i < c->M; ++i) order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return c->rowptr[x + 1] - c->rowptr[x] > c->rowptr[y + 1] - c->rowptr[y];
     });
+    // groups of 64 checks in that order, largest cost first, each to the wave
+    // with the least cost so far that has a round left (cost: three per
+    // chunk of the group's longest row, one per row for its state); a
+    // wave's groups take its rounds 0, 1, ...
+    const int nwv = s.TPB / 64;
+    const int ngr = (c->M + 63) / 64;
+    std::vector<std::pair<int64_t, int>> gcost((size_t)ngr);
+    for (int g = 0; g < ngr; ++g) {
+        const int32_t i0 = order[(size_t)64 * g];  // the group's longest row
+        gcost[(size_t)g] = {-(3 * ((c->rowptr[i0 + 1] - c->rowptr[i0] + rb::kLargeGather - 1) / rb::kLargeGather) + 1), g};
+    }
+    std::sort(gcost.begin(), gcost.end());
+    std::vector<int64_t> wload((size_t)nwv, 0);
+    std::vector<int> wrounds((size_t)nwv, 0);
     T.chk_of.assign((size_t)rb::kLargeRounds * s.TPB, -1);
-    for (int32_t q = 0; q < c->M; ++q) T.chk_of[(size_t)q] = order[(size_t)q];
+    T.rounds = 0;
+    for (const auto &gc : gcost) {
+        int best = -1;
+        for (int w = 0; w < nwv; ++w)
+            if (wrounds[(size_t)w] < rb::kLargeRounds && (best < 0 || wload[(size_t)w] < wload[(size_t)best])) best = w;
+        if (best < 0) break;  // more groups than rounds (the planner rejects such graphs first)
+        const int rnd = wrounds[(size_t)best]++;
+        wload[(size_t)best] += -gc.first;
+        T.rounds = std::max(T.rounds, rnd + 1);
+        for (int lane = 0; lane < 64 && 64 * gc.second + lane < c->M; ++lane)
+            T.chk_of[(size_t)rnd * s.TPB + 64 * best + lane] = order[(size_t)(64 * gc.second + lane)];
+    }
     std::vector<int32_t> fo((size_t)c->N);
     for (int32_t j = 0; j < c->N; ++j) fo[(size_t)j] = j;
     std::stable_sort(fo.begin(), fo.end(), [&](int32_t x, int32_t y) {

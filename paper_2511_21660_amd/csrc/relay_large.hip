@@ -30,8 +30,9 @@
 // go out by fault.
 //
 // Roles.  Thread t owns its slots and the checks chk_of[c][t] (c < rounds):
-// checks sorted by degree and dealt round by round, so the 64 rows a wave
-// handles in one round have nearly the same length.  The graph tables stay in
+// checks sorted by degree form groups of 64 rows of nearly the same length,
+// and the groups are dealt to the waves' rounds so that every wave has about
+// the same number of row chunks to run.  The graph tables stay in
 // global memory, shared by all workgroups and L2-resident: each row's fault
 // slots padded to a multiple of 8 (one aligned 16-byte load per 8 edges), and
 // per slot (first entry, degree) and a 32-byte record of its first 8 entry
@@ -168,9 +169,16 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         // ---------------- check pass: new states from Lambda(t) and the old
         // messages; parity of F(t) per check
         uint32_t unsat_bits = 0;
+        // the first chunk of each row is loaded while the previous row runs
+        // (a round without a check loads chunk 0; rounds without a check may
+        // precede rounds with one)
+        const uint4 *ctab4 = reinterpret_cast<const uint4 *>(a.ctab);
+        uint4 first = ctab4[crb[0]];
 #pragma unroll
         for (int c = 0; c < kLargeRounds; ++c) {
             const int i = ci[c];
+            const uint4 first_c = first;
+            if (c + 1 < kLargeRounds) first = ctab4[crb[c + 1]];
             if (i < 0) continue;
             const uint32_t ra0 = chk + 16u * (uint32_t)crec[c];  // the row's first record
             const u32x3 sto = lds_b<u32x3>(ra0);
@@ -195,8 +203,8 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             // their nu is clip(inf - mu) = L, which leaves m1 <= m2 <= L, the
             // position of the minimum, both parities and the sign bits as
             // they are, so all eight entries run without a per-edge test.
-            const uint4 *rt = reinterpret_cast<const uint4 *>(a.ctab) + crb[c];
-            uint4 cur = rt[0];
+            const uint4 *rt = ctab4 + crb[c];
+            uint4 cur = first_c;
             for (int k = 0; k < deg; k += kLargeGather) {
                 const uint4 pk = cur;
                 cur = rt[k / kLargeGather + 1];
