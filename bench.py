@@ -95,12 +95,16 @@ def lds_bytes_per_edge_update(m, n, e):
     return 8.0 + (8.0 * n + 12.0 * m) / e
 
 
-def lds_bytes_per_edge_update_large(m, n, e):
+def lds_bytes_per_edge_update_large(m, n, e, row_deg):
     """The same for the large-graph kernel's compressed messages: Lambda to
-    the check (4 B) and the check's state (16 B) plus the edge's sign word
-    (4 B) to the fault; per check its state read and written (32 B) and its
-    sign words (2 x 4 B per 32 edges); per fault Lambda read and written."""
-    return 24.0 + 8.0 / 32.0 + (32.0 * m + 8.0 * n) / e
+    the check (4 B) and one 16-byte check record (state and the edge's sign
+    word) to the fault; a byte of nu signs read and written per 8 row
+    positions; per check its state read (12 B) and written to each of its
+    records (12 B, one record per 32 positions); per fault Lambda read and
+    written."""
+    row_deg = np.asarray(row_deg, dtype=np.int64)
+    records = int(np.maximum(1, (row_deg + 31) // 32).sum())
+    return 20.0 + 2.0 / 8.0 + (12.0 * m + 12.0 * records + 8.0 * n) / e
 
 
 def wilson(k, n, z=1.96):
@@ -518,7 +522,8 @@ def run_dem(args, torch, rb, codes, sampling, two_gross=False):
     conv = out["conv"].cpu().numpy()
     iters_launch = int(iters.astype(np.int64).sum())
     kernel = "relay_large_kernel" if two_gross else "relay_block_kernel"
-    lds_b = lds_bytes_per_edge_update_large(M, N, E) if two_gross else lds_bytes_per_edge_update(M, N, E)
+    lds_b = (lds_bytes_per_edge_update_large(M, N, E, np.bincount(prob.rows, minlength=M)) if two_gross
+             else lds_bytes_per_edge_update(M, N, E))
     roof, lds = roofline(kernel, kernel_ms, iters_launch * ops_per_iteration(M, N, E), iters_launch * E, lds_b,
                          stored_traffic(f"{kernel}_dem{tag}_hbm_traffic.txt"))
     # logical failures on the GPU, so that the correction array stays in HBM:
