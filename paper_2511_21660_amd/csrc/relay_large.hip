@@ -61,6 +61,15 @@ __device__ __forceinline__ float clipl(float x, float L) { return __builtin_amdg
 // take no class types)
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+
+// a global-memory float (kept as a global load where the pointer is chosen at
+// run time between two tables)
+__device__ __forceinline__ float ld_global(const void *base, uint32_t byte_off) {
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) float gfloat;
+    return *(gfloat *)((gchar *)base + byte_off);
+}
 
 __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
     __hip_atomic_fetch_or((__attribute__((address_space(3))) uint32_t *)(size_t)byte_addr, v, __ATOMIC_RELAXED,
@@ -69,8 +78,8 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t v) {
 
 // what the fault pass loads for one slot
 struct SlotLoads {
-    int2 fc;    // first entry in fedge, degree
-    uint4 ra;   // first four entry codes
+    i32x2 fc;   // first entry in fedge, degree
+    u32x4 ra;   // first four entry codes
     float gv;   // gamma
     float w0;   // w (lambda(0) = s * w + 0) or the chained anchor
     float lam;  // Lambda
@@ -251,7 +260,11 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
         const bool from_w = PRIOR || r == 1;
         const float *l0src = from_w ? a.w_slot : l0w;
         const float l0mul = from_w ? a.scale : 1.0f;
-        const char *gsrc = reinterpret_cast<const char *>(gcur);
+        // (the leg's gamma row is block-uniform: kept in scalar registers)
+        const uint64_t gaddr = reinterpret_cast<uint64_t>(gcur);
+        const char *gsrc = reinterpret_cast<const char *>(
+            ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(gaddr >> 32)) << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gaddr));
         // slot loads: (first entry, degree), the first kLargeRec entry codes,
         // gamma, lambda(0) (s * w + 0 in leg 1 and under the prior anchor,
         // else the chained anchor: x * 1 + 0 = x, a chained anchor is never
@@ -260,14 +273,15 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             SlotLoads o;
             const uint32_t p = (uint32_t)min((int)tl + TPB * v, N - 1);
             const uint32_t o4 = 4u * p;  // byte offsets from 32-bit products (tables < 4 GiB)
-            o.fc = *reinterpret_cast<const int2 *>(reinterpret_cast<const char *>(a.fcol) + 2u * o4);
-            o.ra = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(a.frec) + 4u * o4);
-            o.gv = TRACE ? a.trace_gamma[a.slot_col[p]] : *reinterpret_cast<const float *>(gsrc + o4);
-            o.w0 = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(l0src) + o4);
+            o.fc = *reinterpret_cast<const i32x2 *>(reinterpret_cast<const char *>(a.fcol) + 2u * o4);
+            o.ra = *reinterpret_cast<const u32x4 *>(reinterpret_cast<const char *>(a.frec) + 4u * o4);
+            o.gv = TRACE ? a.trace_gamma[a.slot_col[p]] : ld_global(gsrc, o4);
+            o.w0 = ld_global(l0src, o4);
             o.lam = lds_b<float>(o4);
-            // the whole record: the compiler would otherwise split it into
-            // loads issued where its entries are used
-            asm volatile("" : "+v"(o.ra.x), "+v"(o.ra.y), "+v"(o.ra.z), "+v"(o.ra.w));
+            // the whole record in four consecutive registers: the compiler
+            // would otherwise split it into loads issued where its entries
+            // are used, or into registers the next load cannot reuse
+            asm volatile("" : "+v"(o.ra));
             return o;
         };
         SlotLoads ring[kLargeAhead + 1];
@@ -395,15 +409,20 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
             const float y = o.gv * clipl(o.lam, L);
             const float x = (1.0f - o.gv) * (l0mul * o.w0 + 0.0f);  // (1 - gamma) lambda(0)
             float acc = clipl(x + y, L);
-            int deg = o.fc.y, q0 = o.fc.x;
-            uint32_t e0 = o.ra.x, e1 = o.ra.y, e2 = o.ra.z, e3 = o.ra.w;
-            asm volatile("" : "+v"(acc), "+v"(deg), "+v"(q0), "+v"(e0), "+v"(e1), "+v"(e2), "+v"(e3) : : "memory");
+            i32x2 fc = o.fc;
+            u32x4 ra = o.ra;
+            asm volatile("" : "+v"(acc), "+v"(fc), "+v"(ra) : : "memory");
+            const int deg = fc.y, q0 = fc.x;
+            const uint32_t e0 = ra.x, e1 = ra.y, e2 = ra.z, e3 = ra.w;
             const u32x4 s0 = st_of(e0), s1 = st_of(e1);
             if (v + kLargeAhead < VR) ahead = issue(v + kLargeAhead);
             if (p >= N) return;
             const float m0 = msg(e0, s0), m1 = msg(e1, s1);
-            acc = deg > 0 ? acc + m0 : acc;
-            acc = deg > 1 ? acc + m1 : acc;
+            if (deg >= 2) {  // every column of the DEM-shaped matrices: no selects
+                acc = (acc + m0) + m1;
+            } else {
+                acc = deg > 0 ? acc + m0 : acc;
+            }
             if (deg > 2) {  // both loads issue together; the fourth entry is read even at degree 3
                 const u32x4 s2 = st_of(e2), s3 = st_of(e3);
                 const float m2 = msg(e2, s2), m3 = msg(e3, s3);
