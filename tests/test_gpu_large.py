@@ -99,10 +99,11 @@ def test_irregular_graphs_on_large_kernel(rb, seed):
         assert_parity(gpu, ref, syn, prob, f"irregular seed={seed} large variant {v}")
 
 
-def test_long_rows_and_sign_words_shared_by_checks(rb):
-    """Rows of degree 1..90 side by side, so that 32-bit words of edge sign
-    bits are shared by up to a dozen checks written by different threads;
-    uniform priors make many |nu| tie at the first iteration."""
+def test_long_rows_over_several_check_records(rb):
+    """Rows of degree 1..90 side by side: long rows span up to three 16-byte
+    check records (state and 32 sign bits each), short rows sit between them
+    in records written by other threads; uniform priors make many |nu| tie
+    at the first iteration."""
     rng = np.random.default_rng(21)
     m, n = 300, 2400
     rows, cols = [], []
