@@ -56,17 +56,6 @@ __device__ __forceinline__ uint32_t lo_half_x4(uint32_t x) {
     return r;
 }
 
-// 2 * x + bit as one add with carry-in (the compare that produced `bit`
-// already is the lane mask the carry-in reads)
-__device__ __forceinline__ uint32_t shift_in(uint32_t x, bool bit) {
-    uint32_t r;
-    unsigned long long carry_out;
-    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3"
-        : "=v"(r), "=s"(carry_out)
-        : "v"(x), "s"(__builtin_amdgcn_ballot_w64(bit)));
-    return r;
-}
-
 // value of lane l ^ 1 (DPP quad permutation 1,0,3,2; the whole wave is active)
 __device__ __forceinline__ int swap_pair(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
 
@@ -141,7 +130,7 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const uint32_t sl = tl + TPB * v;
-            const float wj = a.scale * a.w_slot[sl];  // 0 for spare slots
+            const float wj = a.scale * a.w_slot[sl] + 0.0f;  // 0 for spare slots; -0 enters as +0
             float gj = a.gamma_slot[sl];
             if (TRACE) {
                 const int j = a.slot_col[sl];
@@ -173,7 +162,11 @@ void relay_block_kernel(BlockArgs a) {
         // pass 1: nu = clip(Lambda - mu_old) per edge; min1, min2 and the
         // first position of the minimum, the signs of nu (bit k of sg) and
         // their parity; parity of F over the row.  Pass 2 only writes.
-        bool fpar = sig, neg = sig;
+        // parities as sign bits: Lambda and nu are never -0 (channel LLRs
+        // enter as s * w + 0 and no update turns a nonzero or +0 value into
+        // -0), so a sign bit is the test x < 0; padding entries read
+        // Lambda = +inf and give nu = L, both with a clear sign bit
+        uint32_t fpar_u = sig ? 0x80000000u : 0u;
         float m1 = L, m2 = L;
         int amin = 0;
         uint32_t sg_lo = 0, sg_hi = 0;  // bit k: nu_k < 0
@@ -191,17 +184,15 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
             for (int q = 0; q < W; ++q) {
                 const int k = c + q;
-                fpar ^= lv[q] < 0.0f;
+                fpar_u ^= __float_as_uint(lv[q]);
                 const float nu = clipb(lv[q] - mo[q], L);
-                const bool sn = nu < 0.0f;
-                neg ^= sn;
-                // shift the sign in at the bottom (one add with carry-in): after
+                // shift the sign bit in at the bottom (one funnel shift): after
                 // P processed steps, edge k sits at bit min(P,32)-1-k of sg_lo
                 // (k < 32) or P-1-k of sg_hi
                 if (k < 32)
-                    sg_lo = shift_in(sg_lo, sn);
+                    sg_lo = __builtin_amdgcn_alignbit(sg_lo, __float_as_uint(nu), 31);
                 else
-                    sg_hi = shift_in(sg_hi, sn);
+                    sg_hi = __builtin_amdgcn_alignbit(sg_hi, __float_as_uint(nu), 31);
                 const float av = fabsf(nu);
                 amin = av < m1 ? k : amin;
                 m2 = __builtin_amdgcn_fmed3f(m1, av, m2);
@@ -222,6 +213,10 @@ void relay_block_kernel(BlockArgs a) {
                 chunk(std::integral_constant<int, CH>{}, c, cur);
             cur = nxt;
         }
+        // the row's parities: F over the row, and sigma with the signs of nu
+        // (a popcount of the collected sign bits)
+        bool fpar = (fpar_u >> 31) != 0u;
+        bool neg = sig != ((__popc(sg_lo ^ sg_hi) & 1) != 0);
         // a check split over threads t and t ^ 1: combine the two halves'
         // minima and parities (the first half holds the earlier edges, so it
         // keeps the minimum's position on a tie)
@@ -362,7 +357,7 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
                 for (int v = 0; v < VPT; ++v) {
                     const uint32_t sl = tl + TPB * v;
-                    const float l0 = PRIOR ? a.scale * w0[v] : clipb(lds_b<float>(4u * sl), L);
+                    const float l0 = PRIOR ? a.scale * w0[v] + 0.0f : clipb(lds_b<float>(4u * sl), L);
                     gm[v] = gv[v];
                     xl[v] = (1.0f - gv[v]) * l0;
                 }
