@@ -184,7 +184,7 @@ void relay_block_kernel(BlockArgs a) {
 #pragma unroll
             for (int q = 0; q < W; ++q) {
                 const int k = c + q;
-                fpar_u ^= __float_as_uint(lv[q]);
+                if (q & 1) fpar_u = xor3(fpar_u, __float_as_uint(lv[q - 1]), __float_as_uint(lv[q]));
                 const float nu = clipb(lv[q] - mo[q], L);
                 // shift the sign bit in at the bottom (one funnel shift): after
                 // P processed steps, edge k sits at bit min(P,32)-1-k of sg_lo

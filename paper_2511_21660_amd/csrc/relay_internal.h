@@ -35,6 +35,14 @@ constexpr int kGroupReadPad = 512;
 constexpr int kQueueStride = 32;
 constexpr int kQueueWords = kQueueSplit * kQueueStride;
 
+// a ^ b ^ c as one three-input logic op (the compiler emits two-input XORs
+// for a chain of them)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // Bit-packed I/O (RB_IO_BITS32): syndromes and corrections as uint32 words,
 // entry k in bit k % 32 of word k / 32.  The kernels read a syndrome bit
 // with syn_bit and the strides below count elements of the layout in use

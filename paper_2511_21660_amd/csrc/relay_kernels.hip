@@ -423,10 +423,17 @@ __device__ __forceinline__ void group_loop(const GroupArgs a) {
                     float m1 = L, m2 = L;
 #pragma unroll
                     for (int k = 0; k < DC; ++k) {
-                        fpar ^= __float_as_uint(lv[c - c0][k]);
+                        // (the parities fold two edges per three-input XOR)
+                        if (k & 1)
+                            fpar = xor3(fpar, __float_as_uint(lv[c - c0][k - 1]), __float_as_uint(lv[c - c0][k]));
+                        else if (k == DC - 1)
+                            fpar ^= __float_as_uint(lv[c - c0][k]);
                         const float nu = clipf(lv[c - c0][k] - mo[c - c0][k], L);
                         nb[k] = __float_as_uint(nu);
-                        neg ^= nb[k];
+                        if (k & 1)
+                            neg = xor3(neg, nb[k - 1], nb[k]);
+                        else if (k == DC - 1)
+                            neg ^= nb[k];
                         av[k] = fabsf(nu);
                         // two smallest magnitudes: with m1 <= m2, min(m2, max(m1, av)) is the
                         // median of (m1, av, m2)

@@ -234,7 +234,7 @@ __global__ __launch_bounds__(TPB) void relay_large_kernel(LargeArgs a) {
                 for (int q = 0; q < kLargeGather; ++q) {
                     const uint32_t mag = am == q ? m2o : m1o;
                     const float mo = __uint_as_float(((ob << (24 + q)) & 0x80000000u) ^ mag);
-                    fpar ^= __float_as_uint(lv[q]);
+                    if (q & 1) fpar = xor3(fpar, __float_as_uint(lv[q - 1]), __float_as_uint(lv[q]));
                     const float nu = clipl(lv[q] - mo, L);
                     nb = __builtin_amdgcn_alignbit(nb, __float_as_uint(nu), 31);  // sign of nu -> bit 7 - q
                     const float av = fabsf(nu);
