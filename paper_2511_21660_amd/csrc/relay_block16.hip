@@ -255,12 +255,15 @@ void relay_block16_kernel(BlockArgs a) {
                 lv[q] = lds_b<uint32_t>(ca);
                 mo[q] = lds_b<uint32_t>(mrow + 256u * (c + q));
             }
+            uint32_t dprev = 0;
 #pragma unroll
             for (int q = 0; q < W; ++q) {
                 const int k = c + q;
-                fparw ^= lv[q];
+                // parities two edges per three-input XOR (W is even)
+                if (q & 1) fparw = xor3(fparw, lv[q - 1], lv[q]);
                 const uint32_t d = bits(as_h2(lv[q]) - as_h2(mo[q]));
-                negw ^= d;
+                if (q & 1) negw = xor3(negw, dprev, d);
+                dprev = d;
                 const uint32_t av = umin2(d & kMag, L2);
                 m2 = umin2(m2, umax2(m1, av));
                 m1 = umin2(m1, av);
