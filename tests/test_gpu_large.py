@@ -127,7 +127,7 @@ def test_long_rows_over_several_check_records(rb):
 def test_two_gross_scale_dem(rb):
     """2736 x 26208 DEM-shaped matrix (82.6K edges, rows up to degree 81): the
     large-graph kernel is the configuration chosen; 400 shots decoded, every
-    converged correction valid, 32 sampled shots bit-exact against the
+    converged correction valid, 128 sampled shots bit-exact against the
     oracle (R = 20, S = 1)."""
     prob = codes.dem_problem(2736, 26208)
     _, syn = sampling.sample_batch(prob, 6 << 32, 0, 400)
@@ -136,7 +136,7 @@ def test_two_gross_scale_dem(rb):
     h = prob.dense().astype(np.int64)
     ok = (gpu["corr"].astype(np.int64) @ h.T) % 2 == (syn != 0)
     assert ok[gpu["conv"] == 1].all() and gpu["conv"].mean() > 0.3
-    idx = np.random.default_rng(2).choice(len(syn), 32, replace=False)
+    idx = np.random.default_rng(2).choice(len(syn), 128, replace=False)
     ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, RELAY_DEFAULT, syn[idx],
                         want_llr=True)
     sub = {k: gpu[k][idx] for k in KEYS}

@@ -366,8 +366,10 @@ def dem():
 
 def test_dem_block_kernel_parity(rb, dem):
     """DEM-shaped 936 x 8785 matrix (E = 27,617, row degree up to 63): the
-    block kernel against the oracle on 200 shots, T = 80/60, R = 20, S = 1."""
-    _, syn = sampling.sample_batch(dem, 3 << 32, 0, 200)
+    block kernel against the oracle on 2000 shots (over the first 1000 one per
+    CU, so each slot of the persistent queue runs several shots), T = 80/60,
+    R = 20, S = 1."""
+    _, syn = sampling.sample_batch(dem, 3 << 32, 0, 2000)
     gpu = gpu_decode(rb, dem, RELAY_DEFAULT, syn)
     assert gpu["info"]["threads_per_block"] >= 512
     ref = oracle.decode(dem.m, dem.n, dem.rows, dem.cols, dem.prior, RELAY_DEFAULT, syn,
