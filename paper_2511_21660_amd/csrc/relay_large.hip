@@ -35,8 +35,8 @@
 // the same number of row chunks to run.  The graph tables stay in
 // global memory, shared by all workgroups and L2-resident: each row's fault
 // slots padded to a multiple of 8 (one aligned 16-byte load per 8 edges), and
-// per slot (first entry, degree) and a 32-byte record of its first 8 entry
-// codes.  An entry code (record << 20 | ((k & 31) ^ 24) for row position k)
+// per slot (first entry, degree) and a 16-byte record of its first 4 entry
+// codes (the rest come from the entry table).  An entry code (record << 20 | ((k & 31) ^ 24) for row position k)
 // names the record (bits 20..31) and, in its low five bits, the left shift
 // that moves the edge's sign bit to bit 31 (chunk entry q's bit is bit 7 - q
 // of the chunk's byte).
