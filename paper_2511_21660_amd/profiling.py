@@ -35,18 +35,30 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines, so that editing a
+    comment leaves the hash of a measured build unchanged (a rough cut: a
+    "//" inside a string literal also starts a comment here, which only
+    makes two such sources hash alike)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (ln.split("//", 1)[0].rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def source_hash() -> str:
-    """SHA-256 over the library's kernel and host sources."""
+    """SHA-256 over the code of the library's kernel and host sources
+    (comments and blank lines left out)."""
     h = hashlib.sha256()
     for path in sorted(glob.glob(os.path.join(_HERE, "csrc", "*"))):
-        with open(path, "rb") as f:
+        with open(path, encoding="utf-8") as f:
             h.update(os.path.basename(path).encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
