@@ -168,9 +168,10 @@ rb_status rb_params_default(rb_params *out);
  * (a few lanes per syndrome; small and medium codes), block shapes (one
  * 1024-thread workgroup per syndrome, M <= 1024, N <= 9216, row degree <= 64
  * after splitting rows over lane pairs), large-graph shapes (one workgroup
- * per syndrome with compressed messages, M <= 4096, N <= 32768, P < 2^20
- * with P the edge count after rounding each row up to a multiple of 8,
- * 4N + 16M + P/8 bytes of LDS within 160 KiB).  RB_E_UNSUPPORTED beyond.
+ * per syndrome with compressed messages, M <= 4096, N <= 32768, at most 4096
+ * check records of 16 bytes with one record per 32 edges of a row and at
+ * least one per row, 4N + 16 x records bytes of LDS within 160 KiB).
+ * RB_E_UNSUPPORTED beyond.
  */
 rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32_t *rows,
                     const int32_t *cols, const double *prior_p, const rb_params *params,
