@@ -237,16 +237,29 @@ def test_long_rows_split_over_two_lanes(rb):
     assert_parity(gpu, ref, syn, prob, "long rows")
 
 
-@pytest.mark.parametrize("name,anchor", [("bb144", 0), ("bb144", 1), ("dem", 0)])
+@pytest.mark.parametrize("name,anchor", [("bb144", 0), ("bb144", 1), ("dem", 0), ("dem-large", 0),
+                                         ("dem-large", 1)])
 def test_learned_first_leg_parity(rb, name, anchor):
     """rb_set_leg_gamma / rb_set_prior_scale (a learned first leg inside Relay)
-    against the oracle's gamma1 / scale, on the group kernel ([[144,12,12]]) and
-    the block kernel (DEM-shaped matrix); the table readback shows the row."""
-    prob = codes.dem_problem() if name == "dem" else codes.bb_problem(name, 0.05)
-    _, syn = sampling.sample_batch(prob, 71, 0, 120 if name == "dem" else 400)
+    against the oracle's gamma1 / scale, on the group kernel ([[144,12,12]]),
+    the block kernel (DEM-shaped matrix) and the large-graph kernel chosen
+    before the setters run (its leg-1 memory-term table must follow them);
+    the table readback shows the row."""
+    prob = codes.dem_problem() if name.startswith("dem") else codes.bb_problem(name, 0.05)
+    _, syn = sampling.sample_batch(prob, 71, 0, 120 if name.startswith("dem") else 400)
     g1 = np.random.default_rng(8).uniform(-0.2, 0.6, prob.n).astype(np.float32)
     prm = dict(RELAY_DEFAULT, anchor=anchor, num_legs=6, num_solutions=2)
     dec = rb.Decoder.from_problem(prob, **prm)
+    if name == "dem-large":
+        large = []
+        for v in range(dec.info()["num_variants"]):
+            try:
+                if rb.plan_check(prob.m, prob.n, prob.rows, prob.cols, v)["block_kernel"] == 2:
+                    large.append(v)
+            except rb.RelayError as e:
+                assert e.status == 8
+        assert large
+        dec.set_variant(large[0])
     dec.set_leg_gamma(1, g1)
     dec.set_prior_scale(0.8)
     np.testing.assert_array_equal(dec.gamma_table()[0], g1)
