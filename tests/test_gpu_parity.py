@@ -243,7 +243,7 @@ def test_learned_first_leg_parity(rb, name, anchor):
     """rb_set_leg_gamma / rb_set_prior_scale (a learned first leg inside Relay)
     against the oracle's gamma1 / scale, on the group kernel ([[144,12,12]]),
     the block kernel (DEM-shaped matrix) and the large-graph kernel chosen
-    before the setters run (its leg-1 memory-term table must follow them);
+    before the setters run (its gamma table by fault slot must follow them);
     the table readback shows the row."""
     prob = codes.dem_problem() if name.startswith("dem") else codes.bb_problem(name, 0.05)
     _, syn = sampling.sample_batch(prob, 71, 0, 120 if name.startswith("dem") else 400)
