@@ -142,3 +142,33 @@ def test_two_gross_scale_dem(rb):
     sub = {k: gpu[k][idx] for k in KEYS}
     sub["info"] = gpu["info"]
     assert_parity(sub, ref, syn[idx], prob, "two-gross sample")
+
+
+@pytest.mark.parametrize("anchor", [0, 1])
+def test_very_long_rows_and_heavy_columns(rb, anchor):
+    """Rows of degree up to 250 (eight 32-position records each), columns of
+    degree up to 15 (entries past a slot's first four come from the CSC entry
+    table), columns of degree 0 and 1 beside them, per-column priors; both
+    anchors, S = 2."""
+    rng = np.random.default_rng(33)
+    m, n = 120, 1500
+    h = np.zeros((m, n), np.uint8)
+    for i in range(m):
+        d = int(rng.integers(150, 251)) if i % 10 == 0 else int(rng.integers(2, 30))
+        h[i, rng.choice(n, d, replace=False)] = 1
+    heavy = rng.choice(n, 20, replace=False)
+    for j in heavy:
+        h[rng.choice(m, int(rng.integers(8, 16)), replace=False), j] = 1
+    h[:, rng.choice(np.setdiff1d(np.arange(n), heavy), 30, replace=False)] = 0  # empty columns
+    prior = rng.uniform(0.005, 0.08, n)
+    prob = codes.problem_from_dense("very_long_rows", h, prior, np.zeros((1, n), np.uint8))
+    deg_r, deg_c = h.sum(axis=1), h.sum(axis=0)
+    assert deg_r.max() > 224 and deg_c.max() > 8 and (deg_c == 0).any() and (deg_c == 1).any()
+    _, syn = sampling.sample_batch(prob, 55 + anchor, 0, 120)
+    prm = dict(RELAY_DEFAULT, anchor=anchor, num_legs=6, num_solutions=2)
+    ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, prm, syn, want_llr=True)
+    vs = _large_variants(rb, prob)
+    assert vs
+    for v in vs:
+        gpu = gpu_decode(rb, prob, prm, syn, variant=v)
+        assert_parity(gpu, ref, syn, prob, f"very long rows, anchor {anchor}, large variant {v}")
