@@ -144,6 +144,32 @@ def test_two_gross_scale_dem(rb):
     assert_parity(sub, ref, syn[idx], prob, "two-gross sample")
 
 
+def test_two_gross_full_size_validity_and_sampled_parity(rb):
+    """The two-gross-scale workload at full size, in the launch configuration
+    the benchmark times (the same 2x10^5 seeded syndromes, bit-packed in and
+    out, R = 20, S = 1): the corrections that satisfy H e = s (checked on the
+    CPU from the sparse H) are exactly the converged shots, and 64 sampled
+    shots equal the oracle's bit for bit."""
+    from tests import validity
+
+    prob = codes.dem_problem(2736, 26208)
+    syn, _ = sampling.sample_syndromes_sparse(prob, 0xDE3, 200000)
+    dec = rb.Decoder.from_problem(prob, **dict(RELAY_DEFAULT, io_layout=1))
+    print(f"[parity] two-gross full size: B={len(syn)} variant={dec.info()['variant']}", flush=True)
+    out = dec.decode(torch.from_numpy(rb.pack_bits(syn)).cuda())
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    dec.close()
+    ok = validity.valid_shots(prob, gpu["corr"], syn)
+    np.testing.assert_array_equal(ok, gpu["conv"] == 1)
+    assert 0.3 < ok.mean() < 1.0
+    idx = np.sort(np.random.default_rng(4).choice(len(syn), 64, replace=False))
+    ref = oracle.decode(prob.m, prob.n, prob.rows, prob.cols, prob.prior, RELAY_DEFAULT, syn[idx])
+    np.testing.assert_array_equal(rb.unpack_bits(gpu["corr"][idx], prob.n), ref["corr"])
+    for k in ("conv", "legs", "iters", "weight"):
+        np.testing.assert_array_equal(gpu[k][idx], ref[k], err_msg=k)
+
+
 @pytest.mark.parametrize("anchor", [0, 1])
 def test_very_long_rows_and_heavy_columns(rb, anchor):
     """Rows of degree up to 250 (eight 32-position records each), columns of

@@ -472,6 +472,31 @@ def test_mixed_batch_parity(rb):
     dec.close()
 
 
+def test_mixed_full_size_parity(rb):
+    """The mixed-codes workload at full size, in the launch configuration the
+    benchmark times: the same 4x10^5 seeded syndromes of four BB codes
+    (4:3:2:1, p = 0.04, R = 20), tiles chosen by the autotuner on the first
+    20000 syndromes of each code, one mixed launch; every shot equals the
+    oracle's decode of its own code."""
+    b = 400000
+    probs, code_id, syn, per_code = _mixed_inputs(b)
+    dec = rb.MultiDecoder(probs, **RELAY_DEFAULT)
+    chosen = dec.autotune([torch.from_numpy(per_code[k][1][:20000]).cuda() for k in range(len(probs))], reps=2)
+    print(f"[parity] mixed full size: B={b} tiles={chosen}", flush=True)
+    out = dec.decode(torch.from_numpy(code_id).cuda(), torch.from_numpy(syn).cuda())
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items() if k != "workspace"}
+    dec.close()
+    for k, pr in enumerate(probs):
+        idx, s = per_code[k]
+        ref = oracle.decode(pr.m, pr.n, pr.rows, pr.cols, pr.prior, RELAY_DEFAULT, s)
+        np.testing.assert_array_equal(g["corr"][idx, :pr.n], ref["corr"], err_msg=MIX_CODES[k])
+        for key in ("conv", "legs", "iters", "weight"):
+            np.testing.assert_array_equal(g[key][idx], ref[key], err_msg=f"{MIX_CODES[k]} {key}")
+        ok = (ref["corr"].astype(np.int64) @ pr.dense().astype(np.int64).T) % 2 == s
+        np.testing.assert_array_equal(ok.all(1), ref["conv"] == 1)
+
+
 def test_mixed_batch_every_tile(rb):
     """Every tile of the mixed kernel that fits a code, forced per code
     (rb_set_code_variant), in rounds that give each code its next fitting
