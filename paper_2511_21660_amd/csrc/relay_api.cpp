@@ -15,6 +15,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,6 +43,40 @@ rb_status hip_fail(hipError_t e, const char *what) {
         hipError_t e_ = (call);                     \
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
+
+// No C++ exception leaves the C ABI: every entry point that returns an
+// rb_status is a function-try-block whose handler calls host_exception(),
+// which turns a host allocation failure (std::bad_alloc from a table, a plan
+// or a message) into RB_E_OOM and any other exception into RB_E_INTERNAL.
+// Contexts under construction are held by owning pointers, so nothing leaks
+// on the way out.
+rb_status host_exception() noexcept {
+    const char *msg = "host exception";
+    rb_status st = RB_E_INTERNAL;
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        msg = "host allocation failed";
+        st = RB_E_OOM;
+    } catch (const std::exception &ex) {
+        try {
+            g_last_error = std::string("host exception: ") + ex.what();
+            return st;
+        } catch (...) {
+        }
+    } catch (...) {
+    }
+    try {
+        g_last_error = msg;
+    } catch (...) {
+    }
+    return st;
+}
+
+struct CtxDeleter {
+    void operator()(rb_ctx *c) const { rb_destroy(c); }
+};
+using CtxPtr = std::unique_ptr<rb_ctx, CtxDeleter>;
 
 }  // namespace
 
@@ -1725,7 +1761,8 @@ rb_status host_graph(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int3
         if (rc[k] == rc[k - 1])
             return fail(RB_E_DUPLICATE_ENTRY, "duplicate entry (" + std::to_string(rc[k].first) + ", " +
                                                   std::to_string(rc[k].second) + ")");
-    rb_ctx *c = new (std::nothrow) rb_ctx();
+    CtxPtr own(new (std::nothrow) rb_ctx());
+    rb_ctx *c = own.get();
     if (!c) return fail(RB_E_OOM, "host allocation failed");
     c->M = M;
     c->N = N;
@@ -1760,7 +1797,7 @@ rb_status host_graph(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int3
         c->w64[j] = std::log((1.0 - prior_p[j]) / prior_p[j]);
         c->w[j] = (float)c->w64[j];
     }
-    *out = c;
+    *out = own.release();
     return RB_OK;
 }
 
@@ -1819,7 +1856,7 @@ const char *rb_status_string(rb_status s) {
 
 const char *rb_last_error_message(void) { return g_last_error.c_str(); }
 
-rb_status rb_params_default(rb_params *out) {
+rb_status rb_params_default(rb_params *out) try {
     if (!out) return fail(RB_E_INVALID_ARG, "out is NULL");
     std::memset(out, 0, sizeof(*out));
     out->num_legs = 301;
@@ -1836,11 +1873,13 @@ rb_status rb_params_default(rb_params *out) {
     out->io_layout = RB_IO_BYTES;
     out->precision = RB_PREC_F32;
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32_t *rows,
                     const int32_t *cols, const double *prior_p, const rb_params *params,
-                    int32_t device) {
+                    int32_t device) try {
     g_last_error.clear();
     if (!out) return fail(RB_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -1850,44 +1889,37 @@ rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32
     if (st != RB_OK) return st;
     rb_ctx *c = nullptr;
     if ((st = host_graph(&c, M, N, nnz, rows, cols, prior_p)) != RB_OK) return st;
+    CtxPtr own(c);
     c->device = device;
     c->params = *params;
     const int best = choose_variant(c);
-    if (best < 0) {
-        const std::string msg = unsupported_message(c);
-        delete c;
-        return fail(RB_E_UNSUPPORTED, msg);
-    }
+    if (best < 0) return fail(RB_E_UNSUPPORTED, unsupported_message(c));
 
-    auto bail = [&](rb_status s2) {
-        rb_destroy(c);
-        return s2;
-    };
     hipError_t e = hipSetDevice(device);
-    if (e != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, device);
-    if (e != hipSuccess) return bail(hip_fail(e, "hipGetDeviceProperties"));
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
     c->num_cu = prop.multiProcessorCount;
     const int R = params->num_legs;
     // (both tables end in kGroupReadPad floats of zeros: see relay_internal.h)
     if ((e = hipMalloc(&c->d_w, sizeof(float) * ((size_t)N + rb::kGroupReadPad))) != hipSuccess)
-        return bail(hip_fail(e, "hipMalloc(w)"));
+        return hip_fail(e, "hipMalloc(w)");
     if ((e = hipMalloc(&c->d_gamma, sizeof(float) * ((size_t)N * (size_t)R + rb::kGroupReadPad))) != hipSuccess)
-        return bail(hip_fail(e, "hipMalloc(gamma)"));
+        return hip_fail(e, "hipMalloc(gamma)");
     if ((e = hipMemset(c->d_w + N, 0, sizeof(float) * rb::kGroupReadPad)) != hipSuccess ||
         (e = hipMemset(c->d_gamma + (size_t)N * R, 0, sizeof(float) * rb::kGroupReadPad)) != hipSuccess)
-        return bail(hip_fail(e, "clear table padding"));
+        return hip_fail(e, "clear table padding");
     if ((e = hipMalloc(&c->d_queue, sizeof(unsigned long long) * rb::kQueueWords)) != hipSuccess)
-        return bail(hip_fail(e, "hipMalloc(queue)"));
+        return hip_fail(e, "hipMalloc(queue)");
     if ((e = hipMemcpy(c->d_w, c->w.data(), sizeof(float) * (size_t)N, hipMemcpyHostToDevice)) != hipSuccess)
-        return bail(hip_fail(e, "copy w"));
+        return hip_fail(e, "copy w");
     if ((e = rb::launch_gamma_table(c->d_gamma, R, N, params->seed, params->gamma_first, params->gamma_lo,
                                     params->gamma_hi, nullptr)) != hipSuccess)
-        return bail(hip_fail(e, "gamma table kernel"));
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(hip_fail(e, "gamma table sync"));
+        return hip_fail(e, "gamma table kernel");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "gamma table sync");
     st = plan(c, best);
-    if (st != RB_OK) return bail(st);
+    if (st != RB_OK) return st;
     {
         std::vector<int32_t> rp(c->rowptr.begin(), c->rowptr.end()), cp(c->colptr.begin(), c->colptr.end());
         std::vector<int32_t> ce((size_t)nnz);
@@ -1896,10 +1928,12 @@ rb_status rb_create(rb_ctx **out, int32_t M, int32_t N, int64_t nnz, const int32
             (st = upload(&c->d_colidx, c->colidx, "upload colidx")) != RB_OK ||
             (st = upload(&c->d_colptr, cp, "upload colptr")) != RB_OK ||
             (st = upload(&c->d_cedge, ce, "upload edge map")) != RB_OK)
-            return bail(st);
+            return st;
     }
-    *out = c;
+    *out = own.release();
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 void rb_destroy(rb_ctx *c) {
@@ -2134,7 +2168,7 @@ static rb_status launch(rb_ctx *c, const rb::GroupArgs &a, bool trace, hipStream
 
 rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr, uint8_t *d_conv,
                     int32_t *d_legs, int32_t *d_iters, double *d_weight, float *d_final_llr,
-                    void *stream) {
+                    void *stream) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (B < 0) return fail(RB_E_INVALID_ARG, "B must be >= 0");
@@ -2164,10 +2198,12 @@ rb_status rb_decode(rb_ctx *c, int64_t B, const uint8_t *d_syn, uint8_t *d_corr,
         return RB_OK;
     }
     return launch(c, a, false, (hipStream_t)stream);
+} catch (...) {
+    return host_exception();
 }
 
 rb_status rb_syndrome(const rb_ctx *c, int64_t B, const uint8_t *d_corr, const uint8_t *d_syn_in,
-                      uint8_t *d_syn_out, void *stream) {
+                      uint8_t *d_syn_out, void *stream) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use a single code's context");
@@ -2180,10 +2216,12 @@ rb_status rb_syndrome(const rb_ctx *c, int64_t B, const uint8_t *d_corr, const u
                                c->params.io_layout == RB_IO_BITS32, (hipStream_t)stream),
            "syndrome kernel launch");
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma, float scale,
-                   int32_t T, float *d_trace, void *stream) {
+                   int32_t T, float *d_trace, void *stream) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: trace one code's own context");
@@ -2202,9 +2240,11 @@ rb_status rb_trace(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_ga
     a.trace_T = T;
     a.trace = d_trace;
     return launch(c, a, true, (hipStream_t)stream);
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_set_leg_gamma(rb_ctx *c, int32_t leg, const float *host_gamma) {
+rb_status rb_set_leg_gamma(rb_ctx *c, int32_t leg, const float *host_gamma) try {
     g_last_error.clear();
     if (!c || !host_gamma) return fail(RB_E_INVALID_ARG, "NULL argument");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: set the gamma of a single-code context");
@@ -2228,9 +2268,11 @@ rb_status rb_set_leg_gamma(rb_ctx *c, int32_t leg, const float *host_gamma) {
         RB_HIP(hipDeviceSynchronize(), "gamma by slot");
     }
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_set_prior_scale(rb_ctx *c, float scale) {
+rb_status rb_set_prior_scale(rb_ctx *c, float scale) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: set the scale of a single-code context");
@@ -2240,16 +2282,20 @@ rb_status rb_set_prior_scale(rb_ctx *c, float scale) {
     RB_HIP(hipDeviceSynchronize(), "synchronise before scale update");
     c->prior_scale = scale;
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_get_llr(const rb_ctx *c, float *host_w) {
+rb_status rb_get_llr(const rb_ctx *c, float *host_w) try {
     if (!c || !host_w) return fail(RB_E_INVALID_ARG, "NULL argument");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context");
     std::memcpy(host_w, c->w.data(), sizeof(float) * (size_t)c->N);
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_get_gamma_table(const rb_ctx *c, float *host_gamma) {
+rb_status rb_get_gamma_table(const rb_ctx *c, float *host_gamma) try {
     if (!c || !host_gamma) return fail(RB_E_INVALID_ARG, "NULL argument");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context");
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
@@ -2257,9 +2303,11 @@ rb_status rb_get_gamma_table(const rb_ctx *c, float *host_gamma) {
                      hipMemcpyDeviceToHost),
            "copy gamma table");
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_get_info(const rb_ctx *c, rb_info *info) {
+rb_status rb_get_info(const rb_ctx *c, rb_info *info) try {
     if (!c || !info) return fail(RB_E_INVALID_ARG, "NULL argument");
     std::memset(info, 0, sizeof(*info));
     info->M = c->M;
@@ -2301,9 +2349,11 @@ rb_status rb_get_info(const rb_ctx *c, rb_info *info) {
     info->grid_blocks = c->blocks_per_cu[0] * c->num_cu;
     info->num_variants = total_variants();
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_set_variant(rb_ctx *c, int32_t v) {
+rb_status rb_set_variant(rb_ctx *c, int32_t v) try {
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use rb_autotune_multi");
     if (v < 0 || v >= total_variants()) return fail(RB_E_INVALID_ARG, "variant out of range");
@@ -2311,10 +2361,12 @@ rb_status rb_set_variant(rb_ctx *c, int32_t v) {
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(hipDeviceSynchronize(), "sync before re-plan");
     return plan(c, v);
+} catch (...) {
+    return host_exception();
 }
 
 rb_status rb_plan_check(int32_t M, int32_t N, int64_t nnz, const int32_t *rows, const int32_t *cols,
-                        int32_t variant, rb_plan_report *out) {
+                        int32_t variant, rb_plan_report *out) try {
     g_last_error.clear();
     if (!out) return fail(RB_E_INVALID_ARG, "out is NULL");
     std::memset(out, 0, sizeof(*out));
@@ -2322,12 +2374,10 @@ rb_status rb_plan_check(int32_t M, int32_t N, int64_t nnz, const int32_t *rows, 
     rb_ctx *c = nullptr;
     rb_status st = host_graph(&c, M, N, nnz, rows, cols, nullptr);
     if (st != RB_OK) return st;
+    CtxPtr own(c);
     const int v = variant < 0 ? choose_variant(c) : variant;
-    if (v < 0 || !any_fits(c, v)) {
-        const std::string msg = v < 0 ? unsupported_message(c) : "graph does not fit the variant";
-        delete c;
-        return fail(RB_E_UNSUPPORTED, msg);
-    }
+    if (v < 0 || !any_fits(c, v))
+        return fail(RB_E_UNSUPPORTED, v < 0 ? unsupported_message(c) : "graph does not fit the variant");
     out->variant = v;
     std::string err;
     if (v < rb::num_variants()) {
@@ -2342,9 +2392,10 @@ rb_status rb_plan_check(int32_t M, int32_t N, int64_t nnz, const int32_t *rows, 
         out->block_kernel = 2;
         err = check_large_tables(c, s, large_tables(c, s), out);
     }
-    delete c;
     if (!err.empty()) return fail(RB_E_INTERNAL, "gather tables of variant " + std::to_string(v) + ": " + err);
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 // mean time of one decode of B syndromes with the context's current plan
@@ -2387,7 +2438,7 @@ static rb_status time_variant(rb_ctx *c, int64_t B, const uint8_t *d_syn, int32_
 }
 
 rb_status rb_autotune(rb_ctx *c, int64_t B, const uint8_t *d_syn, int32_t reps,
-                      int32_t *chosen_variant, float *best_ms) {
+                      int32_t *chosen_variant, float *best_ms) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->multi) return fail(RB_E_INVALID_ARG, "mixed-code context: use rb_autotune_multi");
@@ -2446,6 +2497,8 @@ rb_status rb_autotune(rb_ctx *c, int64_t B, const uint8_t *d_syn, int32_t reps,
     if (chosen_variant) *chosen_variant = best;
     if (best_ms) *best_ms = best_t;
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 static int64_t train_shot_floats(const rb_ctx *c, int32_t T, int32_t C) {
@@ -2493,7 +2546,7 @@ static rb_status train_args(const rb_ctx *c, int64_t B, const uint8_t *d_syn, co
 
 rb_status rb_forward_train(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma, const float *d_scale,
                            int32_t T, int32_t ckpt_every, float *d_llr_out, void *d_tape, size_t tape_bytes,
-                           void *stream) {
+                           void *stream) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->h16) return fail(RB_E_UNSUPPORTED, "training runs in FP32: create the context with RB_PREC_F32");
@@ -2506,11 +2559,13 @@ rb_status rb_forward_train(rb_ctx *c, int64_t B, const uint8_t *d_syn, const flo
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(rb::launch_train_forward(a, (hipStream_t)stream), "training forward launch");
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 rb_status rb_backward(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d_gamma, const float *d_scale,
                       int32_t T, int32_t ckpt_every, void *d_tape, size_t tape_bytes, const float *d_dllr,
-                      float *d_dgamma, float *d_dscale, void *stream) {
+                      float *d_dgamma, float *d_dscale, void *stream) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (c->h16) return fail(RB_E_UNSUPPORTED, "training runs in FP32: create the context with RB_PREC_F32");
@@ -2524,6 +2579,8 @@ rb_status rb_backward(rb_ctx *c, int64_t B, const uint8_t *d_syn, const float *d
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(rb::launch_train_backward(a, (hipStream_t)stream), "training backward launch");
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 size_t rb_workspace_size(const rb_ctx *c, int64_t B) {
@@ -2531,7 +2588,7 @@ size_t rb_workspace_size(const rb_ctx *c, int64_t B) {
     return rb::shot_list_bytes(B, c->multi ? (int)c->subs.size() : 1);
 }
 
-rb_status rb_reserve(rb_ctx *c, int64_t B) {
+rb_status rb_reserve(rb_ctx *c, int64_t B) try {
     g_last_error.clear();
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     if (B < 0 || B > INT32_MAX) return fail(RB_E_INVALID_ARG, "B must be in [0, 2^31)");
@@ -2550,6 +2607,8 @@ rb_status rb_reserve(rb_ctx *c, int64_t B) {
     }
     c->ws_capacity = B;
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 namespace {
@@ -2642,7 +2701,7 @@ rb_status upload_codes(rb_ctx *m) {
 }  // namespace
 
 rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *codes, const rb_params *params,
-                          int32_t device) {
+                          int32_t device) try {
     g_last_error.clear();
     if (!out) return fail(RB_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -2651,8 +2710,10 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
     if (st != RB_OK) return st;
     if (params->precision != RB_PREC_F32)
         return fail(RB_E_UNSUPPORTED, "the mixed launch decodes in FP32 (RB_PREC_F32)");
-    rb_ctx *m = new (std::nothrow) rb_ctx();
+    CtxPtr own(new (std::nothrow) rb_ctx());
+    rb_ctx *m = own.get();
     if (!m) return fail(RB_E_OOM, "host allocation failed");
+    m->subs.reserve((size_t)n_codes);  // so that adding a created code cannot throw
     m->multi = true;
     m->device = device;
     m->params = *params;
@@ -2662,7 +2723,6 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
                        params, device);
         if (st != RB_OK) {
             const std::string msg = "code " + std::to_string(k) + ": " + g_last_error;
-            rb_destroy(m);
             return fail(st, msg);
         }
         m->subs.push_back(s);
@@ -2677,14 +2737,8 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
                 best_cost = cost;
             }
         }
-        if (best < 0) {
-            rb_destroy(m);
-            return fail(RB_E_UNSUPPORTED, "code " + std::to_string(k) + " fits no tile of the mixed launch");
-        }
-        if ((st = plan(s, best)) != RB_OK) {
-            rb_destroy(m);
-            return st;
-        }
+        if (best < 0) return fail(RB_E_UNSUPPORTED, "code " + std::to_string(k) + " fits no tile of the mixed launch");
+        if ((st = plan(s, best)) != RB_OK) return st;
         m->m_max = std::max(m->m_max, s->M);
         m->n_max = std::max(m->n_max, s->N);
     }
@@ -2693,17 +2747,13 @@ rb_status rb_create_multi(rb_ctx **out, int32_t n_codes, const rb_code_desc *cod
     m->N = m->n_max;
     std::vector<int32_t> ms;
     for (rb_ctx *s : m->subs) ms.push_back(s->M);
-    if ((st = upload(&m->d_code_m, ms, "upload code rows")) != RB_OK || (st = upload_codes(m)) != RB_OK) {
-        rb_destroy(m);
-        return st;
-    }
+    if ((st = upload(&m->d_code_m, ms, "upload code rows")) != RB_OK || (st = upload_codes(m)) != RB_OK) return st;
     hipError_t e = hipMalloc(&m->d_queues, sizeof(unsigned long long) * rb::kQueueWords * (size_t)n_codes);
-    if (e != hipSuccess) {
-        rb_destroy(m);
-        return hip_fail(e, "hipMalloc(queues)");
-    }
-    *out = m;
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(queues)");
+    *out = own.release();
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 // The mixed launch of rb_decode_multi: shot lists in `ws` (at least
@@ -2763,7 +2813,7 @@ static rb_status check_multi_args(const rb_ctx *c, int64_t B, const int32_t *d_c
 
 rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn, uint8_t *d_corr,
                           uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters, double *d_weight,
-                          float *d_final_llr, void *d_workspace, size_t workspace_bytes, void *stream) {
+                          float *d_final_llr, void *d_workspace, size_t workspace_bytes, void *stream) try {
     g_last_error.clear();
     rb_status st = check_multi_args(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters);
     if (st != RB_OK || B == 0) return st;
@@ -2773,6 +2823,8 @@ rb_status rb_decode_multi(rb_ctx *c, int64_t B, const int32_t *d_code_id, const 
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     return launch_decode_multi(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters, d_weight, d_final_llr,
                                d_workspace, c->d_queues, (hipStream_t)stream);
+} catch (...) {
+    return host_exception();
 }
 
 // Layout of the static scratch for a context of nc codes: nc queues, then
@@ -2793,7 +2845,7 @@ int64_t rb_noalloc_max_batch(const rb_ctx *c) {
 
 rb_status rb_decode_multi_noalloc(rb_ctx *c, int64_t B, const int32_t *d_code_id, const uint8_t *d_syn,
                                   uint8_t *d_corr, uint8_t *d_conv, int32_t *d_legs, int32_t *d_iters,
-                                  double *d_weight, float *d_final_llr, void *stream) {
+                                  double *d_weight, float *d_final_llr, void *stream) try {
     g_last_error.clear();
     rb_status st = check_multi_args(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters);
     if (st != RB_OK || B == 0) return st;
@@ -2809,10 +2861,12 @@ rb_status rb_decode_multi_noalloc(rb_ctx *c, int64_t B, const int32_t *d_code_id
     return launch_decode_multi(c, B, d_code_id, d_syn, d_corr, d_conv, d_legs, d_iters, d_weight, d_final_llr,
                                (unsigned char *)base + noalloc_list_offset(nc), (unsigned long long *)base,
                                (hipStream_t)stream);
+} catch (...) {
+    return host_exception();
 }
 
 rb_status rb_autotune_multi(rb_ctx *c, const int64_t *sample_b, const uint8_t *const *d_samples, int32_t reps,
-                            int32_t *chosen_variants) {
+                            int32_t *chosen_variants) try {
     g_last_error.clear();
     if (!c || !c->multi) return fail(RB_E_INVALID_ARG, "not a mixed-code context");
     if (!sample_b || !d_samples || reps < 1) return fail(RB_E_INVALID_ARG, "bad samples");
@@ -2841,9 +2895,11 @@ rb_status rb_autotune_multi(rb_ctx *c, const int64_t *sample_b, const uint8_t *c
         if (chosen_variants) chosen_variants[k] = s->variant;
     }
     return upload_codes(c);
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_set_code_variant(rb_ctx *c, int32_t k, int32_t variant) {
+rb_status rb_set_code_variant(rb_ctx *c, int32_t k, int32_t variant) try {
     g_last_error.clear();
     if (!c || !c->multi) return fail(RB_E_INVALID_ARG, "not a mixed-code context");
     if (k < 0 || k >= (int32_t)c->subs.size()) return fail(RB_E_INVALID_ARG, "code index out of range");
@@ -2854,14 +2910,18 @@ rb_status rb_set_code_variant(rb_ctx *c, int32_t k, int32_t variant) {
     rb_status st = rb_set_variant(c->subs[(size_t)k], variant);
     if (st != RB_OK) return st;
     return upload_codes(c);
+} catch (...) {
+    return host_exception();
 }
 
-rb_status rb_sync_status(rb_ctx *c) {
+rb_status rb_sync_status(rb_ctx *c) try {
     if (!c) return fail(RB_E_INVALID_ARG, "ctx is NULL");
     RB_HIP(hipSetDevice(c->device), "hipSetDevice");
     RB_HIP(hipDeviceSynchronize(), "device synchronize");
     RB_HIP(hipGetLastError(), "asynchronous error");
     return RB_OK;
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"

@@ -130,3 +130,42 @@ def test_null_arguments(lib):
     assert lib.rb_noalloc_max_batch(None) == 0
     assert lib.rb_set_code_variant(None, 0, 0) == 1
     lib.rb_destroy(None)
+
+
+_OOM_CHILD = r"""
+import ctypes, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_2511_21660_amd import relaybp as rb
+L = rb.load_library()
+# a valid 20000 x 20000 graph of 2x10^7 distinct entries (1000 per row)
+k = np.arange(20_000_000, dtype=np.int64)
+rows = (k // 1000).astype(np.int32)
+cols = ((k % 1000) * 20 + (k // 1000) % 20).astype(np.int32)
+rep = rb.RBPlanReport()
+# cap the address space a little above what the process holds now, so the
+# library's 160 MB of sorted entry pairs cannot be allocated
+vm = int([l.split()[1] for l in open("/proc/self/status") if l.startswith("VmSize:")][0]) * 1024
+resource.setrlimit(resource.RLIMIT_AS, (vm + (32 << 20), resource.RLIM_INFINITY))
+st = L.rb_plan_check(20000, 20000, rows.size, rows.ctypes.data_as(ctypes.c_void_p),
+                     cols.ctypes.data_as(ctypes.c_void_p), -1, ctypes.byref(rep))
+print(st, L.rb_last_error_message().decode(), flush=True)
+"""
+
+
+def test_host_allocation_failure_returns_oom_instead_of_aborting(tmp_path):
+    """A host allocation that fails inside the library (here: the sorted entry
+    list of a large graph, under an address-space cap) comes back as
+    RB_E_OOM with a message; no C++ exception crosses the C ABI."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "oom_child.py"
+    script.write_text(_OOM_CHILD)
+    res = subprocess.run([sys.executable, str(script), root], capture_output=True, text=True, timeout=120,
+                         env=dict(os.environ, OMP_NUM_THREADS="1"))
+    assert res.returncode == 0, res.stderr[-2000:]
+    status, msg = res.stdout.strip().split(" ", 1)
+    assert int(status) == 6 and "allocation" in msg, res.stdout
